@@ -1,0 +1,19 @@
+"""FP64 CPU oracle for the docking hot path -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, readable NumPy code that states what the GPU path must compute:
+genotype -> pose, grid (intermolecular) energy, intramolecular pair energy, the
+analytic genotype gradient, ADADELTA local search and the Lamarckian genetic
+algorithm.  Only the test suite, the smoke check and the benchmark's CPU baseline
+may import it.  The product library never calls it and shares no code with it.
+
+Where the paper (Background, "Design and Structure of MiniMDock") only names a
+part of the method, the functional form is the AutoDock4 lineage the paper builds
+on (its references on AutoDock-GPU and on gradient-based local search in
+AutoDock4); each such reading is listed with its constant values in `constants`.
+
+Pins: every function here is checked by `tests/test_oracle_*.py` against closed
+forms, library routines (scipy interpolation and rotations, torch's Adadelta),
+invariances, finite differences or brute force.  The LGA operator choices beyond
+its invariants are "parity unpinned" (see `lga`).
+"""
+from . import constants, rng, ligand, pose, scoring, adadelta, lga  # noqa: F401
