@@ -1,0 +1,200 @@
+"""Benchmark of the docking hot path on one MI355X.
+
+One step = one complete dock of the production workload (64^3 grid, one ligand of 40 atoms /
+8 rotatable bonds, 20 LGA runs x 150 individuals, 2.5M evaluations per run, ADADELTA local
+search of 300 steps on every individual every generation): initial population, every GA
+generation, every local search, evaluation accounting and best-of-runs, through md_dock.
+Inputs (grid maps, ligand) are resident on the device before the timed region.
+
+Prints one JSON line.  value = energy+gradient evaluations per second (the ADADELTA steps,
+each one energy and gradient evaluation); ligands docked per second and per-ligand latency
+percentiles ride along.  roofline: the local-search kernel's algorithmic work per launch over
+its average launch time, timed with HIP events on the dock's stream.  cpu_baseline: the FP64
+oracle's energy+gradient evaluations per second on the host cores, on a bounded sample of
+random poses of the same ligand and grid.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WORKLOAD = "plain_fp32_production"
+PEAK_FP32_VALU_TFLOPS = 157.3     # MI355X published FP32 vector peak
+PEAK_HBM_GBS = 8000.0
+
+
+def flop_model(n_atoms, n_torsions, n_pairs, sum_moving):
+    """Algorithmic flop-equivalents of one energy+gradient evaluation (transcendentals count 4):
+    pose 24*sum_M + 21*N + 25*T + 30, grid 170*N, pairs 75*P, reductions 12*sum_M + 12*N + 10*T."""
+    N, T, P, M = n_atoms, n_torsions, n_pairs, sum_moving
+    return (24 * M + 21 * N + 25 * T + 30) + 170 * N + 75 * P + (12 * M + 12 * N + 10 * T)
+
+
+def bytes_model(n_atoms, map_bytes=4):
+    """Algorithmic bytes of one evaluation: 8 corners x 3 maps per atom."""
+    return 24 * map_bytes * n_atoms
+
+
+# ------------------------------------------------------------------ CPU baseline (oracle)
+def _oracle_worker(args):
+    seed, budget_s = args
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[var] = "1"      # one thread per process: `cores` counts what is used
+    import numpy as np
+    from oracle import ligand as OL
+    from oracle import scoring as S
+    from workload import configs, synth
+    rec = configs.receptor(WORKLOAD)
+    lig = configs.ligand(WORKLOAD)
+    grid = S.make_grid(rec.maps, rec.origin, rec.spacing)
+    ol = OL.from_synth(lig)
+    genes = synth.random_genes(lig, rec, 4096, seed=seed, margin=2.0).astype(np.float64)
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        S.energy_and_gradient(grid, ol, genes[n % len(genes)], want_margin=False)
+        n += 1
+    return n, time.perf_counter() - t0
+
+
+def cpu_baseline(budget_s=10.0):
+    import multiprocessing as mp
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_worker, [(1000 + i, budget_s) for i in range(cores)])
+    wall = time.perf_counter() - t0
+    n = sum(r[0] for r in res)
+    per_proc = max(r[1] for r in res)
+    cpu = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": n / per_proc, "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle energy+gradient of random poses of the {WORKLOAD} ligand on its "
+                      f"64^3 grid, one process per core, {budget_s:.0f} s each ({n} evals, "
+                      f"{wall:.1f} s wall incl. start-up); CPU: {cpu}"}
+
+
+# ------------------------------------------------------------------ GPU
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--seed", type=int, default=7)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the docking path has "
+              f"no cross-GPU work to measure here", file=sys.stderr)
+        sys.exit(2)
+
+    # the oracle baseline runs first, in spawned processes, before this process touches the GPU
+    base = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)
+
+    import numpy as np
+    import torch
+
+    import paper_2203_02096_amd as md
+    from workload import configs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    md.lib()
+    rec = configs.receptor(WORKLOAD)
+    lig = configs.ligand(WORKLOAD)
+    drec = md.Receptor(rec.maps, rec.origin, rec.spacing, "fp32")
+    dlig = md.Ligand.from_synth(lig)
+    info = md.md_ligand_info(dlig)
+    sp = configs.search_params(WORKLOAD, seed=args.seed)
+    P = md.dock_params(**sp)
+    gens = md.md_dock_planned_generations(P)
+    n_ls = max(0, min(P.pop_size, math.ceil(sp["ls_rate"] * P.pop_size - 1e-4)))
+    ls_evals = P.n_runs * gens * n_ls * P.ls_iters
+    total_evals = P.n_runs * (P.pop_size + gens * ((P.pop_size - P.elitism) + n_ls * P.ls_iters))
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        md.md_dock(drec, dlig, P, stream=stream, want_xyz=False)
+    torch.cuda.synchronize()
+    md.md_profile_reset()
+    md.md_profile_enable(True)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        res = md.md_dock(drec, dlig, P, stream=stream, want_xyz=False)   # blocking
+        lat.append(time.perf_counter() - s0)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    md.md_profile_enable(False)
+    ls_ms, ls_n = md.md_profile_read("local_search")
+    kern = {k: md.md_profile_read(k) for k in md.mdock.KERNELS}
+
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = ls_evals / (elapsed / args.steps)
+    evals_per_ls_launch = P.n_runs * n_ls * P.ls_iters
+    flops_eval = flop_model(info["n_atoms"], info["n_torsions"], info["n_pairs"], info["sum_moving"])
+    avg_ls_s = ls_ms / 1e3 / max(ls_n, 1)
+    achieved_tflops = flops_eval * evals_per_ls_launch / avg_ls_s / 1e12
+    hbm_gbs = bytes_model(info["n_atoms"]) * evals_per_ls_launch / avg_ls_s / 1e9
+    lat_ms = np.array(lat) * 1e3
+    out = {
+        "metric": "energy+gradient evals/s",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "grid": "64^3 x 9 maps FP32, 0.375 A",
+                   "n_atoms": info["n_atoms"], "n_torsions": info["n_torsions"],
+                   "n_pairs": info["n_pairs"], "n_runs": P.n_runs, "pop_size": P.pop_size,
+                   "max_evals_per_run": P.max_evals_per_run, "generations": gens,
+                   "ls_rate": sp["ls_rate"], "ls_iters": P.ls_iters},
+        "ligands_per_s": 1.0 / (elapsed / args.steps),
+        "total_evals_per_s": total_evals / (elapsed / args.steps),
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
+        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_VALU_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_VALU_TFLOPS,
+                     "traffic": None, "kernel": "k_local_search",
+                     "flop_per_eval": flops_eval, "evals_per_launch": evals_per_ls_launch,
+                     "avg_launch_ms": avg_ls_s * 1e3, "launches": ls_n,
+                     "hbm_algorithmic_GBs": hbm_gbs, "hbm_frac": hbm_gbs / PEAK_HBM_GBS},
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kern.items()},
+        "best_energy": float(res["best_energy"][0]),
+        "cpu_baseline": base,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,228 @@
+/*
+ * mdock.h -- C ABI of libmdock, an MI355X (gfx950) implementation of the hot path of
+ * AutoDock-style docking as the MiniMDock miniapp captures it: per-pose energy and
+ * genotype gradient driving ADADELTA local search inside a Lamarckian genetic
+ * algorithm, data-parallel over poses, runs and atoms.
+ *
+ * Paper passages (arXiv 2203.02096):
+ *  - Background, "Design and Structure of MiniMDock": receptor as a 3-D grid
+ *    ("reaction field"), ligand as point atoms with self-interactions (H-bonding,
+ *    van der Waals, desolvation); degrees of freedom = translation + rotatable bonds
+ *    (+ orientation); genetic algorithm with crossover, fitness-based selection and a
+ *    Lamarckian local search on a random sample of each generation; several runs of
+ *    150 individuals at once, answer = best pose over all runs.
+ *  - Section "Approach 1" (listing of decomposed target functions): energy kernel =
+ *    per-atom positions, rotations applied in a fixed order, per-atom energy sum.
+ *  - Section "Removing architecture-specific code" (sum_evals listings): evaluations
+ *    counted per individual and summed per run.
+ * The functional forms the paper leaves out follow the AutoDock4 lineage it builds on;
+ * each is stated at the entry point that computes it.
+ *
+ * Conventions
+ *  - Every call returns md_status; no exception crosses the ABI.  On error nothing is
+ *    written to outputs and no handle is created; md_last_error() gives a message
+ *    (thread-local, valid until the next failing call on the same thread).
+ *  - Handles are owned by the library and freed by their _destroy call.  _create calls
+ *    copy their inputs, so the caller may free them afterwards.
+ *  - "dev" pointers are device memory on the current HIP device (e.g. a torch tensor's
+ *    data_ptr()), owned by the caller.  "host" pointers are ordinary host memory.
+ *  - hip_stream is a hipStream_t passed as void* (NULL = the default stream).  Calls
+ *    that take a stream only enqueue work on it unless stated as blocking.
+ *  - Limits: 1 <= n_atoms <= 128, 0 <= n_torsions <= 32 (so n_genes = 7 + n_torsions
+ *    <= 39).  Exceeding them returns MD_ERANGE.
+ *  - Genotype layout: genes[0:3] translation (Angstrom) of the ligand's reference
+ *    centroid; genes[3:7] orientation quaternion (w, x, y, z), used after
+ *    normalisation; genes[7:] torsion angles (radians) relative to the input
+ *    conformation, right-handed about each rotatable bond taken from its root-side
+ *    atom to its far atom, in the order the torsions were given.
+ */
+#ifndef MDOCK_H
+#define MDOCK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MD_OK = 0,
+  MD_EINVAL = -1,     /* malformed argument (null pointer, bad tree, bad index, NaN ...) */
+  MD_ERANGE = -2,     /* size outside the supported limits */
+  MD_ENOMEM = -3,     /* device or host allocation failed */
+  MD_EDEVICE = -4,    /* a HIP call failed (no device, launch failure ...) */
+  MD_EBUSY = -5,
+  MD_ENOTFOUND = -6,
+  MD_ECANCELED = -7
+} md_status;
+
+typedef enum { MD_MAP_FP32 = 0, MD_MAP_FP16 = 1, MD_MAP_BF16 = 2 } md_map_precision;
+
+typedef struct md_receptor md_receptor;   /* opaque */
+typedef struct md_ligand md_ligand;       /* opaque */
+
+/* ------------------------------------------------------------------ receptor grid
+ * The receptor's "reaction field" (Background, "Design and Structure of MiniMDock"):
+ * n_types atom-type affinity maps, then one electrostatic map (kcal/mol per e) and one
+ * desolvation map (kcal/mol per |e|), all sampled on the same grid.  Node (a, b, c) sits
+ * at origin + spacing * (a, b, c).
+ */
+typedef struct {
+  int nx, ny, nz;       /* nodes per axis, each >= 2 */
+  float spacing;        /* Angstrom, > 0 */
+  float origin[3];      /* Angstrom */
+  int n_types;          /* number of atom-type maps; must be 7 */
+} md_grid_desc;
+
+/* maps: host float32, layout [n_types + 2][nz][ny][nx], finite values.
+ * stored: storage precision on the device (FP16/BF16 round to nearest even; the
+ * interpolation and everything after it stays FP32).  The copy is complete when the
+ * call returns.  Errors: MD_EINVAL (null/non-finite/bad sizes), MD_ENOMEM, MD_EDEVICE. */
+md_status md_receptor_create(const md_grid_desc* desc, const float* maps,
+                             md_map_precision stored, void* hip_stream, md_receptor** out);
+md_status md_receptor_destroy(md_receptor* rec);
+
+/* ------------------------------------------------------------------ ligand
+ * Point atoms joined by a bond tree; the listed bonds are rotatable (degrees of freedom
+ * together with translation and orientation; Background, "Design and Structure of
+ * MiniMDock").  The library moves the reference coordinates so their centroid is the
+ * origin, orients each torsion from the root side, finds each torsion's moving set, and
+ * builds the intramolecular pair list: pairs at least three bonds apart whose path
+ * crosses a rotatable bond.
+ *
+ * type_params: [n_types][7] float, per type: R_eq (A), eps (kcal/mol), volume (A^3),
+ * solvation parameter, H-bond role (0 none, 1 donor, 2 acceptor), R_hb (A), eps_hb.
+ */
+typedef struct {
+  int n_atoms;
+  const float* xyz;          /* host [n_atoms][3], Angstrom */
+  const int* type;           /* host [n_atoms], in [0, n_types) */
+  const float* charge;       /* host [n_atoms], e */
+  int n_bonds;               /* must be n_atoms - 1 */
+  const int* bonds;          /* host [n_bonds][2]; must form a tree */
+  int n_torsions;
+  const int* torsions;       /* host [n_torsions] indices into bonds; each bond must have
+                                further atoms on both ends (no terminal bond), no repeats */
+  int root_atom;             /* anchor of the tree, usually 0 */
+  int n_types;               /* must be 7 */
+  const float* type_params;  /* host [n_types][7] */
+} md_ligand_desc;
+
+/* Validates, preprocesses and uploads (synchronously, current device).
+ * Errors: MD_EINVAL, MD_ERANGE, MD_ENOMEM, MD_EDEVICE. */
+md_status md_ligand_create(const md_ligand_desc* desc, md_ligand** out);
+md_status md_ligand_destroy(md_ligand* lig);
+int md_ligand_num_genes(const md_ligand* lig);     /* 7 + n_torsions, or -1 for NULL */
+int md_ligand_num_atoms(const md_ligand* lig);
+int md_ligand_num_pairs(const md_ligand* lig);     /* intramolecular pairs */
+
+/* Work counts of a prepared ligand, for throughput models: atoms, torsions, intramolecular
+ * pairs and the sum over torsions of the number of atoms each one moves.  Any output pointer
+ * may be NULL.  Errors: MD_EINVAL (NULL ligand). */
+md_status md_ligand_info(const md_ligand* lig, int* n_atoms, int* n_torsions, int* n_pairs,
+                         int* sum_moving);
+
+/* ------------------------------------------------------------------ hot path, one pose
+ * Energy and analytic gradient of n_poses genotypes.  Energy = grid part + pair part:
+ *  grid part, per atom at grid coordinate g = (x - origin)/spacing: if every
+ *    0 <= g_a < n_a - 1, trilinear interpolation of (type map + q*electrostatic +
+ *    |q|*desolvation); otherwise 2^14 + 100 d^2 kcal/mol, d = distance to the grid box;
+ *  pair part (r clamped below 0.5 A, zero gradient there): 12-6 van der Waals or 12-10
+ *    H-bond for donor/acceptor pairs and Gaussian desolvation within 8 A, Coulomb with
+ *    the Mehler-Solmajer distance-dependent dielectric within 20.48 A, AutoDock4 weights.
+ * Gradient: d/dt = net force, d/dq through the torque and the normalisation (tangent to
+ * the unit sphere), d/dtheta_k = axis . sum over moved atoms of arm x force.
+ * genes_dev [n_poses][n_genes] f32, energy_dev [n_poses] f32, grad_dev [n_poses][n_genes]
+ * f32 or NULL (energy only).  Enqueued on hip_stream.  n_poses may be 0.
+ * Errors: MD_EINVAL (null handle/pointer, n_poses < 0), MD_EDEVICE. */
+md_status md_eval(const md_receptor* rec, const md_ligand* lig, int n_poses,
+                  const float* genes_dev, float* energy_dev, float* grad_dev,
+                  void* hip_stream);
+
+/* Posed atom coordinates: xyz_dev [n_poses][n_atoms][3] f32 (receptor frame, Angstrom). */
+md_status md_pose(const md_ligand* lig, int n_poses, const float* genes_dev, float* xyz_dev,
+                  void* hip_stream);
+
+/* ------------------------------------------------------------------ local search
+ * ADADELTA (Zeiler 2012; the gradient-based local search of the AutoDock4 GPU work the
+ * paper cites) from each start genotype: per step, evaluate (E, grad) at x, keep x if E
+ * is strictly below the best so far, then E[g^2] <- rho E[g^2] + (1-rho) g^2,
+ * dx = -sqrt(E[dx^2]+eps)/sqrt(E[g^2]+eps) * g, E[dx^2] <- rho E[dx^2] + (1-rho) dx^2,
+ * x += dx, renormalise the quaternion, wrap torsions to (-pi, pi].  n_iters steps cost
+ * n_iters evaluations.  Outputs the best genotype and its energy.
+ * genes_in_dev/genes_out_dev [n][n_genes] (may alias), energy_out_dev [n];
+ * trace_dev: NULL or [n][n_iters] energies of every step.
+ * Errors: MD_EINVAL (null, n < 0, n_iters < 1, rho not in [0,1), eps <= 0), MD_EDEVICE. */
+md_status md_local_search(const md_receptor* rec, const md_ligand* lig, int n,
+                          const float* genes_in_dev, float* genes_out_dev,
+                          float* energy_out_dev, int n_iters, float rho, float eps,
+                          float* trace_dev, void* hip_stream);
+
+/* ------------------------------------------------------------------ docking
+ * Lamarckian GA (Background, "Design and Structure of MiniMDock"): n_runs independent runs
+ * of pop_size individuals.  Initial individuals: translation uniform in the grid box,
+ * uniform random unit quaternion, torsions uniform in (-pi, pi].  Each generation:
+ * elitism (best copied to slot 0 when elitism = 1), binary tournaments (better wins with
+ * tournament_rate), two-point crossover over the units [t_x, t_y, t_z, q, theta_1..]
+ * with crossover_rate, per-unit mutation with mutation_rate (t += U(-mut_trans,
+ * mut_trans), q <- normalise(r (x) q) with r a rotation by U(-mut_rot, mut_rot) about a
+ * uniform axis, theta += U(-mut_tors, mut_tors)), energy of the new individuals, then
+ * ADADELTA (ls_iters steps, rho, eps) on ceil(ls_rate * pop_size) distinct random
+ * individuals, written back.  Evaluations are counted per individual and summed per run
+ * (sum_evals); a run stops at the first generation boundary where its count reaches
+ * max_evals_per_run or max_generations generations have run.  Random numbers:
+ * SplitMix64 counter hash of (seed, run, generation, individual, purpose, index).
+ */
+typedef struct {
+  int n_runs, pop_size;
+  long long max_evals_per_run;
+  int max_generations;
+  float ls_rate;
+  int ls_iters;
+  float rho, eps;
+  float crossover_rate, mutation_rate, tournament_rate;
+  int elitism;                 /* 0 or 1 */
+  float mut_trans, mut_rot, mut_tors;
+  unsigned long long seed;
+} md_dock_params;
+
+typedef struct {
+  int n_runs, n_genes, n_atoms;   /* capacities set by the caller (>= the problem's) */
+  float* best_energy;             /* host [n_runs], sorted ascending (ties: lower run) */
+  float* best_genes;              /* host [n_runs][n_genes] (row stride = n_genes cap) */
+  float* best_xyz;                /* host [n_runs][n_atoms][3] or NULL */
+  int* run_index;                 /* host [n_runs] original run of each row, or NULL */
+  long long* evals;               /* host [n_runs] or NULL */
+  int* generations;               /* host [n_runs] or NULL */
+} md_dock_result;
+
+/* Blocking: returns when the results are on the host.  Work runs on hip_stream.
+ * Errors: MD_EINVAL (bad parameters or result capacities), MD_ERANGE, MD_ENOMEM,
+ * MD_EDEVICE. */
+md_status md_dock(const md_receptor* rec, const md_ligand* lig, const md_dock_params* params,
+                  md_dock_result* out, void* hip_stream);
+
+/* Number of generations md_dock runs for these parameters (all runs share it). */
+int md_dock_planned_generations(const md_dock_params* params);
+
+/* ------------------------------------------------------------------ kernel timing
+ * When enabled, md_dock brackets every kernel it launches with HIP events on its stream and
+ * accumulates the elapsed times per kernel kind once the call has synchronised.  Process-wide,
+ * not thread-safe; meant for benchmarks.  kind: one of md_kernel_kind. */
+typedef enum {
+  MD_K_INIT_POPULATION = 0, MD_K_GENERATION = 1, MD_K_LS_PICK = 2, MD_K_LOCAL_SEARCH = 3,
+  MD_K_SUM_EVALS = 4, MD_K_BEST_OF_RUNS = 5, MD_K_COUNT = 6
+} md_kernel_kind;
+md_status md_profile_enable(int on);
+md_status md_profile_reset(void);
+/* Total milliseconds and number of timed launches of one kernel kind since the last reset. */
+md_status md_profile_read(int kind, double* total_ms, long long* launches);
+
+const char* md_last_error(void);
+const char* md_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MDOCK_H */

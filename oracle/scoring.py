@@ -54,57 +54,118 @@ def make_grid(maps, origin, spacing) -> Grid:
 
 # ---------------------------------------------------------------- grid term
 def trilinear(vol, g):
-    """Value and d/dg of the trilinear interpolant of vol[z][y][x] at grid point g=(gx,gy,gz),
-    which must satisfy 0 <= g_a < n_a - 1."""
+    """Value and d/dg of the trilinear interpolant of vol[z][y][x] at grid point(s) g=(gx,gy,gz)
+    (shape [3] or [M][3]), each satisfying 0 <= g_a < n_a - 1."""
+    g = np.asarray(g, dtype=np.float64)
+    single = g.ndim == 1
+    g = g.reshape(-1, 3)
     i = np.floor(g).astype(np.int64)
     f = g - i
-    val = 0.0
-    dval = np.zeros(3)
+    val = np.zeros(g.shape[0])
+    dval = np.zeros_like(g)
     for cz in (0, 1):
         for cy in (0, 1):
             for cx in (0, 1):
-                m = vol[i[2] + cz, i[1] + cy, i[0] + cx]
-                wx = f[0] if cx else 1.0 - f[0]
-                wy = f[1] if cy else 1.0 - f[1]
-                wz = f[2] if cz else 1.0 - f[2]
+                m = vol[i[:, 2] + cz, i[:, 1] + cy, i[:, 0] + cx]
+                wx = f[:, 0] if cx else 1.0 - f[:, 0]
+                wy = f[:, 1] if cy else 1.0 - f[:, 1]
+                wz = f[:, 2] if cz else 1.0 - f[:, 2]
                 val += wx * wy * wz * m
                 sx = 1.0 if cx else -1.0
                 sy = 1.0 if cy else -1.0
                 sz = 1.0 if cz else -1.0
-                dval += m * np.array([sx * wy * wz, wx * sy * wz, wx * wy * sz])
+                dval += m[:, None] * np.stack([sx * wy * wz, wx * sy * wz, wx * wy * sz], axis=1)
+    if single:
+        return float(val[0]), dval[0]
     return val, dval
 
 
+def trilinear_abs(vol, g):
+    """Condition scales of the interpolant at g ([M][3]): sum_c w_c |m_c| and, per axis,
+    sum_c |m_c| |d w_c / d g_a| -- the sums of the absolute values of the terms that make up
+    the value and its derivative."""
+    g = np.asarray(g, dtype=np.float64).reshape(-1, 3)
+    i = np.floor(g).astype(np.int64)
+    f = g - i
+    sval = np.zeros(g.shape[0])
+    sder = np.zeros_like(g)
+    for cz in (0, 1):
+        for cy in (0, 1):
+            for cx in (0, 1):
+                m = np.abs(vol[i[:, 2] + cz, i[:, 1] + cy, i[:, 0] + cx])
+                wx = f[:, 0] if cx else 1.0 - f[:, 0]
+                wy = f[:, 1] if cy else 1.0 - f[:, 1]
+                wz = f[:, 2] if cz else 1.0 - f[:, 2]
+                sval += wx * wy * wz * m
+                sder += m[:, None] * np.stack([wy * wz, wx * wz, wx * wy], axis=1)
+    return sval, sder
+
+
 def inside(grid: Grid, x):
+    """Whether point(s) x lie inside the interpolation box, and their grid coordinates."""
     g = (np.asarray(x, np.float64) - grid.origin) / grid.spacing
-    return bool(np.all(g >= 0.0) and np.all(g < grid.n_xyz - 1)), g
+    ins = np.all(g >= 0.0, axis=-1) & np.all(g < grid.n_xyz - 1, axis=-1)
+    return (bool(ins) if np.ndim(ins) == 0 else ins), g
+
+
+def grid_energies(grid: Grid, x, types, charges, with_force_scale=False):
+    """Per-atom grid energies e_i [N], dE/dx_i [N][3] and |term| scales [N] for atoms x [N][3]
+    (with_force_scale: also the per-component |term| scales of dE/dx_i, [N][3])."""
+    x = np.asarray(x, np.float64).reshape(-1, 3)
+    types = np.asarray(types).reshape(-1)
+    q = np.asarray(charges, np.float64).reshape(-1)
+    n = x.shape[0]
+    e = np.zeros(n)
+    de = np.zeros((n, 3))
+    scale = np.zeros(n)
+    fscale = np.zeros((n, 3))
+    ins, g = inside(grid, x)
+    ins = np.atleast_1d(ins)
+    if np.any(ins):
+        gi = g[ins]
+        aq = np.abs(q[ins])
+        vt = np.zeros(gi.shape[0])
+        dt = np.zeros_like(gi)
+        for t in np.unique(types[ins]):
+            sel = types[ins] == t
+            vt[sel], dt[sel] = trilinear(grid.maps[t], gi[sel])
+        ve, dv_e = trilinear(grid.maps[C.N_TYPES], gi)
+        vd, dv_d = trilinear(grid.maps[C.N_TYPES + 1], gi)
+        e[ins] = vt + q[ins] * ve + aq * vd
+        de[ins] = (dt + q[ins][:, None] * dv_e + aq[:, None] * dv_d) / grid.spacing
+        st = np.zeros(gi.shape[0])
+        sdt = np.zeros_like(gi)
+        for t in np.unique(types[ins]):
+            sel = types[ins] == t
+            st[sel], sdt[sel] = trilinear_abs(grid.maps[t], gi[sel])
+        se, sde = trilinear_abs(grid.maps[C.N_TYPES], gi)
+        sd, sdd = trilinear_abs(grid.maps[C.N_TYPES + 1], gi)
+        scale[ins] = st + aq * se + aq * sd
+        fscale[ins] = (sdt + aq[:, None] * sde + aq[:, None] * sdd) / grid.spacing
+    out = ~ins
+    if np.any(out):
+        lo = grid.origin
+        hi = grid.origin + (grid.n_xyz - 1) * grid.spacing
+        d = x[out] - np.clip(x[out], lo, hi)
+        e[out] = C.P_OUT + C.K_OUT * np.sum(d * d, axis=1)
+        de[out] = 2.0 * C.K_OUT * d
+        scale[out] = np.abs(e[out])
+        fscale[out] = np.abs(de[out])
+    if with_force_scale:
+        return e, de, scale, fscale
+    return e, de, scale
 
 
 def atom_grid_energy(grid: Grid, x, atype, charge):
-    """Energy and dE/dx of one atom against the receptor maps; also the sum of the
-    absolute values of the three map contributions (a conditioning scale)."""
-    ins, g = inside(grid, x)
-    if ins:
-        vt, dt = trilinear(grid.maps[atype], g)
-        ve, de = trilinear(grid.maps[C.N_TYPES], g)
-        vd, dd = trilinear(grid.maps[C.N_TYPES + 1], g)
-        aq = abs(charge)
-        e = vt + charge * ve + aq * vd
-        de_dx = (dt + charge * de + aq * dd) / grid.spacing
-        scale = abs(vt) + abs(charge * ve) + abs(aq * vd)
-        return e, de_dx, scale
-    lo = grid.origin
-    hi = grid.origin + (grid.n_xyz - 1) * grid.spacing
-    xc = np.clip(x, lo, hi)
-    d = np.asarray(x) - xc
-    e = C.P_OUT + C.K_OUT * float(d @ d)
-    return e, 2.0 * C.K_OUT * d, abs(e)
+    """Energy, dE/dx and |term| scale of one atom against the receptor maps."""
+    e, de, s = grid_energies(grid, np.asarray(x, np.float64)[None, :], [atype], [charge])
+    return float(e[0]), de[0], float(s[0])
 
 
 # ---------------------------------------------------------------- pair terms
 def dielectric(r):
     """Mehler-Solmajer eps(r) and d eps/dr."""
-    ex = math.exp(-C.DIEL_LAMBDA * C.DIEL_B * r)
+    ex = np.exp(-C.DIEL_LAMBDA * C.DIEL_B * np.asarray(r, np.float64))
     den = 1.0 + C.DIEL_K * ex
     eps = C.DIEL_A + C.DIEL_B / den
     deps = C.DIEL_B * C.DIEL_K * C.DIEL_LAMBDA * C.DIEL_B * ex / (den * den)
@@ -139,30 +200,47 @@ def pair_params(lig, i, j):
     return is_hb, c12, cn, qi * qj, ds
 
 
-def pair_energy(r, is_hb, c12, cn, qq, ds):
-    """Pair energy at distance r, its derivative de/dr, and the sum of |term| values.
-    Returns the three terms separately as well: (e, dedr, scale, (e_vdw_hb, e_el, e_ds))."""
-    rt = max(r, C.R_MIN)
-    clamped = r < C.R_MIN
-    e_lj = e_el = e_ds = 0.0
-    d_lj = d_el = d_ds = 0.0
-    if r < C.CUTOFF:
-        if is_hb:
-            e_lj = C.W_HB * (c12 / rt ** 12 - cn / rt ** 10)
-            d_lj = C.W_HB * (-12.0 * c12 / rt ** 13 + 10.0 * cn / rt ** 11)
+def pair_table(lig):
+    """pair_params of every listed pair as arrays (computed once per ligand)."""
+    cached = getattr(lig, "_pair_table", None)
+    if cached is None:
+        rows = [pair_params(lig, i, j) for (i, j) in lig.pairs]
+        if rows:
+            cols = list(zip(*rows))
+            cached = (np.array(cols[0], bool),) + tuple(np.array(c, np.float64) for c in cols[1:])
         else:
-            e_lj = C.W_VDW * (c12 / rt ** 12 - cn / rt ** 6)
-            d_lj = C.W_VDW * (-12.0 * c12 / rt ** 13 + 6.0 * cn / rt ** 7)
-        gauss = math.exp(-rt * rt / (2.0 * C.DESOLV_SIGMA ** 2))
-        e_ds = C.W_DS * ds * gauss
-        d_ds = -rt / C.DESOLV_SIGMA ** 2 * e_ds
-    if r < C.CUTOFF_EL:
-        eps, deps = dielectric(rt)
-        e_el = C.W_EL * C.COULOMB * qq / (rt * eps)
-        d_el = -C.W_EL * C.COULOMB * qq * (eps + rt * deps) / (rt * eps) ** 2
+            cached = (np.zeros(0, bool),) + tuple(np.zeros(0) for _ in range(4))
+        lig._pair_table = cached
+    return cached
+
+
+def pair_energy(r, is_hb, c12, cn, qq, ds):
+    """Pair energy at distance(s) r, de/dr, the sum of |term| values, and the three terms
+    (e_vdw_or_hb, e_el, e_ds).  Scalars or equal-length arrays."""
+    scalar = np.ndim(r) == 0
+    r = np.atleast_1d(np.asarray(r, np.float64))
+    is_hb = np.broadcast_to(np.asarray(is_hb, bool), r.shape)
+    c12, cn, qq, ds = (np.broadcast_to(np.asarray(a, np.float64), r.shape) for a in (c12, cn, qq, ds))
+    rt = np.maximum(r, C.R_MIN)
+    near = r < C.CUTOFF
+    e_lj = np.where(is_hb, C.W_HB * (c12 / rt ** 12 - cn / rt ** 10),
+                    C.W_VDW * (c12 / rt ** 12 - cn / rt ** 6))
+    d_lj = np.where(is_hb, C.W_HB * (-12.0 * c12 / rt ** 13 + 10.0 * cn / rt ** 11),
+                    C.W_VDW * (-12.0 * c12 / rt ** 13 + 6.0 * cn / rt ** 7))
+    e_ds = C.W_DS * ds * np.exp(-rt * rt / (2.0 * C.DESOLV_SIGMA ** 2))
+    d_ds = -rt / C.DESOLV_SIGMA ** 2 * e_ds
+    e_lj, d_lj = np.where(near, e_lj, 0.0), np.where(near, d_lj, 0.0)
+    e_ds, d_ds = np.where(near, e_ds, 0.0), np.where(near, d_ds, 0.0)
+    eps, deps = dielectric(rt)
+    e_el = C.W_EL * C.COULOMB * qq / (rt * eps)
+    d_el = -C.W_EL * C.COULOMB * qq * (eps + rt * deps) / (rt * eps) ** 2
+    far = r < C.CUTOFF_EL
+    e_el, d_el = np.where(far, e_el, 0.0), np.where(far, d_el, 0.0)
     e = e_lj + e_el + e_ds
-    dedr = 0.0 if clamped else d_lj + d_el + d_ds
-    scale = abs(e_lj) + abs(e_el) + abs(e_ds)
+    dedr = np.where(r < C.R_MIN, 0.0, d_lj + d_el + d_ds)
+    scale = np.abs(e_lj) + np.abs(e_el) + np.abs(e_ds)
+    if scalar:
+        return float(e[0]), float(dedr[0]), float(scale[0]), (float(e_lj[0]), float(e_el[0]), float(e_ds[0]))
     return e, dedr, scale, (e_lj, e_el, e_ds)
 
 
@@ -177,48 +255,45 @@ class EvalResult:
     e_intra: float
     scale_energy: float       # sum of |every atom term and pair term|
     scale_grad: np.ndarray    # [G] sum of |contributions| to each gene's gradient
-    margin: float             # distance (grid units / Angstrom) to the nearest kink
+    margin: float             # distance (grid units / Angstrom) to the nearest kink of any kind
+    margin_energy: float = math.inf   # ... to the nearest discontinuity of the energy itself
 
 
 def energy_and_gradient(grid: Grid, lig, genes, want_margin=True) -> EvalResult:
     genes = np.asarray(genes, dtype=np.float64)
     n = lig.n_atoms
     x = pose(lig, genes)
-    F = np.zeros((n, 3))
-    Fabs = np.zeros((n, 3))
-    e_inter = e_intra = 0.0
-    scale = 0.0
-    margin = math.inf
     # grid part
-    for i in range(n):
-        e, dedx, s = atom_grid_energy(grid, x[i], lig.types[i], lig.charges[i])
-        e_inter += e
-        scale += s
-        F[i] += dedx
-        Fabs[i] += np.abs(dedx)
-        if want_margin:
-            ins, g = inside(grid, x[i])
-            margin = min(margin, float(np.min(np.abs(g))),
-                         float(np.min(np.abs(g - (grid.n_xyz - 1)))))
-            if ins:
-                frac = g - np.floor(g)
-                margin = min(margin, float(np.min(np.minimum(frac, 1.0 - frac))))
+    e_atoms, F, s_atoms, Fabs = grid_energies(grid, x, lig.types, lig.charges, with_force_scale=True)
+    e_inter = float(e_atoms.sum())
+    scale = float(s_atoms.sum())
+    margin = margin_e = math.inf
+    if want_margin:
+        ins, g = inside(grid, x)
+        ins = np.atleast_1d(ins)
+        margin_e = min(float(np.min(np.abs(g))), float(np.min(np.abs(g - (grid.n_xyz - 1)))))
+        margin = margin_e
+        if np.any(ins):
+            frac = g[ins] - np.floor(g[ins])
+            margin = min(margin, float(np.min(np.minimum(frac, 1.0 - frac))))
     # pair part
-    for (i, j) in lig.pairs:
+    e_intra = 0.0
+    if lig.pairs.shape[0]:
+        i, j = lig.pairs[:, 0], lig.pairs[:, 1]
         d = x[i] - x[j]
-        r = float(np.sqrt(d @ d))
-        is_hb, c12, cn, qq, ds = pair_params(lig, i, j)
+        r = np.sqrt(np.sum(d * d, axis=1))
+        is_hb, c12, cn, qq, ds = pair_table(lig)
         e, dedr, s, _ = pair_energy(r, is_hb, c12, cn, qq, ds)
-        e_intra += e
-        scale += s
-        if dedr != 0.0:
-            f = dedr * d / r
-            F[i] += f
-            F[j] -= f
-            Fabs[i] += np.abs(f)
-            Fabs[j] += np.abs(f)
+        e_intra = float(e.sum())
+        scale += float(s.sum())
+        f = np.where(dedr[:, None] != 0.0, dedr[:, None] * d / np.where(r > 0, r, 1.0)[:, None], 0.0)
+        np.add.at(F, i, f)
+        np.add.at(F, j, -f)
+        np.add.at(Fabs, i, np.abs(f))
+        np.add.at(Fabs, j, np.abs(f))
         if want_margin:
-            margin = min(margin, abs(r - C.R_MIN), abs(r - C.CUTOFF), abs(r - C.CUTOFF_EL))
+            margin_e = min(margin_e, float(np.min(np.abs(r - C.CUTOFF))), float(np.min(np.abs(r - C.CUTOFF_EL))))
+            margin = min(margin, margin_e, float(np.min(np.abs(r - C.R_MIN))))
 
     G = lig.n_genes
     grad = np.zeros(G)
@@ -243,7 +318,8 @@ def energy_and_gradient(grid: Grid, lig, genes, want_margin=True) -> EvalResult:
         grad[7 + k] = float(u @ np.cross(arm, F[m]).sum(axis=0))
         sgrad[7 + k] = float(np.sum(np.linalg.norm(arm, axis=1) * np.linalg.norm(Fabs[m], axis=1)))
     return EvalResult(energy=e_inter + e_intra, grad=grad, x=x, forces=F, e_inter=e_inter,
-                      e_intra=e_intra, scale_energy=scale, scale_grad=sgrad, margin=margin)
+                      e_intra=e_intra, scale_energy=scale, scale_grad=sgrad, margin=margin,
+                      margin_energy=margin_e)
 
 
 def energy(grid: Grid, lig, genes) -> float:

@@ -1,0 +1,859 @@
+// gfx950 kernels of libmdock: pose, energy and genotype gradient, ADADELTA local search,
+// GA generation, evaluation accounting and best-of-runs.
+//
+// Mapping: one 64-lane wavefront owns one pose (genotype).  Lanes hold atoms (atom l and,
+// for ligands above 64 atoms, l + 64), then stride over the intramolecular pair list; the
+// per-pose energy and the genotype gradient are wavefront reductions.  Waves of a block are
+// independent (no block barriers), so a block can hold poses of different work.
+//
+// Paper passages: the energy kernel's phases -- per-atom positions, rotations in a fixed
+// order, per-atom energy sum (Section "Approach 1", listing of decomposed target
+// functions) -- and the per-run evaluation sum (Section "Removing architecture-specific
+// code", sum_evals listings).  The method (grid receptor, ligand self-interactions,
+// Lamarckian GA with a local search on a random sample, several runs, best over runs) is
+// from Background, "Design and Structure of MiniMDock".
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace mdock {
+
+namespace {
+
+constexpr float kPi = 3.14159265358979323846f;
+constexpr float kTwoPi = 6.28318530717958647692f;
+
+// ------------------------------------------------------------------ wave utilities
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ float readlane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// Makes this wave's LDS writes visible to its other lanes and keeps the compiler from
+// moving LDS accesses across the point.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Butterfly sum: every lane ends with the same bits (each step adds a commuted pair).
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// ------------------------------------------------------------------ counter-based RNG
+// SplitMix64 (Steele, Lea, Flood 2014) folded over the draw's coordinates.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+enum : uint32_t { kPInit = 1, kPTournament = 2, kPCrossover = 3, kPMutation = 4, kPLsPick = 5 };
+
+__device__ __forceinline__ uint32_t draw_u24(uint64_t seed, uint32_t run, uint32_t gen,
+                                             uint32_t indiv, uint32_t purpose, uint32_t index) {
+  uint64_t h = seed;
+  h = splitmix64(h ^ run);
+  h = splitmix64(h ^ gen);
+  h = splitmix64(h ^ indiv);
+  h = splitmix64(h ^ purpose);
+  h = splitmix64(h ^ index);
+  return (uint32_t)(h >> 40);
+}
+
+__device__ __forceinline__ float draw_uniform(uint64_t seed, uint32_t run, uint32_t gen,
+                                              uint32_t indiv, uint32_t purpose, uint32_t index) {
+  return (float)draw_u24(seed, run, gen, indiv, purpose, index) * (1.0f / 16777216.0f);
+}
+
+__device__ __forceinline__ int draw_int(int n, uint64_t seed, uint32_t run, uint32_t gen,
+                                        uint32_t indiv, uint32_t purpose, uint32_t index) {
+  return (int)(((uint64_t)draw_u24(seed, run, gen, indiv, purpose, index) * (uint64_t)n) >> 24);
+}
+
+__device__ __forceinline__ float wrap_angle(float th) {
+  return th - kTwoPi * ceilf((th - kPi) * (1.0f / kTwoPi));
+}
+
+// ------------------------------------------------------------------ per-wave LDS
+struct WaveLds {
+  float4 x[kMaxAtoms];        // posed coordinates
+  float fx[kMaxAtoms];        // intramolecular forces
+  float fy[kMaxAtoms];
+  float fz[kMaxAtoms];
+  float4 tor_u[kMaxTorsions];   // reference axes
+  float4 tor_p[kMaxTorsions];   // reference pivots
+  float2 tor_cs[kMaxTorsions];  // cos, sin of the current angles
+  float4 post_u[kMaxTorsions];  // posed axes
+  float4 post_p[kMaxTorsions];  // posed pivots
+};
+
+// Per-lane ligand constants for A atoms per lane (atom lane + 64*a).
+template <int A>
+struct AtomRegs {
+  float px[A], py[A], pz[A], q[A];
+  int type[A];
+  uint32_t mask[A];
+  bool valid[A];
+};
+
+template <int A>
+__device__ __forceinline__ void load_ligand(const LigDev& L, WaveLds& s, AtomRegs<A>& at,
+                                            int& my_gene_of_tor) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int a = 0; a < A; ++a) {
+    int i = lane + kWave * a;
+    at.valid[a] = i < L.n_atoms;
+    float4 p = at.valid[a] ? L.atom_p0q[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    at.px[a] = p.x;
+    at.py[a] = p.y;
+    at.pz[a] = p.z;
+    at.q[a] = p.w;
+    at.type[a] = at.valid[a] ? L.atom_type[i] : 0;
+    at.mask[a] = at.valid[a] ? L.atom_mask[i] : 0u;
+  }
+  if (lane < L.n_tors) {
+    s.tor_u[lane] = L.tor_axis[lane];
+    s.tor_p[lane] = L.tor_pivot[lane];
+    my_gene_of_tor = L.tor_gene[lane];
+  } else {
+    my_gene_of_tor = 0;
+  }
+  wave_sync();
+}
+
+// ------------------------------------------------------------------ grid term
+// Trilinear interpolation of (type map + q * electrostatic + |q| * desolvation) and its
+// derivative with respect to the atom position; out-of-grid penalty outside the box.
+template <int PREC>
+__device__ __forceinline__ float map_at(const void* maps, long long idx) {
+  if constexpr (PREC == 0) {
+    return static_cast<const float*>(maps)[idx];
+  } else if constexpr (PREC == 1) {
+    return __half2float(static_cast<const __half*>(maps)[idx]);
+  } else {
+    uint32_t b = (uint32_t)(static_cast<const uint16_t*>(maps)[idx]) << 16;
+    return __uint_as_float(b);
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ float grid_atom(const RecDev& R, float x, float y, float z, int type,
+                                           float q, float& dx, float& dy, float& dz) {
+  const float gx = (x - R.ox) * R.inv_h;
+  const float gy = (y - R.oy) * R.inv_h;
+  const float gz = (z - R.oz) * R.inv_h;
+  const bool inside = gx >= 0.f && gy >= 0.f && gz >= 0.f && gx < (float)(R.nx - 1) &&
+                      gy < (float)(R.ny - 1) && gz < (float)(R.nz - 1);
+  if (!inside) {
+    const float hx = R.ox + (float)(R.nx - 1) * R.h;
+    const float hy = R.oy + (float)(R.ny - 1) * R.h;
+    const float hz = R.oz + (float)(R.nz - 1) * R.h;
+    const float ex = x - fminf(fmaxf(x, R.ox), hx);
+    const float ey = y - fminf(fmaxf(y, R.oy), hy);
+    const float ez = z - fminf(fmaxf(z, R.oz), hz);
+    dx = 2.f * kKout * ex;
+    dy = 2.f * kKout * ey;
+    dz = 2.f * kKout * ez;
+    return kPout + kKout * (ex * ex + ey * ey + ez * ez);
+  }
+  const int ix = (int)gx, iy = (int)gy, iz = (int)gz;
+  const float fx = gx - (float)ix, fy = gy - (float)iy, fz = gz - (float)iz;
+  const long long nx = R.nx, nxy = (long long)R.nx * R.ny;
+  const long long base = (long long)iz * nxy + (long long)iy * nx + ix;
+  const long long mt = (long long)type * R.map_stride + base;
+  const long long me = (long long)kTypes * R.map_stride + base;
+  const long long md = (long long)(kTypes + 1) * R.map_stride + base;
+  const float aq = fabsf(q);
+  float c[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const long long off = ((k >> 2) & 1) * nxy + ((k >> 1) & 1) * nx + (k & 1);
+    c[k] = map_at<PREC>(R.maps, mt + off) + q * map_at<PREC>(R.maps, me + off) +
+           aq * map_at<PREC>(R.maps, md + off);
+  }
+  // c[k]: bit0 = +x, bit1 = +y, bit2 = +z
+  const float ux = 1.f - fx, uy = 1.f - fy, uz = 1.f - fz;
+  const float x00 = ux * c[0] + fx * c[1];
+  const float x10 = ux * c[2] + fx * c[3];
+  const float x01 = ux * c[4] + fx * c[5];
+  const float x11 = ux * c[6] + fx * c[7];
+  const float y0 = uy * x00 + fy * x10;
+  const float y1 = uy * x01 + fy * x11;
+  const float v = uz * y0 + fz * y1;
+  const float d00 = c[1] - c[0], d10 = c[3] - c[2], d01 = c[5] - c[4], d11 = c[7] - c[6];
+  const float dvx = uz * (uy * d00 + fy * d10) + fz * (uy * d01 + fy * d11);
+  const float dvy = uz * (x10 - x00) + fz * (x11 - x01);
+  const float dvz = y1 - y0;
+  dx = dvx * R.inv_h;
+  dy = dvy * R.inv_h;
+  dz = dvz * R.inv_h;
+  return v;
+}
+
+// ------------------------------------------------------------------ pair term
+// Energy of one intramolecular pair at distance r and dE/dr / r (so that the force on i is
+// that factor times (x_i - x_j)).  r is clamped to R_MIN with zero gradient below it.
+__device__ __forceinline__ float pair_term(float r2, bool hb, float4 c, float& f_over_r) {
+  const float r = __builtin_sqrtf(r2);
+  const float rt = fmaxf(r, kRmin);
+  const float ir = __builtin_amdgcn_rcpf(rt);
+  float e = 0.f, dedr = 0.f;
+  if (r < kCutoff) {
+    const float ir2 = ir * ir;
+    const float ir6 = ir2 * ir2 * ir2;
+    const float ir12 = ir6 * ir6;
+    const float irn = hb ? ir6 * ir2 * ir2 : ir6;
+    const float nn = hb ? 10.f : 6.f;
+    const float elj = c.x * ir12 - c.y * irn;
+    const float dlj = (-12.f * c.x * ir12 + nn * c.y * irn) * ir;
+    const float gs = __builtin_amdgcn_exp2f(-rt * rt * (1.4426950408889634f / (2.f * kDesolvSigma * kDesolvSigma)));
+    const float eds = c.w * gs;
+    const float dds = -rt * (1.f / (kDesolvSigma * kDesolvSigma)) * eds;
+    e += elj + eds;
+    dedr += dlj + dds;
+  }
+  if (r < kCutoffEl) {
+    const float ex = __builtin_amdgcn_exp2f(-kDielLambda * kDielB * 1.4426950408889634f * rt);
+    const float den = 1.f + kDielK * ex;
+    const float iden = __builtin_amdgcn_rcpf(den);
+    const float eps = kDielA + kDielB * iden;
+    const float deps = kDielB * kDielK * kDielLambda * kDielB * ex * iden * iden;
+    const float ieps = __builtin_amdgcn_rcpf(eps);
+    const float eel = c.z * ir * ieps;
+    e += eel;
+    dedr += -eel * (ir + deps * ieps);
+  }
+  f_over_r = (r < kRmin) ? 0.f : dedr * ir;
+  return e;
+}
+
+// ------------------------------------------------------------------ one pose
+// Energy (returned, identical in every lane) and, with GRAD, the gradient component of
+// gene `lane` (lanes >= n_genes get 0).  xg: gene `lane` of the pose (lanes < n_genes).
+template <int A, int PREC, bool GRAD>
+__device__ float eval_pose(const LigDev& L, const RecDev& R, WaveLds& s, const AtomRegs<A>& at,
+                           int my_gene_of_tor, float xg, float& g_out) {
+  const int lane = lane_id();
+  const int T = L.n_tors;
+  // rigid-body genes (wave-uniform)
+  const float tx = readlane(xg, 0), ty = readlane(xg, 1), tz = readlane(xg, 2);
+  float qw = readlane(xg, 3), qx = readlane(xg, 4), qy = readlane(xg, 5), qz = readlane(xg, 6);
+  const float qn = __builtin_sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+  const float iqn = 1.f / qn;
+  qw *= iqn;
+  qx *= iqn;
+  qy *= iqn;
+  qz *= iqn;
+  const float r00 = 1.f - 2.f * (qy * qy + qz * qz), r01 = 2.f * (qx * qy - qw * qz),
+              r02 = 2.f * (qx * qz + qw * qy);
+  const float r10 = 2.f * (qx * qy + qw * qz), r11 = 1.f - 2.f * (qx * qx + qz * qz),
+              r12 = 2.f * (qy * qz - qw * qx);
+  const float r20 = 2.f * (qx * qz - qw * qy), r21 = 2.f * (qy * qz + qw * qx),
+              r22 = 1.f - 2.f * (qx * qx + qy * qy);
+
+  // torsion angles -> cos/sin table
+  const float th = __shfl(xg, my_gene_of_tor, kWave);
+  if (lane < T) {
+    float sn, cs;
+    sincosf(th, &sn, &cs);
+    s.tor_cs[lane] = make_float2(cs, sn);
+  }
+  wave_sync();
+
+  // pose: each lane turns its atoms about their torsion chain, deepest torsion first,
+  // about reference-frame axes; then orientation and translation.
+  float x[A], y[A], z[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) {
+    float px = at.px[a], py = at.py[a], pz = at.pz[a];
+    uint32_t m = at.mask[a];
+    while (m) {
+      const int k = 31 - __clz(m);
+      m &= ~(1u << k);
+      const float4 u = s.tor_u[k];
+      const float4 pv = s.tor_p[k];
+      const float2 cs = s.tor_cs[k];
+      const float vx = px - pv.x, vy = py - pv.y, vz = pz - pv.z;
+      const float ud = u.x * vx + u.y * vy + u.z * vz;
+      const float cx = u.y * vz - u.z * vy, cy = u.z * vx - u.x * vz, cz = u.x * vy - u.y * vx;
+      const float omc = (1.f - cs.x) * ud;
+      px = pv.x + vx * cs.x + cx * cs.y + u.x * omc;
+      py = pv.y + vy * cs.x + cy * cs.y + u.y * omc;
+      pz = pv.z + vz * cs.x + cz * cs.y + u.z * omc;
+    }
+    x[a] = r00 * px + r01 * py + r02 * pz + tx;
+    y[a] = r10 * px + r11 * py + r12 * pz + ty;
+    z[a] = r20 * px + r21 * py + r22 * pz + tz;
+    if (at.valid[a]) {
+      const int i = lane + kWave * a;
+      s.x[i] = make_float4(x[a], y[a], z[a], 0.f);
+      if (GRAD) {
+        s.fx[i] = 0.f;
+        s.fy[i] = 0.f;
+        s.fz[i] = 0.f;
+      }
+    }
+  }
+
+  // grid term
+  float e_lane = 0.f;
+  float gfx[A], gfy[A], gfz[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) {
+    gfx[a] = gfy[a] = gfz[a] = 0.f;
+    if (at.valid[a]) {
+      e_lane += grid_atom<PREC>(R, x[a], y[a], z[a], at.type[a], at.q[a], gfx[a], gfy[a], gfz[a]);
+    }
+  }
+  wave_sync();
+
+  // intramolecular pairs, strided over lanes
+  for (int p = lane; p < L.n_pairs; p += kWave) {
+    const uint32_t ij = L.pair_ij[p];
+    const float4 c = L.pair_coef[p];
+    const int i = ij & 0xff, j = (ij >> 8) & 0xff;
+    const bool hb = (ij >> 16) & 1u;
+    const float4 xi = s.x[i], xj = s.x[j];
+    const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+    float fr;
+    e_lane += pair_term(dx * dx + dy * dy + dz * dz, hb, c, fr);
+    if (GRAD) {
+      const float fx = fr * dx, fy = fr * dy, fz = fr * dz;
+      atomicAdd(&s.fx[i], fx);
+      atomicAdd(&s.fy[i], fy);
+      atomicAdd(&s.fz[i], fz);
+      atomicAdd(&s.fx[j], -fx);
+      atomicAdd(&s.fy[j], -fy);
+      atomicAdd(&s.fz[j], -fz);
+    }
+  }
+  const float E = wave_sum(e_lane);
+  if (!GRAD) return E;
+  wave_sync();
+
+  // translation gradient and torque come from the grid forces alone: intramolecular
+  // forces are equal and opposite along each pair's line, so they add neither.
+  float sfx = 0.f, sfy = 0.f, sfz = 0.f, tqx = 0.f, tqy = 0.f, tqz = 0.f;
+  float Fx[A], Fy[A], Fz[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) {
+    const float rx = x[a] - tx, ry = y[a] - ty, rz = z[a] - tz;
+    sfx += gfx[a];
+    sfy += gfy[a];
+    sfz += gfz[a];
+    tqx += ry * gfz[a] - rz * gfy[a];
+    tqy += rz * gfx[a] - rx * gfz[a];
+    tqz += rx * gfy[a] - ry * gfx[a];
+    Fx[a] = gfx[a];
+    Fy[a] = gfy[a];
+    Fz[a] = gfz[a];
+    if (at.valid[a]) {
+      const int i = lane + kWave * a;
+      Fx[a] += s.fx[i];
+      Fy[a] += s.fy[i];
+      Fz[a] += s.fz[i];
+    }
+  }
+  sfx = wave_sum(sfx);
+  sfy = wave_sum(sfy);
+  sfz = wave_sum(sfz);
+  tqx = wave_sum(tqx);
+  tqy = wave_sum(tqy);
+  tqz = wave_sum(tqz);
+
+  float g = 0.f;
+  if (lane == 0) g = sfx;
+  if (lane == 1) g = sfy;
+  if (lane == 2) g = sfz;
+  // dE/dq for q/|q| = (w, v): (-2 tau.v, 2 (w tau - v x tau)) / |q|
+  if (lane == 3) g = -2.f * (tqx * qx + tqy * qy + tqz * qz) * iqn;
+  if (lane == 4) g = 2.f * (qw * tqx - (qy * tqz - qz * tqy)) * iqn;
+  if (lane == 5) g = 2.f * (qw * tqy - (qz * tqx - qx * tqz)) * iqn;
+  if (lane == 6) g = 2.f * (qw * tqz - (qx * tqy - qy * tqx)) * iqn;
+
+  // torsions: posed axis and pivot, then axis . sum over moved atoms of arm x force
+  if (lane < T) {
+    const int2 ab = L.tor_ab[lane];
+    const float4 xa = s.x[ab.x], xb = s.x[ab.y];
+    float ux = xb.x - xa.x, uy = xb.y - xa.y, uz = xb.z - xa.z;
+    const float il = 1.f / __builtin_sqrtf(ux * ux + uy * uy + uz * uz);
+    s.post_u[lane] = make_float4(ux * il, uy * il, uz * il, 0.f);
+    s.post_p[lane] = xa;
+  }
+  wave_sync();
+  for (int k = 0; k < T; ++k) {
+    const float4 u = s.post_u[k];
+    const float4 pa = s.post_p[k];
+    float c = 0.f;
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+      if ((at.mask[a] >> k) & 1u) {
+        const float rx = x[a] - pa.x, ry = y[a] - pa.y, rz = z[a] - pa.z;
+        const float cx = ry * Fz[a] - rz * Fy[a];
+        const float cy = rz * Fx[a] - rx * Fz[a];
+        const float cz = rx * Fy[a] - ry * Fx[a];
+        c += u.x * cx + u.y * cy + u.z * cz;
+      }
+    }
+    c = wave_sum(c);
+    if (lane == L.tor_gene[k]) g = c;
+  }
+  g_out = g;
+  return E;
+}
+
+// ------------------------------------------------------------------ kernels
+template <int A, int PREC>
+__global__ __launch_bounds__(kBlock) void k_eval(LigDev L, RecDev R, int n, const float* __restrict__ genes,
+                                                 float* __restrict__ energy, float* __restrict__ grad) {
+  __shared__ WaveLds lds[kWavesPerBlock];
+  const int w = threadIdx.x / kWave;
+  const int pose = blockIdx.x * kWavesPerBlock + w;
+  if (pose >= n) return;
+  WaveLds& s = lds[w];
+  AtomRegs<A> at;
+  int gtor;
+  load_ligand<A>(L, s, at, gtor);
+  const int lane = lane_id();
+  const int G = L.n_genes;
+  const float xg = lane < G ? genes[(long long)pose * G + lane] : 0.f;
+  float g = 0.f;
+  float E;
+  if (grad) {
+    E = eval_pose<A, PREC, true>(L, R, s, at, gtor, xg, g);
+    if (lane < G) grad[(long long)pose * G + lane] = g;
+  } else {
+    E = eval_pose<A, PREC, false>(L, R, s, at, gtor, xg, g);
+  }
+  if (lane == 0) energy[pose] = E;
+}
+
+template <int A>
+__global__ __launch_bounds__(kBlock) void k_pose(LigDev L, int n, const float* __restrict__ genes,
+                                                 float* __restrict__ xyz) {
+  __shared__ WaveLds lds[kWavesPerBlock];
+  const int w = threadIdx.x / kWave;
+  const int pose = blockIdx.x * kWavesPerBlock + w;
+  if (pose >= n) return;
+  WaveLds& s = lds[w];
+  AtomRegs<A> at;
+  int gtor;
+  load_ligand<A>(L, s, at, gtor);
+  const int lane = lane_id();
+  const int G = L.n_genes;
+  const float xg = lane < G ? genes[(long long)pose * G + lane] : 0.f;
+  float qw = readlane(xg, 3), qx = readlane(xg, 4), qy = readlane(xg, 5), qz = readlane(xg, 6);
+  const float iqn = 1.f / __builtin_sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+  qw *= iqn; qx *= iqn; qy *= iqn; qz *= iqn;
+  const float tx = readlane(xg, 0), ty = readlane(xg, 1), tz = readlane(xg, 2);
+  const float th = __shfl(xg, gtor, kWave);
+  if (lane < L.n_tors) {
+    float sn, cs;
+    sincosf(th, &sn, &cs);
+    s.tor_cs[lane] = make_float2(cs, sn);
+  }
+  wave_sync();
+#pragma unroll
+  for (int a = 0; a < A; ++a) {
+    if (!at.valid[a]) continue;
+    float px = at.px[a], py = at.py[a], pz = at.pz[a];
+    uint32_t m = at.mask[a];
+    while (m) {
+      const int k = 31 - __clz(m);
+      m &= ~(1u << k);
+      const float4 u = s.tor_u[k];
+      const float4 pv = s.tor_p[k];
+      const float2 cs = s.tor_cs[k];
+      const float vx = px - pv.x, vy = py - pv.y, vz = pz - pv.z;
+      const float ud = u.x * vx + u.y * vy + u.z * vz;
+      const float cx = u.y * vz - u.z * vy, cy = u.z * vx - u.x * vz, cz = u.x * vy - u.y * vx;
+      const float omc = (1.f - cs.x) * ud;
+      px = pv.x + vx * cs.x + cx * cs.y + u.x * omc;
+      py = pv.y + vy * cs.x + cy * cs.y + u.y * omc;
+      pz = pv.z + vz * cs.x + cz * cs.y + u.z * omc;
+    }
+    const float r00 = 1.f - 2.f * (qy * qy + qz * qz), r01 = 2.f * (qx * qy - qw * qz), r02 = 2.f * (qx * qz + qw * qy);
+    const float r10 = 2.f * (qx * qy + qw * qz), r11 = 1.f - 2.f * (qx * qx + qz * qz), r12 = 2.f * (qy * qz - qw * qx);
+    const float r20 = 2.f * (qx * qz - qw * qy), r21 = 2.f * (qy * qz + qw * qx), r22 = 1.f - 2.f * (qx * qx + qy * qy);
+    const long long o = ((long long)pose * L.n_atoms + lane + kWave * a) * 3;
+    xyz[o + 0] = r00 * px + r01 * py + r02 * pz + tx;
+    xyz[o + 1] = r10 * px + r11 * py + r12 * pz + ty;
+    xyz[o + 2] = r20 * px + r21 * py + r22 * pz + tz;
+  }
+}
+
+// ADADELTA step on the gene held by this lane, then quaternion renormalisation and torsion
+// wrapping.  Returns the new gene.
+__device__ __forceinline__ float adadelta_update(float x, float g, float& eg2, float& edx2,
+                                                 float rho, float eps, int G) {
+  const int lane = lane_id();
+  float nx = x;
+  if (lane < G) {
+    eg2 = rho * eg2 + (1.f - rho) * g * g;
+    const float dx = -__builtin_sqrtf(edx2 + eps) / __builtin_sqrtf(eg2 + eps) * g;
+    edx2 = rho * edx2 + (1.f - rho) * dx * dx;
+    nx = x + dx;
+  }
+  const float q0 = readlane(nx, 3), q1 = readlane(nx, 4), q2 = readlane(nx, 5), q3 = readlane(nx, 6);
+  const float qn = __builtin_sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+  if (lane >= 3 && lane < 7) nx = nx / qn;
+  if (lane >= 7 && lane < G) nx = wrap_angle(nx);
+  return nx;
+}
+
+// One wave per local search.  rows: optional map wave -> row of genes_in/genes_out.
+template <int A, int PREC>
+__global__ __launch_bounds__(kBlock) void k_local_search(LigDev L, RecDev R, int n, const int* __restrict__ rows,
+                                                         const float* genes_in, float* genes_out,
+                                                         float* __restrict__ energy_out, int* __restrict__ evals,
+                                                         int iters, float rho, float eps,
+                                                         float* __restrict__ trace) {
+  __shared__ WaveLds lds[kWavesPerBlock];
+  const int w = threadIdx.x / kWave;
+  const int job = blockIdx.x * kWavesPerBlock + w;
+  if (job >= n) return;
+  WaveLds& s = lds[w];
+  AtomRegs<A> at;
+  int gtor;
+  load_ligand<A>(L, s, at, gtor);
+  const int lane = lane_id();
+  const int G = L.n_genes;
+  const long long row = rows ? rows[job] : job;
+  float x = lane < G ? genes_in[row * G + lane] : 0.f;
+  float eg2 = 0.f, edx2 = 0.f;
+  float best_x = x;
+  float best_e = __builtin_huge_valf();
+  for (int it = 0; it < iters; ++it) {
+    float g = 0.f;
+    const float E = eval_pose<A, PREC, true>(L, R, s, at, gtor, x, g);
+    if (trace && lane == 0) trace[(long long)job * iters + it] = E;
+    if (E < best_e) {
+      best_e = E;
+      best_x = x;
+    }
+    x = adadelta_update(x, g, eg2, edx2, rho, eps, G);
+  }
+  if (lane < G) genes_out[row * G + lane] = best_x;
+  if (lane == 0) {
+    energy_out[row] = best_e;
+    if (evals) evals[row] += iters;
+  }
+}
+
+// Initial individual `indiv` of run `run` in the lane-per-gene layout.
+__device__ __forceinline__ float initial_gene(const RecDev& R, const GaDev& P, int run, int indiv) {
+  const int lane = lane_id();
+  const uint64_t sd = P.seed;
+  float v = 0.f;
+  if (lane < 3) {
+    const float lo = lane == 0 ? R.ox : (lane == 1 ? R.oy : R.oz);
+    const int nn = lane == 0 ? R.nx : (lane == 1 ? R.ny : R.nz);
+    const float hi = lo + (float)(nn - 1) * R.h;
+    v = lo + draw_uniform(sd, run, 0, indiv, kPInit, lane) * (hi - lo);
+  } else if (lane < 7) {
+    const float u1 = draw_uniform(sd, run, 0, indiv, kPInit, 3);
+    const float u2 = draw_uniform(sd, run, 0, indiv, kPInit, 4);
+    const float u3 = draw_uniform(sd, run, 0, indiv, kPInit, 5);
+    const float s1 = __builtin_sqrtf(1.f - u1), s2 = __builtin_sqrtf(u1);
+    float sa, ca, sb, cb;
+    sincospif(2.f * u2, &sa, &ca);
+    sincospif(2.f * u3, &sb, &cb);
+    v = lane == 3 ? s1 * sa : (lane == 4 ? s1 * ca : (lane == 5 ? s2 * sb : s2 * cb));
+  } else if (lane < P.n_genes) {
+    v = kPi - kTwoPi * draw_uniform(sd, run, 0, indiv, kPInit, 6 + (lane - 7));
+  }
+  return v;
+}
+
+template <int A, int PREC>
+__global__ __launch_bounds__(kBlock) void k_init_population(LigDev L, RecDev R, GaDev P,
+                                                            float* __restrict__ genes,
+                                                            float* __restrict__ energy,
+                                                            int* __restrict__ evals) {
+  __shared__ WaveLds lds[kWavesPerBlock];
+  const int w = threadIdx.x / kWave;
+  const int job = blockIdx.x * kWavesPerBlock + w;
+  if (job >= P.n_runs * P.pop_size) return;
+  WaveLds& s = lds[w];
+  AtomRegs<A> at;
+  int gtor;
+  load_ligand<A>(L, s, at, gtor);
+  const int lane = lane_id();
+  const int G = L.n_genes;
+  const int run = job / P.pop_size, indiv = job % P.pop_size;
+  const float x = initial_gene(R, P, run, indiv);
+  float g;
+  const float E = eval_pose<A, PREC, false>(L, R, s, at, gtor, x, g);
+  if (lane < G) genes[(long long)job * G + lane] = x;
+  if (lane == 0) {
+    energy[job] = E;
+    evals[job] = 1;
+  }
+}
+
+// Lowest energy of a run's population, ties to the lower index (wave-uniform result).
+__device__ __forceinline__ int wave_argmin(const float* __restrict__ E, int n) {
+  const int lane = lane_id();
+  float be = __builtin_huge_valf();
+  int bi = 0x7fffffff;
+  for (int i = lane; i < n; i += kWave) {
+    const float e = E[i];
+    if (e < be || (e == be && i < bi)) {
+      be = e;
+      bi = i;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const float oe = __shfl_xor(be, off, kWave);
+    const int oi = __shfl_xor(bi, off, kWave);
+    if (oe < be || (oe == be && oi < bi)) {
+      be = oe;
+      bi = oi;
+    }
+  }
+  return bi < n ? bi : 0;   // all-NaN input: fall back to index 0, never out of range
+}
+
+__device__ __forceinline__ int tournament(const float* __restrict__ E, const GaDev& P, int run,
+                                          int gen, int slot, int which) {
+  const int a = draw_int(P.pop_size, P.seed, run, gen, slot, kPTournament, 3 * which);
+  const int b = draw_int(P.pop_size, P.seed, run, gen, slot, kPTournament, 3 * which + 1);
+  const float u = draw_uniform(P.seed, run, gen, slot, kPTournament, 3 * which + 2);
+  const float ea = E[a], eb = E[b];
+  const int better = (ea < eb || (ea == eb && a <= b)) ? a : b;
+  const int worse = better == a ? b : a;
+  return u < P.tournament_rate ? better : worse;
+}
+
+// Gene unit of gene g: translation components are units 0..2, the quaternion is unit 3,
+// torsion k is unit 4 + k.
+__device__ __forceinline__ int unit_of(int g) { return g < 3 ? g : (g < 7 ? 3 : g - 3); }
+
+template <int A, int PREC>
+__global__ __launch_bounds__(kBlock) void k_generation(LigDev L, RecDev R, GaDev P, int gen,
+                                                       const float* __restrict__ genes_in,
+                                                       const float* __restrict__ energy_in,
+                                                       float* __restrict__ genes_out,
+                                                       float* __restrict__ energy_out,
+                                                       int* __restrict__ evals) {
+  __shared__ WaveLds lds[kWavesPerBlock];
+  const int w = threadIdx.x / kWave;
+  const int job = blockIdx.x * kWavesPerBlock + w;
+  if (job >= P.n_runs * P.pop_size) return;
+  const int lane = lane_id();
+  const int G = L.n_genes;
+  const int run = job / P.pop_size, slot = job % P.pop_size;
+  const long long rbase = (long long)run * P.pop_size;
+  const float* E = energy_in + rbase;
+  if (slot < P.elitism) {
+    const int e = wave_argmin(E, P.pop_size);
+    if (lane < G) genes_out[(long long)job * G + lane] = genes_in[(rbase + e) * G + lane];
+    if (lane == 0) {
+      energy_out[job] = E[e];
+      evals[job] = 0;
+    }
+    return;
+  }
+  WaveLds& s = lds[w];
+  AtomRegs<A> at;
+  int gtor;
+  load_ligand<A>(L, s, at, gtor);
+  const int pa = tournament(E, P, run, gen, slot, 0);
+  const int pb = tournament(E, P, run, gen, slot, 1);
+  const float xa = lane < G ? genes_in[(rbase + pa) * G + lane] : 0.f;
+  const float xb = lane < G ? genes_in[(rbase + pb) * G + lane] : 0.f;
+  // two-point crossover over gene units
+  float x = xa;
+  if (draw_uniform(P.seed, run, gen, slot, kPCrossover, 0) < P.crossover_rate) {
+    const int U = 4 + L.n_tors;
+    const int c1 = draw_int(U + 1, P.seed, run, gen, slot, kPCrossover, 1);
+    const int c2 = draw_int(U + 1, P.seed, run, gen, slot, kPCrossover, 2);
+    const int lo = min(c1, c2), hi = max(c1, c2);
+    const int u = unit_of(lane);
+    if (u >= lo && u < hi) x = xb;
+  }
+  // mutation, per unit
+  const int m = unit_of(lane < G ? lane : 0);
+  const bool mut = lane < G && draw_uniform(P.seed, run, gen, slot, kPMutation, 4 * m) < P.mutation_rate;
+  if (mut && m < 3) {
+    x += (2.f * draw_uniform(P.seed, run, gen, slot, kPMutation, 4 * m + 1) - 1.f) * P.mut_trans;
+  } else if (mut && m >= 4) {
+    x = wrap_angle(x + (2.f * draw_uniform(P.seed, run, gen, slot, kPMutation, 4 * m + 1) - 1.f) * P.mut_tors);
+  }
+  // quaternion unit (identical decision in lanes 3..6): q <- normalise(r (x) q)
+  const float cw = readlane(x, 3), cx = readlane(x, 4), cy = readlane(x, 5), cz = readlane(x, 6);
+  if (draw_uniform(P.seed, run, gen, slot, kPMutation, 12) < P.mutation_rate) {
+    const float alpha = (2.f * draw_uniform(P.seed, run, gen, slot, kPMutation, 13) - 1.f) * P.mut_rot;
+    const float zz = 2.f * draw_uniform(P.seed, run, gen, slot, kPMutation, 14) - 1.f;
+    const float phi = draw_uniform(P.seed, run, gen, slot, kPMutation, 15);
+    const float rxy = __builtin_sqrtf(fmaxf(0.f, 1.f - zz * zz));
+    float sp, cp;
+    sincospif(2.f * phi, &sp, &cp);
+    float sh, ch;
+    sincosf(0.5f * alpha, &sh, &ch);
+    const float rw = ch, rx = sh * rxy * cp, ry = sh * rxy * sp, rz = sh * zz;
+    const float nw = rw * cw - rx * cx - ry * cy - rz * cz;
+    const float nx = rw * cx + rx * cw + ry * cz - rz * cy;
+    const float ny = rw * cy - rx * cz + ry * cw + rz * cx;
+    const float nz = rw * cz + rx * cy - ry * cx + rz * cw;
+    const float inv = 1.f / __builtin_sqrtf(nw * nw + nx * nx + ny * ny + nz * nz);
+    if (lane == 3) x = nw * inv;
+    if (lane == 4) x = nx * inv;
+    if (lane == 5) x = ny * inv;
+    if (lane == 6) x = nz * inv;
+  }
+  float g;
+  const float Enew = eval_pose<A, PREC, false>(L, R, s, at, gtor, x, g);
+  if (lane < G) genes_out[(long long)job * G + lane] = x;
+  if (lane == 0) {
+    energy_out[job] = Enew;
+    evals[job] = 1;
+  }
+}
+
+// Local-search picks of one run: the n_ls individuals with the lowest random keys (ties to
+// the lower index), written as global rows in key order.  One wave per run.
+__global__ __launch_bounds__(kBlock) void k_ls_pick(GaDev P, int gen, int* __restrict__ rows) {
+  __shared__ uint32_t keys[kWavesPerBlock][1024];
+  const int w = threadIdx.x / kWave;
+  const int run = blockIdx.x * kWavesPerBlock + w;
+  if (run >= P.n_runs) return;
+  const int lane = lane_id();
+  for (int i = lane; i < P.pop_size; i += kWave)
+    keys[w][i] = draw_u24(P.seed, run, gen, i, kPLsPick, 0);
+  wave_sync();
+  for (int i = lane; i < P.pop_size; i += kWave) {
+    const uint32_t ki = keys[w][i];
+    int rank = 0;
+    for (int j = 0; j < P.pop_size; ++j) {
+      const uint32_t kj = keys[w][j];
+      rank += (kj < ki || (kj == ki && j < i)) ? 1 : 0;
+    }
+    if (rank < P.n_ls) rows[run * P.n_ls + rank] = run * P.pop_size + i;
+  }
+}
+
+// Per-run evaluation sum (the miniapp's sum_evals): evals_of_runs[run] += sum of the
+// per-individual counts of this generation.  One wave per run.
+__global__ __launch_bounds__(kBlock) void k_sum_evals(GaDev P, const int* __restrict__ evals,
+                                                      long long* __restrict__ evals_of_runs) {
+  const int w = threadIdx.x / kWave;
+  const int run = blockIdx.x * kWavesPerBlock + w;
+  if (run >= P.n_runs) return;
+  const int lane = lane_id();
+  int sum = 0;
+  for (int i = lane; i < P.pop_size; i += kWave) sum += evals[run * P.pop_size + i];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, kWave);
+  if (lane == 0) evals_of_runs[run] += sum;
+}
+
+__global__ __launch_bounds__(kBlock) void k_best_of_runs(GaDev P, const float* __restrict__ genes,
+                                                         const float* __restrict__ energy,
+                                                         int* __restrict__ best_row,
+                                                         float* __restrict__ best_energy,
+                                                         float* __restrict__ best_genes) {
+  const int w = threadIdx.x / kWave;
+  const int run = blockIdx.x * kWavesPerBlock + w;
+  if (run >= P.n_runs) return;
+  const int lane = lane_id();
+  const long long base = (long long)run * P.pop_size;
+  const int b = wave_argmin(energy + base, P.pop_size);
+  if (lane < P.n_genes) best_genes[run * P.n_genes + lane] = genes[(base + b) * P.n_genes + lane];
+  if (lane == 0) {
+    best_row[run] = (int)(base + b);
+    best_energy[run] = energy[base + b];
+  }
+}
+
+inline unsigned blocks_for(long long waves) {
+  return (unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+}
+
+}  // namespace
+
+#define MDOCK_DISPATCH(KERNEL, GRID, STREAM, ...)                                              \
+  do {                                                                                        \
+    const bool two = L.n_atoms > kWave;                                                       \
+    switch (R.precision * 2 + (two ? 1 : 0)) {                                                \
+      case 0: hipLaunchKernelGGL((KERNEL<1, 0>), GRID, dim3(kBlock), 0, STREAM, __VA_ARGS__); break; \
+      case 1: hipLaunchKernelGGL((KERNEL<2, 0>), GRID, dim3(kBlock), 0, STREAM, __VA_ARGS__); break; \
+      case 2: hipLaunchKernelGGL((KERNEL<1, 1>), GRID, dim3(kBlock), 0, STREAM, __VA_ARGS__); break; \
+      case 3: hipLaunchKernelGGL((KERNEL<2, 1>), GRID, dim3(kBlock), 0, STREAM, __VA_ARGS__); break; \
+      case 4: hipLaunchKernelGGL((KERNEL<1, 2>), GRID, dim3(kBlock), 0, STREAM, __VA_ARGS__); break; \
+      default: hipLaunchKernelGGL((KERNEL<2, 2>), GRID, dim3(kBlock), 0, STREAM, __VA_ARGS__); break; \
+    }                                                                                         \
+  } while (0)
+
+hipError_t launch_eval(const LigDev& L, const RecDev& R, int n, const float* genes, float* energy,
+                       float* grad, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  MDOCK_DISPATCH(k_eval, dim3(blocks_for(n)), s, L, R, n, genes, energy, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_pose(const LigDev& L, int n, const float* genes, float* xyz, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (L.n_atoms > kWave)
+    hipLaunchKernelGGL((k_pose<2>), dim3(blocks_for(n)), dim3(kBlock), 0, s, L, n, genes, xyz);
+  else
+    hipLaunchKernelGGL((k_pose<1>), dim3(blocks_for(n)), dim3(kBlock), 0, s, L, n, genes, xyz);
+  return hipGetLastError();
+}
+
+hipError_t launch_local_search(const LigDev& L, const RecDev& R, int n, const int* rows,
+                               const float* genes_in, float* genes_out, float* energy_out,
+                               int* evals, int iters, float rho, float eps, float* trace,
+                               hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  MDOCK_DISPATCH(k_local_search, dim3(blocks_for(n)), s, L, R, n, rows, genes_in, genes_out,
+                 energy_out, evals, iters, rho, eps, trace);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_population(const LigDev& L, const RecDev& R, const GaDev& P, float* genes,
+                                  float* energy, int* evals, hipStream_t s) {
+  MDOCK_DISPATCH(k_init_population, dim3(blocks_for((long long)P.n_runs * P.pop_size)), s, L, R, P,
+                 genes, energy, evals);
+  return hipGetLastError();
+}
+
+hipError_t launch_generation(const LigDev& L, const RecDev& R, const GaDev& P, int gen,
+                             const float* genes_in, const float* energy_in, float* genes_out,
+                             float* energy_out, int* evals, hipStream_t s) {
+  MDOCK_DISPATCH(k_generation, dim3(blocks_for((long long)P.n_runs * P.pop_size)), s, L, R, P, gen,
+                 genes_in, energy_in, genes_out, energy_out, evals);
+  return hipGetLastError();
+}
+
+hipError_t launch_ls_pick(const GaDev& P, int gen, int* rows, hipStream_t s) {
+  hipLaunchKernelGGL(k_ls_pick, dim3(blocks_for(P.n_runs)), dim3(kBlock), 0, s, P, gen, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_evals(const GaDev& P, const int* evals, long long* evals_of_runs,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_evals, dim3(blocks_for(P.n_runs)), dim3(kBlock), 0, s, P, evals,
+                     evals_of_runs);
+  return hipGetLastError();
+}
+
+hipError_t launch_best_of_runs(const GaDev& P, const float* genes, const float* energy,
+                               int* best_row, float* best_energy, float* best_genes,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_best_of_runs, dim3(blocks_for(P.n_runs)), dim3(kBlock), 0, s, P, genes,
+                     energy, best_row, best_energy, best_genes);
+  return hipGetLastError();
+}
+
+}  // namespace mdock

@@ -1,0 +1,282 @@
+"""Thin Python binding of libmdock (include/mdock.h): argument marshalling only.
+
+Device buffers are torch CUDA (HIP) tensors; streams are torch streams.  Every step of
+the docking path runs in the library's HIP kernels; nothing here computes.  If
+libmdock.so has not been built the first call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmdock.so")
+
+MD_OK, MD_EINVAL, MD_ERANGE, MD_ENOMEM, MD_EDEVICE = 0, -1, -2, -3, -4
+PRECISION = {"fp32": 0, "fp16": 1, "bf16": 2}
+
+_lib = None
+
+
+class MdockError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libmdock status {status}: {msg}")
+        self.status = status
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("spacing", C.c_float),
+                ("origin", C.c_float * 3), ("n_types", C.c_int)]
+
+
+class LigandDesc(C.Structure):
+    _fields_ = [("n_atoms", C.c_int), ("xyz", C.POINTER(C.c_float)), ("type", C.POINTER(C.c_int)),
+                ("charge", C.POINTER(C.c_float)), ("n_bonds", C.c_int), ("bonds", C.POINTER(C.c_int)),
+                ("n_torsions", C.c_int), ("torsions", C.POINTER(C.c_int)), ("root_atom", C.c_int),
+                ("n_types", C.c_int), ("type_params", C.POINTER(C.c_float))]
+
+
+class DockParams(C.Structure):
+    _fields_ = [("n_runs", C.c_int), ("pop_size", C.c_int), ("max_evals_per_run", C.c_longlong),
+                ("max_generations", C.c_int), ("ls_rate", C.c_float), ("ls_iters", C.c_int),
+                ("rho", C.c_float), ("eps", C.c_float), ("crossover_rate", C.c_float),
+                ("mutation_rate", C.c_float), ("tournament_rate", C.c_float), ("elitism", C.c_int),
+                ("mut_trans", C.c_float), ("mut_rot", C.c_float), ("mut_tors", C.c_float),
+                ("seed", C.c_ulonglong)]
+
+
+class DockResult(C.Structure):
+    _fields_ = [("n_runs", C.c_int), ("n_genes", C.c_int), ("n_atoms", C.c_int),
+                ("best_energy", C.POINTER(C.c_float)), ("best_genes", C.POINTER(C.c_float)),
+                ("best_xyz", C.POINTER(C.c_float)), ("run_index", C.POINTER(C.c_int)),
+                ("evals", C.POINTER(C.c_longlong)), ("generations", C.POINTER(C.c_int))]
+
+
+# name -> (restype, argtypes); the complete exported surface of include/mdock.h
+SIGNATURES = {
+    "md_receptor_create": (C.c_int, [C.POINTER(GridDesc), C.POINTER(C.c_float), C.c_int, C.c_void_p,
+                                     C.POINTER(C.c_void_p)]),
+    "md_receptor_destroy": (C.c_int, [C.c_void_p]),
+    "md_ligand_create": (C.c_int, [C.POINTER(LigandDesc), C.POINTER(C.c_void_p)]),
+    "md_ligand_destroy": (C.c_int, [C.c_void_p]),
+    "md_ligand_num_genes": (C.c_int, [C.c_void_p]),
+    "md_ligand_num_atoms": (C.c_int, [C.c_void_p]),
+    "md_ligand_num_pairs": (C.c_int, [C.c_void_p]),
+    "md_eval": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "md_pose": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "md_local_search": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_int, C.c_float, C.c_float, C.c_void_p, C.c_void_p]),
+    "md_dock": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(DockParams), C.POINTER(DockResult), C.c_void_p]),
+    "md_dock_planned_generations": (C.c_int, [C.POINTER(DockParams)]),
+    "md_ligand_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                 C.POINTER(C.c_int)]),
+    "md_profile_enable": (C.c_int, [C.c_int]),
+    "md_profile_reset": (C.c_int, []),
+    "md_profile_read": (C.c_int, [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
+    "md_last_error": (C.c_char_p, []),
+    "md_version": (C.c_char_p, []),
+}
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2203_02096_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status, what):
+    if status != MD_OK:
+        raise MdockError(status, lib().md_last_error().decode())
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, name, shape=None, dtype=None):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _fptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int))
+
+
+class Receptor:
+    """Grid maps on the device (md_receptor_create)."""
+
+    def __init__(self, maps, origin, spacing, precision="fp32", stream=None):
+        maps = np.ascontiguousarray(maps, dtype=np.float32)
+        if maps.ndim != 4:
+            raise ValueError("maps must be [n_types+2][nz][ny][nx]")
+        nm, nz, ny, nx = maps.shape
+        d = GridDesc(nx, ny, nz, float(spacing), (C.c_float * 3)(*[float(v) for v in origin]), nm - 2)
+        h = C.c_void_p()
+        self._maps_ref = maps
+        _check(lib().md_receptor_create(C.byref(d), _fptr(maps), PRECISION[precision],
+                                        _stream_ptr(stream) if stream is not False else None, C.byref(h)),
+               "md_receptor_create")
+        self.handle = h
+        self.shape = (nx, ny, nz)
+        self.precision = precision
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.md_receptor_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Ligand:
+    """Preprocessed ligand on the device (md_ligand_create)."""
+
+    def __init__(self, xyz, types, charges, bonds, torsions, type_params, root=0):
+        self._xyz = np.ascontiguousarray(xyz, dtype=np.float32).reshape(-1, 3)
+        self._types = np.ascontiguousarray(types, dtype=np.int32).reshape(-1)
+        self._q = np.ascontiguousarray(charges, dtype=np.float32).reshape(-1)
+        self._bonds = np.ascontiguousarray(bonds, dtype=np.int32).reshape(-1, 2)
+        self._tors = np.ascontiguousarray(torsions, dtype=np.int32).reshape(-1)
+        self._tp = np.ascontiguousarray(type_params, dtype=np.float32).reshape(-1, 7)
+        d = LigandDesc(self._xyz.shape[0], _fptr(self._xyz), _iptr(self._types), _fptr(self._q),
+                       self._bonds.shape[0], _iptr(self._bonds), self._tors.shape[0], _iptr(self._tors),
+                       int(root), self._tp.shape[0], _fptr(self._tp))
+        h = C.c_void_p()
+        _check(lib().md_ligand_create(C.byref(d), C.byref(h)), "md_ligand_create")
+        self.handle = h
+        self.n_genes = lib().md_ligand_num_genes(h)
+        self.n_atoms = lib().md_ligand_num_atoms(h)
+        self.n_pairs = lib().md_ligand_num_pairs(h)
+
+    @classmethod
+    def from_synth(cls, lig):
+        return cls(lig.xyz, lig.types, lig.charges, lig.bonds, lig.torsions, lig.type_params,
+                   getattr(lig, "root", 0))
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.md_ligand_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def md_eval(rec: Receptor, lig: Ligand, genes, energy, grad=None, stream=None):
+    import torch
+    n = genes.shape[0] if genes.ndim == 2 else 0
+    gp = _dev_ptr(genes, "genes", (n, lig.n_genes), torch.float32)
+    ep = _dev_ptr(energy, "energy", (n,), torch.float32)
+    dp = _dev_ptr(grad, "grad", (n, lig.n_genes), torch.float32) if grad is not None else None
+    _check(lib().md_eval(rec.handle, lig.handle, n, gp, ep, dp, _stream_ptr(stream)), "md_eval")
+
+
+def md_pose(lig: Ligand, genes, xyz, stream=None):
+    import torch
+    n = genes.shape[0]
+    _check(lib().md_pose(lig.handle, n, _dev_ptr(genes, "genes", (n, lig.n_genes), torch.float32),
+                         _dev_ptr(xyz, "xyz", (n, lig.n_atoms, 3), torch.float32), _stream_ptr(stream)),
+           "md_pose")
+
+
+def md_local_search(rec: Receptor, lig: Ligand, genes_in, genes_out, energy_out, n_iters=300,
+                    rho=0.8, eps=1e-2, trace=None, stream=None):
+    import torch
+    n = genes_in.shape[0]
+    tp = _dev_ptr(trace, "trace", (n, n_iters), torch.float32) if trace is not None else None
+    _check(lib().md_local_search(rec.handle, lig.handle, n,
+                                 _dev_ptr(genes_in, "genes_in", (n, lig.n_genes), torch.float32),
+                                 _dev_ptr(genes_out, "genes_out", (n, lig.n_genes), torch.float32),
+                                 _dev_ptr(energy_out, "energy_out", (n,), torch.float32),
+                                 int(n_iters), float(rho), float(eps), tp, _stream_ptr(stream)),
+           "md_local_search")
+
+
+def dock_params(**kw) -> DockParams:
+    p = DockParams()
+    defaults = dict(n_runs=1, pop_size=150, max_evals_per_run=2_500_000, max_generations=27000,
+                    ls_rate=0.06, ls_iters=300, rho=0.8, eps=1e-2, crossover_rate=0.8,
+                    mutation_rate=0.02, tournament_rate=0.6, elitism=1, mut_trans=2.0,
+                    mut_rot=float(np.pi / 2), mut_tors=float(np.pi), seed=7)
+    defaults.update(kw)
+    for k, v in defaults.items():
+        setattr(p, k, v)
+    return p
+
+
+def md_dock_planned_generations(params: DockParams) -> int:
+    return lib().md_dock_planned_generations(C.byref(params))
+
+
+def md_dock(rec: Receptor, lig: Ligand, params: DockParams, stream=None, want_xyz=True):
+    R, G, N = params.n_runs, lig.n_genes, lig.n_atoms
+    be = np.zeros(R, np.float32)
+    bg = np.zeros((R, G), np.float32)
+    bx = np.zeros((R, N, 3), np.float32)
+    ri = np.zeros(R, np.int32)
+    ev = np.zeros(R, np.int64)
+    gn = np.zeros(R, np.int32)
+    res = DockResult(R, G, N, _fptr(be), _fptr(bg), _fptr(bx) if want_xyz else None, _iptr(ri),
+                     ev.ctypes.data_as(C.POINTER(C.c_longlong)), _iptr(gn))
+    _check(lib().md_dock(rec.handle, lig.handle, C.byref(params), C.byref(res), _stream_ptr(stream)),
+           "md_dock")
+    return dict(best_energy=be, best_genes=bg, best_xyz=bx if want_xyz else None, run_index=ri,
+                evals=ev, generations=gn)
+
+
+KERNELS = {"init_population": 0, "generation": 1, "ls_pick": 2, "local_search": 3, "sum_evals": 4,
+           "best_of_runs": 5}
+
+
+def md_ligand_info(lig: Ligand):
+    v = [C.c_int() for _ in range(4)]
+    _check(lib().md_ligand_info(lig.handle, *[C.byref(x) for x in v]), "md_ligand_info")
+    return dict(n_atoms=v[0].value, n_torsions=v[1].value, n_pairs=v[2].value, sum_moving=v[3].value)
+
+
+def md_profile_enable(on=True):
+    _check(lib().md_profile_enable(int(bool(on))), "md_profile_enable")
+
+
+def md_profile_reset():
+    _check(lib().md_profile_reset(), "md_profile_reset")
+
+
+def md_profile_read(kind):
+    ms, n = C.c_double(), C.c_longlong()
+    _check(lib().md_profile_read(KERNELS.get(kind, kind), C.byref(ms), C.byref(n)), "md_profile_read")
+    return ms.value, n.value

@@ -1,0 +1,72 @@
+"""Shared helpers of the GPU parity tests: oracle evaluation of many poses and the
+acceptance rule for energies and gradients.
+
+Tolerance rule (energies 1e-4, gradients 1e-3, relative): the reference value of a pose is a
+sum of many terms of both signs (a clash term can reach 1e9 kcal/mol while the total is a few
+kcal/mol), so "relative" is taken against the larger of |reference| and the sum of the
+absolute values of the terms that make it up (the oracle's condition scale):
+    |E_gpu - E_ref| <= 1e-4 * max(|E_ref|, S_E)
+    |g_gpu - g_ref| <= 1e-3 * max(|g_ref|, S_k)     per gene k.
+FP32 evaluation of such a sum carries an error of a few ulp of S, so the rule bounds what the
+arithmetic can deliver; the plain relative error against |E_ref| is reported beside it.
+The energy is piecewise smooth.  A pose whose FP32 coordinates could fall on the other side of
+a kink than the FP64 ones is compared only where the compared quantity is continuous there:
+energies are skipped within KINK of a grid box face or a hard cutoff (the energy jumps),
+gradients also within KINK of a trilinear cell face or the 0.5 A clamp (the gradient jumps).
+KINK = 5e-5 (grid units for faces, Angstrom for distances) is several times the FP32 error of a
+posed coordinate in these boxes (|x| <= 20 A: 8 ulp ~ 1.5e-5 A ~ 4e-5 grid units).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import ligand as OL
+from oracle import scoring as S
+
+E_TOL = 1e-4
+G_TOL = 1e-3
+KINK = 5e-5
+
+
+def oracle_grid(rec):
+    return S.make_grid(rec.maps, rec.origin, rec.spacing)
+
+
+def oracle_ligand(lig):
+    return OL.from_synth(lig)
+
+
+def oracle_eval_many(grid, olig, genes):
+    return [S.energy_and_gradient(grid, olig, np.asarray(g, np.float64)) for g in genes]
+
+
+def compare(ref, e_gpu, g_gpu=None):
+    """Returns a dict of error statistics; raises AssertionError on a violation."""
+    n = len(ref)
+    checked = checked_e = 0
+    worst_e = worst_g = 0.0
+    plain_e = []
+    fails = []
+    for p in range(n):
+        r = ref[p]
+        scale_e = max(abs(r.energy), r.scale_energy)
+        err_e = abs(float(e_gpu[p]) - r.energy) / scale_e
+        if r.margin_energy >= KINK:
+            worst_e = max(worst_e, err_e)
+            if err_e > E_TOL:
+                fails.append(("energy", p, float(e_gpu[p]), r.energy, err_e))
+            plain_e.append(abs(float(e_gpu[p]) - r.energy) / max(abs(r.energy), 1e-30))
+            checked_e += 1
+        if r.margin >= KINK:
+            if g_gpu is not None:
+                scale_g = np.maximum(np.abs(r.grad), r.scale_grad)
+                err_g = np.abs(np.asarray(g_gpu[p], np.float64) - r.grad) / np.maximum(scale_g, 1e-30)
+                worst_g = max(worst_g, float(err_g.max()))
+                if np.any(err_g > G_TOL):
+                    k = int(np.argmax(err_g))
+                    fails.append(("grad", p, k, float(g_gpu[p][k]), r.grad[k], float(err_g[k])))
+            checked += 1
+    stats = dict(n=n, checked=checked, checked_energy=checked_e, worst_energy=worst_e, worst_grad=worst_g,
+                 median_plain_rel_energy=float(np.median(plain_e)) if plain_e else 0.0)
+    assert not fails, (fails[:5], stats)
+    return stats
