@@ -32,18 +32,29 @@ __device__ __forceinline__ float readlane(float v, int l) {
 }
 
 // Makes this wave's LDS writes visible to its other lanes and keeps the compiler from
-// moving LDS accesses across the point.
+// moving LDS accesses across the point (a wavefront executes its LDS operations in order).
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Butterfly sum: every lane ends with the same bits (each step adds a commuted pair).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
+
+// Wavefront sum through DPP lane moves: quad swaps, half-row and row mirrors, then the row
+// broadcasts of lanes 15 and 31; lane 63 ends with the total, which is returned to every lane
+// (a wave-uniform value).  The addition order is fixed, so the result is deterministic.
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
+  v += dpp<0xb1, 0xf>(v);    // quad_perm [1,0,3,2]
+  v += dpp<0x4e, 0xf>(v);    // quad_perm [2,3,0,1]
+  v += dpp<0x141, 0xf>(v);   // row_half_mirror
+  v += dpp<0x140, 0xf>(v);   // row_mirror
+  v += dpp<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  return readlane(v, 63);
 }
 
 // ------------------------------------------------------------------ counter-based RNG
@@ -82,31 +93,64 @@ __device__ __forceinline__ float wrap_angle(float th) {
   return th - kTwoPi * ceilf((th - kPi) * (1.0f / kTwoPi));
 }
 
-// ------------------------------------------------------------------ per-wave LDS
-struct WaveLds {
-  float4 x[kMaxAtoms];        // posed coordinates
-  float fx[kMaxAtoms];        // intramolecular forces
-  float fy[kMaxAtoms];
-  float fz[kMaxAtoms];
-  float4 tor_u[kMaxTorsions];   // reference axes
-  float4 tor_p[kMaxTorsions];   // reference pivots
-  float2 tor_cs[kMaxTorsions];  // cos, sin of the current angles
-  float4 post_u[kMaxTorsions];  // posed axes
-  float4 post_p[kMaxTorsions];  // posed pivots
+// ------------------------------------------------------------------ LDS layout
+// Dynamic LDS of a block: the ligand's pair records (the first `pl` of them, shared by the
+// block's waves and staged once per launch), then per wave the posed coordinates and the
+// intramolecular force accumulators of its pose.
+struct BlockLds {
+  const float4* pair_coef;   // [pl]
+  const uint32_t* pair_ij;   // [pl]
+  int pl;
+  float4* x;                 // this wave: [64*A] posed x, y, z
+  float4* f;                 // this wave: [64*A] intramolecular force x, y, z
 };
 
-// Per-lane ligand constants for A atoms per lane (atom lane + 64*a).
+__host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
+
+__host__ __device__ inline size_t lds_bytes(int pl, int A) {
+  return align16((size_t)pl * 16) + align16((size_t)pl * 4) + (size_t)kWavesPerBlock * 2 * 16 * kWave * A;
+}
+
+extern __shared__ __align__(16) unsigned char g_lds[];
+
+// All threads of the block stage the pair records, then synchronise.  Must be reached by every
+// wave of the block before any of them leaves.
+template <int A>
+__device__ __forceinline__ BlockLds stage_block(const LigDev& L, int pl) {
+  BlockLds b;
+  float4* pc = reinterpret_cast<float4*>(g_lds);
+  uint32_t* pij = reinterpret_cast<uint32_t*>(g_lds + align16((size_t)pl * 16));
+  for (int p = threadIdx.x; p < pl; p += blockDim.x) {
+    pc[p] = L.pair_coef[p];
+    pij[p] = L.pair_ij[p];
+  }
+  __syncthreads();
+  float4* waves = reinterpret_cast<float4*>(g_lds + align16((size_t)pl * 16) + align16((size_t)pl * 4));
+  const int w = threadIdx.x / kWave;
+  b.pair_coef = pc;
+  b.pair_ij = pij;
+  b.pl = pl;
+  b.x = waves + (size_t)w * 2 * kWave * A;
+  b.f = b.x + kWave * A;
+  return b;
+}
+
+// Per-lane ligand constants for A atoms per lane (atom lane + 64*a) and, in lanes k < T, the
+// constants of torsion k (reference axis and pivot, its two atoms, its gene index).  Loops over
+// torsions fetch them with readlane, so the inner loops touch no memory.
 template <int A>
 struct AtomRegs {
   float px[A], py[A], pz[A], q[A];
   int type[A];
   uint32_t mask[A];
   bool valid[A];
+  int gene_of_tor;
+  float tux, tuy, tuz, tpx, tpy, tpz;
+  int ta, tb;
 };
 
 template <int A>
-__device__ __forceinline__ void load_ligand(const LigDev& L, WaveLds& s, AtomRegs<A>& at,
-                                            int& my_gene_of_tor) {
+__device__ __forceinline__ void load_ligand(const LigDev& L, AtomRegs<A>& at) {
   const int lane = lane_id();
 #pragma unroll
   for (int a = 0; a < A; ++a) {
@@ -120,19 +164,30 @@ __device__ __forceinline__ void load_ligand(const LigDev& L, WaveLds& s, AtomReg
     at.type[a] = at.valid[a] ? L.atom_type[i] : 0;
     at.mask[a] = at.valid[a] ? L.atom_mask[i] : 0u;
   }
+  at.gene_of_tor = 0;
+  at.tux = at.tuy = at.tuz = at.tpx = at.tpy = at.tpz = 0.f;
+  at.ta = at.tb = 0;
   if (lane < L.n_tors) {
-    s.tor_u[lane] = L.tor_axis[lane];
-    s.tor_p[lane] = L.tor_pivot[lane];
-    my_gene_of_tor = L.tor_gene[lane];
-  } else {
-    my_gene_of_tor = 0;
+    at.gene_of_tor = L.tor_gene[lane];
+    const float4 u = L.tor_axis[lane], pv = L.tor_pivot[lane];
+    const int2 ab = L.tor_ab[lane];
+    at.tux = u.x;
+    at.tuy = u.y;
+    at.tuz = u.z;
+    at.tpx = pv.x;
+    at.tpy = pv.y;
+    at.tpz = pv.z;
+    at.ta = ab.x;
+    at.tb = ab.y;
   }
-  wave_sync();
 }
+
+__device__ __forceinline__ int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
 // ------------------------------------------------------------------ grid term
 // Trilinear interpolation of (type map + q * electrostatic + |q| * desolvation) and its
 // derivative with respect to the atom position; out-of-grid penalty outside the box.
+// Split in two so the corner loads are in flight while the pair term runs.
 template <int PREC>
 __device__ __forceinline__ float map_at(const void* maps, long long idx) {
   if constexpr (PREC == 0) {
@@ -145,42 +200,70 @@ __device__ __forceinline__ float map_at(const void* maps, long long idx) {
   }
 }
 
+struct GridFetch {
+  float mt[8], me[8], md[8];   // corner values of the type, electrostatic and desolvation maps;
+                               // corner bit0 = +x, bit1 = +y, bit2 = +z
+  float fx, fy, fz;            // fractional position in the cell
+  float ex, ey, ez;            // outside: offset from the box
+  float q;
+  bool inside;
+};
+
 template <int PREC>
-__device__ __forceinline__ float grid_atom(const RecDev& R, float x, float y, float z, int type,
-                                           float q, float& dx, float& dy, float& dz) {
+__device__ __forceinline__ void grid_fetch(const RecDev& R, float x, float y, float z, int type, float q,
+                                           bool valid, GridFetch& g) {
   const float gx = (x - R.ox) * R.inv_h;
   const float gy = (y - R.oy) * R.inv_h;
   const float gz = (z - R.oz) * R.inv_h;
-  const bool inside = gx >= 0.f && gy >= 0.f && gz >= 0.f && gx < (float)(R.nx - 1) &&
-                      gy < (float)(R.ny - 1) && gz < (float)(R.nz - 1);
-  if (!inside) {
-    const float hx = R.ox + (float)(R.nx - 1) * R.h;
-    const float hy = R.oy + (float)(R.ny - 1) * R.h;
-    const float hz = R.oz + (float)(R.nz - 1) * R.h;
-    const float ex = x - fminf(fmaxf(x, R.ox), hx);
-    const float ey = y - fminf(fmaxf(y, R.oy), hy);
-    const float ez = z - fminf(fmaxf(z, R.oz), hz);
-    dx = 2.f * kKout * ex;
-    dy = 2.f * kKout * ey;
-    dz = 2.f * kKout * ez;
-    return kPout + kKout * (ex * ex + ey * ey + ez * ez);
-  }
-  const int ix = (int)gx, iy = (int)gy, iz = (int)gz;
-  const float fx = gx - (float)ix, fy = gy - (float)iy, fz = gz - (float)iz;
-  const long long nx = R.nx, nxy = (long long)R.nx * R.ny;
-  const long long base = (long long)iz * nxy + (long long)iy * nx + ix;
-  const long long mt = (long long)type * R.map_stride + base;
-  const long long me = (long long)kTypes * R.map_stride + base;
-  const long long md = (long long)(kTypes + 1) * R.map_stride + base;
-  const float aq = fabsf(q);
-  float c[8];
+  g.inside = valid && gx >= 0.f && gy >= 0.f && gz >= 0.f && gx < (float)(R.nx - 1) &&
+             gy < (float)(R.ny - 1) && gz < (float)(R.nz - 1);
+  const float hx = R.ox + (float)(R.nx - 1) * R.h;
+  const float hy = R.oy + (float)(R.ny - 1) * R.h;
+  const float hz = R.oz + (float)(R.nz - 1) * R.h;
+  g.ex = x - fminf(fmaxf(x, R.ox), hx);
+  g.ey = y - fminf(fmaxf(y, R.oy), hy);
+  g.ez = z - fminf(fmaxf(z, R.oz), hz);
+  g.fx = g.fy = g.fz = 0.f;
+  g.q = q;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const long long off = ((k >> 2) & 1) * nxy + ((k >> 1) & 1) * nx + (k & 1);
-    c[k] = map_at<PREC>(R.maps, mt + off) + q * map_at<PREC>(R.maps, me + off) +
-           aq * map_at<PREC>(R.maps, md + off);
+  for (int k = 0; k < 8; ++k) g.mt[k] = g.me[k] = g.md[k] = 0.f;
+  if (g.inside) {
+    const int ix = (int)gx, iy = (int)gy, iz = (int)gz;
+    g.fx = gx - (float)ix;
+    g.fy = gy - (float)iy;
+    g.fz = gz - (float)iz;
+    const long long nx = R.nx, nxy = (long long)R.nx * R.ny;
+    const long long base = (long long)iz * nxy + (long long)iy * nx + ix;
+    const long long mt = (long long)type * R.map_stride + base;
+    const long long me = (long long)kTypes * R.map_stride + base;
+    const long long md = (long long)(kTypes + 1) * R.map_stride + base;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const long long off = ((k >> 2) & 1) * nxy + ((k >> 1) & 1) * nx + (k & 1);
+      g.mt[k] = map_at<PREC>(R.maps, mt + off);
+      g.me[k] = map_at<PREC>(R.maps, me + off);
+      g.md[k] = map_at<PREC>(R.maps, md + off);
+    }
   }
-  // c[k]: bit0 = +x, bit1 = +y, bit2 = +z
+}
+
+__device__ __forceinline__ float grid_finish(const RecDev& R, const GridFetch& g, bool valid, float& dx,
+                                             float& dy, float& dz) {
+  if (!valid) {
+    dx = dy = dz = 0.f;
+    return 0.f;
+  }
+  if (!g.inside) {
+    dx = 2.f * kKout * g.ex;
+    dy = 2.f * kKout * g.ey;
+    dz = 2.f * kKout * g.ez;
+    return kPout + kKout * (g.ex * g.ex + g.ey * g.ey + g.ez * g.ez);
+  }
+  float c[8];
+  const float aq = fabsf(g.q);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) c[k] = g.mt[k] + g.q * g.me[k] + aq * g.md[k];
+  const float fx = g.fx, fy = g.fy, fz = g.fz;
   const float ux = 1.f - fx, uy = 1.f - fy, uz = 1.f - fz;
   const float x00 = ux * c[0] + fx * c[1];
   const float x10 = ux * c[2] + fx * c[3];
@@ -190,18 +273,15 @@ __device__ __forceinline__ float grid_atom(const RecDev& R, float x, float y, fl
   const float y1 = uy * x01 + fy * x11;
   const float v = uz * y0 + fz * y1;
   const float d00 = c[1] - c[0], d10 = c[3] - c[2], d01 = c[5] - c[4], d11 = c[7] - c[6];
-  const float dvx = uz * (uy * d00 + fy * d10) + fz * (uy * d01 + fy * d11);
-  const float dvy = uz * (x10 - x00) + fz * (x11 - x01);
-  const float dvz = y1 - y0;
-  dx = dvx * R.inv_h;
-  dy = dvy * R.inv_h;
-  dz = dvz * R.inv_h;
+  dx = (uz * (uy * d00 + fy * d10) + fz * (uy * d01 + fy * d11)) * R.inv_h;
+  dy = (uz * (x10 - x00) + fz * (x11 - x01)) * R.inv_h;
+  dz = (y1 - y0) * R.inv_h;
   return v;
 }
 
 // ------------------------------------------------------------------ pair term
-// Energy of one intramolecular pair at distance r and dE/dr / r (so that the force on i is
-// that factor times (x_i - x_j)).  r is clamped to R_MIN with zero gradient below it.
+// Energy of one intramolecular pair at squared distance r2 and dE/dr / r (so that the force on
+// i is that factor times (x_i - x_j)).  r is clamped to R_MIN with zero gradient below it.
 __device__ __forceinline__ float pair_term(float r2, bool hb, float4 c, float& f_over_r) {
   const float r = __builtin_sqrtf(r2);
   const float rt = fmaxf(r, kRmin);
@@ -236,12 +316,32 @@ __device__ __forceinline__ float pair_term(float r2, bool hb, float4 c, float& f
   return e;
 }
 
+template <bool GRAD>
+__device__ __forceinline__ float pair_one(const BlockLds& b, uint32_t ij, float4 c) {
+  const int i = ij & 0xff, j = (ij >> 8) & 0xff;
+  const bool hb = (ij >> 16) & 1u;
+  const float4 xi = b.x[i], xj = b.x[j];
+  const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+  float fr;
+  const float e = pair_term(dx * dx + dy * dy + dz * dz, hb, c, fr);
+  if (GRAD) {
+    const float fx = fr * dx, fy = fr * dy, fz = fr * dz;
+    atomicAdd(&b.f[i].x, fx);
+    atomicAdd(&b.f[i].y, fy);
+    atomicAdd(&b.f[i].z, fz);
+    atomicAdd(&b.f[j].x, -fx);
+    atomicAdd(&b.f[j].y, -fy);
+    atomicAdd(&b.f[j].z, -fz);
+  }
+  return e;
+}
+
 // ------------------------------------------------------------------ one pose
 // Energy (returned, identical in every lane) and, with GRAD, the gradient component of
 // gene `lane` (lanes >= n_genes get 0).  xg: gene `lane` of the pose (lanes < n_genes).
 template <int A, int PREC, bool GRAD>
-__device__ float eval_pose(const LigDev& L, const RecDev& R, WaveLds& s, const AtomRegs<A>& at,
-                           int my_gene_of_tor, float xg, float& g_out) {
+__device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, const AtomRegs<A>& at,
+                           float xg, float& g_out) {
   const int lane = lane_id();
   const int T = L.n_tors;
   // rigid-body genes (wave-uniform)
@@ -260,82 +360,72 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, WaveLds& s, const A
   const float r20 = 2.f * (qx * qz - qw * qy), r21 = 2.f * (qy * qz + qw * qx),
               r22 = 1.f - 2.f * (qx * qx + qy * qy);
 
-  // torsion angles -> cos/sin table
-  const float th = __shfl(xg, my_gene_of_tor, kWave);
-  if (lane < T) {
-    float sn, cs;
-    sincosf(th, &sn, &cs);
-    s.tor_cs[lane] = make_float2(cs, sn);
-  }
-  wave_sync();
+  // torsion angle of torsion `lane` (internal order) -> cos, sin in that lane
+  const float th = __shfl(xg, at.gene_of_tor, kWave);
+  float tsn = 0.f, tcs = 1.f;
+  if (lane < T) sincosf(th, &tsn, &tcs);
 
-  // pose: each lane turns its atoms about their torsion chain, deepest torsion first,
-  // about reference-frame axes; then orientation and translation.
-  float x[A], y[A], z[A];
+  // pose: torsions from the deepest to the root-most, each about its reference-frame axis,
+  // applied by every lane whose atom it moves; then orientation and translation.
+  float px[A], py[A], pz[A];
 #pragma unroll
   for (int a = 0; a < A; ++a) {
-    float px = at.px[a], py = at.py[a], pz = at.pz[a];
-    uint32_t m = at.mask[a];
-    while (m) {
-      const int k = 31 - __clz(m);
-      m &= ~(1u << k);
-      const float4 u = s.tor_u[k];
-      const float4 pv = s.tor_p[k];
-      const float2 cs = s.tor_cs[k];
-      const float vx = px - pv.x, vy = py - pv.y, vz = pz - pv.z;
-      const float ud = u.x * vx + u.y * vy + u.z * vz;
-      const float cx = u.y * vz - u.z * vy, cy = u.z * vx - u.x * vz, cz = u.x * vy - u.y * vx;
-      const float omc = (1.f - cs.x) * ud;
-      px = pv.x + vx * cs.x + cx * cs.y + u.x * omc;
-      py = pv.y + vy * cs.x + cy * cs.y + u.y * omc;
-      pz = pv.z + vz * cs.x + cz * cs.y + u.z * omc;
-    }
-    x[a] = r00 * px + r01 * py + r02 * pz + tx;
-    y[a] = r10 * px + r11 * py + r12 * pz + ty;
-    z[a] = r20 * px + r21 * py + r22 * pz + tz;
-    if (at.valid[a]) {
-      const int i = lane + kWave * a;
-      s.x[i] = make_float4(x[a], y[a], z[a], 0.f);
-      if (GRAD) {
-        s.fx[i] = 0.f;
-        s.fy[i] = 0.f;
-        s.fz[i] = 0.f;
+    px[a] = at.px[a];
+    py[a] = at.py[a];
+    pz[a] = at.pz[a];
+  }
+  for (int k = T - 1; k >= 0; --k) {
+    const float ux = readlane(at.tux, k), uy = readlane(at.tuy, k), uz = readlane(at.tuz, k);
+    const float vpx = readlane(at.tpx, k), vpy = readlane(at.tpy, k), vpz = readlane(at.tpz, k);
+    const float cs = readlane(tcs, k), sn = readlane(tsn, k);
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+      if ((at.mask[a] >> k) & 1u) {
+        const float vx = px[a] - vpx, vy = py[a] - vpy, vz = pz[a] - vpz;
+        const float ud = ux * vx + uy * vy + uz * vz;
+        const float cx = uy * vz - uz * vy, cy = uz * vx - ux * vz, cz = ux * vy - uy * vx;
+        const float omc = (1.f - cs) * ud;
+        px[a] = vpx + vx * cs + cx * sn + ux * omc;
+        py[a] = vpy + vy * cs + cy * sn + uy * omc;
+        pz[a] = vpz + vz * cs + cz * sn + uz * omc;
       }
     }
   }
-
-  // grid term
-  float e_lane = 0.f;
-  float gfx[A], gfy[A], gfz[A];
+  float x[A], y[A], z[A];
 #pragma unroll
   for (int a = 0; a < A; ++a) {
-    gfx[a] = gfy[a] = gfz[a] = 0.f;
-    if (at.valid[a]) {
-      e_lane += grid_atom<PREC>(R, x[a], y[a], z[a], at.type[a], at.q[a], gfx[a], gfy[a], gfz[a]);
-    }
+    x[a] = r00 * px[a] + r01 * py[a] + r02 * pz[a] + tx;
+    y[a] = r10 * px[a] + r11 * py[a] + r12 * pz[a] + ty;
+    z[a] = r20 * px[a] + r21 * py[a] + r22 * pz[a] + tz;
+    const int i = lane + kWave * a;
+    b.x[i] = make_float4(x[a], y[a], z[a], 0.f);
+    if (GRAD) b.f[i] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
+
+  // grid term: issue the corner loads now, finish after the pair term
+  GridFetch gf[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) grid_fetch<PREC>(R, x[a], y[a], z[a], at.type[a], at.q[a], at.valid[a], gf[a]);
   wave_sync();
 
-  // intramolecular pairs, strided over lanes
-  for (int p = lane; p < L.n_pairs; p += kWave) {
-    const uint32_t ij = L.pair_ij[p];
-    const float4 c = L.pair_coef[p];
-    const int i = ij & 0xff, j = (ij >> 8) & 0xff;
-    const bool hb = (ij >> 16) & 1u;
-    const float4 xi = s.x[i], xj = s.x[j];
-    const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-    float fr;
-    e_lane += pair_term(dx * dx + dy * dy + dz * dz, hb, c, fr);
-    if (GRAD) {
-      const float fx = fr * dx, fy = fr * dy, fz = fr * dz;
-      atomicAdd(&s.fx[i], fx);
-      atomicAdd(&s.fy[i], fy);
-      atomicAdd(&s.fz[i], fz);
-      atomicAdd(&s.fx[j], -fx);
-      atomicAdd(&s.fy[j], -fy);
-      atomicAdd(&s.fz[j], -fz);
-    }
+  // intramolecular pairs, strided over lanes, two at a time: first the records staged in
+  // LDS, then (large ligands only) the rest from global memory
+  float e_lane = 0.f;
+  const int P = L.n_pairs;
+  for (int p = lane; p < b.pl; p += 2 * kWave) {
+    const bool two = p + kWave < b.pl;
+    const uint32_t ij0 = b.pair_ij[p];
+    const float4 c0 = b.pair_coef[p];
+    const uint32_t ij1 = two ? b.pair_ij[p + kWave] : 0u;
+    const float4 c1 = two ? b.pair_coef[p + kWave] : make_float4(0.f, 0.f, 0.f, 0.f);
+    e_lane += pair_one<GRAD>(b, ij0, c0);
+    if (two) e_lane += pair_one<GRAD>(b, ij1, c1);
   }
+  for (int p = b.pl + lane; p < P; p += kWave) e_lane += pair_one<GRAD>(b, L.pair_ij[p], L.pair_coef[p]);
+
+  float gfx[A], gfy[A], gfz[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) e_lane += grid_finish(R, gf[a], at.valid[a], gfx[a], gfy[a], gfz[a]);
   const float E = wave_sum(e_lane);
   if (!GRAD) return E;
   wave_sync();
@@ -353,15 +443,10 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, WaveLds& s, const A
     tqx += ry * gfz[a] - rz * gfy[a];
     tqy += rz * gfx[a] - rx * gfz[a];
     tqz += rx * gfy[a] - ry * gfx[a];
-    Fx[a] = gfx[a];
-    Fy[a] = gfy[a];
-    Fz[a] = gfz[a];
-    if (at.valid[a]) {
-      const int i = lane + kWave * a;
-      Fx[a] += s.fx[i];
-      Fy[a] += s.fy[i];
-      Fz[a] += s.fz[i];
-    }
+    const float4 fi = b.f[lane + kWave * a];
+    Fx[a] = gfx[a] + fi.x;
+    Fy[a] = gfy[a] + fi.y;
+    Fz[a] = gfz[a] + fi.z;
   }
   sfx = wave_sum(sfx);
   sfy = wave_sum(sfy);
@@ -380,32 +465,38 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, WaveLds& s, const A
   if (lane == 5) g = 2.f * (qw * tqy - (qz * tqx - qx * tqz)) * iqn;
   if (lane == 6) g = 2.f * (qw * tqz - (qx * tqy - qy * tqx)) * iqn;
 
-  // torsions: posed axis and pivot, then axis . sum over moved atoms of arm x force
+  // torsions: lane k forms the posed axis and pivot of torsion k; then for each k every lane
+  // adds axis . (arm x force) of its atoms moved by k
+  float aux = 0.f, auy = 0.f, auz = 0.f, apx = 0.f, apy = 0.f, apz = 0.f;
   if (lane < T) {
-    const int2 ab = L.tor_ab[lane];
-    const float4 xa = s.x[ab.x], xb = s.x[ab.y];
-    float ux = xb.x - xa.x, uy = xb.y - xa.y, uz = xb.z - xa.z;
-    const float il = 1.f / __builtin_sqrtf(ux * ux + uy * uy + uz * uz);
-    s.post_u[lane] = make_float4(ux * il, uy * il, uz * il, 0.f);
-    s.post_p[lane] = xa;
+    const float4 xa = b.x[at.ta], xb = b.x[at.tb];
+    aux = xb.x - xa.x;
+    auy = xb.y - xa.y;
+    auz = xb.z - xa.z;
+    const float il = __builtin_amdgcn_rsqf(aux * aux + auy * auy + auz * auz);
+    aux *= il;
+    auy *= il;
+    auz *= il;
+    apx = xa.x;
+    apy = xa.y;
+    apz = xa.z;
   }
-  wave_sync();
   for (int k = 0; k < T; ++k) {
-    const float4 u = s.post_u[k];
-    const float4 pa = s.post_p[k];
+    const float ux = readlane(aux, k), uy = readlane(auy, k), uz = readlane(auz, k);
+    const float pax = readlane(apx, k), pay = readlane(apy, k), paz = readlane(apz, k);
     float c = 0.f;
 #pragma unroll
     for (int a = 0; a < A; ++a) {
       if ((at.mask[a] >> k) & 1u) {
-        const float rx = x[a] - pa.x, ry = y[a] - pa.y, rz = z[a] - pa.z;
+        const float rx = x[a] - pax, ry = y[a] - pay, rz = z[a] - paz;
         const float cx = ry * Fz[a] - rz * Fy[a];
         const float cy = rz * Fx[a] - rx * Fz[a];
         const float cz = rx * Fy[a] - ry * Fx[a];
-        c += u.x * cx + u.y * cy + u.z * cz;
+        c += ux * cx + uy * cy + uz * cz;
       }
     }
     c = wave_sum(c);
-    if (lane == L.tor_gene[k]) g = c;
+    if (lane == readlane_i(at.gene_of_tor, k)) g = c;
   }
   g_out = g;
   return E;
@@ -413,26 +504,23 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, WaveLds& s, const A
 
 // ------------------------------------------------------------------ kernels
 template <int A, int PREC>
-__global__ __launch_bounds__(kBlock) void k_eval(LigDev L, RecDev R, int n, const float* __restrict__ genes,
+__global__ __launch_bounds__(kBlock) void k_eval(LigDev L, RecDev R, int n, int pl, const float* __restrict__ genes,
                                                  float* __restrict__ energy, float* __restrict__ grad) {
-  __shared__ WaveLds lds[kWavesPerBlock];
-  const int w = threadIdx.x / kWave;
-  const int pose = blockIdx.x * kWavesPerBlock + w;
+  const BlockLds b = stage_block<A>(L, pl);
+  const int pose = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
   if (pose >= n) return;
-  WaveLds& s = lds[w];
   AtomRegs<A> at;
-  int gtor;
-  load_ligand<A>(L, s, at, gtor);
+  load_ligand<A>(L, at);
   const int lane = lane_id();
   const int G = L.n_genes;
   const float xg = lane < G ? genes[(long long)pose * G + lane] : 0.f;
   float g = 0.f;
   float E;
   if (grad) {
-    E = eval_pose<A, PREC, true>(L, R, s, at, gtor, xg, g);
+    E = eval_pose<A, PREC, true>(L, R, b, at, xg, g);
     if (lane < G) grad[(long long)pose * G + lane] = g;
   } else {
-    E = eval_pose<A, PREC, false>(L, R, s, at, gtor, xg, g);
+    E = eval_pose<A, PREC, false>(L, R, b, at, xg, g);
   }
   if (lane == 0) energy[pose] = E;
 }
@@ -440,54 +528,55 @@ __global__ __launch_bounds__(kBlock) void k_eval(LigDev L, RecDev R, int n, cons
 template <int A>
 __global__ __launch_bounds__(kBlock) void k_pose(LigDev L, int n, const float* __restrict__ genes,
                                                  float* __restrict__ xyz) {
-  __shared__ WaveLds lds[kWavesPerBlock];
-  const int w = threadIdx.x / kWave;
-  const int pose = blockIdx.x * kWavesPerBlock + w;
+  const int pose = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
   if (pose >= n) return;
-  WaveLds& s = lds[w];
   AtomRegs<A> at;
-  int gtor;
-  load_ligand<A>(L, s, at, gtor);
+  load_ligand<A>(L, at);
   const int lane = lane_id();
   const int G = L.n_genes;
+  const int T = L.n_tors;
   const float xg = lane < G ? genes[(long long)pose * G + lane] : 0.f;
   float qw = readlane(xg, 3), qx = readlane(xg, 4), qy = readlane(xg, 5), qz = readlane(xg, 6);
   const float iqn = 1.f / __builtin_sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
   qw *= iqn; qx *= iqn; qy *= iqn; qz *= iqn;
   const float tx = readlane(xg, 0), ty = readlane(xg, 1), tz = readlane(xg, 2);
-  const float th = __shfl(xg, gtor, kWave);
-  if (lane < L.n_tors) {
-    float sn, cs;
-    sincosf(th, &sn, &cs);
-    s.tor_cs[lane] = make_float2(cs, sn);
+  const float th = __shfl(xg, at.gene_of_tor, kWave);
+  float tsn = 0.f, tcs = 1.f;
+  if (lane < T) sincosf(th, &tsn, &tcs);
+  float px[A], py[A], pz[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) {
+    px[a] = at.px[a];
+    py[a] = at.py[a];
+    pz[a] = at.pz[a];
   }
-  wave_sync();
+  for (int k = T - 1; k >= 0; --k) {
+    const float ux = readlane(at.tux, k), uy = readlane(at.tuy, k), uz = readlane(at.tuz, k);
+    const float vpx = readlane(at.tpx, k), vpy = readlane(at.tpy, k), vpz = readlane(at.tpz, k);
+    const float cs = readlane(tcs, k), sn = readlane(tsn, k);
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+      if ((at.mask[a] >> k) & 1u) {
+        const float vx = px[a] - vpx, vy = py[a] - vpy, vz = pz[a] - vpz;
+        const float ud = ux * vx + uy * vy + uz * vz;
+        const float cx = uy * vz - uz * vy, cy = uz * vx - ux * vz, cz = ux * vy - uy * vx;
+        const float omc = (1.f - cs) * ud;
+        px[a] = vpx + vx * cs + cx * sn + ux * omc;
+        py[a] = vpy + vy * cs + cy * sn + uy * omc;
+        pz[a] = vpz + vz * cs + cz * sn + uz * omc;
+      }
+    }
+  }
+  const float r00 = 1.f - 2.f * (qy * qy + qz * qz), r01 = 2.f * (qx * qy - qw * qz), r02 = 2.f * (qx * qz + qw * qy);
+  const float r10 = 2.f * (qx * qy + qw * qz), r11 = 1.f - 2.f * (qx * qx + qz * qz), r12 = 2.f * (qy * qz - qw * qx);
+  const float r20 = 2.f * (qx * qz - qw * qy), r21 = 2.f * (qy * qz + qw * qx), r22 = 1.f - 2.f * (qx * qx + qy * qy);
 #pragma unroll
   for (int a = 0; a < A; ++a) {
     if (!at.valid[a]) continue;
-    float px = at.px[a], py = at.py[a], pz = at.pz[a];
-    uint32_t m = at.mask[a];
-    while (m) {
-      const int k = 31 - __clz(m);
-      m &= ~(1u << k);
-      const float4 u = s.tor_u[k];
-      const float4 pv = s.tor_p[k];
-      const float2 cs = s.tor_cs[k];
-      const float vx = px - pv.x, vy = py - pv.y, vz = pz - pv.z;
-      const float ud = u.x * vx + u.y * vy + u.z * vz;
-      const float cx = u.y * vz - u.z * vy, cy = u.z * vx - u.x * vz, cz = u.x * vy - u.y * vx;
-      const float omc = (1.f - cs.x) * ud;
-      px = pv.x + vx * cs.x + cx * cs.y + u.x * omc;
-      py = pv.y + vy * cs.x + cy * cs.y + u.y * omc;
-      pz = pv.z + vz * cs.x + cz * cs.y + u.z * omc;
-    }
-    const float r00 = 1.f - 2.f * (qy * qy + qz * qz), r01 = 2.f * (qx * qy - qw * qz), r02 = 2.f * (qx * qz + qw * qy);
-    const float r10 = 2.f * (qx * qy + qw * qz), r11 = 1.f - 2.f * (qx * qx + qz * qz), r12 = 2.f * (qy * qz - qw * qx);
-    const float r20 = 2.f * (qx * qz - qw * qy), r21 = 2.f * (qy * qz + qw * qx), r22 = 1.f - 2.f * (qx * qx + qy * qy);
     const long long o = ((long long)pose * L.n_atoms + lane + kWave * a) * 3;
-    xyz[o + 0] = r00 * px + r01 * py + r02 * pz + tx;
-    xyz[o + 1] = r10 * px + r11 * py + r12 * pz + ty;
-    xyz[o + 2] = r20 * px + r21 * py + r22 * pz + tz;
+    xyz[o + 0] = r00 * px[a] + r01 * py[a] + r02 * pz[a] + tx;
+    xyz[o + 1] = r10 * px[a] + r11 * py[a] + r12 * pz[a] + ty;
+    xyz[o + 2] = r20 * px[a] + r21 * py[a] + r22 * pz[a] + tz;
   }
 }
 
@@ -512,19 +601,17 @@ __device__ __forceinline__ float adadelta_update(float x, float g, float& eg2, f
 
 // One wave per local search.  rows: optional map wave -> row of genes_in/genes_out.
 template <int A, int PREC>
-__global__ __launch_bounds__(kBlock) void k_local_search(LigDev L, RecDev R, int n, const int* __restrict__ rows,
+__global__ __launch_bounds__(kBlock) void k_local_search(LigDev L, RecDev R, int n, int pl,
+                                                         const int* __restrict__ rows,
                                                          const float* genes_in, float* genes_out,
                                                          float* __restrict__ energy_out, int* __restrict__ evals,
                                                          int iters, float rho, float eps,
                                                          float* __restrict__ trace) {
-  __shared__ WaveLds lds[kWavesPerBlock];
-  const int w = threadIdx.x / kWave;
-  const int job = blockIdx.x * kWavesPerBlock + w;
+  const BlockLds b = stage_block<A>(L, pl);
+  const int job = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
   if (job >= n) return;
-  WaveLds& s = lds[w];
   AtomRegs<A> at;
-  int gtor;
-  load_ligand<A>(L, s, at, gtor);
+  load_ligand<A>(L, at);
   const int lane = lane_id();
   const int G = L.n_genes;
   const long long row = rows ? rows[job] : job;
@@ -534,7 +621,7 @@ __global__ __launch_bounds__(kBlock) void k_local_search(LigDev L, RecDev R, int
   float best_e = __builtin_huge_valf();
   for (int it = 0; it < iters; ++it) {
     float g = 0.f;
-    const float E = eval_pose<A, PREC, true>(L, R, s, at, gtor, x, g);
+    const float E = eval_pose<A, PREC, true>(L, R, b, at, x, g);
     if (trace && lane == 0) trace[(long long)job * iters + it] = E;
     if (E < best_e) {
       best_e = E;
@@ -575,24 +662,21 @@ __device__ __forceinline__ float initial_gene(const RecDev& R, const GaDev& P, i
 }
 
 template <int A, int PREC>
-__global__ __launch_bounds__(kBlock) void k_init_population(LigDev L, RecDev R, GaDev P,
+__global__ __launch_bounds__(kBlock) void k_init_population(LigDev L, RecDev R, GaDev P, int pl,
                                                             float* __restrict__ genes,
                                                             float* __restrict__ energy,
                                                             int* __restrict__ evals) {
-  __shared__ WaveLds lds[kWavesPerBlock];
-  const int w = threadIdx.x / kWave;
-  const int job = blockIdx.x * kWavesPerBlock + w;
+  const BlockLds b = stage_block<A>(L, pl);
+  const int job = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
   if (job >= P.n_runs * P.pop_size) return;
-  WaveLds& s = lds[w];
   AtomRegs<A> at;
-  int gtor;
-  load_ligand<A>(L, s, at, gtor);
+  load_ligand<A>(L, at);
   const int lane = lane_id();
   const int G = L.n_genes;
   const int run = job / P.pop_size, indiv = job % P.pop_size;
   const float x = initial_gene(R, P, run, indiv);
   float g;
-  const float E = eval_pose<A, PREC, false>(L, R, s, at, gtor, x, g);
+  const float E = eval_pose<A, PREC, false>(L, R, b, at, x, g);
   if (lane < G) genes[(long long)job * G + lane] = x;
   if (lane == 0) {
     energy[job] = E;
@@ -640,15 +724,14 @@ __device__ __forceinline__ int tournament(const float* __restrict__ E, const GaD
 __device__ __forceinline__ int unit_of(int g) { return g < 3 ? g : (g < 7 ? 3 : g - 3); }
 
 template <int A, int PREC>
-__global__ __launch_bounds__(kBlock) void k_generation(LigDev L, RecDev R, GaDev P, int gen,
+__global__ __launch_bounds__(kBlock) void k_generation(LigDev L, RecDev R, GaDev P, int gen, int pl,
                                                        const float* __restrict__ genes_in,
                                                        const float* __restrict__ energy_in,
                                                        float* __restrict__ genes_out,
                                                        float* __restrict__ energy_out,
                                                        int* __restrict__ evals) {
-  __shared__ WaveLds lds[kWavesPerBlock];
-  const int w = threadIdx.x / kWave;
-  const int job = blockIdx.x * kWavesPerBlock + w;
+  const BlockLds b = stage_block<A>(L, pl);
+  const int job = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
   if (job >= P.n_runs * P.pop_size) return;
   const int lane = lane_id();
   const int G = L.n_genes;
@@ -664,10 +747,8 @@ __global__ __launch_bounds__(kBlock) void k_generation(LigDev L, RecDev R, GaDev
     }
     return;
   }
-  WaveLds& s = lds[w];
   AtomRegs<A> at;
-  int gtor;
-  load_ligand<A>(L, s, at, gtor);
+  load_ligand<A>(L, at);
   const int pa = tournament(E, P, run, gen, slot, 0);
   const int pb = tournament(E, P, run, gen, slot, 1);
   const float xa = lane < G ? genes_in[(rbase + pa) * G + lane] : 0.f;
@@ -713,7 +794,7 @@ __global__ __launch_bounds__(kBlock) void k_generation(LigDev L, RecDev R, GaDev
     if (lane == 6) x = nz * inv;
   }
   float g;
-  const float Enew = eval_pose<A, PREC, false>(L, R, s, at, gtor, x, g);
+  const float Enew = eval_pose<A, PREC, false>(L, R, b, at, x, g);
   if (lane < G) genes_out[(long long)job * G + lane] = x;
   if (lane == 0) {
     energy_out[job] = Enew;
@@ -782,23 +863,30 @@ inline unsigned blocks_for(long long waves) {
 
 }  // namespace
 
-#define MDOCK_DISPATCH(KERNEL, GRID, STREAM, ...)                                              \
-  do {                                                                                        \
-    const bool two = L.n_atoms > kWave;                                                       \
-    switch (R.precision * 2 + (two ? 1 : 0)) {                                                \
-      case 0: hipLaunchKernelGGL((KERNEL<1, 0>), GRID, dim3(kBlock), 0, STREAM, __VA_ARGS__); break; \
-      case 1: hipLaunchKernelGGL((KERNEL<2, 0>), GRID, dim3(kBlock), 0, STREAM, __VA_ARGS__); break; \
-      case 2: hipLaunchKernelGGL((KERNEL<1, 1>), GRID, dim3(kBlock), 0, STREAM, __VA_ARGS__); break; \
-      case 3: hipLaunchKernelGGL((KERNEL<2, 1>), GRID, dim3(kBlock), 0, STREAM, __VA_ARGS__); break; \
-      case 4: hipLaunchKernelGGL((KERNEL<1, 2>), GRID, dim3(kBlock), 0, STREAM, __VA_ARGS__); break; \
-      default: hipLaunchKernelGGL((KERNEL<2, 2>), GRID, dim3(kBlock), 0, STREAM, __VA_ARGS__); break; \
-    }                                                                                         \
+// Pair records staged in LDS per block (the rest are read from global memory).
+constexpr int kPairLdsMax = 2048;
+
+#define MDOCK_DISPATCH(KERNEL, GRID, STREAM, ...)                                                   \
+  do {                                                                                             \
+    const bool two = L.n_atoms > kWave;                                                            \
+    const int pl = L.n_pairs < kPairLdsMax ? L.n_pairs : kPairLdsMax;                              \
+    const size_t sm = lds_bytes(pl, two ? 2 : 1);                                                  \
+    switch (R.precision * 2 + (two ? 1 : 0)) {                                                     \
+      case 0: hipLaunchKernelGGL((KERNEL<1, 0>), GRID, dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
+      case 1: hipLaunchKernelGGL((KERNEL<2, 0>), GRID, dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
+      case 2: hipLaunchKernelGGL((KERNEL<1, 1>), GRID, dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
+      case 3: hipLaunchKernelGGL((KERNEL<2, 1>), GRID, dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
+      case 4: hipLaunchKernelGGL((KERNEL<1, 2>), GRID, dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
+      default: hipLaunchKernelGGL((KERNEL<2, 2>), GRID, dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
+    }                                                                                              \
   } while (0)
+
+#define MDOCK_PL (L.n_pairs < kPairLdsMax ? L.n_pairs : kPairLdsMax)
 
 hipError_t launch_eval(const LigDev& L, const RecDev& R, int n, const float* genes, float* energy,
                        float* grad, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  MDOCK_DISPATCH(k_eval, dim3(blocks_for(n)), s, L, R, n, genes, energy, grad);
+  MDOCK_DISPATCH(k_eval, dim3(blocks_for(n)), s, L, R, n, MDOCK_PL, genes, energy, grad);
   return hipGetLastError();
 }
 
@@ -816,7 +904,7 @@ hipError_t launch_local_search(const LigDev& L, const RecDev& R, int n, const in
                                int* evals, int iters, float rho, float eps, float* trace,
                                hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  MDOCK_DISPATCH(k_local_search, dim3(blocks_for(n)), s, L, R, n, rows, genes_in, genes_out,
+  MDOCK_DISPATCH(k_local_search, dim3(blocks_for(n)), s, L, R, n, MDOCK_PL, rows, genes_in, genes_out,
                  energy_out, evals, iters, rho, eps, trace);
   return hipGetLastError();
 }
@@ -824,7 +912,7 @@ hipError_t launch_local_search(const LigDev& L, const RecDev& R, int n, const in
 hipError_t launch_init_population(const LigDev& L, const RecDev& R, const GaDev& P, float* genes,
                                   float* energy, int* evals, hipStream_t s) {
   MDOCK_DISPATCH(k_init_population, dim3(blocks_for((long long)P.n_runs * P.pop_size)), s, L, R, P,
-                 genes, energy, evals);
+                 MDOCK_PL, genes, energy, evals);
   return hipGetLastError();
 }
 
@@ -832,7 +920,7 @@ hipError_t launch_generation(const LigDev& L, const RecDev& R, const GaDev& P, i
                              const float* genes_in, const float* energy_in, float* genes_out,
                              float* energy_out, int* evals, hipStream_t s) {
   MDOCK_DISPATCH(k_generation, dim3(blocks_for((long long)P.n_runs * P.pop_size)), s, L, R, P, gen,
-                 genes_in, energy_in, genes_out, energy_out, evals);
+                 MDOCK_PL, genes_in, energy_in, genes_out, energy_out, evals);
   return hipGetLastError();
 }
 

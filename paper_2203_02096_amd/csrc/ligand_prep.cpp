@@ -179,6 +179,25 @@ std::string prepare_ligand(int n, const float* xyz, const int* type, const float
       out.pair_coef.push_back(make_float4((float)c12, (float)cn, (float)qq, (float)ds));
     }
   }
+  // Interleave the pairs round-robin over their first atom, so that the 64 pairs a wavefront
+  // handles at once touch mostly distinct atoms (their force updates then rarely hit the same
+  // LDS address at the same time).
+  {
+    std::vector<std::vector<size_t>> by_i(n);
+    for (size_t p = 0; p < out.pair_ij.size(); ++p) by_i[out.pair_ij[p] & 0xff].push_back(p);
+    std::vector<uint32_t> ij;
+    std::vector<float4> coef;
+    ij.reserve(out.pair_ij.size());
+    coef.reserve(out.pair_ij.size());
+    for (size_t round = 0; ij.size() < out.pair_ij.size(); ++round)
+      for (int i = 0; i < n; ++i)
+        if (round < by_i[i].size()) {
+          ij.push_back(out.pair_ij[by_i[i][round]]);
+          coef.push_back(out.pair_coef[by_i[i][round]]);
+        }
+    out.pair_ij.swap(ij);
+    out.pair_coef.swap(coef);
+  }
   return std::string();
 }
 
