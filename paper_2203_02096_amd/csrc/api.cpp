@@ -209,6 +209,7 @@ md_status md_ligand_create(const md_ligand_desc* d, md_ligand** out) {
   const size_t o_gene = off; off = align16(off + T * sizeof(int));
   const size_t o_ij = off; off = align16(off + P * sizeof(uint32_t));
   const size_t o_coef = off; off = align16(off + P * sizeof(float4));
+  const size_t o_inc = off; off = align16(off + h.inc.size() * sizeof(uint32_t));
   std::vector<char> buf(std::max<size_t>(off, 16), 0);
   auto put = [&](size_t o, const void* p, size_t n) { if (n) std::memcpy(buf.data() + o, p, n); };
   put(o_p0q, h.atom_p0q.data(), N * sizeof(float4));
@@ -220,6 +221,7 @@ md_status md_ligand_create(const md_ligand_desc* d, md_ligand** out) {
   put(o_gene, h.tor_gene.data(), T * sizeof(int));
   put(o_ij, h.pair_ij.data(), P * sizeof(uint32_t));
   put(o_coef, h.pair_coef.data(), P * sizeof(float4));
+  put(o_inc, h.inc.data(), h.inc.size() * sizeof(uint32_t));
   hipError_t e = hipGetDevice(&l->device);
   if (e == hipSuccess) e = hipMalloc(&l->d_buf, buf.size());
   if (e == hipSuccess) e = hipMemcpy(l->d_buf, buf.data(), buf.size(), hipMemcpyHostToDevice);
@@ -243,6 +245,9 @@ md_status md_ligand_create(const md_ligand_desc* d, md_ligand** out) {
   L.tor_gene = reinterpret_cast<const int*>(b + o_gene);
   L.pair_ij = reinterpret_cast<const uint32_t*>(b + o_ij);
   L.pair_coef = reinterpret_cast<const float4*>(b + o_coef);
+  L.inc_width = h.inc_width;
+  L.inc_stride = h.inc_stride;
+  L.inc = reinterpret_cast<const uint32_t*>(b + o_inc);
   *out = l;
   return MD_OK;
 }

@@ -17,6 +17,11 @@ constexpr int kTypes = 7;
 constexpr int kMaps = kTypes + 2;
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
+// Pair records kept in LDS per block; their per-pose force scalars also live in LDS and reach
+// the atoms through the incidence table.  Pairs beyond this index (ligands above ~70 atoms)
+// are read from global memory and their forces accumulated with LDS atomics.
+constexpr int kPairLdsMax = 2048;
+constexpr uint32_t kIncNone = 0xffffffffu;
 
 // Scoring constants (AutoDock4 force-field forms and weights).
 constexpr float kWvdw = 0.1662f;
@@ -51,6 +56,9 @@ struct LigDev {
   const uint32_t* pair_ij;    // [P] i | j << 8 | hbond << 16
   const float4* pair_coef;    // [P] weighted C12, weighted C6 or C10, W_el*332*qi*qj,
                               //     W_ds*(S_i V_j + S_j V_i)
+  int inc_width;              // incidences of the busiest atom (pairs below kPairLdsMax)
+  int inc_stride;             // 64 * atoms per lane
+  const uint32_t* inc;        // [inc_width][inc_stride]: pair | partner << 16, or kIncNone
 };
 
 struct RecDev {
@@ -82,6 +90,8 @@ struct LigHost {
   std::vector<int> tor_gene;
   std::vector<uint32_t> pair_ij;
   std::vector<float4> pair_coef;
+  int inc_width = 0, inc_stride = 64;
+  std::vector<uint32_t> inc;
 };
 
 // Returns an empty string on success, else a message; `range_error` tells MD_ERANGE apart.

@@ -94,44 +94,73 @@ __device__ __forceinline__ float wrap_angle(float th) {
 }
 
 // ------------------------------------------------------------------ LDS layout
-// Dynamic LDS of a block: the ligand's pair records (the first `pl` of them, shared by the
-// block's waves and staged once per launch), then per wave the posed coordinates and the
-// intramolecular force accumulators of its pose.
+// Dynamic LDS of a block, shared part (staged once per launch): the first `pl` pair records
+// and, when it fits, the incidence table.  Then per wave: posed coordinates, the force scalars
+// of its pairs (dE/dr / r) and the force accumulators of the pairs beyond `pl`.
 struct BlockLds {
   const float4* pair_coef;   // [pl]
   const uint32_t* pair_ij;   // [pl]
+  const uint32_t* inc;       // [inc_width][inc_stride], LDS or global
   int pl;
   float4* x;                 // this wave: [64*A] posed x, y, z
-  float4* f;                 // this wave: [64*A] intramolecular force x, y, z
+  float4* f;                 // this wave: [64*A] forces of pairs beyond pl (atomics)
+  float* fr;                 // this wave: [pl] pair force scalars
 };
 
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
 
-__host__ __device__ inline size_t lds_bytes(int pl, int A) {
-  return align16((size_t)pl * 16) + align16((size_t)pl * 4) + (size_t)kWavesPerBlock * 2 * 16 * kWave * A;
+constexpr size_t kIncLdsMax = 16384;   // bytes of incidence table staged in LDS
+
+__host__ __device__ inline size_t inc_bytes(int width, int stride) { return (size_t)width * stride * 4; }
+
+__host__ __device__ inline size_t lds_shared_bytes(int pl, int inc_w, int inc_s) {
+  const size_t ib = inc_bytes(inc_w, inc_s);
+  return align16((size_t)pl * 16) + align16((size_t)pl * 4) + (ib <= kIncLdsMax ? align16(ib) : 0);
+}
+
+__host__ __device__ inline size_t lds_wave_bytes(int pl, int A) {
+  return (size_t)2 * 16 * kWave * A + align16((size_t)pl * 4);
+}
+
+__host__ __device__ inline size_t lds_bytes(int pl, int inc_w, int inc_s, int A) {
+  return lds_shared_bytes(pl, inc_w, inc_s) + (size_t)kWavesPerBlock * lds_wave_bytes(pl, A);
 }
 
 extern __shared__ __align__(16) unsigned char g_lds[];
 
-// All threads of the block stage the pair records, then synchronise.  Must be reached by every
+// All threads of the block stage the shared part, then synchronise.  Must be reached by every
 // wave of the block before any of them leaves.
 template <int A>
 __device__ __forceinline__ BlockLds stage_block(const LigDev& L, int pl) {
   BlockLds b;
-  float4* pc = reinterpret_cast<float4*>(g_lds);
-  uint32_t* pij = reinterpret_cast<uint32_t*>(g_lds + align16((size_t)pl * 16));
+  unsigned char* cur = g_lds;
+  float4* pc = reinterpret_cast<float4*>(cur);
+  cur += align16((size_t)pl * 16);
+  uint32_t* pij = reinterpret_cast<uint32_t*>(cur);
+  cur += align16((size_t)pl * 4);
   for (int p = threadIdx.x; p < pl; p += blockDim.x) {
     pc[p] = L.pair_coef[p];
     pij[p] = L.pair_ij[p];
   }
+  const size_t ib = inc_bytes(L.inc_width, L.inc_stride);
+  if (ib <= kIncLdsMax) {
+    uint32_t* inc = reinterpret_cast<uint32_t*>(cur);
+    const int ne = L.inc_width * L.inc_stride;
+    for (int k = threadIdx.x; k < ne; k += blockDim.x) inc[k] = L.inc[k];
+    b.inc = inc;
+    cur += align16(ib);
+  } else {
+    b.inc = L.inc;
+  }
   __syncthreads();
-  float4* waves = reinterpret_cast<float4*>(g_lds + align16((size_t)pl * 16) + align16((size_t)pl * 4));
   const int w = threadIdx.x / kWave;
+  cur += (size_t)w * lds_wave_bytes(pl, A);
   b.pair_coef = pc;
   b.pair_ij = pij;
   b.pl = pl;
-  b.x = waves + (size_t)w * 2 * kWave * A;
+  b.x = reinterpret_cast<float4*>(cur);
   b.f = b.x + kWave * A;
+  b.fr = reinterpret_cast<float*>(b.f + kWave * A);
   return b;
 }
 
@@ -316,15 +345,19 @@ __device__ __forceinline__ float pair_term(float r2, bool hb, float4 c, float& f
   return e;
 }
 
+// One pair.  GRAD and `slot` >= 0: the force scalar goes to the wave's LDS slot (gathered per
+// atom later); GRAD and slot < 0: the force is added to both atoms with LDS atomics.
 template <bool GRAD>
-__device__ __forceinline__ float pair_one(const BlockLds& b, uint32_t ij, float4 c) {
+__device__ __forceinline__ float pair_one(const BlockLds& b, uint32_t ij, float4 c, int slot) {
   const int i = ij & 0xff, j = (ij >> 8) & 0xff;
   const bool hb = (ij >> 16) & 1u;
   const float4 xi = b.x[i], xj = b.x[j];
   const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
   float fr;
   const float e = pair_term(dx * dx + dy * dy + dz * dz, hb, c, fr);
-  if (GRAD) {
+  if (GRAD && slot >= 0) {
+    b.fr[slot] = fr;
+  } else if (GRAD) {
     const float fx = fr * dx, fy = fr * dy, fz = fr * dz;
     atomicAdd(&b.f[i].x, fx);
     atomicAdd(&b.f[i].y, fy);
@@ -399,7 +432,7 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, 
     z[a] = r20 * px[a] + r21 * py[a] + r22 * pz[a] + tz;
     const int i = lane + kWave * a;
     b.x[i] = make_float4(x[a], y[a], z[a], 0.f);
-    if (GRAD) b.f[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (GRAD && L.n_pairs > b.pl) b.f[i] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
 
   // grid term: issue the corner loads now, finish after the pair term
@@ -418,10 +451,10 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, 
     const float4 c0 = b.pair_coef[p];
     const uint32_t ij1 = two ? b.pair_ij[p + kWave] : 0u;
     const float4 c1 = two ? b.pair_coef[p + kWave] : make_float4(0.f, 0.f, 0.f, 0.f);
-    e_lane += pair_one<GRAD>(b, ij0, c0);
-    if (two) e_lane += pair_one<GRAD>(b, ij1, c1);
+    e_lane += pair_one<GRAD>(b, ij0, c0, p);
+    if (two) e_lane += pair_one<GRAD>(b, ij1, c1, p + kWave);
   }
-  for (int p = b.pl + lane; p < P; p += kWave) e_lane += pair_one<GRAD>(b, L.pair_ij[p], L.pair_coef[p]);
+  for (int p = b.pl + lane; p < P; p += kWave) e_lane += pair_one<GRAD>(b, L.pair_ij[p], L.pair_coef[p], -1);
 
   float gfx[A], gfy[A], gfz[A];
 #pragma unroll
@@ -443,10 +476,30 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, 
     tqx += ry * gfz[a] - rz * gfy[a];
     tqy += rz * gfx[a] - rx * gfz[a];
     tqz += rx * gfy[a] - ry * gfx[a];
-    const float4 fi = b.f[lane + kWave * a];
-    Fx[a] = gfx[a] + fi.x;
-    Fy[a] = gfy[a] + fi.y;
-    Fz[a] = gfz[a] + fi.z;
+    Fx[a] = gfx[a];
+    Fy[a] = gfy[a];
+    Fz[a] = gfz[a];
+    if (L.n_pairs > b.pl) {
+      const float4 fi = b.f[lane + kWave * a];
+      Fx[a] += fi.x;
+      Fy[a] += fi.y;
+      Fz[a] += fi.z;
+    }
+  }
+  // intramolecular forces: each atom gathers (dE/dr / r) * (x_self - x_partner) over its
+  // incidence list, in a fixed order
+  for (int t = 0; t < L.inc_width; ++t) {
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+      const uint32_t e = b.inc[t * L.inc_stride + lane + kWave * a];
+      if (e != kIncNone) {
+        const float fr = b.fr[e & 0xffffu];
+        const float4 xo = b.x[e >> 16];
+        Fx[a] += fr * (x[a] - xo.x);
+        Fy[a] += fr * (y[a] - xo.y);
+        Fz[a] += fr * (z[a] - xo.z);
+      }
+    }
   }
   sfx = wave_sum(sfx);
   sfy = wave_sum(sfy);
@@ -863,14 +916,11 @@ inline unsigned blocks_for(long long waves) {
 
 }  // namespace
 
-// Pair records staged in LDS per block (the rest are read from global memory).
-constexpr int kPairLdsMax = 2048;
-
 #define MDOCK_DISPATCH(KERNEL, GRID, STREAM, ...)                                                   \
   do {                                                                                             \
     const bool two = L.n_atoms > kWave;                                                            \
     const int pl = L.n_pairs < kPairLdsMax ? L.n_pairs : kPairLdsMax;                              \
-    const size_t sm = lds_bytes(pl, two ? 2 : 1);                                                  \
+    const size_t sm = lds_bytes(pl, L.inc_width, L.inc_stride, two ? 2 : 1);                        \
     switch (R.precision * 2 + (two ? 1 : 0)) {                                                     \
       case 0: hipLaunchKernelGGL((KERNEL<1, 0>), GRID, dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
       case 1: hipLaunchKernelGGL((KERNEL<2, 0>), GRID, dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \

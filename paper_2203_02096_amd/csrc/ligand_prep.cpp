@@ -198,6 +198,24 @@ std::string prepare_ligand(int n, const float* xyz, const int* type, const float
     out.pair_ij.swap(ij);
     out.pair_coef.swap(coef);
   }
+  // Incidence table: for every atom, the pairs (among the first kPairLdsMax) it belongs to and
+  // the partner atom, one column per atom so that a wavefront reads a row in one access.
+  {
+    const int P = (int)std::min<size_t>(out.pair_ij.size(), (size_t)kPairLdsMax);
+    std::vector<std::vector<uint32_t>> per(n);
+    for (int p = 0; p < P; ++p) {
+      const uint32_t i = out.pair_ij[p] & 0xff, j = (out.pair_ij[p] >> 8) & 0xff;
+      per[i].push_back((uint32_t)p | (j << 16));
+      per[j].push_back((uint32_t)p | (i << 16));
+    }
+    size_t w = 0;
+    for (auto& v : per) w = std::max(w, v.size());
+    out.inc_width = (int)w;
+    out.inc_stride = n > 64 ? 128 : 64;
+    out.inc.assign(w * out.inc_stride, kIncNone);
+    for (int a = 0; a < n; ++a)
+      for (size_t t = 0; t < per[a].size(); ++t) out.inc[t * out.inc_stride + a] = per[a][t];
+  }
   return std::string();
 }
 
