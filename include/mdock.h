@@ -203,6 +203,18 @@ typedef struct {
 md_status md_dock(const md_receptor* rec, const md_ligand* lig, const md_dock_params* params,
                   md_dock_result* out, void* hip_stream);
 
+/* Many docking jobs at once (ligands of different sizes against one receptor): every GA phase
+ * is one launch (per atoms-per-lane class) over all jobs, through a device-side job table, so
+ * small and large ligands share the GPU.  Each job's result is the same as docking it alone
+ * (its random numbers depend only on its own seed and run, generation and individual).
+ * Blocking.  Errors: as md_dock, for the first job found invalid (message names it). */
+typedef struct {
+  const md_ligand* ligand;
+  md_dock_params params;
+  md_dock_result* result;
+} md_dock_job;
+md_status md_dock_batch(const md_receptor* rec, int n_jobs, const md_dock_job* jobs, void* hip_stream);
+
 /* Number of generations md_dock runs for these parameters (all runs share it). */
 int md_dock_planned_generations(const md_dock_params* params);
 

@@ -209,7 +209,8 @@ md_status md_ligand_create(const md_ligand_desc* d, md_ligand** out) {
   const size_t o_gene = off; off = align16(off + T * sizeof(int));
   const size_t o_ij = off; off = align16(off + P * sizeof(uint32_t));
   const size_t o_coef = off; off = align16(off + P * sizeof(float4));
-  const size_t o_inc = off; off = align16(off + h.inc.size() * sizeof(uint32_t));
+  const size_t o_rows = off; off = align16(off + h.inc_rows.size() * sizeof(int2));
+  const size_t o_inc = off; off = align16(off + h.inc.size() * sizeof(uint16_t));
   std::vector<char> buf(std::max<size_t>(off, 16), 0);
   auto put = [&](size_t o, const void* p, size_t n) { if (n) std::memcpy(buf.data() + o, p, n); };
   put(o_p0q, h.atom_p0q.data(), N * sizeof(float4));
@@ -221,7 +222,8 @@ md_status md_ligand_create(const md_ligand_desc* d, md_ligand** out) {
   put(o_gene, h.tor_gene.data(), T * sizeof(int));
   put(o_ij, h.pair_ij.data(), P * sizeof(uint32_t));
   put(o_coef, h.pair_coef.data(), P * sizeof(float4));
-  put(o_inc, h.inc.data(), h.inc.size() * sizeof(uint32_t));
+  put(o_rows, h.inc_rows.data(), h.inc_rows.size() * sizeof(int2));
+  put(o_inc, h.inc.data(), h.inc.size() * sizeof(uint16_t));
   hipError_t e = hipGetDevice(&l->device);
   if (e == hipSuccess) e = hipMalloc(&l->d_buf, buf.size());
   if (e == hipSuccess) e = hipMemcpy(l->d_buf, buf.data(), buf.size(), hipMemcpyHostToDevice);
@@ -245,9 +247,15 @@ md_status md_ligand_create(const md_ligand_desc* d, md_ligand** out) {
   L.tor_gene = reinterpret_cast<const int*>(b + o_gene);
   L.pair_ij = reinterpret_cast<const uint32_t*>(b + o_ij);
   L.pair_coef = reinterpret_cast<const float4*>(b + o_coef);
-  L.inc_width = h.inc_width;
+  L.chunk = h.chunk;
+  L.n_chunks = h.n_chunks;
+  L.pl = h.pl;
+  L.inc_lds = h.inc_lds;
   L.inc_stride = h.inc_stride;
-  L.inc = reinterpret_cast<const uint32_t*>(b + o_inc);
+  L.inc_total = h.inc_rows.empty() ? 0 : h.inc_rows.back().x + h.inc_rows.back().y;
+  L.lds_bytes = h.lds_bytes;
+  L.inc_rows = reinterpret_cast<const int2*>(b + o_rows);
+  L.inc = reinterpret_cast<const uint16_t*>(b + o_inc);
   *out = l;
   return MD_OK;
 }
@@ -327,8 +335,8 @@ md_status md_local_search(const md_receptor* rec, const md_ligand* lig, int n, c
     return fail(MD_EINVAL, "md_local_search: rho must be in [0,1) and eps > 0");
   if (n == 0) return MD_OK;
   if (!genes_in || !genes_out || !energy_out) return fail(MD_EINVAL, "md_local_search: null buffer");
-  MD_HIP(launch_local_search(lig->dev, rec->dev, n, nullptr, genes_in, genes_out, energy_out, nullptr,
-                             n_iters, rho, eps, trace, static_cast<hipStream_t>(hip_stream)),
+  MD_HIP(launch_local_search(lig->dev, rec->dev, n, genes_in, genes_out, energy_out, n_iters, rho, eps,
+                             trace, static_cast<hipStream_t>(hip_stream)),
          "md_local_search launch");
   return MD_OK;
 }
@@ -347,124 +355,223 @@ int md_dock_planned_generations(const md_dock_params* p) {
   return gens;
 }
 
-md_status md_dock(const md_receptor* rec, const md_ligand* lig, const md_dock_params* p,
-                  md_dock_result* out, void* hip_stream) {
-  if (!rec || !lig || !p || !out) return fail(MD_EINVAL, "md_dock: null argument");
-  if (p->n_runs < 1 || p->pop_size < 2) return fail(MD_EINVAL, "md_dock: need n_runs >= 1 and pop_size >= 2");
-  if (p->pop_size > 1024) return fail(MD_ERANGE, "md_dock: pop_size must be <= 1024");
-  if ((long long)p->n_runs * p->pop_size > (1ll << 26)) return fail(MD_ERANGE, "md_dock: n_runs * pop_size too large");
-  if (p->elitism != 0 && p->elitism != 1) return fail(MD_EINVAL, "md_dock: elitism must be 0 or 1");
-  if (p->max_generations < 0 || p->max_evals_per_run < 0) return fail(MD_EINVAL, "md_dock: negative budget");
-  if (!(p->ls_rate >= 0.f && p->ls_rate <= 1.f)) return fail(MD_EINVAL, "md_dock: ls_rate must be in [0,1]");
-  const int n_ls = n_local_search(p);
-  if (n_ls > 0 && p->ls_iters < 1) return fail(MD_EINVAL, "md_dock: ls_iters must be >= 1");
-  if (!(p->rho >= 0.f && p->rho < 1.f) || !(p->eps > 0.f)) return fail(MD_EINVAL, "md_dock: bad rho/eps");
+}  // extern "C"
+
+namespace {
+
+std::string check_params(const md_dock_params* p) {
+  if (p->n_runs < 1 || p->pop_size < 2) return "need n_runs >= 1 and pop_size >= 2";
+  if (p->pop_size > 1024) return "pop_size must be <= 1024";
+  if ((long long)p->n_runs * p->pop_size > (1ll << 26)) return "n_runs * pop_size too large";
+  if (p->elitism != 0 && p->elitism != 1) return "elitism must be 0 or 1";
+  if (p->max_generations < 0 || p->max_evals_per_run < 0) return "negative budget";
+  if (!(p->ls_rate >= 0.f && p->ls_rate <= 1.f)) return "ls_rate must be in [0,1]";
+  if (n_local_search(p) > 0 && p->ls_iters < 1) return "ls_iters must be >= 1";
+  if (!(p->rho >= 0.f && p->rho < 1.f) || !(p->eps > 0.f)) return "bad rho/eps";
   const float rates[3] = {p->crossover_rate, p->mutation_rate, p->tournament_rate};
   for (float r : rates)
-    if (!(r >= 0.f && r <= 1.f)) return fail(MD_EINVAL, "md_dock: rates must be in [0,1]");
+    if (!(r >= 0.f && r <= 1.f)) return "rates must be in [0,1]";
   if (!std::isfinite(p->mut_trans) || !std::isfinite(p->mut_rot) || !std::isfinite(p->mut_tors))
-    return fail(MD_EINVAL, "md_dock: non-finite mutation size");
-  const int G = lig->dev.n_genes, N = lig->dev.n_atoms, runs = p->n_runs, pop = p->pop_size;
-  if (out->n_runs < runs || out->n_genes < G || !out->best_energy || !out->best_genes)
-    return fail(MD_EINVAL, "md_dock: result buffers too small or null");
-  if (out->best_xyz && out->n_atoms < N) return fail(MD_EINVAL, "md_dock: best_xyz capacity too small");
+    return "non-finite mutation size";
+  return std::string();
+}
 
-  GaDev P{};
-  P.n_runs = runs;
-  P.pop_size = pop;
-  P.n_genes = G;
-  P.n_ls = n_ls;
-  P.ls_iters = p->ls_iters;
-  P.elitism = p->elitism;
-  P.rho = p->rho;
-  P.eps = p->eps;
-  P.crossover_rate = p->crossover_rate;
-  P.mutation_rate = p->mutation_rate;
-  P.tournament_rate = p->tournament_rate;
-  P.mut_trans = p->mut_trans;
-  P.mut_rot = p->mut_rot;
-  P.mut_tors = p->mut_tors;
-  P.seed = p->seed;
-  const int gens = md_dock_planned_generations(p);
-
-  const size_t rows = (size_t)runs * pop;
+struct Carve {
   size_t off = 0;
-  const size_t o_ga = off; off = align16(off + rows * G * 4);
-  const size_t o_gb = off; off = align16(off + rows * G * 4);
-  const size_t o_ea = off; off = align16(off + rows * 4);
-  const size_t o_eb = off; off = align16(off + rows * 4);
-  const size_t o_ev = off; off = align16(off + rows * 4);
-  const size_t o_er = off; off = align16(off + (size_t)runs * 8);
-  const size_t o_ls = off; off = align16(off + (size_t)runs * std::max(n_ls, 1) * 4);
-  const size_t o_br = off; off = align16(off + (size_t)runs * 4);
-  const size_t o_be = off; off = align16(off + (size_t)runs * 4);
-  const size_t o_bg = off; off = align16(off + (size_t)runs * G * 4);
-  const size_t o_bx = off; off = align16(off + (size_t)runs * N * 3 * 4);
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off = align16(off + bytes);
+    return o;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+md_status md_dock_batch(const md_receptor* rec, int n_jobs, const md_dock_job* jobs, void* hip_stream) {
+  if (!rec || n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(MD_EINVAL, "md_dock_batch: null argument");
+  if (n_jobs == 0) return MD_OK;
+  if (n_jobs > (1 << 20)) return fail(MD_ERANGE, "md_dock_batch: too many jobs");
+  for (int j = 0; j < n_jobs; ++j) {
+    const md_dock_job& jb = jobs[j];
+    if (!jb.ligand || !jb.result) return fail(MD_EINVAL, "md_dock_batch: job " + std::to_string(j) + ": null ligand or result");
+    const std::string e = check_params(&jb.params);
+    if (!e.empty()) {
+      const bool range = e.find("<=") != std::string::npos || e.find("too large") != std::string::npos;
+      return fail(range ? MD_ERANGE : MD_EINVAL, "md_dock_batch: job " + std::to_string(j) + ": " + e);
+    }
+    const md_dock_result* out = jb.result;
+    const int G = jb.ligand->dev.n_genes, N = jb.ligand->dev.n_atoms;
+    if (out->n_runs < jb.params.n_runs || out->n_genes < G || !out->best_energy || !out->best_genes)
+      return fail(MD_EINVAL, "md_dock_batch: job " + std::to_string(j) + ": result buffers too small or null");
+    if (out->best_xyz && out->n_atoms < N)
+      return fail(MD_EINVAL, "md_dock_batch: job " + std::to_string(j) + ": best_xyz capacity too small");
+  }
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
+
+  // workspace: job table, block tables, per-job populations, then one results region
+  std::vector<JobDev> table(n_jobs);
+  std::vector<int2> pop_blocks[2], ls_blocks[2], run_blocks;
+  int lds_pop[2] = {0, 0}, lds_ls[2] = {0, 0};
+  int max_planned = 0;
+  Carve cv;
+  const size_t o_table = cv.take(sizeof(JobDev) * n_jobs);
+  struct Offs { size_t ga, gb, ea, eb, ev, lsr, br; size_t be, bg, er, bx; };
+  std::vector<Offs> offs(n_jobs);
+  for (int j = 0; j < n_jobs; ++j) {
+    const md_dock_params& p = jobs[j].params;
+    const LigDev& L = jobs[j].ligand->dev;
+    const size_t rows = (size_t)p.n_runs * p.pop_size;
+    const int n_ls = n_local_search(&p);
+    Offs& o = offs[j];
+    o.ga = cv.take(rows * L.n_genes * 4);
+    o.gb = cv.take(rows * L.n_genes * 4);
+    o.ea = cv.take(rows * 4);
+    o.eb = cv.take(rows * 4);
+    o.ev = cv.take(rows * 4);
+    o.lsr = cv.take((size_t)p.n_runs * std::max(n_ls, 1) * 4);
+    o.br = cv.take((size_t)p.n_runs * 4);
+    const int A = L.n_atoms > kWave ? 2 : 1;
+    const int b = A - 1;
+    for (long long w = 0; w < (long long)rows; w += kWavesPerBlock) pop_blocks[b].push_back(make_int2(j, (int)w));
+    for (long long w = 0; w < (long long)p.n_runs * n_ls; w += kWavesPerBlock) ls_blocks[b].push_back(make_int2(j, (int)w));
+    for (int r = 0; r < p.n_runs; r += kWavesPerBlock) run_blocks.push_back(make_int2(j, r));
+    lds_pop[b] = std::max(lds_pop[b], L.lds_bytes);
+    if (n_ls > 0) lds_ls[b] = std::max(lds_ls[b], L.lds_bytes);
+    max_planned = std::max(max_planned, md_dock_planned_generations(&p));
+  }
+  const size_t o_blocks = cv.take(sizeof(int2) * (pop_blocks[0].size() + pop_blocks[1].size() +
+                                                  ls_blocks[0].size() + ls_blocks[1].size() + run_blocks.size()));
+  const size_t o_results = cv.off;
+  for (int j = 0; j < n_jobs; ++j) {
+    const md_dock_params& p = jobs[j].params;
+    const LigDev& L = jobs[j].ligand->dev;
+    Offs& o = offs[j];
+    o.be = cv.take((size_t)p.n_runs * 4);
+    o.bg = cv.take((size_t)p.n_runs * L.n_genes * 4);
+    o.er = cv.take((size_t)p.n_runs * 8);
+    o.bx = jobs[j].result->best_xyz ? cv.take((size_t)p.n_runs * L.n_atoms * 12) : 0;
+  }
+  const size_t results_bytes = cv.off - o_results;
+
   char* w = nullptr;
-  MD_HIP(hipMallocAsync(reinterpret_cast<void**>(&w), off, s), "md_dock workspace");
-  float* ga = reinterpret_cast<float*>(w + o_ga);
-  float* gb = reinterpret_cast<float*>(w + o_gb);
-  float* ea = reinterpret_cast<float*>(w + o_ea);
-  float* eb = reinterpret_cast<float*>(w + o_eb);
-  int* ev = reinterpret_cast<int*>(w + o_ev);
-  long long* er = reinterpret_cast<long long*>(w + o_er);
-  int* lsr = reinterpret_cast<int*>(w + o_ls);
-  int* br = reinterpret_cast<int*>(w + o_br);
-  float* be = reinterpret_cast<float*>(w + o_be);
-  float* bg = reinterpret_cast<float*>(w + o_bg);
-  float* bx = reinterpret_cast<float*>(w + o_bx);
+  MD_HIP(hipMallocAsync(reinterpret_cast<void**>(&w), cv.off, s), "md_dock workspace");
+  for (int j = 0; j < n_jobs; ++j) {
+    const md_dock_params& p = jobs[j].params;
+    const Offs& o = offs[j];
+    JobDev& J = table[j];
+    J.L = jobs[j].ligand->dev;
+    GaDev& P = J.P;
+    P.n_runs = p.n_runs;
+    P.pop_size = p.pop_size;
+    P.n_genes = J.L.n_genes;
+    P.n_ls = n_local_search(&p);
+    P.ls_iters = p.ls_iters;
+    P.elitism = p.elitism;
+    P.rho = p.rho;
+    P.eps = p.eps;
+    P.crossover_rate = p.crossover_rate;
+    P.mutation_rate = p.mutation_rate;
+    P.tournament_rate = p.tournament_rate;
+    P.mut_trans = p.mut_trans;
+    P.mut_rot = p.mut_rot;
+    P.mut_tors = p.mut_tors;
+    P.seed = p.seed;
+    J.genes[0] = reinterpret_cast<float*>(w + o.ga);
+    J.genes[1] = reinterpret_cast<float*>(w + o.gb);
+    J.energy[0] = reinterpret_cast<float*>(w + o.ea);
+    J.energy[1] = reinterpret_cast<float*>(w + o.eb);
+    J.evals = reinterpret_cast<int*>(w + o.ev);
+    J.evals_of_runs = reinterpret_cast<long long*>(w + o.er);
+    J.ls_rows = reinterpret_cast<int*>(w + o.lsr);
+    J.best_row = reinterpret_cast<int*>(w + o.br);
+    J.best_energy = reinterpret_cast<float*>(w + o.be);
+    J.best_genes = reinterpret_cast<float*>(w + o.bg);
+    J.gen = 0;
+    J.cur = 0;
+    J.planned = md_dock_planned_generations(&p);
+    J.state = kJobInit;
+  }
+  std::vector<int2> blocks;
+  size_t bo[6];
+  bo[0] = 0;
+  blocks.insert(blocks.end(), pop_blocks[0].begin(), pop_blocks[0].end()); bo[1] = blocks.size();
+  blocks.insert(blocks.end(), pop_blocks[1].begin(), pop_blocks[1].end()); bo[2] = blocks.size();
+  blocks.insert(blocks.end(), ls_blocks[0].begin(), ls_blocks[0].end()); bo[3] = blocks.size();
+  blocks.insert(blocks.end(), ls_blocks[1].begin(), ls_blocks[1].end()); bo[4] = blocks.size();
+  blocks.insert(blocks.end(), run_blocks.begin(), run_blocks.end()); bo[5] = blocks.size();
+  JobDev* d_table = reinterpret_cast<JobDev*>(w + o_table);
+  const int2* d_blocks = reinterpret_cast<const int2*>(w + o_blocks);
+  const RecDev& R = rec->dev;
 
   LaunchTimer timer(s);
-  const LigDev& L = lig->dev;
-  const RecDev& R = rec->dev;
-  hipError_t e = hipMemsetAsync(er, 0, (size_t)runs * 8, s);
+  hipError_t e = hipMemcpyAsync(d_table, table.data(), sizeof(JobDev) * n_jobs, hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
-    e = timer.run(MD_K_INIT_POPULATION, [&] { return launch_init_population(L, R, P, ga, ea, ev, s); });
-  if (e == hipSuccess) e = timer.run(MD_K_SUM_EVALS, [&] { return launch_sum_evals(P, ev, er, s); });
-  for (int g = 1; g <= gens && e == hipSuccess; ++g) {
-    e = timer.run(MD_K_GENERATION, [&] { return launch_generation(L, R, P, g, ga, ea, gb, eb, ev, s); });
-    if (e == hipSuccess && n_ls > 0)
-      e = timer.run(MD_K_LS_PICK, [&] { return launch_ls_pick(P, g, lsr, s); });
-    if (e == hipSuccess && n_ls > 0)
-      e = timer.run(MD_K_LOCAL_SEARCH, [&] {
-        return launch_local_search(L, R, runs * n_ls, lsr, gb, gb, eb, ev, P.ls_iters, P.rho, P.eps,
-                                   nullptr, s);
+    e = hipMemcpyAsync(w + o_blocks, blocks.data(), sizeof(int2) * blocks.size(), hipMemcpyHostToDevice, s);
+  for (int b = 0; b < 2 && e == hipSuccess; ++b)
+    e = timer.run(MD_K_INIT_POPULATION, [&] {
+      return launch_ga_init(d_table, d_blocks + bo[b], (int)(bo[b + 1] - bo[b]), b + 1, lds_pop[b], R, s);
+    });
+  if (e == hipSuccess) e = timer.run(MD_K_SUM_EVALS, [&] { return launch_ga_advance(d_table, n_jobs, s); });
+  for (int g = 1; g <= max_planned && e == hipSuccess; ++g) {
+    for (int b = 0; b < 2 && e == hipSuccess; ++b)
+      e = timer.run(MD_K_GENERATION, [&] {
+        return launch_ga_generation(d_table, d_blocks + bo[b], (int)(bo[b + 1] - bo[b]), b + 1, lds_pop[b], R, s);
       });
-    if (e == hipSuccess) e = timer.run(MD_K_SUM_EVALS, [&] { return launch_sum_evals(P, ev, er, s); });
-    std::swap(ga, gb);
-    std::swap(ea, eb);
+    if (e == hipSuccess && bo[4] > bo[2])
+      e = timer.run(MD_K_LS_PICK, [&] { return launch_ga_ls_pick(d_table, d_blocks + bo[4], (int)(bo[5] - bo[4]), s); });
+    for (int b = 0; b < 2 && e == hipSuccess; ++b)
+      e = timer.run(MD_K_LOCAL_SEARCH, [&] {
+        return launch_ga_local_search(d_table, d_blocks + bo[2 + b], (int)(bo[3 + b] - bo[2 + b]), b + 1,
+                                      lds_ls[b], R, s);
+      });
+    if (e == hipSuccess) e = timer.run(MD_K_SUM_EVALS, [&] { return launch_ga_advance(d_table, n_jobs, s); });
   }
-  if (e == hipSuccess)
-    e = timer.run(MD_K_BEST_OF_RUNS, [&] { return launch_best_of_runs(P, ga, ea, br, be, bg, s); });
-  if (e == hipSuccess && out->best_xyz) e = launch_pose(lig->dev, runs, bg, bx, s);
-  std::vector<float> h_be(runs), h_bg((size_t)runs * G), h_bx(out->best_xyz ? (size_t)runs * N * 3 : 0);
-  std::vector<long long> h_er(runs);
-  if (e == hipSuccess) e = hipMemcpyAsync(h_be.data(), be, runs * 4, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(h_bg.data(), bg, (size_t)runs * G * 4, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(h_er.data(), er, (size_t)runs * 8, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess && out->best_xyz)
-    e = hipMemcpyAsync(h_bx.data(), bx, h_bx.size() * 4, hipMemcpyDeviceToHost, s);
+  for (int j = 0; j < n_jobs && e == hipSuccess; ++j)
+    if (jobs[j].result->best_xyz)
+      e = launch_pose(table[j].L, jobs[j].params.n_runs, table[j].best_genes,
+                      reinterpret_cast<float*>(w + offs[j].bx), s);
+  std::vector<char> host(results_bytes);
+  if (e == hipSuccess) e = hipMemcpyAsync(host.data(), w + o_results, results_bytes, hipMemcpyDeviceToHost, s);
   hipError_t ef = hipFreeAsync(w, s);
   if (e == hipSuccess) e = ef;
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   timer.collect(e == hipSuccess);
   if (e != hipSuccess) return hip_fail(e, "md_dock");
 
-  std::vector<int> order(runs);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return h_be[a] < h_be[b]; });
-  for (int k = 0; k < runs; ++k) {
-    const int r = order[k];
-    out->best_energy[k] = h_be[r];
-    std::memcpy(out->best_genes + (size_t)k * out->n_genes, h_bg.data() + (size_t)r * G, G * 4);
-    if (out->best_xyz)
-      std::memcpy(out->best_xyz + (size_t)k * out->n_atoms * 3, h_bx.data() + (size_t)r * N * 3, (size_t)N * 12);
-    if (out->run_index) out->run_index[k] = r;
-    if (out->evals) out->evals[k] = h_er[r];
-    if (out->generations) out->generations[k] = gens;
+  for (int j = 0; j < n_jobs; ++j) {
+    const md_dock_params& p = jobs[j].params;
+    md_dock_result* out = jobs[j].result;
+    const int runs = p.n_runs, G = table[j].L.n_genes, N = table[j].L.n_atoms;
+    const float* be = reinterpret_cast<const float*>(host.data() + (offs[j].be - o_results));
+    const float* bg = reinterpret_cast<const float*>(host.data() + (offs[j].bg - o_results));
+    const long long* er = reinterpret_cast<const long long*>(host.data() + (offs[j].er - o_results));
+    const float* bx = out->best_xyz ? reinterpret_cast<const float*>(host.data() + (offs[j].bx - o_results)) : nullptr;
+    std::vector<int> order(runs);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return be[a] < be[b]; });
+    for (int k = 0; k < runs; ++k) {
+      const int r = order[k];
+      out->best_energy[k] = be[r];
+      std::memcpy(out->best_genes + (size_t)k * out->n_genes, bg + (size_t)r * G, (size_t)G * 4);
+      if (out->best_xyz) std::memcpy(out->best_xyz + (size_t)k * out->n_atoms * 3, bx + (size_t)r * N * 3, (size_t)N * 12);
+      if (out->run_index) out->run_index[k] = r;
+      if (out->evals) out->evals[k] = er[r];
+      if (out->generations) out->generations[k] = table[j].planned;
+    }
   }
   return MD_OK;
+}
+
+md_status md_dock(const md_receptor* rec, const md_ligand* lig, const md_dock_params* p,
+                  md_dock_result* out, void* hip_stream) {
+  if (!rec || !lig || !p || !out) return fail(MD_EINVAL, "md_dock: null argument");
+  md_dock_job job;
+  job.ligand = lig;
+  job.params = *p;
+  job.result = out;
+  return md_dock_batch(rec, 1, &job, hip_stream);
 }
 
 }  // extern "C"

@@ -17,11 +17,14 @@ constexpr int kTypes = 7;
 constexpr int kMaps = kTypes + 2;
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
-// Pair records kept in LDS per block; their per-pose force scalars also live in LDS and reach
-// the atoms through the incidence table.  Pairs beyond this index (ligands above ~70 atoms)
-// are read from global memory and their forces accumulated with LDS atomics.
-constexpr int kPairLdsMax = 2048;
-constexpr uint32_t kIncNone = 0xffffffffu;
+// LDS plan of a ligand: pairs are processed in chunks of `chunk`; each chunk's pair forces are
+// kept in LDS and gathered per atom through that chunk's incidence table before the next chunk.
+// The first `pl` pair records (and the incidence tables, when small) are staged in LDS once per
+// block; the plan keeps a block's dynamic LDS within kLdsBudget.
+constexpr size_t kLdsBudget = 65536;
+constexpr size_t kIncLdsMax = 16384;
+constexpr int kChunkMax = 1024;
+constexpr uint32_t kIncNone = 0xffffu;
 
 // Scoring constants (AutoDock4 force-field forms and weights).
 constexpr float kWvdw = 0.1662f;
@@ -56,9 +59,15 @@ struct LigDev {
   const uint32_t* pair_ij;    // [P] i | j << 8 | hbond << 16
   const float4* pair_coef;    // [P] weighted C12, weighted C6 or C10, W_el*332*qi*qj,
                               //     W_ds*(S_i V_j + S_j V_i)
-  int inc_width;              // incidences of the busiest atom (pairs below kPairLdsMax)
+  int chunk, n_chunks;        // pairs per chunk, number of chunks
+  int pl;                     // pair records staged in LDS (a prefix of the list)
+  int inc_lds;                // incidence tables staged in LDS (1) or read from global memory (0)
   int inc_stride;             // 64 * atoms per lane
-  const uint32_t* inc;        // [inc_width][inc_stride]: pair | partner << 16, or kIncNone
+  int inc_total;              // rows of all chunks' incidence tables
+  int lds_bytes;              // dynamic LDS of one block
+  const int2* inc_rows;       // [n_chunks] first row and number of rows of each chunk's table
+  const uint16_t* inc;        // [inc_total][inc_stride]: index in chunk | (second atom) << 15,
+                              // or kIncNone
 };
 
 struct RecDev {
@@ -79,6 +88,27 @@ struct GaDev {
   unsigned long long seed;
 };
 
+// One docking job (ligand + search parameters + its device buffers) in the job table the GA
+// kernels read.  gen / cur / state are advanced on the device by the generation epilogue.
+enum : int { kJobEmpty = 0, kJobInit = 1, kJobRunning = 2, kJobDone = 3 };
+
+struct JobDev {
+  LigDev L;
+  GaDev P;
+  float* genes[2];            // populations [runs*pop][G]; genes[cur] is the current one
+  float* energy[2];           // [runs*pop]
+  int* evals;                 // [runs*pop] evaluations of the current generation, per individual
+  long long* evals_of_runs;   // [runs] cumulative evaluations
+  int* ls_rows;               // [runs*n_ls] rows picked for local search this generation
+  int* best_row;              // [runs] outputs once done
+  float* best_energy;         // [runs]
+  float* best_genes;          // [runs][G]
+  int gen;                    // next generation (1-based)
+  int cur;                    // index of the current population buffer
+  int planned;                // generations to run
+  int state;                  // kJob*
+};
+
 // Host-side ligand after preprocessing (arrays in internal torsion order).
 struct LigHost {
   int n_atoms = 0, n_tors = 0, n_genes = 0;
@@ -90,9 +120,22 @@ struct LigHost {
   std::vector<int> tor_gene;
   std::vector<uint32_t> pair_ij;
   std::vector<float4> pair_coef;
-  int inc_width = 0, inc_stride = 64;
-  std::vector<uint32_t> inc;
+  int chunk = 1, n_chunks = 0, pl = 0, inc_lds = 1, inc_stride = 64, lds_bytes = 0;
+  std::vector<int2> inc_rows;
+  std::vector<uint16_t> inc;
 };
+
+// LDS layout helpers shared by the host plan and the kernels.
+__host__ __device__ inline size_t lds_align16(size_t v) { return (v + 15) & ~size_t(15); }
+__host__ __device__ inline size_t lds_wave_bytes(int chunk, int A) {
+  return (size_t)16 * kWave * A + 3 * lds_align16((size_t)chunk * 4);
+}
+__host__ __device__ inline size_t lds_pairs_bytes(int pl) {
+  return lds_align16((size_t)pl * 16) + lds_align16((size_t)pl * 4);
+}
+__host__ __device__ inline size_t lds_inc_bytes(int rows, int stride) {
+  return lds_align16((size_t)rows * stride * 2);
+}
 
 // Returns an empty string on success, else a message; `range_error` tells MD_ERANGE apart.
 std::string prepare_ligand(int n_atoms, const float* xyz, const int* type, const float* charge,
@@ -104,20 +147,18 @@ std::string prepare_ligand(int n_atoms, const float* xyz, const int* type, const
 hipError_t launch_eval(const LigDev& L, const RecDev& R, int n, const float* genes, float* energy,
                        float* grad, hipStream_t s);
 hipError_t launch_pose(const LigDev& L, int n, const float* genes, float* xyz, hipStream_t s);
-hipError_t launch_local_search(const LigDev& L, const RecDev& R, int n, const int* rows,
-                               const float* genes_in, float* genes_out, float* energy_out,
-                               int* evals, int iters, float rho, float eps, float* trace,
-                               hipStream_t s);
-hipError_t launch_init_population(const LigDev& L, const RecDev& R, const GaDev& P, float* genes,
-                                  float* energy, int* evals, hipStream_t s);
-hipError_t launch_generation(const LigDev& L, const RecDev& R, const GaDev& P, int gen,
-                             const float* genes_in, const float* energy_in, float* genes_out,
-                             float* energy_out, int* evals, hipStream_t s);
-hipError_t launch_ls_pick(const GaDev& P, int gen, int* rows, hipStream_t s);
-hipError_t launch_sum_evals(const GaDev& P, const int* evals, long long* evals_of_runs,
-                            hipStream_t s);
-hipError_t launch_best_of_runs(const GaDev& P, const float* genes, const float* energy,
-                               int* best_row, float* best_energy, float* best_genes,
-                               hipStream_t s);
+hipError_t launch_local_search(const LigDev& L, const RecDev& R, int n, const float* genes_in,
+                               float* genes_out, float* energy_out, int iters, float rho, float eps,
+                               float* trace, hipStream_t s);
+// GA phases over a job table.  blocks: [n_blocks] (job, first wave of the block within the
+// job's work for this phase).  A: atoms per lane of every job in the table; lds: dynamic LDS.
+hipError_t launch_ga_init(JobDev* jobs, const int2* blocks, int n_blocks, int A, int lds,
+                          const RecDev& R, hipStream_t s);
+hipError_t launch_ga_generation(JobDev* jobs, const int2* blocks, int n_blocks, int A, int lds,
+                                const RecDev& R, hipStream_t s);
+hipError_t launch_ga_ls_pick(JobDev* jobs, const int2* blocks, int n_blocks, hipStream_t s);
+hipError_t launch_ga_local_search(JobDev* jobs, const int2* blocks, int n_blocks, int A, int lds,
+                                  const RecDev& R, hipStream_t s);
+hipError_t launch_ga_advance(JobDev* jobs, int n_jobs, hipStream_t s);
 
 }  // namespace mdock

@@ -94,73 +94,55 @@ __device__ __forceinline__ float wrap_angle(float th) {
 }
 
 // ------------------------------------------------------------------ LDS layout
-// Dynamic LDS of a block, shared part (staged once per launch): the first `pl` pair records
-// and, when it fits, the incidence table.  Then per wave: posed coordinates, the force scalars
-// of its pairs (dE/dr / r) and the force accumulators of the pairs beyond `pl`.
+// Dynamic LDS of a block (sizes from the ligand's plan): the staged pair records and, when
+// small, the chunks' incidence tables, shared by the block's waves; then per wave the posed
+// coordinates and the force of each pair of the current chunk on its first atom.
 struct BlockLds {
   const float4* pair_coef;   // [pl]
   const uint32_t* pair_ij;   // [pl]
-  const uint32_t* inc;       // [inc_width][inc_stride], LDS or global
-  int pl;
+  const uint16_t* inc;       // [inc_total][inc_stride], LDS or global
   float4* x;                 // this wave: [64*A] posed x, y, z
-  float4* f;                 // this wave: [64*A] forces of pairs beyond pl (atomics)
-  float* fr;                 // this wave: [pl] pair force scalars
+  float* fpx;                // this wave: [chunk] force of each pair on its first atom
+  float* fpy;
+  float* fpz;
 };
-
-__host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
-
-constexpr size_t kIncLdsMax = 16384;   // bytes of incidence table staged in LDS
-
-__host__ __device__ inline size_t inc_bytes(int width, int stride) { return (size_t)width * stride * 4; }
-
-__host__ __device__ inline size_t lds_shared_bytes(int pl, int inc_w, int inc_s) {
-  const size_t ib = inc_bytes(inc_w, inc_s);
-  return align16((size_t)pl * 16) + align16((size_t)pl * 4) + (ib <= kIncLdsMax ? align16(ib) : 0);
-}
-
-__host__ __device__ inline size_t lds_wave_bytes(int pl, int A) {
-  return (size_t)2 * 16 * kWave * A + align16((size_t)pl * 4);
-}
-
-__host__ __device__ inline size_t lds_bytes(int pl, int inc_w, int inc_s, int A) {
-  return lds_shared_bytes(pl, inc_w, inc_s) + (size_t)kWavesPerBlock * lds_wave_bytes(pl, A);
-}
 
 extern __shared__ __align__(16) unsigned char g_lds[];
 
 // All threads of the block stage the shared part, then synchronise.  Must be reached by every
 // wave of the block before any of them leaves.
 template <int A>
-__device__ __forceinline__ BlockLds stage_block(const LigDev& L, int pl) {
+__device__ __forceinline__ BlockLds stage_block(const LigDev& L) {
   BlockLds b;
   unsigned char* cur = g_lds;
+  const int pl = L.pl;
   float4* pc = reinterpret_cast<float4*>(cur);
-  cur += align16((size_t)pl * 16);
-  uint32_t* pij = reinterpret_cast<uint32_t*>(cur);
-  cur += align16((size_t)pl * 4);
+  uint32_t* pij = reinterpret_cast<uint32_t*>(cur + lds_align16((size_t)pl * 16));
+  cur += lds_pairs_bytes(pl);
   for (int p = threadIdx.x; p < pl; p += blockDim.x) {
     pc[p] = L.pair_coef[p];
     pij[p] = L.pair_ij[p];
   }
-  const size_t ib = inc_bytes(L.inc_width, L.inc_stride);
-  if (ib <= kIncLdsMax) {
-    uint32_t* inc = reinterpret_cast<uint32_t*>(cur);
-    const int ne = L.inc_width * L.inc_stride;
+  if (L.inc_lds) {
+    uint16_t* inc = reinterpret_cast<uint16_t*>(cur);
+    const int ne = L.inc_total * L.inc_stride;
     for (int k = threadIdx.x; k < ne; k += blockDim.x) inc[k] = L.inc[k];
     b.inc = inc;
-    cur += align16(ib);
+    cur += lds_inc_bytes(L.inc_total, L.inc_stride);
   } else {
     b.inc = L.inc;
   }
   __syncthreads();
   const int w = threadIdx.x / kWave;
-  cur += (size_t)w * lds_wave_bytes(pl, A);
+  cur += (size_t)w * lds_wave_bytes(L.chunk, A);
   b.pair_coef = pc;
   b.pair_ij = pij;
-  b.pl = pl;
   b.x = reinterpret_cast<float4*>(cur);
-  b.f = b.x + kWave * A;
-  b.fr = reinterpret_cast<float*>(b.f + kWave * A);
+  cur += (size_t)16 * kWave * A;
+  const size_t cb = lds_align16((size_t)L.chunk * 4);
+  b.fpx = reinterpret_cast<float*>(cur);
+  b.fpy = reinterpret_cast<float*>(cur + cb);
+  b.fpz = reinterpret_cast<float*>(cur + 2 * cb);
   return b;
 }
 
@@ -311,12 +293,16 @@ __device__ __forceinline__ float grid_finish(const RecDev& R, const GridFetch& g
 // ------------------------------------------------------------------ pair term
 // Energy of one intramolecular pair at squared distance r2 and dE/dr / r (so that the force on
 // i is that factor times (x_i - x_j)).  r is clamped to R_MIN with zero gradient below it.
+// Four transcendentals: 1/r~ by rsq, the desolvation Gaussian and the dielectric exponential
+// by exp2, and one reciprocal that serves both 1/eps and d eps/dr / eps:
+//   eps = A + B/den = D/den with D = A den + B, so 1/eps = den^2 q and
+//   (d eps/dr)/eps = B k lambda B e q, where q = 1/(den D).
 __device__ __forceinline__ float pair_term(float r2, bool hb, float4 c, float& f_over_r) {
-  const float r = __builtin_sqrtf(r2);
-  const float rt = fmaxf(r, kRmin);
-  const float ir = __builtin_amdgcn_rcpf(rt);
+  const float rt2 = fmaxf(r2, kRmin * kRmin);
+  const float ir = __builtin_amdgcn_rsqf(rt2);      // 1 / max(r, R_MIN)
+  const float rt = rt2 * ir;
   float e = 0.f, dedr = 0.f;
-  if (r < kCutoff) {
+  if (r2 < kCutoff * kCutoff) {
     const float ir2 = ir * ir;
     const float ir6 = ir2 * ir2 * ir2;
     const float ir12 = ir6 * ir6;
@@ -324,29 +310,28 @@ __device__ __forceinline__ float pair_term(float r2, bool hb, float4 c, float& f
     const float nn = hb ? 10.f : 6.f;
     const float elj = c.x * ir12 - c.y * irn;
     const float dlj = (-12.f * c.x * ir12 + nn * c.y * irn) * ir;
-    const float gs = __builtin_amdgcn_exp2f(-rt * rt * (1.4426950408889634f / (2.f * kDesolvSigma * kDesolvSigma)));
+    const float gs = __builtin_amdgcn_exp2f(-rt2 * (1.4426950408889634f / (2.f * kDesolvSigma * kDesolvSigma)));
     const float eds = c.w * gs;
     const float dds = -rt * (1.f / (kDesolvSigma * kDesolvSigma)) * eds;
     e += elj + eds;
     dedr += dlj + dds;
   }
-  if (r < kCutoffEl) {
+  if (r2 < kCutoffEl * kCutoffEl) {
     const float ex = __builtin_amdgcn_exp2f(-kDielLambda * kDielB * 1.4426950408889634f * rt);
     const float den = 1.f + kDielK * ex;
-    const float iden = __builtin_amdgcn_rcpf(den);
-    const float eps = kDielA + kDielB * iden;
-    const float deps = kDielB * kDielK * kDielLambda * kDielB * ex * iden * iden;
-    const float ieps = __builtin_amdgcn_rcpf(eps);
+    const float D = kDielA * den + kDielB;
+    const float q = __builtin_amdgcn_rcpf(den * D);
+    const float ieps = den * den * q;
     const float eel = c.z * ir * ieps;
     e += eel;
-    dedr += -eel * (ir + deps * ieps);
+    dedr += -eel * (ir + kDielB * kDielK * kDielLambda * kDielB * ex * q);
   }
-  f_over_r = (r < kRmin) ? 0.f : dedr * ir;
+  f_over_r = (r2 < kRmin * kRmin) ? 0.f : dedr * ir;
   return e;
 }
 
-// One pair.  GRAD and `slot` >= 0: the force scalar goes to the wave's LDS slot (gathered per
-// atom later); GRAD and slot < 0: the force is added to both atoms with LDS atomics.
+// One pair.  With GRAD the force on its first atom, (dE/dr / r)(x_i - x_j), goes to the wave's
+// LDS slot, to be gathered per atom with the sign of each end.
 template <bool GRAD>
 __device__ __forceinline__ float pair_one(const BlockLds& b, uint32_t ij, float4 c, int slot) {
   const int i = ij & 0xff, j = (ij >> 8) & 0xff;
@@ -355,16 +340,39 @@ __device__ __forceinline__ float pair_one(const BlockLds& b, uint32_t ij, float4
   const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
   float fr;
   const float e = pair_term(dx * dx + dy * dy + dz * dz, hb, c, fr);
-  if (GRAD && slot >= 0) {
-    b.fr[slot] = fr;
-  } else if (GRAD) {
-    const float fx = fr * dx, fy = fr * dy, fz = fr * dz;
-    atomicAdd(&b.f[i].x, fx);
-    atomicAdd(&b.f[i].y, fy);
-    atomicAdd(&b.f[i].z, fz);
-    atomicAdd(&b.f[j].x, -fx);
-    atomicAdd(&b.f[j].y, -fy);
-    atomicAdd(&b.f[j].z, -fz);
+  if (GRAD) {
+    b.fpx[slot] = fr * dx;
+    b.fpy[slot] = fr * dy;
+    b.fpz[slot] = fr * dz;
+  }
+  return e;
+}
+
+// Pairs [p0, p1) of the list, strided over lanes two at a time; records from LDS below L.pl,
+// else from global memory (separate loops, so LDS-only chunks carry no global-load waits).
+// slot = pair index - base.
+template <bool GRAD>
+__device__ __forceinline__ float pair_range(const LigDev& L, const BlockLds& b, int p0, int p1, int base) {
+  const int lane = lane_id();
+  float e = 0.f;
+  const int pm = min(p1, L.pl);
+  for (int p = p0 + lane; p < pm; p += 2 * kWave) {
+    const bool two = p + kWave < pm;
+    const uint32_t ij0 = b.pair_ij[p];
+    const float4 c0 = b.pair_coef[p];
+    const uint32_t ij1 = two ? b.pair_ij[p + kWave] : 0u;
+    const float4 c1 = two ? b.pair_coef[p + kWave] : make_float4(0.f, 0.f, 0.f, 0.f);
+    e += pair_one<GRAD>(b, ij0, c0, p - base);
+    if (two) e += pair_one<GRAD>(b, ij1, c1, p + kWave - base);
+  }
+  for (int p = max(p0, L.pl) + lane; p < p1; p += 2 * kWave) {
+    const bool two = p + kWave < p1;
+    const uint32_t ij0 = L.pair_ij[p];
+    const float4 c0 = L.pair_coef[p];
+    const uint32_t ij1 = two ? L.pair_ij[p + kWave] : 0u;
+    const float4 c1 = two ? L.pair_coef[p + kWave] : make_float4(0.f, 0.f, 0.f, 0.f);
+    e += pair_one<GRAD>(b, ij0, c0, p - base);
+    if (two) e += pair_one<GRAD>(b, ij1, c1, p + kWave - base);
   }
   return e;
 }
@@ -396,7 +404,12 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, 
   // torsion angle of torsion `lane` (internal order) -> cos, sin in that lane
   const float th = __shfl(xg, at.gene_of_tor, kWave);
   float tsn = 0.f, tcs = 1.f;
-  if (lane < T) sincosf(th, &tsn, &tcs);
+  if (lane < T) {
+    // v_sin / v_cos take the angle in revolutions
+    const float rev = th * 0.15915494309189535f;
+    tsn = __builtin_amdgcn_sinf(rev);
+    tcs = __builtin_amdgcn_cosf(rev);
+  }
 
   // pose: torsions from the deepest to the root-most, each about its reference-frame axis,
   // applied by every lane whose atom it moves; then orientation and translation.
@@ -432,7 +445,6 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, 
     z[a] = r20 * px[a] + r21 * py[a] + r22 * pz[a] + tz;
     const int i = lane + kWave * a;
     b.x[i] = make_float4(x[a], y[a], z[a], 0.f);
-    if (GRAD && L.n_pairs > b.pl) b.f[i] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
 
   // grid term: issue the corner loads now, finish after the pair term
@@ -441,20 +453,37 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, 
   for (int a = 0; a < A; ++a) grid_fetch<PREC>(R, x[a], y[a], z[a], at.type[a], at.q[a], at.valid[a], gf[a]);
   wave_sync();
 
-  // intramolecular pairs, strided over lanes, two at a time: first the records staged in
-  // LDS, then (large ligands only) the rest from global memory
+  // intramolecular pairs, chunk by chunk; with GRAD each chunk's pair forces are gathered per
+  // atom over the chunk's incidence table (fixed order: deterministic, no atomics)
   float e_lane = 0.f;
+  float Fx[A], Fy[A], Fz[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) Fx[a] = Fy[a] = Fz[a] = 0.f;
   const int P = L.n_pairs;
-  for (int p = lane; p < b.pl; p += 2 * kWave) {
-    const bool two = p + kWave < b.pl;
-    const uint32_t ij0 = b.pair_ij[p];
-    const float4 c0 = b.pair_coef[p];
-    const uint32_t ij1 = two ? b.pair_ij[p + kWave] : 0u;
-    const float4 c1 = two ? b.pair_coef[p + kWave] : make_float4(0.f, 0.f, 0.f, 0.f);
-    e_lane += pair_one<GRAD>(b, ij0, c0, p);
-    if (two) e_lane += pair_one<GRAD>(b, ij1, c1, p + kWave);
+  if (!GRAD) {
+    e_lane += pair_range<false>(L, b, 0, P, 0);
+  } else {
+    for (int c = 0; c < L.n_chunks; ++c) {
+      const int c0 = c * L.chunk;
+      e_lane += pair_range<true>(L, b, c0, min(P, c0 + L.chunk), c0);
+      wave_sync();
+      const int2 rows = L.inc_rows[c];
+      for (int t = rows.x; t < rows.x + rows.y; ++t) {
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+          const uint32_t e = b.inc[t * L.inc_stride + lane + kWave * a];
+          if (e != kIncNone) {
+            const uint32_t p = e & 0x7fffu;
+            const float sg = (e & 0x8000u) ? -1.f : 1.f;
+            Fx[a] += sg * b.fpx[p];
+            Fy[a] += sg * b.fpy[p];
+            Fz[a] += sg * b.fpz[p];
+          }
+        }
+      }
+      wave_sync();
+    }
   }
-  for (int p = b.pl + lane; p < P; p += kWave) e_lane += pair_one<GRAD>(b, L.pair_ij[p], L.pair_coef[p], -1);
 
   float gfx[A], gfy[A], gfz[A];
 #pragma unroll
@@ -466,7 +495,6 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, 
   // translation gradient and torque come from the grid forces alone: intramolecular
   // forces are equal and opposite along each pair's line, so they add neither.
   float sfx = 0.f, sfy = 0.f, sfz = 0.f, tqx = 0.f, tqy = 0.f, tqz = 0.f;
-  float Fx[A], Fy[A], Fz[A];
 #pragma unroll
   for (int a = 0; a < A; ++a) {
     const float rx = x[a] - tx, ry = y[a] - ty, rz = z[a] - tz;
@@ -476,30 +504,9 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, 
     tqx += ry * gfz[a] - rz * gfy[a];
     tqy += rz * gfx[a] - rx * gfz[a];
     tqz += rx * gfy[a] - ry * gfx[a];
-    Fx[a] = gfx[a];
-    Fy[a] = gfy[a];
-    Fz[a] = gfz[a];
-    if (L.n_pairs > b.pl) {
-      const float4 fi = b.f[lane + kWave * a];
-      Fx[a] += fi.x;
-      Fy[a] += fi.y;
-      Fz[a] += fi.z;
-    }
-  }
-  // intramolecular forces: each atom gathers (dE/dr / r) * (x_self - x_partner) over its
-  // incidence list, in a fixed order
-  for (int t = 0; t < L.inc_width; ++t) {
-#pragma unroll
-    for (int a = 0; a < A; ++a) {
-      const uint32_t e = b.inc[t * L.inc_stride + lane + kWave * a];
-      if (e != kIncNone) {
-        const float fr = b.fr[e & 0xffffu];
-        const float4 xo = b.x[e >> 16];
-        Fx[a] += fr * (x[a] - xo.x);
-        Fy[a] += fr * (y[a] - xo.y);
-        Fz[a] += fr * (z[a] - xo.z);
-      }
-    }
+    Fx[a] += gfx[a];
+    Fy[a] += gfy[a];
+    Fz[a] += gfz[a];
   }
   sfx = wave_sum(sfx);
   sfy = wave_sum(sfy);
@@ -557,9 +564,9 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, 
 
 // ------------------------------------------------------------------ kernels
 template <int A, int PREC>
-__global__ __launch_bounds__(kBlock) void k_eval(LigDev L, RecDev R, int n, int pl, const float* __restrict__ genes,
+__global__ __launch_bounds__(kBlock) void k_eval(LigDev L, RecDev R, int n, const float* __restrict__ genes,
                                                  float* __restrict__ energy, float* __restrict__ grad) {
-  const BlockLds b = stage_block<A>(L, pl);
+  const BlockLds b = stage_block<A>(L);
   const int pose = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
   if (pose >= n) return;
   AtomRegs<A> at;
@@ -652,41 +659,47 @@ __device__ __forceinline__ float adadelta_update(float x, float g, float& eg2, f
   return nx;
 }
 
-// One wave per local search.  rows: optional map wave -> row of genes_in/genes_out.
+// ADADELTA from genes_in[row_in] for `iters` steps; the best genotype goes to genes_out[row_out]
+// and its energy is returned (wave-uniform).  trace: NULL or [iters] energies of every step.
 template <int A, int PREC>
-__global__ __launch_bounds__(kBlock) void k_local_search(LigDev L, RecDev R, int n, int pl,
-                                                         const int* __restrict__ rows,
-                                                         const float* genes_in, float* genes_out,
-                                                         float* __restrict__ energy_out, int* __restrict__ evals,
-                                                         int iters, float rho, float eps,
-                                                         float* __restrict__ trace) {
-  const BlockLds b = stage_block<A>(L, pl);
-  const int job = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-  if (job >= n) return;
-  AtomRegs<A> at;
-  load_ligand<A>(L, at);
+__device__ float local_search_wave(const LigDev& L, const RecDev& R, const BlockLds& b, const AtomRegs<A>& at,
+                                   const float* genes_in, long long row_in, float* genes_out,
+                                   long long row_out, int iters, float rho, float eps, float* trace) {
   const int lane = lane_id();
   const int G = L.n_genes;
-  const long long row = rows ? rows[job] : job;
-  float x = lane < G ? genes_in[row * G + lane] : 0.f;
+  float x = lane < G ? genes_in[row_in * G + lane] : 0.f;
   float eg2 = 0.f, edx2 = 0.f;
   float best_x = x;
   float best_e = __builtin_huge_valf();
   for (int it = 0; it < iters; ++it) {
     float g = 0.f;
     const float E = eval_pose<A, PREC, true>(L, R, b, at, x, g);
-    if (trace && lane == 0) trace[(long long)job * iters + it] = E;
+    if (trace && lane == 0) trace[it] = E;
     if (E < best_e) {
       best_e = E;
       best_x = x;
     }
     x = adadelta_update(x, g, eg2, edx2, rho, eps, G);
   }
-  if (lane < G) genes_out[row * G + lane] = best_x;
-  if (lane == 0) {
-    energy_out[row] = best_e;
-    if (evals) evals[row] += iters;
-  }
+  if (lane < G) genes_out[row_out * G + lane] = best_x;
+  return best_e;
+}
+
+// Standalone local search: one wave per start genotype.
+template <int A, int PREC>
+__global__ __launch_bounds__(kBlock) void k_local_search(LigDev L, RecDev R, int n,
+                                                         const float* genes_in, float* genes_out,
+                                                         float* __restrict__ energy_out,
+                                                         int iters, float rho, float eps,
+                                                         float* __restrict__ trace) {
+  const BlockLds b = stage_block<A>(L);
+  const int job = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  if (job >= n) return;
+  AtomRegs<A> at;
+  load_ligand<A>(L, at);
+  const float E = local_search_wave<A, PREC>(L, R, b, at, genes_in, job, genes_out, job, iters, rho, eps,
+                                             trace ? trace + (long long)job * iters : nullptr);
+  if (lane_id() == 0) energy_out[job] = E;
 }
 
 // Initial individual `indiv` of run `run` in the lane-per-gene layout.
@@ -714,30 +727,7 @@ __device__ __forceinline__ float initial_gene(const RecDev& R, const GaDev& P, i
   return v;
 }
 
-template <int A, int PREC>
-__global__ __launch_bounds__(kBlock) void k_init_population(LigDev L, RecDev R, GaDev P, int pl,
-                                                            float* __restrict__ genes,
-                                                            float* __restrict__ energy,
-                                                            int* __restrict__ evals) {
-  const BlockLds b = stage_block<A>(L, pl);
-  const int job = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-  if (job >= P.n_runs * P.pop_size) return;
-  AtomRegs<A> at;
-  load_ligand<A>(L, at);
-  const int lane = lane_id();
-  const int G = L.n_genes;
-  const int run = job / P.pop_size, indiv = job % P.pop_size;
-  const float x = initial_gene(R, P, run, indiv);
-  float g;
-  const float E = eval_pose<A, PREC, false>(L, R, b, at, x, g);
-  if (lane < G) genes[(long long)job * G + lane] = x;
-  if (lane == 0) {
-    energy[job] = E;
-    evals[job] = 1;
-  }
-}
-
-// Lowest energy of a run's population, ties to the lower index (wave-uniform result).
+// Lowest energy among n, ties to the lower index (wave-uniform result).
 __device__ __forceinline__ int wave_argmin(const float* __restrict__ E, int n) {
   const int lane = lane_id();
   float be = __builtin_huge_valf();
@@ -776,32 +766,12 @@ __device__ __forceinline__ int tournament(const float* __restrict__ E, const GaD
 // torsion k is unit 4 + k.
 __device__ __forceinline__ int unit_of(int g) { return g < 3 ? g : (g < 7 ? 3 : g - 3); }
 
-template <int A, int PREC>
-__global__ __launch_bounds__(kBlock) void k_generation(LigDev L, RecDev R, GaDev P, int gen, int pl,
-                                                       const float* __restrict__ genes_in,
-                                                       const float* __restrict__ energy_in,
-                                                       float* __restrict__ genes_out,
-                                                       float* __restrict__ energy_out,
-                                                       int* __restrict__ evals) {
-  const BlockLds b = stage_block<A>(L, pl);
-  const int job = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-  if (job >= P.n_runs * P.pop_size) return;
+// New individual `slot` of run `run` (slot >= elitism): tournaments, two-point crossover,
+// mutation; lane-per-gene layout.
+__device__ float offspring_gene(const GaDev& P, const float* __restrict__ genes_in,
+                                const float* __restrict__ E, long long rbase, int G, int T, int run,
+                                int gen, int slot) {
   const int lane = lane_id();
-  const int G = L.n_genes;
-  const int run = job / P.pop_size, slot = job % P.pop_size;
-  const long long rbase = (long long)run * P.pop_size;
-  const float* E = energy_in + rbase;
-  if (slot < P.elitism) {
-    const int e = wave_argmin(E, P.pop_size);
-    if (lane < G) genes_out[(long long)job * G + lane] = genes_in[(rbase + e) * G + lane];
-    if (lane == 0) {
-      energy_out[job] = E[e];
-      evals[job] = 0;
-    }
-    return;
-  }
-  AtomRegs<A> at;
-  load_ligand<A>(L, at);
   const int pa = tournament(E, P, run, gen, slot, 0);
   const int pb = tournament(E, P, run, gen, slot, 1);
   const float xa = lane < G ? genes_in[(rbase + pa) * G + lane] : 0.f;
@@ -809,7 +779,7 @@ __global__ __launch_bounds__(kBlock) void k_generation(LigDev L, RecDev R, GaDev
   // two-point crossover over gene units
   float x = xa;
   if (draw_uniform(P.seed, run, gen, slot, kPCrossover, 0) < P.crossover_rate) {
-    const int U = 4 + L.n_tors;
+    const int U = 4 + T;
     const int c1 = draw_int(U + 1, P.seed, run, gen, slot, kPCrossover, 1);
     const int c2 = draw_int(U + 1, P.seed, run, gen, slot, kPCrossover, 2);
     const int lo = min(c1, c2), hi = max(c1, c2);
@@ -846,25 +816,95 @@ __global__ __launch_bounds__(kBlock) void k_generation(LigDev L, RecDev R, GaDev
     if (lane == 5) x = ny * inv;
     if (lane == 6) x = nz * inv;
   }
+  return x;
+}
+
+// ------------------------------------------------------------------ GA over a job table
+// Every block belongs to one job (blocks[blockIdx.x] = (job, first wave)); a block whose job is
+// not in the phase's state leaves before staging anything (uniform per block).
+
+template <int A, int PREC>
+__global__ __launch_bounds__(kBlock) void k_ga_init(JobDev* __restrict__ jobs, const int2* __restrict__ blocks,
+                                                    RecDev R) {
+  const int2 bt = blocks[blockIdx.x];
+  JobDev& J = jobs[bt.x];
+  if (J.state != kJobInit) return;
+  const LigDev L = J.L;
+  const GaDev P = J.P;
+  const BlockLds b = stage_block<A>(L);
+  const int w = bt.y + threadIdx.x / kWave;
+  if (w >= P.n_runs * P.pop_size) return;
+  AtomRegs<A> at;
+  load_ligand<A>(L, at);
+  const int lane = lane_id();
+  const int G = L.n_genes;
+  const int run = w / P.pop_size, indiv = w % P.pop_size;
+  const float x = initial_gene(R, P, run, indiv);
+  float g;
+  const float E = eval_pose<A, PREC, false>(L, R, b, at, x, g);
+  float* genes = J.genes[J.cur];
+  if (lane < G) genes[(long long)w * G + lane] = x;
+  if (lane == 0) {
+    J.energy[J.cur][w] = E;
+    J.evals[w] = 1;
+  }
+}
+
+template <int A, int PREC>
+__global__ __launch_bounds__(kBlock) void k_ga_generation(JobDev* __restrict__ jobs,
+                                                          const int2* __restrict__ blocks, RecDev R) {
+  const int2 bt = blocks[blockIdx.x];
+  JobDev& J = jobs[bt.x];
+  if (J.state != kJobRunning) return;
+  const LigDev L = J.L;
+  const GaDev P = J.P;
+  const int gen = J.gen, cur = J.cur;
+  const BlockLds b = stage_block<A>(L);
+  const int w = bt.y + threadIdx.x / kWave;
+  if (w >= P.n_runs * P.pop_size) return;
+  const int lane = lane_id();
+  const int G = L.n_genes;
+  const int run = w / P.pop_size, slot = w % P.pop_size;
+  const long long rbase = (long long)run * P.pop_size;
+  const float* genes_in = J.genes[cur];
+  float* genes_out = J.genes[cur ^ 1];
+  const float* E = J.energy[cur] + rbase;
+  float* energy_out = J.energy[cur ^ 1];
+  if (slot < P.elitism) {
+    const int e = wave_argmin(E, P.pop_size);
+    if (lane < G) genes_out[(long long)w * G + lane] = genes_in[(rbase + e) * G + lane];
+    if (lane == 0) {
+      energy_out[w] = E[e];
+      J.evals[w] = 0;
+    }
+    return;
+  }
+  AtomRegs<A> at;
+  load_ligand<A>(L, at);
+  const float x = offspring_gene(P, genes_in, E, rbase, G, L.n_tors, run, gen, slot);
   float g;
   const float Enew = eval_pose<A, PREC, false>(L, R, b, at, x, g);
-  if (lane < G) genes_out[(long long)job * G + lane] = x;
+  if (lane < G) genes_out[(long long)w * G + lane] = x;
   if (lane == 0) {
-    energy_out[job] = Enew;
-    evals[job] = 1;
+    energy_out[w] = Enew;
+    J.evals[w] = 1;
   }
 }
 
 // Local-search picks of one run: the n_ls individuals with the lowest random keys (ties to
-// the lower index), written as global rows in key order.  One wave per run.
-__global__ __launch_bounds__(kBlock) void k_ls_pick(GaDev P, int gen, int* __restrict__ rows) {
+// the lower index), written as rows in key order.  One wave per run.
+__global__ __launch_bounds__(kBlock) void k_ga_ls_pick(JobDev* __restrict__ jobs, const int2* __restrict__ blocks) {
   __shared__ uint32_t keys[kWavesPerBlock][1024];
+  const int2 bt = blocks[blockIdx.x];
+  JobDev& J = jobs[bt.x];
+  if (J.state != kJobRunning) return;
+  const GaDev P = J.P;
+  const int gen = J.gen;
   const int w = threadIdx.x / kWave;
-  const int run = blockIdx.x * kWavesPerBlock + w;
-  if (run >= P.n_runs) return;
+  const int run = bt.y + w;
+  if (run >= P.n_runs || P.n_ls <= 0) return;
   const int lane = lane_id();
-  for (int i = lane; i < P.pop_size; i += kWave)
-    keys[w][i] = draw_u24(P.seed, run, gen, i, kPLsPick, 0);
+  for (int i = lane; i < P.pop_size; i += kWave) keys[w][i] = draw_u24(P.seed, run, gen, i, kPLsPick, 0);
   wave_sync();
   for (int i = lane; i < P.pop_size; i += kWave) {
     const uint32_t ki = keys[w][i];
@@ -873,40 +913,77 @@ __global__ __launch_bounds__(kBlock) void k_ls_pick(GaDev P, int gen, int* __res
       const uint32_t kj = keys[w][j];
       rank += (kj < ki || (kj == ki && j < i)) ? 1 : 0;
     }
-    if (rank < P.n_ls) rows[run * P.n_ls + rank] = run * P.pop_size + i;
+    if (rank < P.n_ls) J.ls_rows[run * P.n_ls + rank] = run * P.pop_size + i;
   }
 }
 
-// Per-run evaluation sum (the miniapp's sum_evals): evals_of_runs[run] += sum of the
-// per-individual counts of this generation.  One wave per run.
-__global__ __launch_bounds__(kBlock) void k_sum_evals(GaDev P, const int* __restrict__ evals,
-                                                      long long* __restrict__ evals_of_runs) {
-  const int w = threadIdx.x / kWave;
-  const int run = blockIdx.x * kWavesPerBlock + w;
-  if (run >= P.n_runs) return;
-  const int lane = lane_id();
-  int sum = 0;
-  for (int i = lane; i < P.pop_size; i += kWave) sum += evals[run * P.pop_size + i];
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, kWave);
-  if (lane == 0) evals_of_runs[run] += sum;
+template <int A, int PREC>
+__global__ __launch_bounds__(kBlock) void k_ga_local_search(JobDev* __restrict__ jobs,
+                                                            const int2* __restrict__ blocks, RecDev R) {
+  const int2 bt = blocks[blockIdx.x];
+  JobDev& J = jobs[bt.x];
+  if (J.state != kJobRunning) return;
+  const LigDev L = J.L;
+  const GaDev P = J.P;
+  const int cur = J.cur;
+  const BlockLds b = stage_block<A>(L);
+  const int w = bt.y + threadIdx.x / kWave;
+  if (w >= P.n_runs * P.n_ls) return;
+  AtomRegs<A> at;
+  load_ligand<A>(L, at);
+  const long long row = J.ls_rows[w];
+  float* pop = J.genes[cur ^ 1];
+  const float E = local_search_wave<A, PREC>(L, R, b, at, pop, row, pop, row, P.ls_iters, P.rho, P.eps, nullptr);
+  if (lane_id() == 0) {
+    J.energy[cur ^ 1][row] = E;
+    J.evals[row] += P.ls_iters;
+  }
 }
 
-__global__ __launch_bounds__(kBlock) void k_best_of_runs(GaDev P, const float* __restrict__ genes,
-                                                         const float* __restrict__ energy,
-                                                         int* __restrict__ best_row,
-                                                         float* __restrict__ best_energy,
-                                                         float* __restrict__ best_genes) {
-  const int w = threadIdx.x / kWave;
-  const int run = blockIdx.x * kWavesPerBlock + w;
-  if (run >= P.n_runs) return;
+// Generation epilogue, one wave per job: the per-run evaluation sum (the miniapp's
+// sum_evals), then the job's state advances -- a freshly initialised job starts running, a
+// running job swaps its population buffers and moves to the next generation -- and a job whose
+// planned generations are done gets its best individual per run.
+__global__ __launch_bounds__(kBlock) void k_ga_advance(JobDev* __restrict__ jobs, int n_jobs) {
+  const int j = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  if (j >= n_jobs) return;
+  JobDev& J = jobs[j];
+  const int state = J.state;
+  if (state != kJobInit && state != kJobRunning) return;
+  const GaDev P = J.P;
   const int lane = lane_id();
-  const long long base = (long long)run * P.pop_size;
-  const int b = wave_argmin(energy + base, P.pop_size);
-  if (lane < P.n_genes) best_genes[run * P.n_genes + lane] = genes[(base + b) * P.n_genes + lane];
+  for (int run = 0; run < P.n_runs; ++run) {
+    int sum = 0;
+    for (int i = lane; i < P.pop_size; i += kWave) sum += J.evals[run * P.pop_size + i];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) sum += __shfl_xor(sum, off, kWave);
+    if (lane == 0) J.evals_of_runs[run] = (state == kJobInit ? 0ll : J.evals_of_runs[run]) + sum;
+  }
+  int cur = J.cur, gen = J.gen;
+  if (state == kJobInit) {
+    gen = 1;
+  } else {
+    cur ^= 1;
+    gen += 1;
+  }
+  const bool done = gen > J.planned;
+  if (done) {
+    const float* genes = J.genes[cur];
+    const float* energy = J.energy[cur];
+    for (int run = 0; run < P.n_runs; ++run) {
+      const long long base = (long long)run * P.pop_size;
+      const int bi = wave_argmin(energy + base, P.pop_size);
+      if (lane < P.n_genes) J.best_genes[run * P.n_genes + lane] = genes[(base + bi) * P.n_genes + lane];
+      if (lane == 0) {
+        J.best_row[run] = (int)(base + bi);
+        J.best_energy[run] = energy[base + bi];
+      }
+    }
+  }
   if (lane == 0) {
-    best_row[run] = (int)(base + b);
-    best_energy[run] = energy[base + b];
+    J.cur = cur;
+    J.gen = gen;
+    J.state = done ? kJobDone : kJobRunning;
   }
 }
 
@@ -919,8 +996,7 @@ inline unsigned blocks_for(long long waves) {
 #define MDOCK_DISPATCH(KERNEL, GRID, STREAM, ...)                                                   \
   do {                                                                                             \
     const bool two = L.n_atoms > kWave;                                                            \
-    const int pl = L.n_pairs < kPairLdsMax ? L.n_pairs : kPairLdsMax;                              \
-    const size_t sm = lds_bytes(pl, L.inc_width, L.inc_stride, two ? 2 : 1);                        \
+    const size_t sm = (size_t)L.lds_bytes;                                                         \
     switch (R.precision * 2 + (two ? 1 : 0)) {                                                     \
       case 0: hipLaunchKernelGGL((KERNEL<1, 0>), GRID, dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
       case 1: hipLaunchKernelGGL((KERNEL<2, 0>), GRID, dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
@@ -931,12 +1007,11 @@ inline unsigned blocks_for(long long waves) {
     }                                                                                              \
   } while (0)
 
-#define MDOCK_PL (L.n_pairs < kPairLdsMax ? L.n_pairs : kPairLdsMax)
 
 hipError_t launch_eval(const LigDev& L, const RecDev& R, int n, const float* genes, float* energy,
                        float* grad, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  MDOCK_DISPATCH(k_eval, dim3(blocks_for(n)), s, L, R, n, MDOCK_PL, genes, energy, grad);
+  MDOCK_DISPATCH(k_eval, dim3(blocks_for(n)), s, L, R, n, genes, energy, grad);
   return hipGetLastError();
 }
 
@@ -949,48 +1024,58 @@ hipError_t launch_pose(const LigDev& L, int n, const float* genes, float* xyz, h
   return hipGetLastError();
 }
 
-hipError_t launch_local_search(const LigDev& L, const RecDev& R, int n, const int* rows,
-                               const float* genes_in, float* genes_out, float* energy_out,
-                               int* evals, int iters, float rho, float eps, float* trace,
-                               hipStream_t s) {
+hipError_t launch_local_search(const LigDev& L, const RecDev& R, int n, const float* genes_in,
+                               float* genes_out, float* energy_out, int iters, float rho, float eps,
+                               float* trace, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  MDOCK_DISPATCH(k_local_search, dim3(blocks_for(n)), s, L, R, n, MDOCK_PL, rows, genes_in, genes_out,
-                 energy_out, evals, iters, rho, eps, trace);
+  MDOCK_DISPATCH(k_local_search, dim3(blocks_for(n)), s, L, R, n, genes_in, genes_out, energy_out,
+                 iters, rho, eps, trace);
   return hipGetLastError();
 }
 
-hipError_t launch_init_population(const LigDev& L, const RecDev& R, const GaDev& P, float* genes,
-                                  float* energy, int* evals, hipStream_t s) {
-  MDOCK_DISPATCH(k_init_population, dim3(blocks_for((long long)P.n_runs * P.pop_size)), s, L, R, P,
-                 MDOCK_PL, genes, energy, evals);
+#define MDOCK_GA_DISPATCH(KERNEL, A, LDS, NB, STREAM, ...)                                          \
+  do {                                                                                             \
+    const size_t sm = (size_t)(LDS);                                                               \
+    switch (R.precision * 2 + ((A) == 2 ? 1 : 0)) {                                               \
+      case 0: hipLaunchKernelGGL((KERNEL<1, 0>), dim3(NB), dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
+      case 1: hipLaunchKernelGGL((KERNEL<2, 0>), dim3(NB), dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
+      case 2: hipLaunchKernelGGL((KERNEL<1, 1>), dim3(NB), dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
+      case 3: hipLaunchKernelGGL((KERNEL<2, 1>), dim3(NB), dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
+      case 4: hipLaunchKernelGGL((KERNEL<1, 2>), dim3(NB), dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
+      default: hipLaunchKernelGGL((KERNEL<2, 2>), dim3(NB), dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
+    }                                                                                              \
+  } while (0)
+
+hipError_t launch_ga_init(JobDev* jobs, const int2* blocks, int n_blocks, int A, int lds, const RecDev& R,
+                          hipStream_t s) {
+  if (n_blocks <= 0) return hipSuccess;
+  MDOCK_GA_DISPATCH(k_ga_init, A, lds, n_blocks, s, jobs, blocks, R);
   return hipGetLastError();
 }
 
-hipError_t launch_generation(const LigDev& L, const RecDev& R, const GaDev& P, int gen,
-                             const float* genes_in, const float* energy_in, float* genes_out,
-                             float* energy_out, int* evals, hipStream_t s) {
-  MDOCK_DISPATCH(k_generation, dim3(blocks_for((long long)P.n_runs * P.pop_size)), s, L, R, P, gen,
-                 MDOCK_PL, genes_in, energy_in, genes_out, energy_out, evals);
+hipError_t launch_ga_generation(JobDev* jobs, const int2* blocks, int n_blocks, int A, int lds,
+                                const RecDev& R, hipStream_t s) {
+  if (n_blocks <= 0) return hipSuccess;
+  MDOCK_GA_DISPATCH(k_ga_generation, A, lds, n_blocks, s, jobs, blocks, R);
   return hipGetLastError();
 }
 
-hipError_t launch_ls_pick(const GaDev& P, int gen, int* rows, hipStream_t s) {
-  hipLaunchKernelGGL(k_ls_pick, dim3(blocks_for(P.n_runs)), dim3(kBlock), 0, s, P, gen, rows);
+hipError_t launch_ga_ls_pick(JobDev* jobs, const int2* blocks, int n_blocks, hipStream_t s) {
+  if (n_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ga_ls_pick, dim3(n_blocks), dim3(kBlock), 0, s, jobs, blocks);
   return hipGetLastError();
 }
 
-hipError_t launch_sum_evals(const GaDev& P, const int* evals, long long* evals_of_runs,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_evals, dim3(blocks_for(P.n_runs)), dim3(kBlock), 0, s, P, evals,
-                     evals_of_runs);
+hipError_t launch_ga_local_search(JobDev* jobs, const int2* blocks, int n_blocks, int A, int lds,
+                                  const RecDev& R, hipStream_t s) {
+  if (n_blocks <= 0) return hipSuccess;
+  MDOCK_GA_DISPATCH(k_ga_local_search, A, lds, n_blocks, s, jobs, blocks, R);
   return hipGetLastError();
 }
 
-hipError_t launch_best_of_runs(const GaDev& P, const float* genes, const float* energy,
-                               int* best_row, float* best_energy, float* best_genes,
-                               hipStream_t s) {
-  hipLaunchKernelGGL(k_best_of_runs, dim3(blocks_for(P.n_runs)), dim3(kBlock), 0, s, P, genes,
-                     energy, best_row, best_energy, best_genes);
+hipError_t launch_ga_advance(JobDev* jobs, int n_jobs, hipStream_t s) {
+  if (n_jobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ga_advance, dim3(blocks_for(n_jobs)), dim3(kBlock), 0, s, jobs, n_jobs);
   return hipGetLastError();
 }
 

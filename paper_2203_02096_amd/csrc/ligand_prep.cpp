@@ -198,23 +198,45 @@ std::string prepare_ligand(int n, const float* xyz, const int* type, const float
     out.pair_ij.swap(ij);
     out.pair_coef.swap(coef);
   }
-  // Incidence table: for every atom, the pairs (among the first kPairLdsMax) it belongs to and
-  // the partner atom, one column per atom so that a wavefront reads a row in one access.
+  // LDS plan and incidence tables.  Chunk size: all pairs when they fit, else halved until the
+  // per-wave force buffers of a block fit the budget.  Each chunk's table lists, for every
+  // atom, the chunk's pairs it belongs to with the sign of its end, one column per atom so that
+  // a wavefront reads a row in one access.
   {
-    const int P = (int)std::min<size_t>(out.pair_ij.size(), (size_t)kPairLdsMax);
-    std::vector<std::vector<uint32_t>> per(n);
-    for (int p = 0; p < P; ++p) {
-      const uint32_t i = out.pair_ij[p] & 0xff, j = (out.pair_ij[p] >> 8) & 0xff;
-      per[i].push_back((uint32_t)p | (j << 16));
-      per[j].push_back((uint32_t)p | (i << 16));
+    const int P = (int)out.pair_ij.size();
+    const int A = n > kWave ? 2 : 1;
+    out.inc_stride = kWave * A;
+    int C = std::max(1, std::min(P, kChunkMax));
+    while (C > 64 && (size_t)kWavesPerBlock * lds_wave_bytes(C, A) > kLdsBudget * 5 / 8) C = (C + 1) / 2;
+    out.chunk = C;
+    out.n_chunks = P == 0 ? 0 : (P + C - 1) / C;
+    out.inc_rows.clear();
+    out.inc.clear();
+    int total = 0;
+    for (int c = 0; c < out.n_chunks; ++c) {
+      const int c0 = c * C, c1 = std::min(P, c0 + C);
+      std::vector<std::vector<uint16_t>> per(n);
+      for (int p = c0; p < c1; ++p) {
+        const uint32_t i = out.pair_ij[p] & 0xff, j = (out.pair_ij[p] >> 8) & 0xff;
+        per[i].push_back((uint16_t)(p - c0));              // first atom: +force
+        per[j].push_back((uint16_t)((p - c0) | 0x8000));   // second atom: -force
+      }
+      size_t w = 0;
+      for (auto& v : per) w = std::max(w, v.size());
+      out.inc_rows.push_back(make_int2(total, (int)w));
+      out.inc.resize((size_t)(total + (int)w) * out.inc_stride, (uint16_t)kIncNone);
+      for (int a = 0; a < n; ++a)
+        for (size_t t = 0; t < per[a].size(); ++t) out.inc[(total + t) * out.inc_stride + a] = per[a][t];
+      total += (int)w;
     }
-    size_t w = 0;
-    for (auto& v : per) w = std::max(w, v.size());
-    out.inc_width = (int)w;
-    out.inc_stride = n > 64 ? 128 : 64;
-    out.inc.assign(w * out.inc_stride, kIncNone);
-    for (int a = 0; a < n; ++a)
-      for (size_t t = 0; t < per[a].size(); ++t) out.inc[t * out.inc_stride + a] = per[a][t];
+    const size_t waves = (size_t)kWavesPerBlock * lds_wave_bytes(C, A);
+    const size_t ib = lds_inc_bytes(total, out.inc_stride);
+    out.inc_lds = (ib <= kIncLdsMax && waves + ib <= kLdsBudget) ? 1 : 0;
+    const size_t fixed = waves + (out.inc_lds ? ib : 0);
+    int pl = P;
+    while (pl > 0 && fixed + lds_pairs_bytes(pl) > kLdsBudget) pl = std::max(0, pl - 64);
+    out.pl = pl;
+    out.lds_bytes = (int)(fixed + lds_pairs_bytes(pl));
   }
   return std::string();
 }

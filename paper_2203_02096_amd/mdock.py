@@ -54,6 +54,10 @@ class DockResult(C.Structure):
                 ("evals", C.POINTER(C.c_longlong)), ("generations", C.POINTER(C.c_int))]
 
 
+class DockJob(C.Structure):
+    _fields_ = [("ligand", C.c_void_p), ("params", DockParams), ("result", C.POINTER(DockResult))]
+
+
 # name -> (restype, argtypes); the complete exported surface of include/mdock.h
 SIGNATURES = {
     "md_receptor_create": (C.c_int, [C.POINTER(GridDesc), C.POINTER(C.c_float), C.c_int, C.c_void_p,
@@ -69,6 +73,7 @@ SIGNATURES = {
     "md_local_search": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_int, C.c_float, C.c_float, C.c_void_p, C.c_void_p]),
     "md_dock": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(DockParams), C.POINTER(DockResult), C.c_void_p]),
+    "md_dock_batch": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(DockJob), C.c_void_p]),
     "md_dock_planned_generations": (C.c_int, [C.POINTER(DockParams)]),
     "md_ligand_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                  C.POINTER(C.c_int)]),
@@ -242,20 +247,39 @@ def md_dock_planned_generations(params: DockParams) -> int:
     return lib().md_dock_planned_generations(C.byref(params))
 
 
-def md_dock(rec: Receptor, lig: Ligand, params: DockParams, stream=None, want_xyz=True):
+def _result(params, lig, want_xyz):
     R, G, N = params.n_runs, lig.n_genes, lig.n_atoms
-    be = np.zeros(R, np.float32)
-    bg = np.zeros((R, G), np.float32)
-    bx = np.zeros((R, N, 3), np.float32)
-    ri = np.zeros(R, np.int32)
-    ev = np.zeros(R, np.int64)
-    gn = np.zeros(R, np.int32)
-    res = DockResult(R, G, N, _fptr(be), _fptr(bg), _fptr(bx) if want_xyz else None, _iptr(ri),
-                     ev.ctypes.data_as(C.POINTER(C.c_longlong)), _iptr(gn))
+    arrs = dict(best_energy=np.zeros(R, np.float32), best_genes=np.zeros((R, G), np.float32),
+                best_xyz=np.zeros((R, N, 3), np.float32) if want_xyz else None,
+                run_index=np.zeros(R, np.int32), evals=np.zeros(R, np.int64),
+                generations=np.zeros(R, np.int32))
+    res = DockResult(R, G, N, _fptr(arrs["best_energy"]), _fptr(arrs["best_genes"]),
+                     _fptr(arrs["best_xyz"]) if want_xyz else None, _iptr(arrs["run_index"]),
+                     arrs["evals"].ctypes.data_as(C.POINTER(C.c_longlong)), _iptr(arrs["generations"]))
+    return res, arrs
+
+
+def md_dock(rec: Receptor, lig: Ligand, params: DockParams, stream=None, want_xyz=True):
+    res, arrs = _result(params, lig, want_xyz)
     _check(lib().md_dock(rec.handle, lig.handle, C.byref(params), C.byref(res), _stream_ptr(stream)),
            "md_dock")
-    return dict(best_energy=be, best_genes=bg, best_xyz=bx if want_xyz else None, run_index=ri,
-                evals=ev, generations=gn)
+    return arrs
+
+
+def md_dock_batch(rec: Receptor, jobs, stream=None, want_xyz=True):
+    """jobs: sequence of (Ligand, DockParams); returns one result dict per job."""
+    jobs = list(jobs)
+    keep, out = [], []
+    arr = (DockJob * max(1, len(jobs)))()
+    for k, (lig, params) in enumerate(jobs):
+        res, arrs = _result(params, lig, want_xyz)
+        keep.append(res)
+        out.append(arrs)
+        arr[k].ligand = lig.handle
+        arr[k].params = params
+        arr[k].result = C.pointer(res)
+    _check(lib().md_dock_batch(rec.handle, len(jobs), arr, _stream_ptr(stream)), "md_dock_batch")
+    return out
 
 
 KERNELS = {"init_population": 0, "generation": 1, "ls_pick": 2, "local_search": 3, "sum_evals": 4,

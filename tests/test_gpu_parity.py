@@ -238,3 +238,56 @@ def test_dock_production_sampled(md):
         ref = S.energy_and_gradient(grid, ol, res["best_genes"][k].astype(np.float64))
         assert abs(ref.energy - res["best_energy"][k]) <= 1e-4 * max(abs(ref.energy), ref.scale_energy)
     _say(f"[dock production] best energies {res['best_energy'][:5]}")
+
+
+BATCH_SIZES = [(10, 3), (30, 8), (64, 12), (65, 14), (100, 32)]
+
+
+def test_dock_batch_equals_alone(md):
+    """Ligands of different sizes docked in one batch give bitwise the same answer as each
+    docked alone (their random numbers and arithmetic do not depend on the batch)."""
+    rec, drec = _receptor(md, 64, 102)
+    ligs = [synth.make_ligand(n, t, 400 + k, configs.type_params()) for k, (n, t) in enumerate(BATCH_SIZES)]
+    dligs = [md.Ligand.from_synth(l) for l in ligs]
+    params = [md.dock_params(**configs.search_params("batched_fp32", n_runs=3, pop_size=40,
+                                                     max_generations=3, ls_rate=0.2, ls_iters=40,
+                                                     seed=50 + k)) for k in range(len(ligs))]
+    batch = md.md_dock_batch(drec, list(zip(dligs, params)))
+    for k in range(len(ligs)):
+        alone = md.md_dock(drec, dligs[k], params[k])
+        _say(f"[batch] ligand {BATCH_SIZES[k]}: best {batch[k]['best_energy'][0]:.5g} alone {alone['best_energy'][0]:.5g}")
+        for key in ("best_energy", "best_genes", "best_xyz", "run_index", "evals", "generations"):
+            assert np.array_equal(batch[k][key], alone[key]), (k, key)
+        assert np.all(batch[k]["evals"] == 40 + 3 * (39 + 8 * 40))
+
+
+def test_dock_batch_energies_match_oracle(md):
+    """Every job's reported best energy is the oracle's energy of its reported pose, and its
+    reported coordinates are the oracle's pose of its reported genes."""
+    from oracle import pose as OP
+    from oracle import scoring as S
+    rec, drec = _receptor(md, 64, 102)
+    ligs = [synth.make_ligand(n, t, 500 + k, configs.type_params()) for k, (n, t) in enumerate(BATCH_SIZES)]
+    dligs = [md.Ligand.from_synth(l) for l in ligs]
+    params = [md.dock_params(**configs.search_params("batched_fp32", n_runs=2, pop_size=30,
+                                                     max_generations=2, ls_rate=0.1, ls_iters=30,
+                                                     seed=9)) for _ in ligs]
+    res = md.md_dock_batch(drec, list(zip(dligs, params)))
+    grid = oracle_grid(rec)
+    for lig, r in zip(ligs, res):
+        ol = oracle_ligand(lig)
+        for k in range(2):
+            g = r["best_genes"][k].astype(np.float64)
+            ref = S.energy_and_gradient(grid, ol, g)
+            if ref.margin_energy >= 5e-5:
+                assert abs(ref.energy - r["best_energy"][k]) <= 1e-4 * max(abs(ref.energy), ref.scale_energy)
+            assert np.abs(r["best_xyz"][k] - OP.pose(ol, g)).max() < 2e-4
+
+
+def test_dock_batch_rejects_bad_job(md):
+    rec, drec = _receptor(md, 40, 101)
+    lig = md.Ligand.from_synth(configs.ligand("plain_fp32_small"))
+    good = md.dock_params(**configs.search_params("plain_fp32_small", max_generations=1))
+    bad = md.dock_params(**configs.search_params("plain_fp32_small", pop_size=1))
+    with pytest.raises(md.MdockError, match="job 1"):
+        md.md_dock_batch(drec, [(lig, good), (lig, bad)])
