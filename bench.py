@@ -126,11 +126,24 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the timed region, one plain device copy of this size (a known-size "
                          "dispatch for calibrating byte counters under a profiler)")
+    ap.add_argument("--workload", default=WORKLOAD,
+                    choices=[WORKLOAD, "batched_fp32", "serving_fp16"],
+                    help="plain_fp32_production (default): one ligand, 20 runs; batched_fp32: 256 "
+                         "ligands in one batch; serving_fp16: Poisson arrivals into the server")
+    ap.add_argument("--generations", type=int, default=50,
+                    help="batched_fp32: generations per timed batch (the full budget takes ~878)")
+    ap.add_argument("--rates", default="50,100,200,350,500",
+                    help="serving_fp16: arrival rates (ligands/s)")
+    ap.add_argument("--requests", type=int, default=300, help="serving_fp16: requests per rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the docking path has "
               f"no cross-GPU work to measure here", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched_fp32":
+        return bench_batched(args)
+    if args.workload == "serving_fp16":
+        return bench_serving(args)
 
     # the oracle baseline runs first, in spawned processes, before this process touches the GPU
     base = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)
@@ -222,6 +235,129 @@ def main():
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
+    print(json.dumps(out), flush=True)
+
+
+def _common(md):
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    md.lib()
+
+
+def bench_batched(args):
+    """256 ligands (10-100 atoms, 0-32 rotatable bonds) against one 64^3 FP32 map set, 10 runs x
+    150 each, docked together through md_dock_batch (one launch per GA phase for all of them).
+    A timed batch runs --generations generations; evaluations/s are measured, ligands/s at the
+    full 2.5M-evaluation budget are projected from them."""
+    import numpy as np
+    import torch
+
+    import paper_2203_02096_amd as md
+    from workload import configs
+    _common(md)
+    name = "batched_fp32"
+    rec = configs.receptor(name)
+    drec = md.Receptor(rec.maps, rec.origin, rec.spacing, "fp32")
+    ligs = configs.batched_ligands(name)
+    dligs = [md.Ligand.from_synth(l) for l in ligs]
+    sp = configs.search_params(name, seed=args.seed, max_generations=args.generations)
+    P = md.dock_params(**sp)
+    jobs = [(d, P) for d in dligs]
+    n_ls = max(0, min(P.pop_size, math.ceil(sp["ls_rate"] * P.pop_size - 1e-4)))
+    gens = md.md_dock_planned_generations(P)
+    per_gen = (P.pop_size - P.elitism) + n_ls * P.ls_iters
+    total_evals = len(jobs) * P.n_runs * (P.pop_size + gens * per_gen)
+    ls_evals = len(jobs) * P.n_runs * gens * n_ls * P.ls_iters
+    md.md_dock_batch(drec, jobs[:8], want_xyz=False)      # warm-up
+    torch.cuda.synchronize()
+    md.md_profile_reset()
+    md.md_profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        md.md_dock_batch(drec, jobs, want_xyz=False)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    md.md_profile_enable(False)
+    full = configs.search_params(name)
+    full_gens = md.md_dock_planned_generations(md.dock_params(**full))
+    evals_per_ligand_full = P.n_runs * (P.pop_size + full_gens * per_gen)
+    rate = total_evals / dt
+    sizes = np.array([l.n_atoms for l in ligs])
+    out = {"metric": "energy+gradient evals/s", "value": ls_evals / dt, "unit": "evals/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": 1, "ms_per_step": dt * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": name, "n_ligands": len(ligs), "atoms": [int(sizes.min()), int(sizes.max())],
+                      "mean_atoms": float(sizes.mean()), "n_runs": P.n_runs, "pop_size": P.pop_size,
+                      "generations_timed": gens, "ls_rate": sp["ls_rate"], "ls_iters": P.ls_iters},
+           "total_evals_per_s": rate,
+           "ligands_per_s_projected": rate / evals_per_ligand_full,
+           "projection": f"total evals/s / {evals_per_ligand_full} evals per ligand at the full budget "
+                         f"({full_gens} generations)",
+           "kernel_ms_per_step": {k: md.md_profile_read(k)[0] / args.steps for k in md.mdock.KERNELS}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_serving(args):
+    """Requests arrive as a Poisson stream at each rate; every request is 10 runs x 150 with a
+    250k-evaluation budget per run against a 96^3 map set stored in FP16, for a ligand of
+    log-normal size (median 35 atoms, 10-120).  The server batches resident requests
+    continuously; latency = completion - arrival."""
+    import numpy as np
+
+    import paper_2203_02096_amd as md
+    from workload import configs, synth
+    _common(md)
+    name = "serving_fp16"
+    rec = configs.receptor(name)
+    drec = md.Receptor(rec.maps, rec.origin, rec.spacing, "fp16")
+    sizes = configs.serving_sizes(args.requests, seed=205)
+    ligs = [md.Ligand.from_synth(synth.make_ligand(n, t, 9000 + k, configs.type_params()))
+            for k, (n, t) in enumerate(sizes)]
+    sp = configs.search_params(name, seed=args.seed)
+    P = md.dock_params(**sp)
+    n_ls = max(0, min(P.pop_size, math.ceil(sp["ls_rate"] * P.pop_size - 1e-4)))
+    gens = md.md_dock_planned_generations(P)
+    evals_per_req = P.n_runs * (P.pop_size + gens * ((P.pop_size - P.elitism) + n_ls * P.ls_iters))
+    results = []
+    for rate in [float(r) for r in args.rates.split(",")]:
+        srv = md.Server(drec, hbm_budget_bytes=8 << 30, max_slots=256)
+        rng = np.random.default_rng([args.seed, int(rate)])
+        gaps = rng.exponential(1.0 / rate, len(ligs))
+        tickets = []
+        t_start = time.perf_counter()
+        t_next = t_start
+        for k, lig in enumerate(ligs):
+            t_next += gaps[k]
+            delay = t_next - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            p = md.dock_params(**{**sp, "seed": args.seed * 1000 + k})
+            tickets.append(srv.submit(lig, p))
+        for t in tickets:
+            srv.wait(t, want_xyz=False)
+        t_end = time.perf_counter()
+        lat = np.array([(lambda a: a[2] - a[0])(srv.times(t)) for t in tickets]) * 1e3
+        done = [srv.times(t)[2] for t in tickets]
+        first = min(srv.times(t)[0] for t in tickets)
+        st = srv.stats()
+        srv.close()
+        steady = lat[len(lat) // 10:]
+        results.append({"rate": rate, "p50_ms": float(np.percentile(steady, 50)),
+                        "p99_ms": float(np.percentile(steady, 99)),
+                        "ligands_per_s": len(tickets) / (max(done) - first),
+                        "evals_per_s": len(tickets) * evals_per_req / (max(done) - first),
+                        "wall_s": t_end - t_start, "ticks": st["ticks"]})
+        print(json.dumps({"partial": results[-1]}), file=sys.stderr, flush=True)
+    best = max(results, key=lambda r: r["ligands_per_s"])
+    out = {"metric": "ligands docked/s (serving)", "value": best["ligands_per_s"], "unit": "ligands/s",
+           "n_gpus": 1, "steps": len(results), "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": name, "grid": "96^3 x 9 maps FP16", "requests_per_rate": len(ligs),
+                      "n_runs": P.n_runs, "pop_size": P.pop_size, "generations": gens,
+                      "evals_per_request": evals_per_req, "median_atoms": float(np.median([n for n, _ in sizes]))},
+           "rates": results}
     print(json.dumps(out), flush=True)
 
 

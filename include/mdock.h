@@ -218,6 +218,47 @@ md_status md_dock_batch(const md_receptor* rec, int n_jobs, const md_dock_job* j
 /* Number of generations md_dock runs for these parameters (all runs share it). */
 int md_dock_planned_generations(const md_dock_params* params);
 
+/* ------------------------------------------------------------------ serving
+ * Continuous batching for a stream of docking requests against one receptor (the paper's
+ * high-throughput screening workflow over many heterogeneous ligands; introduction and its
+ * workflow figure).  A worker thread admits queued requests (FIFO) into free slots while their
+ * device buffers (populations, counters, results) fit in a pool of hbm_budget_bytes, advances
+ * every resident request by one generation per tick with the batched GA kernels, and retires
+ * finished requests at once, freeing their slot and memory for the next admission.  A
+ * request's result equals md_dock of the same ligand and parameters.
+ * The receptor and every submitted ligand must stay alive until the server is destroyed (or
+ * the request is released).  Calls are thread-safe.  md_server_destroy drops queued requests,
+ * lets resident ones finish, and must not race with md_server_wait on another thread. */
+typedef struct md_server md_server;   /* opaque */
+typedef struct {
+  size_t hbm_budget_bytes;   /* device memory pool for request buffers, >= 1 MiB */
+  int max_slots;             /* requests resident at once, 1..4096 */
+} md_server_params;
+typedef struct {
+  long long ticks, completed;
+  int queued, resident;
+  size_t pool_used_bytes;
+  double busy_seconds;       /* wall time spent running ticks */
+} md_server_stats;
+/* Errors: MD_EINVAL, MD_ERANGE, MD_ENOMEM, MD_EDEVICE. */
+md_status md_server_create(const md_receptor* rec, const md_server_params* params, md_server** out);
+/* Queues a request; *ticket identifies it.  MD_ENOMEM if it can never fit the pool. */
+md_status md_server_submit(md_server* srv, const md_ligand* lig, const md_dock_params* params,
+                           unsigned long long* ticket);
+/* *done = 1 once finished (results written to out if non-NULL), canceled or failed
+ * (MD_ECANCELED / MD_EDEVICE).  MD_ENOTFOUND for an unknown ticket. */
+md_status md_server_poll(md_server* srv, unsigned long long ticket, md_dock_result* out, int* done);
+/* Blocks until the request finishes (timeout_s < 0: no limit; MD_EBUSY on timeout). */
+md_status md_server_wait(md_server* srv, unsigned long long ticket, md_dock_result* out, double timeout_s);
+md_status md_server_cancel(md_server* srv, unsigned long long ticket);
+/* Host monotonic times (s) of submission, admission to a slot and completion. */
+md_status md_server_request_times(md_server* srv, unsigned long long ticket, double* submit_s,
+                                  double* start_s, double* end_s);
+/* Forgets a finished request (frees its host-side result); MD_EBUSY while it runs. */
+md_status md_server_release(md_server* srv, unsigned long long ticket);
+md_status md_server_get_stats(md_server* srv, md_server_stats* out);
+md_status md_server_destroy(md_server* srv);
+
 /* ------------------------------------------------------------------ kernel timing
  * When enabled, md_dock brackets every kernel it launches with HIP events on its stream and
  * accumulates the elapsed times per kernel kind once the call has synchronised.  Process-wide,

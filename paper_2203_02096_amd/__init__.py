@@ -3,6 +3,6 @@
 The package holds the C-ABI library sources (csrc/), the build script and a thin ctypes
 binding whose functions carry the C names (md_eval, md_local_search, md_dock, ...).
 """
-from .mdock import (Ligand, MdockError, Receptor, dock_params, lib, md_dock, md_dock_batch,  # noqa: F401
+from .mdock import (Ligand, MdockError, Receptor, Server, dock_params, lib, md_dock, md_dock_batch,  # noqa: F401
                     md_dock_planned_generations, md_eval, md_ligand_info, md_local_search, md_pose,
                     md_profile_enable, md_profile_read, md_profile_reset)

@@ -15,19 +15,6 @@
 
 using namespace mdock;
 
-struct md_receptor {
-  RecDev dev{};
-  void* d_maps = nullptr;
-  int device = 0;
-};
-
-struct md_ligand {
-  LigDev dev{};
-  void* d_buf = nullptr;
-  LigHost host;
-  int device = 0;
-};
-
 namespace {
 
 thread_local std::string g_error;
@@ -386,6 +373,12 @@ struct Carve {
 };
 
 }  // namespace
+
+namespace mdock {
+md_status server_fail(md_status st, const std::string& msg) { return fail(st, msg); }
+int n_local_search_of(const md_dock_params* p) { return n_local_search(p); }
+std::string check_dock_params(const md_dock_params* p) { return check_params(p); }
+}  // namespace mdock
 
 extern "C" {
 

@@ -162,3 +162,17 @@ hipError_t launch_ga_local_search(JobDev* jobs, const int2* blocks, int n_blocks
 hipError_t launch_ga_advance(JobDev* jobs, int n_jobs, hipStream_t s);
 
 }  // namespace mdock
+
+// Library handles (opaque to callers of include/mdock.h).
+struct md_receptor {
+  mdock::RecDev dev{};
+  void* d_maps = nullptr;
+  int device = 0;
+};
+
+struct md_ligand {
+  mdock::LigDev dev{};
+  void* d_buf = nullptr;
+  mdock::LigHost host;
+  int device = 0;
+};

@@ -348,13 +348,15 @@ __device__ __forceinline__ float pair_one(const BlockLds& b, uint32_t ij, float4
   return e;
 }
 
-// Pairs [p0, p1) of the list, strided over lanes two at a time; records from LDS below L.pl,
+// Pairs [p0, p1) of the list (p0 a multiple of 64), strided over lanes two at a time; records
+// from LDS below L.pl,
 // else from global memory (separate loops, so LDS-only chunks carry no global-load waits).
-// slot = pair index - base.
+// slot = pair index - base.  Energies are added to e in pair order, so the sum does not depend
+// on how the list is cut into chunks.
 template <bool GRAD>
-__device__ __forceinline__ float pair_range(const LigDev& L, const BlockLds& b, int p0, int p1, int base) {
+__device__ __forceinline__ void pair_range(const LigDev& L, const BlockLds& b, int p0, int p1, int base,
+                                           float& e) {
   const int lane = lane_id();
-  float e = 0.f;
   const int pm = min(p1, L.pl);
   for (int p = p0 + lane; p < pm; p += 2 * kWave) {
     const bool two = p + kWave < pm;
@@ -365,7 +367,9 @@ __device__ __forceinline__ float pair_range(const LigDev& L, const BlockLds& b, 
     e += pair_one<GRAD>(b, ij0, c0, p - base);
     if (two) e += pair_one<GRAD>(b, ij1, c1, p + kWave - base);
   }
-  for (int p = max(p0, L.pl) + lane; p < p1; p += 2 * kWave) {
+  // pair p is always handled by lane p mod 64 (p0 is a multiple of 64), whatever the split
+  const int g0 = max(p0, L.pl);
+  for (int p = g0 + ((lane - g0) & (kWave - 1)); p < p1; p += 2 * kWave) {
     const bool two = p + kWave < p1;
     const uint32_t ij0 = L.pair_ij[p];
     const float4 c0 = L.pair_coef[p];
@@ -374,7 +378,6 @@ __device__ __forceinline__ float pair_range(const LigDev& L, const BlockLds& b, 
     e += pair_one<GRAD>(b, ij0, c0, p - base);
     if (two) e += pair_one<GRAD>(b, ij1, c1, p + kWave - base);
   }
-  return e;
 }
 
 // ------------------------------------------------------------------ one pose
@@ -461,11 +464,11 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, 
   for (int a = 0; a < A; ++a) Fx[a] = Fy[a] = Fz[a] = 0.f;
   const int P = L.n_pairs;
   if (!GRAD) {
-    e_lane += pair_range<false>(L, b, 0, P, 0);
+    pair_range<false>(L, b, 0, P, 0, e_lane);
   } else {
     for (int c = 0; c < L.n_chunks; ++c) {
       const int c0 = c * L.chunk;
-      e_lane += pair_range<true>(L, b, c0, min(P, c0 + L.chunk), c0);
+      pair_range<true>(L, b, c0, min(P, c0 + L.chunk), c0, e_lane);
       wave_sync();
       const int2 rows = L.inc_rows[c];
       for (int t = rows.x; t < rows.x + rows.y; ++t) {

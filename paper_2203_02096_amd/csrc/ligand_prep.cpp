@@ -208,6 +208,9 @@ std::string prepare_ligand(int n, const float* xyz, const int* type, const float
     out.inc_stride = kWave * A;
     int C = std::max(1, std::min(P, kChunkMax));
     while (C > 64 && (size_t)kWavesPerBlock * lds_wave_bytes(C, A) > kLdsBudget * 5 / 8) C = (C + 1) / 2;
+    // several chunks: a multiple of the wavefront width, so every pair stays on the lane it has
+    // in a single pass over the list (the energy-only path) and the sums agree bitwise
+    if (C < P) C = std::max(kWave, C / kWave * kWave);
     out.chunk = C;
     out.n_chunks = P == 0 ? 0 : (P + C - 1) / C;
     out.inc_rows.clear();

@@ -1,0 +1,570 @@
+// Continuous-batching docking server of libmdock (md_server_* in include/mdock.h).
+//
+// The paper's screening workflow docks a large, heterogeneous stream of ligands against one
+// receptor, which makes scheduling and load balance part of the problem (introduction, the
+// high-throughput workflow figure and the paragraph on heterogeneously sized ligands).  Here
+// requests arrive while others run: a worker thread admits queued requests into free slots as
+// long as their device buffers fit in a fixed HBM pool, runs one generation of every resident
+// request per tick through the same job-table kernels as md_dock_batch, and retires finished
+// requests at once, so their slots and memory are reused on the next tick.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+#include "mdock.h"
+
+namespace mdock {
+// shared with api.cpp
+md_status server_fail(md_status st, const std::string& msg);
+int n_local_search_of(const md_dock_params* p);
+std::string check_dock_params(const md_dock_params* p);
+}  // namespace mdock
+
+using namespace mdock;
+
+namespace {
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// First-fit allocator over one device pool (offsets only).
+class Pool {
+ public:
+  explicit Pool(size_t size) { free_[0] = size; }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = align256(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes, start = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[start] = rest;
+        used_ += bytes;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = align256(bytes);
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto next = std::next(it);
+    if (next != free_.end() && it->first + it->second == next->first) {
+      it->second += next->second;
+      free_.erase(next);
+    }
+    if (it != free_.begin()) {
+      auto prev = std::prev(it);
+      if (prev->first + prev->second == it->first) {
+        prev->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t used() const { return used_; }
+
+ private:
+  std::map<size_t, size_t> free_;
+  size_t used_ = 0;
+};
+
+enum ReqState { kQueued, kResident, kFinished, kCanceled, kFailed };
+
+struct Request {
+  unsigned long long ticket = 0;
+  const md_ligand* lig = nullptr;
+  md_dock_params params{};
+  ReqState state = kQueued;
+  int slot = -1;
+  size_t off = 0, bytes = 0;
+  // offsets inside the request's pool block
+  size_t o_ga, o_gb, o_ea, o_eb, o_ev, o_er, o_lsr, o_br, o_be, o_bg, o_bx;
+  int planned = 0;
+  double t_submit = 0, t_start = 0, t_end = 0;
+  // results (runs sorted by energy)
+  std::vector<float> best_energy, best_genes, best_xyz;
+  std::vector<int> run_index;
+  std::vector<long long> evals;
+  std::string error;
+};
+
+}  // namespace
+
+struct md_server {
+  const md_receptor* rec = nullptr;
+  md_server_params params{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char* pool_base = nullptr;
+  std::unique_ptr<Pool> pool;
+  JobDev* d_table = nullptr;     // [max_slots]
+  JobDev* h_table = nullptr;     // pinned mirror
+  int2* d_blocks = nullptr;
+  size_t blocks_cap = 0;
+  std::vector<std::shared_ptr<Request>> slots;   // resident request per slot (or null)
+
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::shared_ptr<Request>> queue;
+  std::map<unsigned long long, std::shared_ptr<Request>> requests;
+  unsigned long long next_ticket = 1;
+  bool stop = false;
+  std::thread worker;
+  // statistics
+  long long ticks = 0, completed = 0;
+  double busy_s = 0;
+  std::string fatal;
+};
+
+namespace {
+
+void layout(Request& r) {
+  const LigDev& L = r.lig->dev;
+  const md_dock_params& p = r.params;
+  const size_t rows = (size_t)p.n_runs * p.pop_size;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t o = off;
+    off = (off + b + 15) & ~size_t(15);
+    return o;
+  };
+  r.o_ga = take(rows * L.n_genes * 4);
+  r.o_gb = take(rows * L.n_genes * 4);
+  r.o_ea = take(rows * 4);
+  r.o_eb = take(rows * 4);
+  r.o_ev = take(rows * 4);
+  r.o_er = take((size_t)p.n_runs * 8);
+  r.o_lsr = take((size_t)p.n_runs * std::max(n_local_search_of(&p), 1) * 4);
+  r.o_br = take((size_t)p.n_runs * 4);
+  r.o_be = take((size_t)p.n_runs * 4);
+  r.o_bg = take((size_t)p.n_runs * L.n_genes * 4);
+  r.o_bx = take((size_t)p.n_runs * L.n_atoms * 12);
+  r.bytes = off;
+}
+
+JobDev make_job(md_server* s, const Request& r) {
+  JobDev J{};
+  const md_dock_params& p = r.params;
+  char* w = s->pool_base + r.off;
+  J.L = r.lig->dev;
+  GaDev& P = J.P;
+  P.n_runs = p.n_runs;
+  P.pop_size = p.pop_size;
+  P.n_genes = J.L.n_genes;
+  P.n_ls = n_local_search_of(&p);
+  P.ls_iters = p.ls_iters;
+  P.elitism = p.elitism;
+  P.rho = p.rho;
+  P.eps = p.eps;
+  P.crossover_rate = p.crossover_rate;
+  P.mutation_rate = p.mutation_rate;
+  P.tournament_rate = p.tournament_rate;
+  P.mut_trans = p.mut_trans;
+  P.mut_rot = p.mut_rot;
+  P.mut_tors = p.mut_tors;
+  P.seed = p.seed;
+  J.genes[0] = reinterpret_cast<float*>(w + r.o_ga);
+  J.genes[1] = reinterpret_cast<float*>(w + r.o_gb);
+  J.energy[0] = reinterpret_cast<float*>(w + r.o_ea);
+  J.energy[1] = reinterpret_cast<float*>(w + r.o_eb);
+  J.evals = reinterpret_cast<int*>(w + r.o_ev);
+  J.evals_of_runs = reinterpret_cast<long long*>(w + r.o_er);
+  J.ls_rows = reinterpret_cast<int*>(w + r.o_lsr);
+  J.best_row = reinterpret_cast<int*>(w + r.o_br);
+  J.best_energy = reinterpret_cast<float*>(w + r.o_be);
+  J.best_genes = reinterpret_cast<float*>(w + r.o_bg);
+  J.gen = 0;
+  J.cur = 0;
+  J.planned = r.planned;
+  J.state = kJobInit;
+  return J;
+}
+
+// One tick: every resident request advances by one phase sequence.  Returns the HIP status.
+hipError_t run_tick(md_server* s, bool any_init, bool any_running) {
+  std::vector<int2> pop[2], ls[2], run;
+  int lds_pop[2] = {0, 0}, lds_ls[2] = {0, 0};
+  const int n_slots = (int)s->slots.size();
+  for (int j = 0; j < n_slots; ++j) {
+    const auto& r = s->slots[j];
+    if (!r) continue;
+    const LigDev& L = r->lig->dev;
+    const md_dock_params& p = r->params;
+    const int b = L.n_atoms > kWave ? 1 : 0;
+    const long long rows = (long long)p.n_runs * p.pop_size;
+    const int n_ls = n_local_search_of(&p);
+    for (long long w = 0; w < rows; w += kWavesPerBlock) pop[b].push_back(make_int2(j, (int)w));
+    for (long long w = 0; w < (long long)p.n_runs * n_ls; w += kWavesPerBlock) ls[b].push_back(make_int2(j, (int)w));
+    for (int q = 0; q < p.n_runs; q += kWavesPerBlock) run.push_back(make_int2(j, q));
+    lds_pop[b] = std::max(lds_pop[b], L.lds_bytes);
+    if (n_ls > 0) lds_ls[b] = std::max(lds_ls[b], L.lds_bytes);
+  }
+  std::vector<int2> all;
+  size_t bo[6];
+  bo[0] = 0;
+  all.insert(all.end(), pop[0].begin(), pop[0].end()); bo[1] = all.size();
+  all.insert(all.end(), pop[1].begin(), pop[1].end()); bo[2] = all.size();
+  all.insert(all.end(), ls[0].begin(), ls[0].end()); bo[3] = all.size();
+  all.insert(all.end(), ls[1].begin(), ls[1].end()); bo[4] = all.size();
+  all.insert(all.end(), run.begin(), run.end()); bo[5] = all.size();
+  hipError_t e = hipSuccess;
+  if (all.size() > s->blocks_cap) {
+    if (s->d_blocks) (void)hipFree(s->d_blocks);
+    s->blocks_cap = std::max<size_t>(all.size(), 2 * s->blocks_cap);
+    e = hipMalloc(&s->d_blocks, s->blocks_cap * sizeof(int2));
+    if (e != hipSuccess) {
+      s->d_blocks = nullptr;
+      s->blocks_cap = 0;
+      return e;
+    }
+  }
+  if (!all.empty()) e = hipMemcpyAsync(s->d_blocks, all.data(), all.size() * sizeof(int2), hipMemcpyHostToDevice, s->stream);
+  const RecDev& R = s->rec->dev;
+  for (int b = 0; b < 2 && e == hipSuccess && any_init; ++b)
+    e = launch_ga_init(s->d_table, s->d_blocks + bo[b], (int)(bo[b + 1] - bo[b]), b + 1, lds_pop[b], R, s->stream);
+  if (any_running) {
+    for (int b = 0; b < 2 && e == hipSuccess; ++b)
+      e = launch_ga_generation(s->d_table, s->d_blocks + bo[b], (int)(bo[b + 1] - bo[b]), b + 1, lds_pop[b], R, s->stream);
+    if (e == hipSuccess) e = launch_ga_ls_pick(s->d_table, s->d_blocks + bo[4], (int)(bo[5] - bo[4]), s->stream);
+    for (int b = 0; b < 2 && e == hipSuccess; ++b)
+      e = launch_ga_local_search(s->d_table, s->d_blocks + bo[2 + b], (int)(bo[3 + b] - bo[2 + b]), b + 1,
+                                 lds_ls[b], R, s->stream);
+  }
+  if (e == hipSuccess) e = launch_ga_advance(s->d_table, n_slots, s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->h_table, s->d_table, sizeof(JobDev) * n_slots, hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  return e;
+}
+
+// Copy a finished request's results to the host (called by the worker, stream idle).
+hipError_t collect(md_server* s, Request& r) {
+  const LigDev& L = r.lig->dev;
+  const int runs = r.params.n_runs, G = L.n_genes, N = L.n_atoms;
+  char* w = s->pool_base + r.off;
+  hipError_t e = launch_pose(L, runs, reinterpret_cast<float*>(w + r.o_bg), reinterpret_cast<float*>(w + r.o_bx), s->stream);
+  std::vector<float> be(runs), bg((size_t)runs * G), bx((size_t)runs * N * 3);
+  std::vector<long long> er(runs);
+  if (e == hipSuccess) e = hipMemcpyAsync(be.data(), w + r.o_be, runs * 4, hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(bg.data(), w + r.o_bg, bg.size() * 4, hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(bx.data(), w + r.o_bx, bx.size() * 4, hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(er.data(), w + r.o_er, runs * 8, hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return e;
+  std::vector<int> order(runs);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return be[a] < be[b]; });
+  r.best_energy.resize(runs);
+  r.best_genes.resize((size_t)runs * G);
+  r.best_xyz.resize((size_t)runs * N * 3);
+  r.run_index.resize(runs);
+  r.evals.resize(runs);
+  for (int k = 0; k < runs; ++k) {
+    const int q = order[k];
+    r.best_energy[k] = be[q];
+    std::memcpy(&r.best_genes[(size_t)k * G], &bg[(size_t)q * G], (size_t)G * 4);
+    std::memcpy(&r.best_xyz[(size_t)k * N * 3], &bx[(size_t)q * N * 3], (size_t)N * 12);
+    r.run_index[k] = q;
+    r.evals[k] = er[q];
+  }
+  return hipSuccess;
+}
+
+void worker_loop(md_server* s) {
+  (void)hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (true) {
+    // admit queued requests into free slots while their buffers fit in the pool
+    std::vector<int> admitted;
+    for (int j = 0; j < (int)s->slots.size() && !s->queue.empty(); ++j) {
+      if (s->slots[j]) continue;
+      auto r = s->queue.front();
+      size_t off;
+      if (!s->pool->alloc(r->bytes, &off)) break;    // head of line waits for memory
+      s->queue.pop_front();
+      r->off = off;
+      r->slot = j;
+      r->state = kResident;
+      r->t_start = now_s();
+      s->slots[j] = r;
+      s->h_table[j] = make_job(s, *r);
+      admitted.push_back(j);
+    }
+    bool any = false, any_init = !admitted.empty(), any_running = false;
+    for (auto& r : s->slots)
+      if (r) {
+        any = true;
+        if (s->h_table[r->slot].state == kJobRunning) any_running = true;
+      }
+    if (!any) {
+      if (s->stop) break;
+      s->cv_work.wait(lk);
+      continue;
+    }
+    // upload new slots' job entries, run one tick without holding the lock
+    std::vector<std::pair<int, JobDev>> uploads;
+    for (int j : admitted) uploads.push_back({j, s->h_table[j]});
+    lk.unlock();
+    const double t0 = now_s();
+    hipError_t e = hipSuccess;
+    for (auto& u : uploads)
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(s->d_table + u.first, &u.second, sizeof(JobDev), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess) e = run_tick(s, any_init, any_running);
+    std::vector<std::shared_ptr<Request>> finished;
+    if (e == hipSuccess) {
+      for (auto& r : s->slots)
+        if (r && s->h_table[r->slot].state == kJobDone) finished.push_back(r);
+      for (auto& r : finished)
+        if (e == hipSuccess) e = collect(s, *r);
+    }
+    const double t1 = now_s();
+    lk.lock();
+    s->busy_s += t1 - t0;
+    ++s->ticks;
+    if (e != hipSuccess) {
+      s->fatal = std::string("device error in the serving loop: ") + hipGetErrorString(e);
+      for (auto& r : s->slots)
+        if (r) {
+          r->state = kFailed;
+          r->error = s->fatal;
+        }
+      for (auto& r : s->queue) {
+        r->state = kFailed;
+        r->error = s->fatal;
+      }
+      s->queue.clear();
+      std::fill(s->slots.begin(), s->slots.end(), nullptr);
+      s->cv_done.notify_all();
+      break;
+    }
+    for (auto& r : finished) {
+      r->t_end = t1;
+      if (r->state == kResident) {
+        r->state = kFinished;
+        ++s->completed;
+      }
+      s->pool->release(r->off, r->bytes);
+      s->slots[r->slot] = nullptr;
+      s->h_table[r->slot].state = kJobEmpty;
+    }
+    // requests canceled while resident: drop them from their slots (device entry marked empty)
+    for (int j = 0; j < (int)s->slots.size(); ++j) {
+      auto& r = s->slots[j];
+      if (r && r->state == kCanceled) {
+        JobDev empty{};
+        empty.state = kJobEmpty;
+        s->h_table[j] = empty;
+        (void)hipMemcpy(s->d_table + j, &empty, sizeof(JobDev), hipMemcpyHostToDevice);
+        s->pool->release(r->off, r->bytes);
+        r = nullptr;
+      }
+    }
+    if (!finished.empty()) s->cv_done.notify_all();
+  }
+}
+
+md_status fill_result(const Request& r, md_dock_result* out) {
+  const int runs = r.params.n_runs, G = r.lig->dev.n_genes, N = r.lig->dev.n_atoms;
+  if (out->n_runs < runs || out->n_genes < G || !out->best_energy || !out->best_genes)
+    return server_fail(MD_EINVAL, "md_server: result buffers too small or null");
+  if (out->best_xyz && out->n_atoms < N) return server_fail(MD_EINVAL, "md_server: best_xyz capacity too small");
+  for (int k = 0; k < runs; ++k) {
+    out->best_energy[k] = r.best_energy[k];
+    std::memcpy(out->best_genes + (size_t)k * out->n_genes, &r.best_genes[(size_t)k * G], (size_t)G * 4);
+    if (out->best_xyz)
+      std::memcpy(out->best_xyz + (size_t)k * out->n_atoms * 3, &r.best_xyz[(size_t)k * N * 3], (size_t)N * 12);
+    if (out->run_index) out->run_index[k] = r.run_index[k];
+    if (out->evals) out->evals[k] = r.evals[k];
+    if (out->generations) out->generations[k] = r.planned;
+  }
+  return MD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+md_status md_server_create(const md_receptor* rec, const md_server_params* p, md_server** out) {
+  if (!rec || !p || !out) return server_fail(MD_EINVAL, "md_server_create: null argument");
+  if (p->max_slots < 1 || p->max_slots > 4096) return server_fail(MD_ERANGE, "md_server_create: max_slots must be in [1, 4096]");
+  if (p->hbm_budget_bytes < (1u << 20)) return server_fail(MD_EINVAL, "md_server_create: hbm_budget_bytes must be >= 1 MiB");
+  auto* s = new (std::nothrow) md_server();
+  if (!s) return server_fail(MD_ENOMEM, "md_server_create: out of host memory");
+  s->rec = rec;
+  s->params = *p;
+  hipError_t e = hipGetDevice(&s->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s->pool_base), p->hbm_budget_bytes);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s->d_table), sizeof(JobDev) * p->max_slots);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&s->h_table), sizeof(JobDev) * p->max_slots);
+  if (e != hipSuccess) {
+    if (s->pool_base) (void)hipFree(s->pool_base);
+    if (s->d_table) (void)hipFree(s->d_table);
+    if (s->h_table) (void)hipHostFree(s->h_table);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+    return e == hipErrorOutOfMemory ? server_fail(MD_ENOMEM, "md_server_create: out of device memory")
+                                    : server_fail(MD_EDEVICE, std::string("md_server_create: ") + hipGetErrorString(e));
+  }
+  for (int j = 0; j < p->max_slots; ++j) {
+    JobDev empty{};
+    empty.state = kJobEmpty;
+    s->h_table[j] = empty;
+  }
+  e = hipMemcpy(s->d_table, s->h_table, sizeof(JobDev) * p->max_slots, hipMemcpyHostToDevice);
+  s->pool.reset(new Pool(p->hbm_budget_bytes));
+  s->slots.assign(p->max_slots, nullptr);
+  s->worker = std::thread(worker_loop, s);
+  *out = s;
+  return e == hipSuccess ? MD_OK : server_fail(MD_EDEVICE, "md_server_create: table upload failed");
+}
+
+md_status md_server_submit(md_server* s, const md_ligand* lig, const md_dock_params* p, unsigned long long* ticket) {
+  if (!s || !lig || !p || !ticket) return server_fail(MD_EINVAL, "md_server_submit: null argument");
+  const std::string err = check_dock_params(p);
+  if (!err.empty()) return server_fail(MD_EINVAL, "md_server_submit: " + err);
+  auto r = std::make_shared<Request>();
+  r->lig = lig;
+  r->params = *p;
+  r->planned = md_dock_planned_generations(p);
+  layout(*r);
+  if (r->bytes > s->params.hbm_budget_bytes)
+    return server_fail(MD_ENOMEM, "md_server_submit: request needs more device memory than the server's budget");
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (!s->fatal.empty()) return server_fail(MD_EDEVICE, s->fatal);
+  r->ticket = s->next_ticket++;
+  r->t_submit = now_s();
+  s->requests[r->ticket] = r;
+  s->queue.push_back(r);
+  *ticket = r->ticket;
+  s->cv_work.notify_one();
+  return MD_OK;
+}
+
+md_status md_server_poll(md_server* s, unsigned long long ticket, md_dock_result* out, int* done) {
+  if (!s || !done) return server_fail(MD_EINVAL, "md_server_poll: null argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->requests.find(ticket);
+  if (it == s->requests.end()) return server_fail(MD_ENOTFOUND, "md_server_poll: unknown ticket");
+  const Request& r = *it->second;
+  *done = (r.state == kFinished || r.state == kCanceled || r.state == kFailed) ? 1 : 0;
+  if (r.state == kCanceled) return server_fail(MD_ECANCELED, "md_server_poll: request was canceled");
+  if (r.state == kFailed) return server_fail(MD_EDEVICE, r.error);
+  if (r.state == kFinished && out) return fill_result(r, out);
+  return MD_OK;
+}
+
+md_status md_server_wait(md_server* s, unsigned long long ticket, md_dock_result* out, double timeout_s) {
+  if (!s) return server_fail(MD_EINVAL, "md_server_wait: null server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->requests.find(ticket);
+  if (it == s->requests.end()) return server_fail(MD_ENOTFOUND, "md_server_wait: unknown ticket");
+  std::shared_ptr<Request> r = it->second;
+  auto finished = [&] { return r->state == kFinished || r->state == kCanceled || r->state == kFailed; };
+  if (timeout_s < 0) {
+    s->cv_done.wait(lk, finished);
+  } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), finished)) {
+    return server_fail(MD_EBUSY, "md_server_wait: timed out");
+  }
+  if (r->state == kCanceled) return server_fail(MD_ECANCELED, "md_server_wait: request was canceled");
+  if (r->state == kFailed) return server_fail(MD_EDEVICE, r->error);
+  return out ? fill_result(*r, out) : MD_OK;
+}
+
+md_status md_server_cancel(md_server* s, unsigned long long ticket) {
+  if (!s) return server_fail(MD_EINVAL, "md_server_cancel: null server");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->requests.find(ticket);
+  if (it == s->requests.end()) return server_fail(MD_ENOTFOUND, "md_server_cancel: unknown ticket");
+  auto& r = it->second;
+  if (r->state == kQueued) {
+    s->queue.erase(std::remove(s->queue.begin(), s->queue.end(), r), s->queue.end());
+    r->state = kCanceled;
+  } else if (r->state == kResident) {
+    r->state = kCanceled;   // the worker frees the slot after the current tick
+  }
+  s->cv_done.notify_all();
+  return MD_OK;
+}
+
+md_status md_server_request_times(md_server* s, unsigned long long ticket, double* submit_s, double* start_s,
+                                  double* end_s) {
+  if (!s) return server_fail(MD_EINVAL, "md_server_request_times: null server");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->requests.find(ticket);
+  if (it == s->requests.end()) return server_fail(MD_ENOTFOUND, "md_server_request_times: unknown ticket");
+  if (submit_s) *submit_s = it->second->t_submit;
+  if (start_s) *start_s = it->second->t_start;
+  if (end_s) *end_s = it->second->t_end;
+  return MD_OK;
+}
+
+md_status md_server_release(md_server* s, unsigned long long ticket) {
+  if (!s) return server_fail(MD_EINVAL, "md_server_release: null server");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->requests.find(ticket);
+  if (it == s->requests.end()) return server_fail(MD_ENOTFOUND, "md_server_release: unknown ticket");
+  const ReqState st = it->second->state;
+  if (st == kQueued || st == kResident) return server_fail(MD_EBUSY, "md_server_release: request still running");
+  s->requests.erase(it);
+  return MD_OK;
+}
+
+md_status md_server_get_stats(md_server* s, md_server_stats* out) {
+  if (!s || !out) return server_fail(MD_EINVAL, "md_server_get_stats: null argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  out->ticks = s->ticks;
+  out->completed = s->completed;
+  out->queued = (int)s->queue.size();
+  int resident = 0;
+  for (auto& r : s->slots) resident += r ? 1 : 0;
+  out->resident = resident;
+  out->pool_used_bytes = s->pool->used();
+  out->busy_seconds = s->busy_s;
+  return MD_OK;
+}
+
+md_status md_server_destroy(md_server* s) {
+  if (!s) return MD_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    for (auto& r : s->queue) r->state = kCanceled;   // queued work is dropped, resident work drains
+    s->queue.clear();
+    s->cv_work.notify_all();
+  }
+  if (s->worker.joinable()) s->worker.join();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->cv_done.notify_all();
+  }
+  if (s->d_blocks) (void)hipFree(s->d_blocks);
+  (void)hipFree(s->d_table);
+  (void)hipHostFree(s->h_table);
+  (void)hipFree(s->pool_base);
+  (void)hipStreamDestroy(s->stream);
+  delete s;
+  return MD_OK;
+}
+
+}  // extern "C"

@@ -54,6 +54,15 @@ class DockResult(C.Structure):
                 ("evals", C.POINTER(C.c_longlong)), ("generations", C.POINTER(C.c_int))]
 
 
+class ServerParams(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("ticks", C.c_longlong), ("completed", C.c_longlong), ("queued", C.c_int),
+                ("resident", C.c_int), ("pool_used_bytes", C.c_size_t), ("busy_seconds", C.c_double)]
+
+
 class DockJob(C.Structure):
     _fields_ = [("ligand", C.c_void_p), ("params", DockParams), ("result", C.POINTER(DockResult))]
 
@@ -75,6 +84,16 @@ SIGNATURES = {
     "md_dock": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(DockParams), C.POINTER(DockResult), C.c_void_p]),
     "md_dock_batch": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(DockJob), C.c_void_p]),
     "md_dock_planned_generations": (C.c_int, [C.POINTER(DockParams)]),
+    "md_server_create": (C.c_int, [C.c_void_p, C.POINTER(ServerParams), C.POINTER(C.c_void_p)]),
+    "md_server_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(DockParams), C.POINTER(C.c_ulonglong)]),
+    "md_server_poll": (C.c_int, [C.c_void_p, C.c_ulonglong, C.POINTER(DockResult), C.POINTER(C.c_int)]),
+    "md_server_wait": (C.c_int, [C.c_void_p, C.c_ulonglong, C.POINTER(DockResult), C.c_double]),
+    "md_server_cancel": (C.c_int, [C.c_void_p, C.c_ulonglong]),
+    "md_server_request_times": (C.c_int, [C.c_void_p, C.c_ulonglong, C.POINTER(C.c_double),
+                                          C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "md_server_release": (C.c_int, [C.c_void_p, C.c_ulonglong]),
+    "md_server_get_stats": (C.c_int, [C.c_void_p, C.POINTER(ServerStats)]),
+    "md_server_destroy": (C.c_int, [C.c_void_p]),
     "md_ligand_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                  C.POINTER(C.c_int)]),
     "md_profile_enable": (C.c_int, [C.c_int]),
@@ -304,3 +323,64 @@ def md_profile_read(kind):
     ms, n = C.c_double(), C.c_longlong()
     _check(lib().md_profile_read(KERNELS.get(kind, kind), C.byref(ms), C.byref(n)), "md_profile_read")
     return ms.value, n.value
+
+
+class Server:
+    """Continuous-batching docking server (md_server_*).  Keep the receptor and every submitted
+    Ligand alive while the server runs."""
+
+    def __init__(self, rec: Receptor, hbm_budget_bytes=1 << 30, max_slots=64):
+        h = C.c_void_p()
+        p = ServerParams(int(hbm_budget_bytes), int(max_slots))
+        _check(lib().md_server_create(rec.handle, C.byref(p), C.byref(h)), "md_server_create")
+        self.handle = h
+        self._rec = rec
+        self._ligs = {}
+
+    def submit(self, lig: Ligand, params: DockParams) -> int:
+        t = C.c_ulonglong()
+        _check(lib().md_server_submit(self.handle, lig.handle, C.byref(params), C.byref(t)), "md_server_submit")
+        self._ligs[t.value] = (lig, params)
+        return t.value
+
+    def wait(self, ticket: int, timeout_s: float = -1.0, want_xyz=True):
+        lig, params = self._ligs[ticket]
+        res, arrs = _result(params, lig, want_xyz)
+        _check(lib().md_server_wait(self.handle, ticket, C.byref(res), float(timeout_s)), "md_server_wait")
+        return arrs
+
+    def poll(self, ticket: int, want_xyz=True):
+        lig, params = self._ligs[ticket]
+        res, arrs = _result(params, lig, want_xyz)
+        done = C.c_int()
+        _check(lib().md_server_poll(self.handle, ticket, C.byref(res), C.byref(done)), "md_server_poll")
+        return arrs if done.value else None
+
+    def cancel(self, ticket: int):
+        _check(lib().md_server_cancel(self.handle, ticket), "md_server_cancel")
+
+    def times(self, ticket: int):
+        a, b, c = C.c_double(), C.c_double(), C.c_double()
+        _check(lib().md_server_request_times(self.handle, ticket, C.byref(a), C.byref(b), C.byref(c)),
+               "md_server_request_times")
+        return a.value, b.value, c.value
+
+    def release(self, ticket: int):
+        _check(lib().md_server_release(self.handle, ticket), "md_server_release")
+        self._ligs.pop(ticket, None)
+
+    def stats(self):
+        st = ServerStats()
+        _check(lib().md_server_get_stats(self.handle, C.byref(st)), "md_server_get_stats")
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.md_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
