@@ -185,7 +185,7 @@ md_status md_ligand_create(const md_ligand_desc* d, md_ligand** out) {
     return fail(range ? MD_ERANGE : MD_EINVAL, "md_ligand_create: " + err);
   }
   const LigHost& h = l->host;
-  const size_t N = h.n_atoms, T = h.n_tors, P = h.pair_ij.size();
+  const size_t N = h.n_atoms, T = h.n_tors, S = h.pair_ij.size();   // S: scheduled slots
   size_t off = 0;
   const size_t o_p0q = off; off = align16(off + N * sizeof(float4));
   const size_t o_type = off; off = align16(off + N * sizeof(int));
@@ -194,10 +194,8 @@ md_status md_ligand_create(const md_ligand_desc* d, md_ligand** out) {
   const size_t o_piv = off; off = align16(off + T * sizeof(float4));
   const size_t o_ab = off; off = align16(off + T * sizeof(int2));
   const size_t o_gene = off; off = align16(off + T * sizeof(int));
-  const size_t o_ij = off; off = align16(off + P * sizeof(uint32_t));
-  const size_t o_coef = off; off = align16(off + P * sizeof(float4));
-  const size_t o_rows = off; off = align16(off + h.inc_rows.size() * sizeof(int2));
-  const size_t o_inc = off; off = align16(off + h.inc.size() * sizeof(uint16_t));
+  const size_t o_ij = off; off = align16(off + S * sizeof(uint32_t));
+  const size_t o_coef = off; off = align16(off + S * sizeof(float4));
   std::vector<char> buf(std::max<size_t>(off, 16), 0);
   auto put = [&](size_t o, const void* p, size_t n) { if (n) std::memcpy(buf.data() + o, p, n); };
   put(o_p0q, h.atom_p0q.data(), N * sizeof(float4));
@@ -207,10 +205,8 @@ md_status md_ligand_create(const md_ligand_desc* d, md_ligand** out) {
   put(o_piv, h.tor_pivot.data(), T * sizeof(float4));
   put(o_ab, h.tor_ab.data(), T * sizeof(int2));
   put(o_gene, h.tor_gene.data(), T * sizeof(int));
-  put(o_ij, h.pair_ij.data(), P * sizeof(uint32_t));
-  put(o_coef, h.pair_coef.data(), P * sizeof(float4));
-  put(o_rows, h.inc_rows.data(), h.inc_rows.size() * sizeof(int2));
-  put(o_inc, h.inc.data(), h.inc.size() * sizeof(uint16_t));
+  put(o_ij, h.pair_ij.data(), S * sizeof(uint32_t));
+  put(o_coef, h.pair_coef.data(), S * sizeof(float4));
   hipError_t e = hipGetDevice(&l->device);
   if (e == hipSuccess) e = hipMalloc(&l->d_buf, buf.size());
   if (e == hipSuccess) e = hipMemcpy(l->d_buf, buf.data(), buf.size(), hipMemcpyHostToDevice);
@@ -223,7 +219,7 @@ md_status md_ligand_create(const md_ligand_desc* d, md_ligand** out) {
   LigDev& L = l->dev;
   L.n_atoms = (int)N;
   L.n_tors = (int)T;
-  L.n_pairs = (int)P;
+  L.n_pairs = h.n_pairs;
   L.n_genes = h.n_genes;
   L.atom_p0q = reinterpret_cast<const float4*>(b + o_p0q);
   L.atom_type = reinterpret_cast<const int*>(b + o_type);
@@ -234,15 +230,11 @@ md_status md_ligand_create(const md_ligand_desc* d, md_ligand** out) {
   L.tor_gene = reinterpret_cast<const int*>(b + o_gene);
   L.pair_ij = reinterpret_cast<const uint32_t*>(b + o_ij);
   L.pair_coef = reinterpret_cast<const float4*>(b + o_coef);
-  L.chunk = h.chunk;
-  L.n_chunks = h.n_chunks;
-  L.pl = h.pl;
-  L.inc_lds = h.inc_lds;
-  L.inc_stride = h.inc_stride;
-  L.inc_total = h.inc_rows.empty() ? 0 : h.inc_rows.back().x + h.inc_rows.back().y;
+  L.n_rows = h.n_rows;
+  L.pl_rows = h.pl_rows;
+  L.group_lanes = h.group_lanes;
+  L.n_copies = h.n_copies;
   L.lds_bytes = h.lds_bytes;
-  L.inc_rows = reinterpret_cast<const int2*>(b + o_rows);
-  L.inc = reinterpret_cast<const uint16_t*>(b + o_inc);
   *out = l;
   return MD_OK;
 }

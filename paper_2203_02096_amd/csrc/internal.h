@@ -17,14 +17,14 @@ constexpr int kTypes = 7;
 constexpr int kMaps = kTypes + 2;
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
-// LDS plan of a ligand: pairs are processed in chunks of `chunk`; each chunk's pair forces are
-// kept in LDS and gathered per atom through that chunk's incidence table before the next chunk.
-// The first `pl` pair records (and the incidence tables, when small) are staged in LDS once per
+// Pair schedule of a ligand: the intramolecular pairs are laid out in rows of 64 (one pair per
+// lane).  The lanes of a row form groups of `group_lanes` consecutive lanes, and within a group
+// no atom occurs twice in a row, so every lane can add its pair's force into its group's copy of
+// the per-atom force array with a plain read-modify-write (no atomics, no conflicts); the copies
+// are summed per atom once per evaluation.  The first `pl_rows` rows are staged in LDS once per
 // block; the plan keeps a block's dynamic LDS within kLdsBudget.
 constexpr size_t kLdsBudget = 65536;
-constexpr size_t kIncLdsMax = 16384;
-constexpr int kChunkMax = 1024;
-constexpr uint32_t kIncNone = 0xffffu;
+constexpr uint32_t kPairPad = 1u << 17;   // empty slot of a row: zero coefficients, no force
 
 // Scoring constants (AutoDock4 force-field forms and weights).
 constexpr float kWvdw = 0.1662f;
@@ -56,18 +56,14 @@ struct LigDev {
   const float4* tor_pivot;    // [T] reference position of the root-side atom a
   const int2* tor_ab;         // [T] atoms (a, b)
   const int* tor_gene;        // [T] gene index (7 + caller's torsion index)
-  const uint32_t* pair_ij;    // [P] i | j << 8 | hbond << 16
-  const float4* pair_coef;    // [P] weighted C12, weighted C6 or C10, W_el*332*qi*qj,
-                              //     W_ds*(S_i V_j + S_j V_i)
-  int chunk, n_chunks;        // pairs per chunk, number of chunks
-  int pl;                     // pair records staged in LDS (a prefix of the list)
-  int inc_lds;                // incidence tables staged in LDS (1) or read from global memory (0)
-  int inc_stride;             // 64 * atoms per lane
-  int inc_total;              // rows of all chunks' incidence tables
+  const uint32_t* pair_ij;    // [n_rows*64] i | j << 8 | hbond << 16 (| kPairPad)
+  const float4* pair_coef;    // [n_rows*64] weighted C12, weighted C6 or C10, W_el*332*qi*qj,
+                              //     W_ds*(S_i V_j + S_j V_i); zero in empty slots
+  int n_rows;                 // rows of 64 pair slots
+  int pl_rows;                // rows staged in LDS (a prefix)
+  int group_lanes;            // lanes per conflict-free group
+  int n_copies;               // force-array copies (groups in use)
   int lds_bytes;              // dynamic LDS of one block
-  const int2* inc_rows;       // [n_chunks] first row and number of rows of each chunk's table
-  const uint16_t* inc;        // [inc_total][inc_stride]: index in chunk | (second atom) << 15,
-                              // or kIncNone
 };
 
 struct RecDev {
@@ -118,24 +114,18 @@ struct LigHost {
   std::vector<float4> tor_axis, tor_pivot;
   std::vector<int2> tor_ab;
   std::vector<int> tor_gene;
-  std::vector<uint32_t> pair_ij;
+  std::vector<uint32_t> pair_ij;   // scheduled rows, padded (see LigDev)
   std::vector<float4> pair_coef;
-  int chunk = 1, n_chunks = 0, pl = 0, inc_lds = 1, inc_stride = 64, lds_bytes = 0;
-  std::vector<int2> inc_rows;
-  std::vector<uint16_t> inc;
+  int n_pairs = 0, n_rows = 0, pl_rows = 0, group_lanes = 64, n_copies = 1, lds_bytes = 0;
 };
 
 // LDS layout helpers shared by the host plan and the kernels.
 __host__ __device__ inline size_t lds_align16(size_t v) { return (v + 15) & ~size_t(15); }
-__host__ __device__ inline size_t lds_wave_bytes(int chunk, int A) {
-  return (size_t)16 * kWave * A + 3 * lds_align16((size_t)chunk * 4);
+// per wave: posed coordinates [64*A] and the force-array copies [n_copies][n_atoms], float4 each
+__host__ __device__ inline size_t lds_wave_bytes(int n_atoms, int n_copies, int A) {
+  return (size_t)16 * kWave * A + (size_t)16 * n_copies * n_atoms;
 }
-__host__ __device__ inline size_t lds_pairs_bytes(int pl) {
-  return lds_align16((size_t)pl * 16) + lds_align16((size_t)pl * 4);
-}
-__host__ __device__ inline size_t lds_inc_bytes(int rows, int stride) {
-  return lds_align16((size_t)rows * stride * 2);
-}
+__host__ __device__ inline size_t lds_pairs_bytes(int rows) { return (size_t)rows * kWave * (16 + 4); }
 
 // Returns an empty string on success, else a message; `range_error` tells MD_ERANGE apart.
 std::string prepare_ligand(int n_atoms, const float* xyz, const int* type, const float* charge,

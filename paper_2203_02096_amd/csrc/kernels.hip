@@ -94,55 +94,46 @@ __device__ __forceinline__ float wrap_angle(float th) {
 }
 
 // ------------------------------------------------------------------ LDS layout
-// Dynamic LDS of a block (sizes from the ligand's plan): the staged pair records and, when
-// small, the chunks' incidence tables, shared by the block's waves; then per wave the posed
-// coordinates and the force of each pair of the current chunk on its first atom.
+// Dynamic LDS of a block (sizes from the ligand's plan): the staged pair rows, shared by the
+// block's waves; then per wave the posed coordinates and the force-array copies, one per lane
+// group of the pair schedule.
 struct BlockLds {
-  const float4* pair_coef;   // [pl]
-  const uint32_t* pair_ij;   // [pl]
-  const uint16_t* inc;       // [inc_total][inc_stride], LDS or global
+  const float4* pair_coef;   // [pl_rows*64]
+  const uint32_t* pair_ij;   // [pl_rows*64]
   float4* x;                 // this wave: [64*A] posed x, y, z
-  float* fpx;                // this wave: [chunk] force of each pair on its first atom
-  float* fpy;
-  float* fpz;
+  float4* f;                 // this wave: [n_copies][n_atoms] intramolecular forces
+  float4* fg;                // this lane's group copy
 };
 
 extern __shared__ __align__(16) unsigned char g_lds[];
 
-// All threads of the block stage the shared part, then synchronise.  Must be reached by every
-// wave of the block before any of them leaves.
+// All threads of the block stage the shared part and clear their force copies, then
+// synchronise.  Must be reached by every wave of the block before any of them leaves.
 template <int A>
 __device__ __forceinline__ BlockLds stage_block(const LigDev& L) {
   BlockLds b;
   unsigned char* cur = g_lds;
-  const int pl = L.pl;
+  const int ns = L.pl_rows * kWave;
   float4* pc = reinterpret_cast<float4*>(cur);
-  uint32_t* pij = reinterpret_cast<uint32_t*>(cur + lds_align16((size_t)pl * 16));
-  cur += lds_pairs_bytes(pl);
-  for (int p = threadIdx.x; p < pl; p += blockDim.x) {
+  uint32_t* pij = reinterpret_cast<uint32_t*>(cur + (size_t)ns * 16);
+  cur += lds_pairs_bytes(L.pl_rows);
+  for (int p = threadIdx.x; p < ns; p += blockDim.x) {
     pc[p] = L.pair_coef[p];
     pij[p] = L.pair_ij[p];
   }
-  if (L.inc_lds) {
-    uint16_t* inc = reinterpret_cast<uint16_t*>(cur);
-    const int ne = L.inc_total * L.inc_stride;
-    for (int k = threadIdx.x; k < ne; k += blockDim.x) inc[k] = L.inc[k];
-    b.inc = inc;
-    cur += lds_inc_bytes(L.inc_total, L.inc_stride);
-  } else {
-    b.inc = L.inc;
-  }
-  __syncthreads();
   const int w = threadIdx.x / kWave;
-  cur += (size_t)w * lds_wave_bytes(L.chunk, A);
+  const int lane = lane_id();
+  cur += (size_t)w * lds_wave_bytes(L.n_atoms, L.n_copies, A);
   b.pair_coef = pc;
   b.pair_ij = pij;
   b.x = reinterpret_cast<float4*>(cur);
   cur += (size_t)16 * kWave * A;
-  const size_t cb = lds_align16((size_t)L.chunk * 4);
-  b.fpx = reinterpret_cast<float*>(cur);
-  b.fpy = reinterpret_cast<float*>(cur + cb);
-  b.fpz = reinterpret_cast<float*>(cur + 2 * cb);
+  b.f = reinterpret_cast<float4*>(cur);
+  const int nf = L.n_copies * L.n_atoms;
+  for (int k = lane; k < nf; k += kWave) b.f[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+  const int g = min(lane / L.group_lanes, max(L.n_copies - 1, 0));
+  b.fg = b.f + g * L.n_atoms;
+  __syncthreads();
   return b;
 }
 
@@ -330,54 +321,62 @@ __device__ __forceinline__ float pair_term(float r2, bool hb, float4 c, float& f
   return e;
 }
 
-// One pair.  With GRAD the force on its first atom, (dE/dr / r)(x_i - x_j), goes to the wave's
-// LDS slot, to be gathered per atom with the sign of each end.
+// One pair slot.  With GRAD the pair's force, (dE/dr / r)(x_i - x_j) on i and its negative on
+// j, is added into the lane group's force copy; within a group no atom occurs twice in a row,
+// and a wave's LDS operations complete in order, so the updates never collide.
 template <bool GRAD>
-__device__ __forceinline__ float pair_one(const BlockLds& b, uint32_t ij, float4 c, int slot) {
+__device__ __forceinline__ float pair_one(const BlockLds& b, uint32_t ij, float4 c) {
   const int i = ij & 0xff, j = (ij >> 8) & 0xff;
   const bool hb = (ij >> 16) & 1u;
   const float4 xi = b.x[i], xj = b.x[j];
   const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
   float fr;
   const float e = pair_term(dx * dx + dy * dy + dz * dz, hb, c, fr);
-  if (GRAD) {
-    b.fpx[slot] = fr * dx;
-    b.fpy[slot] = fr * dy;
-    b.fpz[slot] = fr * dz;
+  if (GRAD && !(ij & kPairPad)) {
+    const float fx = fr * dx, fy = fr * dy, fz = fr * dz;
+    float4 fi = b.fg[i], fj = b.fg[j];
+    fi.x += fx;
+    fi.y += fy;
+    fi.z += fz;
+    fj.x -= fx;
+    fj.y -= fy;
+    fj.z -= fz;
+    b.fg[i] = fi;
+    b.fg[j] = fj;
   }
   return e;
 }
 
-// Pairs [p0, p1) of the list (p0 a multiple of 64), strided over lanes two at a time; records
-// from LDS below L.pl,
-// else from global memory (separate loops, so LDS-only chunks carry no global-load waits).
-// slot = pair index - base.  Energies are added to e in pair order, so the sum does not depend
-// on how the list is cut into chunks.
+// All pair rows: the LDS-staged prefix, then the rest from global memory with the next row's
+// records loaded while the current one is evaluated.  Each lane adds its slots' energies in row
+// order, so the energy-only and the gradient paths give the same sum.
 template <bool GRAD>
-__device__ __forceinline__ void pair_range(const LigDev& L, const BlockLds& b, int p0, int p1, int base,
-                                           float& e) {
+__device__ __forceinline__ float pair_rows(const LigDev& L, const BlockLds& b) {
   const int lane = lane_id();
-  const int pm = min(p1, L.pl);
-  for (int p = p0 + lane; p < pm; p += 2 * kWave) {
-    const bool two = p + kWave < pm;
-    const uint32_t ij0 = b.pair_ij[p];
-    const float4 c0 = b.pair_coef[p];
-    const uint32_t ij1 = two ? b.pair_ij[p + kWave] : 0u;
-    const float4 c1 = two ? b.pair_coef[p + kWave] : make_float4(0.f, 0.f, 0.f, 0.f);
-    e += pair_one<GRAD>(b, ij0, c0, p - base);
-    if (two) e += pair_one<GRAD>(b, ij1, c1, p + kWave - base);
+  float e = 0.f;
+  const int pr = L.pl_rows, nr = L.n_rows;
+  for (int r = 0; r < pr; ++r) {
+    const int s = r * kWave + lane;
+    e += pair_one<GRAD>(b, b.pair_ij[s], b.pair_coef[s]);
   }
-  // pair p is always handled by lane p mod 64 (p0 is a multiple of 64), whatever the split
-  const int g0 = max(p0, L.pl);
-  for (int p = g0 + ((lane - g0) & (kWave - 1)); p < p1; p += 2 * kWave) {
-    const bool two = p + kWave < p1;
-    const uint32_t ij0 = L.pair_ij[p];
-    const float4 c0 = L.pair_coef[p];
-    const uint32_t ij1 = two ? L.pair_ij[p + kWave] : 0u;
-    const float4 c1 = two ? L.pair_coef[p + kWave] : make_float4(0.f, 0.f, 0.f, 0.f);
-    e += pair_one<GRAD>(b, ij0, c0, p - base);
-    if (two) e += pair_one<GRAD>(b, ij1, c1, p + kWave - base);
+  if (pr < nr) {
+    int s = pr * kWave + lane;
+    uint32_t ij = L.pair_ij[s];
+    float4 c = L.pair_coef[s];
+    for (int r = pr; r < nr; ++r) {
+      uint32_t ij_n = kPairPad;
+      float4 c_n = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (r + 1 < nr) {
+        ij_n = L.pair_ij[s + kWave];
+        c_n = L.pair_coef[s + kWave];
+      }
+      e += pair_one<GRAD>(b, ij, c);
+      ij = ij_n;
+      c = c_n;
+      s += kWave;
+    }
   }
+  return e;
 }
 
 // ------------------------------------------------------------------ one pose
@@ -456,35 +455,26 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, 
   for (int a = 0; a < A; ++a) grid_fetch<PREC>(R, x[a], y[a], z[a], at.type[a], at.q[a], at.valid[a], gf[a]);
   wave_sync();
 
-  // intramolecular pairs, chunk by chunk; with GRAD each chunk's pair forces are gathered per
-  // atom over the chunk's incidence table (fixed order: deterministic, no atomics)
-  float e_lane = 0.f;
+  // intramolecular pairs; with GRAD each atom then sums (and clears) its force copies
+  float e_lane = pair_rows<GRAD>(L, b);
   float Fx[A], Fy[A], Fz[A];
 #pragma unroll
   for (int a = 0; a < A; ++a) Fx[a] = Fy[a] = Fz[a] = 0.f;
-  const int P = L.n_pairs;
-  if (!GRAD) {
-    pair_range<false>(L, b, 0, P, 0, e_lane);
-  } else {
-    for (int c = 0; c < L.n_chunks; ++c) {
-      const int c0 = c * L.chunk;
-      pair_range<true>(L, b, c0, min(P, c0 + L.chunk), c0, e_lane);
-      wave_sync();
-      const int2 rows = L.inc_rows[c];
-      for (int t = rows.x; t < rows.x + rows.y; ++t) {
+  if (GRAD) {
+    wave_sync();
+    const int N = L.n_atoms, K = L.n_copies;
 #pragma unroll
-        for (int a = 0; a < A; ++a) {
-          const uint32_t e = b.inc[t * L.inc_stride + lane + kWave * a];
-          if (e != kIncNone) {
-            const uint32_t p = e & 0x7fffu;
-            const float sg = (e & 0x8000u) ? -1.f : 1.f;
-            Fx[a] += sg * b.fpx[p];
-            Fy[a] += sg * b.fpy[p];
-            Fz[a] += sg * b.fpz[p];
-          }
+    for (int a = 0; a < A; ++a) {
+      if (at.valid[a]) {
+        const int i = lane + kWave * a;
+        for (int g = 0; g < K; ++g) {
+          const float4 v = b.f[g * N + i];
+          Fx[a] += v.x;
+          Fy[a] += v.y;
+          Fz[a] += v.z;
+          b.f[g * N + i] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
       }
-      wave_sync();
     }
   }
 

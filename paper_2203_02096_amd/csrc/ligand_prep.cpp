@@ -179,67 +179,73 @@ std::string prepare_ligand(int n, const float* xyz, const int* type, const float
       out.pair_coef.push_back(make_float4((float)c12, (float)cn, (float)qq, (float)ds));
     }
   }
-  // Interleave the pairs round-robin over their first atom, so that the 64 pairs a wavefront
-  // handles at once touch mostly distinct atoms (their force updates then rarely hit the same
-  // LDS address at the same time).
-  {
-    std::vector<std::vector<size_t>> by_i(n);
-    for (size_t p = 0; p < out.pair_ij.size(); ++p) by_i[out.pair_ij[p] & 0xff].push_back(p);
-    std::vector<uint32_t> ij;
-    std::vector<float4> coef;
-    ij.reserve(out.pair_ij.size());
-    coef.reserve(out.pair_ij.size());
-    for (size_t round = 0; ij.size() < out.pair_ij.size(); ++round)
-      for (int i = 0; i < n; ++i)
-        if (round < by_i[i].size()) {
-          ij.push_back(out.pair_ij[by_i[i][round]]);
-          coef.push_back(out.pair_coef[by_i[i][round]]);
-        }
-    out.pair_ij.swap(ij);
-    out.pair_coef.swap(coef);
-  }
-  // LDS plan and incidence tables.  Chunk size: all pairs when they fit, else halved until the
-  // per-wave force buffers of a block fit the budget.  Each chunk's table lists, for every
-  // atom, the chunk's pairs it belongs to with the sign of its end, one column per atom so that
-  // a wavefront reads a row in one access.
+  // Pair schedule: rows of 64 slots, lanes split into groups of about N/3 lanes in which no atom
+  // occurs twice per row (so the kernel's per-group force updates never collide).  Greedy row by
+  // row: the remaining pairs whose atoms have the most pairs left go first, each into the first
+  // group where both of its atoms are still free.  Empty slots are padding records.
   {
     const int P = (int)out.pair_ij.size();
     const int A = n > kWave ? 2 : 1;
-    out.inc_stride = kWave * A;
-    int C = std::max(1, std::min(P, kChunkMax));
-    while (C > 64 && (size_t)kWavesPerBlock * lds_wave_bytes(C, A) > kLdsBudget * 5 / 8) C = (C + 1) / 2;
-    // several chunks: a multiple of the wavefront width, so every pair stays on the lane it has
-    // in a single pass over the list (the energy-only path) and the sums agree bitwise
-    if (C < P) C = std::max(kWave, C / kWave * kWave);
-    out.chunk = C;
-    out.n_chunks = P == 0 ? 0 : (P + C - 1) / C;
-    out.inc_rows.clear();
-    out.inc.clear();
-    int total = 0;
-    for (int c = 0; c < out.n_chunks; ++c) {
-      const int c0 = c * C, c1 = std::min(P, c0 + C);
-      std::vector<std::vector<uint16_t>> per(n);
-      for (int p = c0; p < c1; ++p) {
-        const uint32_t i = out.pair_ij[p] & 0xff, j = (out.pair_ij[p] >> 8) & 0xff;
-        per[i].push_back((uint16_t)(p - c0));              // first atom: +force
-        per[j].push_back((uint16_t)((p - c0) | 0x8000));   // second atom: -force
-      }
-      size_t w = 0;
-      for (auto& v : per) w = std::max(w, v.size());
-      out.inc_rows.push_back(make_int2(total, (int)w));
-      out.inc.resize((size_t)(total + (int)w) * out.inc_stride, (uint16_t)kIncNone);
-      for (int a = 0; a < n; ++a)
-        for (size_t t = 0; t < per[a].size(); ++t) out.inc[(total + t) * out.inc_stride + a] = per[a][t];
-      total += (int)w;
+    const int want = std::max(1, std::min(kWave, n / 3));
+    const int K = (kWave + want - 1) / want;
+    const int m = (kWave + K - 1) / K;
+    std::vector<int> left(n, 0);
+    for (uint32_t v : out.pair_ij) {
+      ++left[v & 0xff];
+      ++left[(v >> 8) & 0xff];
     }
-    const size_t waves = (size_t)kWavesPerBlock * lds_wave_bytes(C, A);
-    const size_t ib = lds_inc_bytes(total, out.inc_stride);
-    out.inc_lds = (ib <= kIncLdsMax && waves + ib <= kLdsBudget) ? 1 : 0;
-    const size_t fixed = waves + (out.inc_lds ? ib : 0);
-    int pl = P;
-    while (pl > 0 && fixed + lds_pairs_bytes(pl) > kLdsBudget) pl = std::max(0, pl - 64);
-    out.pl = pl;
-    out.lds_bytes = (int)(fixed + lds_pairs_bytes(pl));
+    std::vector<int> rem(P);
+    std::iota(rem.begin(), rem.end(), 0);
+    std::vector<uint32_t> ij;
+    std::vector<float4> coef;
+    int groups_used = 0;
+    while (!rem.empty()) {
+      std::stable_sort(rem.begin(), rem.end(), [&](int x, int y) {
+        const uint32_t a = out.pair_ij[x], b = out.pair_ij[y];
+        return left[a & 0xff] + left[(a >> 8) & 0xff] > left[b & 0xff] + left[(b >> 8) & 0xff];
+      });
+      std::vector<int> slot(kWave, -1);
+      std::vector<uint64_t> used(2 * K, 0);
+      std::vector<int> fill(K);
+      for (int g = 0; g < K; ++g) fill[g] = g * m;
+      std::vector<int> next;
+      for (int p : rem) {
+        const int i = out.pair_ij[p] & 0xff, j = (out.pair_ij[p] >> 8) & 0xff;
+        bool placed = false;
+        for (int g = 0; g < K && !placed; ++g) {
+          const int end = std::min(kWave, (g + 1) * m);
+          const bool bi = (used[2 * g + (i >> 6)] >> (i & 63)) & 1u;
+          const bool bj = (used[2 * g + (j >> 6)] >> (j & 63)) & 1u;
+          if (fill[g] < end && !bi && !bj) {
+            slot[fill[g]++] = p;
+            used[2 * g + (i >> 6)] |= 1ull << (i & 63);
+            used[2 * g + (j >> 6)] |= 1ull << (j & 63);
+            --left[i];
+            --left[j];
+            groups_used = std::max(groups_used, g + 1);
+            placed = true;
+          }
+        }
+        if (!placed) next.push_back(p);
+      }
+      for (int l = 0; l < kWave; ++l) {
+        ij.push_back(slot[l] < 0 ? kPairPad : out.pair_ij[slot[l]]);
+        coef.push_back(slot[l] < 0 ? make_float4(0.f, 0.f, 0.f, 0.f) : out.pair_coef[slot[l]]);
+      }
+      rem.swap(next);
+    }
+    out.n_pairs = P;
+    out.n_rows = (int)(ij.size() / kWave);
+    out.pair_ij.swap(ij);
+    out.pair_coef.swap(coef);
+    out.group_lanes = m;
+    out.n_copies = groups_used;
+    // LDS: per-wave buffers first, then as many pair rows as fit
+    const size_t waves = (size_t)kWavesPerBlock * lds_wave_bytes(n, out.n_copies, A);
+    int pr = out.n_rows;
+    while (pr > 0 && waves + lds_pairs_bytes(pr) > kLdsBudget) --pr;
+    out.pl_rows = pr;
+    out.lds_bytes = (int)(waves + lds_pairs_bytes(pr));
   }
   return std::string();
 }
