@@ -269,6 +269,13 @@ md_status md_profile_enable(int on) {
   return MD_OK;
 }
 
+md_status md_set_graphs(int on) {
+  set_use_graphs(on != 0);
+  return MD_OK;
+}
+
+int md_graphs_enabled(void) { return use_graphs() ? 1 : 0; }
+
 md_status md_profile_reset(void) {
   for (int k = 0; k < MD_K_COUNT; ++k) {
     g_prof.total_ms[k] = 0.0;
@@ -397,8 +404,7 @@ md_status md_dock_batch(const md_receptor* rec, int n_jobs, const md_dock_job* j
 
   // workspace: job table, block tables, per-job populations, then one results region
   std::vector<JobDev> table(n_jobs);
-  std::vector<int2> pop_blocks[2], ls_blocks[2], run_blocks;
-  int lds_pop[2] = {0, 0}, lds_ls[2] = {0, 0};
+  std::vector<SchedJob> sched_jobs(n_jobs);
   int max_planned = 0;
   Carve cv;
   const size_t o_table = cv.take(sizeof(JobDev) * n_jobs);
@@ -417,17 +423,12 @@ md_status md_dock_batch(const md_receptor* rec, int n_jobs, const md_dock_job* j
     o.ev = cv.take(rows * 4);
     o.lsr = cv.take((size_t)p.n_runs * std::max(n_ls, 1) * 4);
     o.br = cv.take((size_t)p.n_runs * 4);
-    const int A = L.n_atoms > kWave ? 2 : 1;
-    const int b = A - 1;
-    for (long long w = 0; w < (long long)rows; w += kWavesPerBlock) pop_blocks[b].push_back(make_int2(j, (int)w));
-    for (long long w = 0; w < (long long)p.n_runs * n_ls; w += kWavesPerBlock) ls_blocks[b].push_back(make_int2(j, (int)w));
-    for (int r = 0; r < p.n_runs; r += kWavesPerBlock) run_blocks.push_back(make_int2(j, r));
-    lds_pop[b] = std::max(lds_pop[b], L.lds_bytes);
-    if (n_ls > 0) lds_ls[b] = std::max(lds_ls[b], L.lds_bytes);
+    sched_jobs[j] = SchedJob{j, &jobs[j].ligand->dev, p.n_runs, p.pop_size, n_ls, p.ls_iters};
     max_planned = std::max(max_planned, md_dock_planned_generations(&p));
   }
-  const size_t o_blocks = cv.take(sizeof(int2) * (pop_blocks[0].size() + pop_blocks[1].size() +
-                                                  ls_blocks[0].size() + ls_blocks[1].size() + run_blocks.size()));
+  GenSchedule sched;
+  build_schedule(sched_jobs, sched);
+  const size_t o_blocks = cv.take(sizeof(int2) * std::max<size_t>(sched.blocks.size(), 1));
   const size_t o_results = cv.off;
   for (int j = 0; j < n_jobs; ++j) {
     const md_dock_params& p = jobs[j].params;
@@ -478,40 +479,30 @@ md_status md_dock_batch(const md_receptor* rec, int n_jobs, const md_dock_job* j
     J.planned = md_dock_planned_generations(&p);
     J.state = kJobInit;
   }
-  std::vector<int2> blocks;
-  size_t bo[6];
-  bo[0] = 0;
-  blocks.insert(blocks.end(), pop_blocks[0].begin(), pop_blocks[0].end()); bo[1] = blocks.size();
-  blocks.insert(blocks.end(), pop_blocks[1].begin(), pop_blocks[1].end()); bo[2] = blocks.size();
-  blocks.insert(blocks.end(), ls_blocks[0].begin(), ls_blocks[0].end()); bo[3] = blocks.size();
-  blocks.insert(blocks.end(), ls_blocks[1].begin(), ls_blocks[1].end()); bo[4] = blocks.size();
-  blocks.insert(blocks.end(), run_blocks.begin(), run_blocks.end()); bo[5] = blocks.size();
   JobDev* d_table = reinterpret_cast<JobDev*>(w + o_table);
   const int2* d_blocks = reinterpret_cast<const int2*>(w + o_blocks);
   const RecDev& R = rec->dev;
 
+  // Initial populations, then the generations: one launch at a time when profiling (each is
+  // timed), else one captured generation replayed max_planned times (jobs that finish early
+  // skip the rest on the device).
   LaunchTimer timer(s);
+  const LaunchHook hook = [&](int kind, const std::function<hipError_t()>& f) { return timer.run(kind, f); };
   hipError_t e = hipMemcpyAsync(d_table, table.data(), sizeof(JobDev) * n_jobs, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(w + o_blocks, blocks.data(), sizeof(int2) * blocks.size(), hipMemcpyHostToDevice, s);
-  for (int b = 0; b < 2 && e == hipSuccess; ++b)
-    e = timer.run(MD_K_INIT_POPULATION, [&] {
-      return launch_ga_init(d_table, d_blocks + bo[b], (int)(bo[b + 1] - bo[b]), b + 1, lds_pop[b], R, s);
-    });
+  if (e == hipSuccess && !sched.blocks.empty())
+    e = hipMemcpyAsync(w + o_blocks, sched.blocks.data(), sizeof(int2) * sched.blocks.size(),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_init_phase(sched, d_table, d_blocks, R, s, &hook);
   if (e == hipSuccess) e = timer.run(MD_K_SUM_EVALS, [&] { return launch_ga_advance(d_table, n_jobs, s); });
-  for (int g = 1; g <= max_planned && e == hipSuccess; ++g) {
-    for (int b = 0; b < 2 && e == hipSuccess; ++b)
-      e = timer.run(MD_K_GENERATION, [&] {
-        return launch_ga_generation(d_table, d_blocks + bo[b], (int)(bo[b + 1] - bo[b]), b + 1, lds_pop[b], R, s);
-      });
-    if (e == hipSuccess && bo[4] > bo[2])
-      e = timer.run(MD_K_LS_PICK, [&] { return launch_ga_ls_pick(d_table, d_blocks + bo[4], (int)(bo[5] - bo[4]), s); });
-    for (int b = 0; b < 2 && e == hipSuccess; ++b)
-      e = timer.run(MD_K_LOCAL_SEARCH, [&] {
-        return launch_ga_local_search(d_table, d_blocks + bo[2 + b], (int)(bo[3 + b] - bo[2 + b]), b + 1,
-                                      lds_ls[b], R, s);
-      });
-    if (e == hipSuccess) e = timer.run(MD_K_SUM_EVALS, [&] { return launch_ga_advance(d_table, n_jobs, s); });
+  if (g_prof.on || !use_graphs() || max_planned < 2) {
+    for (int g = 1; g <= max_planned && e == hipSuccess; ++g)
+      e = launch_generation_phase(sched, d_table, n_jobs, d_blocks, R, s, &hook);
+  } else {
+    GenGraph graph;
+    if (e == hipSuccess) e = graph.capture(sched, d_table, n_jobs, d_blocks, R);
+    for (int g = 1; g <= max_planned && e == hipSuccess; ++g) e = graph.launch(s);
+    // the graph's launches read the workspace: finish them before the graph is destroyed
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
   }
   for (int j = 0; j < n_jobs && e == hipSuccess; ++j)
     if (jobs[j].result->best_xyz)

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -21,10 +22,12 @@ constexpr int kBlock = kWave * kWavesPerBlock;
 // lane).  The lanes of a row form groups of `group_lanes` consecutive lanes, and within a group
 // no atom occurs twice in a row, so every lane can add its pair's force into its group's copy of
 // the per-atom force array with a plain read-modify-write (no atomics, no conflicts); the copies
-// are summed per atom once per evaluation.  The first `pl_rows` rows are staged in LDS once per
-// block; the plan keeps a block's dynamic LDS within kLdsBudget.
+// are summed per atom once per evaluation.  An empty slot names atom N (one past the last) at
+// both ends with zero coefficients: the coordinate and force arrays have a spare entry there, so
+// it needs no branch.  The first `pl_rows` rows are staged in LDS once per block; the plan keeps
+// a block's dynamic LDS within kLdsBudget.
 constexpr size_t kLdsBudget = 65536;
-constexpr uint32_t kPairPad = 1u << 17;   // empty slot of a row: zero coefficients, no force
+constexpr uint32_t kPairPad = 1u << 17;   // marks an empty slot (informational)
 
 // Scoring constants (AutoDock4 force-field forms and weights).
 constexpr float kWvdw = 0.1662f;
@@ -105,6 +108,12 @@ struct JobDev {
   int state;                  // kJob*
 };
 
+// Tunable choices of a ligand's plan (see plan_ligand).
+struct PlanParams {
+  int lds_budget = (int)kLdsBudget;   // dynamic LDS of one block, bytes
+  int group_div = 3;                  // lanes per conflict-free group ~ n_atoms / group_div
+};
+
 // Host-side ligand after preprocessing (arrays in internal torsion order).
 struct LigHost {
   int n_atoms = 0, n_tors = 0, n_genes = 0;
@@ -114,16 +123,20 @@ struct LigHost {
   std::vector<float4> tor_axis, tor_pivot;
   std::vector<int2> tor_ab;
   std::vector<int> tor_gene;
+  std::vector<uint32_t> raw_ij;    // pair list before scheduling
+  std::vector<float4> raw_coef;
   std::vector<uint32_t> pair_ij;   // scheduled rows, padded (see LigDev)
   std::vector<float4> pair_coef;
   int n_pairs = 0, n_rows = 0, pl_rows = 0, group_lanes = 64, n_copies = 1, lds_bytes = 0;
+  PlanParams plan;
 };
 
 // LDS layout helpers shared by the host plan and the kernels.
 __host__ __device__ inline size_t lds_align16(size_t v) { return (v + 15) & ~size_t(15); }
-// per wave: posed coordinates [64*A] and the force-array copies [n_copies][n_atoms], float4 each
+// per wave: posed coordinates [64*A + 1] and the force-array copies [n_copies][n_atoms + 1],
+// float4 each (the last entry of each is the spare one that empty slots name)
 __host__ __device__ inline size_t lds_wave_bytes(int n_atoms, int n_copies, int A) {
-  return (size_t)16 * kWave * A + (size_t)16 * n_copies * n_atoms;
+  return (size_t)16 * (kWave * A + 1) + (size_t)16 * n_copies * (n_atoms + 1);
 }
 __host__ __device__ inline size_t lds_pairs_bytes(int rows) { return (size_t)rows * kWave * (16 + 4); }
 
@@ -132,6 +145,8 @@ std::string prepare_ligand(int n_atoms, const float* xyz, const int* type, const
                            int n_bonds, const int* bonds, int n_torsions, const int* torsions,
                            int root, int n_types, const float* type_params, LigHost& out,
                            bool& range_error);
+// (Re)computes the pair schedule and LDS plan of a prepared ligand.
+void plan_ligand(LigHost& h, const PlanParams& pp);
 
 // Kernel launchers (kernels.hip).  All return hipSuccess or the launch error.
 hipError_t launch_eval(const LigDev& L, const RecDev& R, int n, const float* genes, float* energy,
@@ -150,6 +165,45 @@ hipError_t launch_ga_ls_pick(JobDev* jobs, const int2* blocks, int n_blocks, hip
 hipError_t launch_ga_local_search(JobDev* jobs, const int2* blocks, int n_blocks, int A, int lds,
                                   const RecDev& R, hipStream_t s);
 hipError_t launch_ga_advance(JobDev* jobs, int n_jobs, hipStream_t s);
+
+// Per-generation launch schedule over a job table (schedule.cpp).
+struct SchedJob {
+  int slot;                   // index in the job table
+  const LigDev* L;
+  int n_runs, pop_size, n_ls, ls_iters;
+};
+struct PhaseLaunch {
+  int A, lds, first, count;   // atoms per lane, dynamic LDS, range in the block array
+};
+struct GenSchedule {
+  std::vector<int2> blocks;   // (slot, first wave) of every block of every launch
+  std::vector<PhaseLaunch> pop, ls;
+  int run_first = 0, run_count = 0;
+};
+// Optional wrapper around each launch (kind: md_kernel_kind), e.g. for timing.
+using LaunchHook = std::function<hipError_t(int, const std::function<hipError_t()>&)>;
+void build_schedule(const std::vector<SchedJob>& jobs, GenSchedule& out);
+hipError_t launch_init_phase(const GenSchedule& g, JobDev* table, const int2* d_blocks, const RecDev& R,
+                             hipStream_t s, const LaunchHook* hook);
+hipError_t launch_generation_phase(const GenSchedule& g, JobDev* table, int n_table, const int2* d_blocks,
+                                   const RecDev& R, hipStream_t s, const LaunchHook* hook);
+// One generation captured as a HIP graph (on a private stream) and replayed on any stream.
+class GenGraph {
+ public:
+  GenGraph() = default;
+  GenGraph(const GenGraph&) = delete;
+  GenGraph& operator=(const GenGraph&) = delete;
+  ~GenGraph() { reset(); }
+  hipError_t capture(const GenSchedule& g, JobDev* table, int n_table, const int2* d_blocks, const RecDev& R);
+  hipError_t launch(hipStream_t s) const;
+  bool ready() const { return exec_ != nullptr; }
+  void reset();
+
+ private:
+  hipGraphExec_t exec_ = nullptr;
+};
+bool use_graphs();
+void set_use_graphs(bool on);
 
 }  // namespace mdock
 

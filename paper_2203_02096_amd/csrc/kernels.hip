@@ -100,15 +100,15 @@ __device__ __forceinline__ float wrap_angle(float th) {
 struct BlockLds {
   const float4* pair_coef;   // [pl_rows*64]
   const uint32_t* pair_ij;   // [pl_rows*64]
-  float4* x;                 // this wave: [64*A] posed x, y, z
-  float4* f;                 // this wave: [n_copies][n_atoms] intramolecular forces
+  float4* x;                 // this wave: [64*A + 1] posed x, y, z
+  float4* f;                 // this wave: [n_copies][n_atoms + 1] intramolecular forces
   float4* fg;                // this lane's group copy
 };
 
 extern __shared__ __align__(16) unsigned char g_lds[];
 
-// All threads of the block stage the shared part and clear their force copies, then
-// synchronise.  Must be reached by every wave of the block before any of them leaves.
+// All threads of the block stage the shared part and clear their wave's coordinate and force
+// arrays, then synchronise.  Must be reached by every wave of the block before any leaves.
 template <int A>
 __device__ __forceinline__ BlockLds stage_block(const LigDev& L) {
   BlockLds b;
@@ -127,12 +127,14 @@ __device__ __forceinline__ BlockLds stage_block(const LigDev& L) {
   b.pair_coef = pc;
   b.pair_ij = pij;
   b.x = reinterpret_cast<float4*>(cur);
-  cur += (size_t)16 * kWave * A;
+  cur += (size_t)16 * (kWave * A + 1);
   b.f = reinterpret_cast<float4*>(cur);
-  const int nf = L.n_copies * L.n_atoms;
-  for (int k = lane; k < nf; k += kWave) b.f[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (lane == 0) b.x[kWave * A] = z;
+  const int nf = L.n_copies * (L.n_atoms + 1);
+  for (int k = lane; k < nf; k += kWave) b.f[k] = z;
   const int g = min(lane / L.group_lanes, max(L.n_copies - 1, 0));
-  b.fg = b.f + g * L.n_atoms;
+  b.fg = b.f + g * (L.n_atoms + 1);
   __syncthreads();
   return b;
 }
@@ -289,93 +291,120 @@ __device__ __forceinline__ float grid_finish(const RecDev& R, const GridFetch& g
 //   eps = A + B/den = D/den with D = A den + B, so 1/eps = den^2 q and
 //   (d eps/dr)/eps = B k lambda B e q, where q = 1/(den D).
 __device__ __forceinline__ float pair_term(float r2, bool hb, float4 c, float& f_over_r) {
+  // No automatic contraction here: every fused multiply-add is written out, so the energy-only
+  // and the gradient instantiations compute the energy with the same operations.
+#pragma clang fp contract(off)
   const float rt2 = fmaxf(r2, kRmin * kRmin);
   const float ir = __builtin_amdgcn_rsqf(rt2);      // 1 / max(r, R_MIN)
   const float rt = rt2 * ir;
-  float e = 0.f, dedr = 0.f;
-  if (r2 < kCutoff * kCutoff) {
-    const float ir2 = ir * ir;
-    const float ir6 = ir2 * ir2 * ir2;
-    const float ir12 = ir6 * ir6;
-    const float irn = hb ? ir6 * ir2 * ir2 : ir6;
-    const float nn = hb ? 10.f : 6.f;
-    const float elj = c.x * ir12 - c.y * irn;
-    const float dlj = (-12.f * c.x * ir12 + nn * c.y * irn) * ir;
-    const float gs = __builtin_amdgcn_exp2f(-rt2 * (1.4426950408889634f / (2.f * kDesolvSigma * kDesolvSigma)));
-    const float eds = c.w * gs;
-    const float dds = -rt * (1.f / (kDesolvSigma * kDesolvSigma)) * eds;
-    e += elj + eds;
-    dedr += dlj + dds;
-  }
-  if (r2 < kCutoffEl * kCutoffEl) {
-    const float ex = __builtin_amdgcn_exp2f(-kDielLambda * kDielB * 1.4426950408889634f * rt);
-    const float den = 1.f + kDielK * ex;
-    const float D = kDielA * den + kDielB;
-    const float q = __builtin_amdgcn_rcpf(den * D);
-    const float ieps = den * den * q;
-    const float eel = c.z * ir * ieps;
-    e += eel;
-    dedr += -eel * (ir + kDielB * kDielK * kDielLambda * kDielB * ex * q);
-  }
+  // dispersion / H-bond and desolvation, inside the 8 A cutoff
+  const float ir2 = ir * ir;
+  const float ir6 = ir2 * ir2 * ir2;
+  const float ir12 = ir6 * ir6;
+  const float irn = hb ? ir6 * ir2 * ir2 : ir6;
+  const float nn = hb ? 10.f : 6.f;
+  const float a12 = c.x * ir12;
+  const float elj = __builtin_fmaf(-c.y, irn, a12);
+  const float dlj = __builtin_fmaf(nn * c.y, irn, -12.f * a12) * ir;
+  const float gs = __builtin_amdgcn_exp2f(rt2 * (-1.4426950408889634f / (2.f * kDesolvSigma * kDesolvSigma)));
+  const float eds = c.w * gs;
+  const float dds = (rt * (-1.f / (kDesolvSigma * kDesolvSigma))) * eds;
+  // electrostatics with the distance-dependent dielectric, inside the 20.48 A cutoff
+  const float ex = __builtin_amdgcn_exp2f(rt * (-kDielLambda * kDielB * 1.4426950408889634f));
+  const float den = __builtin_fmaf(kDielK, ex, 1.f);
+  const float D = __builtin_fmaf(kDielA, den, kDielB);
+  const float q = __builtin_amdgcn_rcpf(den * D);
+  const float ieps = (den * den) * q;
+  const float eel = (c.z * ir) * ieps;
+  const float del = __builtin_fmaf(ex * (kDielB * kDielK * kDielLambda * kDielB), q, ir) * -eel;
+  const bool in1 = r2 < kCutoff * kCutoff, in2 = r2 < kCutoffEl * kCutoffEl;
+  const float e = (in1 ? elj + eds : 0.f) + (in2 ? eel : 0.f);
+  const float dedr = (in1 ? dlj + dds : 0.f) + (in2 ? del : 0.f);
   f_over_r = (r2 < kRmin * kRmin) ? 0.f : dedr * ir;
   return e;
 }
 
-// One pair slot.  With GRAD the pair's force, (dE/dr / r)(x_i - x_j) on i and its negative on
-// j, is added into the lane group's force copy; within a group no atom occurs twice in a row,
-// and a wave's LDS operations complete in order, so the updates never collide.
+// The pair rows.  Within a lane group no atom occurs twice in a row and a wave's LDS operations
+// complete in order, so each lane adds its pair's force, (dE/dr / r)(x_i - x_j) on i and its
+// negative on j, into its group's force copy with a plain read-modify-write.  Software
+// pipelined one row deep: a row's force entries and the next row's records are requested before
+// the row's arithmetic, the next row's coordinates before its force writes (the coordinates are
+// not written here, and the force reads follow the previous row's writes in program order).
+// A two-row-deep pipeline measured slower: its extra registers cost a wave per SIMD.  Each lane
+// adds its slots' energies in row order, so the energy-only and gradient paths agree bitwise.
+struct P3 {
+  float x, y, z;
+};
+
+__device__ __forceinline__ P3 load_p3(const float4* a, int k) {
+  const float4* p = a + k;
+  return P3{p->x, p->y, p->z};
+}
+
 template <bool GRAD>
-__device__ __forceinline__ float pair_one(const BlockLds& b, uint32_t ij, float4 c) {
-  const int i = ij & 0xff, j = (ij >> 8) & 0xff;
-  const bool hb = (ij >> 16) & 1u;
-  const float4 xi = b.x[i], xj = b.x[j];
+__device__ __forceinline__ float pair_slot(uint32_t ij, float4 c, P3 xi, P3 xj, P3& fi, P3& fj) {
   const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+  const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
   float fr;
-  const float e = pair_term(dx * dx + dy * dy + dz * dz, hb, c, fr);
-  if (GRAD && !(ij & kPairPad)) {
+  const float e = pair_term(r2, (ij >> 16) & 1u, c, fr);
+  if (GRAD) {
     const float fx = fr * dx, fy = fr * dy, fz = fr * dz;
-    float4 fi = b.fg[i], fj = b.fg[j];
     fi.x += fx;
     fi.y += fy;
     fi.z += fz;
     fj.x -= fx;
     fj.y -= fy;
     fj.z -= fz;
-    b.fg[i] = fi;
-    b.fg[j] = fj;
   }
   return e;
 }
 
-// All pair rows: the LDS-staged prefix, then the rest from global memory with the next row's
-// records loaded while the current one is evaluated.  Each lane adds its slots' energies in row
-// order, so the energy-only and the gradient paths give the same sum.
+template <bool GRAD, bool FROM_LDS>
+__device__ __forceinline__ void pair_span(const LigDev& L, const BlockLds& b, int r0, int r1, float& e) {
+  if (r0 >= r1) return;
+  const int lane = lane_id();
+  const uint32_t* pij = FROM_LDS ? b.pair_ij : L.pair_ij;
+  const float4* pc = FROM_LDS ? b.pair_coef : L.pair_coef;
+  int s = r0 * kWave + lane;
+  uint32_t ij = pij[s];
+  float4 c = pc[s];
+  P3 xi = load_p3(b.x, ij & 0xff), xj = load_p3(b.x, (ij >> 8) & 0xff);
+  for (int r = r0; r < r1; ++r) {
+    const int i = ij & 0xff, j = (ij >> 8) & 0xff;
+    P3 fi, fj;
+    if (GRAD) {
+      fi = load_p3(b.fg, i);
+      fj = load_p3(b.fg, j);
+    }
+    const int sn = (r + 1 < r1) ? s + kWave : s;
+    const uint32_t ij_n = pij[sn];
+    const float4 c_n = pc[sn];
+    e += pair_slot<GRAD>(ij, c, xi, xj, fi, fj);
+    const int i_n = ij_n & 0xff, j_n = (ij_n >> 8) & 0xff;
+    const P3 xi_n = load_p3(b.x, i_n), xj_n = load_p3(b.x, j_n);
+    if (GRAD) {
+      float4* pi = b.fg + i;
+      float4* pj = b.fg + j;
+      pi->x = fi.x;
+      pi->y = fi.y;
+      pi->z = fi.z;
+      pj->x = fj.x;
+      pj->y = fj.y;
+      pj->z = fj.z;
+    }
+    ij = ij_n;
+    c = c_n;
+    xi = xi_n;
+    xj = xj_n;
+    s = sn;
+  }
+}
+
 template <bool GRAD>
 __device__ __forceinline__ float pair_rows(const LigDev& L, const BlockLds& b) {
-  const int lane = lane_id();
   float e = 0.f;
-  const int pr = L.pl_rows, nr = L.n_rows;
-  for (int r = 0; r < pr; ++r) {
-    const int s = r * kWave + lane;
-    e += pair_one<GRAD>(b, b.pair_ij[s], b.pair_coef[s]);
-  }
-  if (pr < nr) {
-    int s = pr * kWave + lane;
-    uint32_t ij = L.pair_ij[s];
-    float4 c = L.pair_coef[s];
-    for (int r = pr; r < nr; ++r) {
-      uint32_t ij_n = kPairPad;
-      float4 c_n = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (r + 1 < nr) {
-        ij_n = L.pair_ij[s + kWave];
-        c_n = L.pair_coef[s + kWave];
-      }
-      e += pair_one<GRAD>(b, ij, c);
-      ij = ij_n;
-      c = c_n;
-      s += kWave;
-    }
-  }
+  pair_span<GRAD, true>(L, b, 0, L.pl_rows, e);
+  pair_span<GRAD, false>(L, b, L.pl_rows, L.n_rows, e);
   return e;
 }
 
@@ -468,11 +497,11 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, 
       if (at.valid[a]) {
         const int i = lane + kWave * a;
         for (int g = 0; g < K; ++g) {
-          const float4 v = b.f[g * N + i];
+          const float4 v = b.f[g * (N + 1) + i];
           Fx[a] += v.x;
           Fy[a] += v.y;
           Fz[a] += v.z;
-          b.f[g * N + i] = make_float4(0.f, 0.f, 0.f, 0.f);
+          b.f[g * (N + 1) + i] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
       }
     }

@@ -179,75 +179,85 @@ std::string prepare_ligand(int n, const float* xyz, const int* type, const float
       out.pair_coef.push_back(make_float4((float)c12, (float)cn, (float)qq, (float)ds));
     }
   }
-  // Pair schedule: rows of 64 slots, lanes split into groups of about N/3 lanes in which no atom
-  // occurs twice per row (so the kernel's per-group force updates never collide).  Greedy row by
-  // row: the remaining pairs whose atoms have the most pairs left go first, each into the first
-  // group where both of its atoms are still free.  Empty slots are padding records.
-  {
-    const int P = (int)out.pair_ij.size();
-    const int A = n > kWave ? 2 : 1;
-    const int want = std::max(1, std::min(kWave, n / 3));
-    const int K = (kWave + want - 1) / want;
-    const int m = (kWave + K - 1) / K;
-    std::vector<int> left(n, 0);
-    for (uint32_t v : out.pair_ij) {
-      ++left[v & 0xff];
-      ++left[(v >> 8) & 0xff];
-    }
-    std::vector<int> rem(P);
-    std::iota(rem.begin(), rem.end(), 0);
-    std::vector<uint32_t> ij;
-    std::vector<float4> coef;
-    int groups_used = 0;
-    while (!rem.empty()) {
-      std::stable_sort(rem.begin(), rem.end(), [&](int x, int y) {
-        const uint32_t a = out.pair_ij[x], b = out.pair_ij[y];
-        return left[a & 0xff] + left[(a >> 8) & 0xff] > left[b & 0xff] + left[(b >> 8) & 0xff];
-      });
-      std::vector<int> slot(kWave, -1);
-      std::vector<uint64_t> used(2 * K, 0);
-      std::vector<int> fill(K);
-      for (int g = 0; g < K; ++g) fill[g] = g * m;
-      std::vector<int> next;
-      for (int p : rem) {
-        const int i = out.pair_ij[p] & 0xff, j = (out.pair_ij[p] >> 8) & 0xff;
-        bool placed = false;
-        for (int g = 0; g < K && !placed; ++g) {
-          const int end = std::min(kWave, (g + 1) * m);
-          const bool bi = (used[2 * g + (i >> 6)] >> (i & 63)) & 1u;
-          const bool bj = (used[2 * g + (j >> 6)] >> (j & 63)) & 1u;
-          if (fill[g] < end && !bi && !bj) {
-            slot[fill[g]++] = p;
-            used[2 * g + (i >> 6)] |= 1ull << (i & 63);
-            used[2 * g + (j >> 6)] |= 1ull << (j & 63);
-            --left[i];
-            --left[j];
-            groups_used = std::max(groups_used, g + 1);
-            placed = true;
-          }
-        }
-        if (!placed) next.push_back(p);
-      }
-      for (int l = 0; l < kWave; ++l) {
-        ij.push_back(slot[l] < 0 ? kPairPad : out.pair_ij[slot[l]]);
-        coef.push_back(slot[l] < 0 ? make_float4(0.f, 0.f, 0.f, 0.f) : out.pair_coef[slot[l]]);
-      }
-      rem.swap(next);
-    }
-    out.n_pairs = P;
-    out.n_rows = (int)(ij.size() / kWave);
-    out.pair_ij.swap(ij);
-    out.pair_coef.swap(coef);
-    out.group_lanes = m;
-    out.n_copies = groups_used;
-    // LDS: per-wave buffers first, then as many pair rows as fit
-    const size_t waves = (size_t)kWavesPerBlock * lds_wave_bytes(n, out.n_copies, A);
-    int pr = out.n_rows;
-    while (pr > 0 && waves + lds_pairs_bytes(pr) > kLdsBudget) --pr;
-    out.pl_rows = pr;
-    out.lds_bytes = (int)(waves + lds_pairs_bytes(pr));
-  }
+  out.raw_ij = out.pair_ij;
+  out.raw_coef = out.pair_coef;
+  plan_ligand(out, PlanParams());
   return std::string();
+}
+
+
+// Pair schedule: rows of 64 slots, lanes split into groups of about N/div lanes in which no atom
+// occurs twice per row (so the kernel's per-group force updates never collide).  Greedy row by
+// row: the remaining pairs whose atoms have the most pairs left go first, each into the first
+// group where both of its atoms are still free.  Empty slots name the spare atom N.  Then the
+// LDS plan: per-wave buffers first, then as many pair rows as fit the block budget.
+void plan_ligand(LigHost& out, const PlanParams& pp) {
+  const int n = out.n_atoms;
+  const int P = (int)out.raw_ij.size();
+  const int A = n > kWave ? 2 : 1;
+  const int div = std::max(2, std::min(8, pp.group_div));
+  const int want = std::max(1, std::min(kWave, n / div));
+  const int K = (kWave + want - 1) / want;
+  const int m = (kWave + K - 1) / K;
+  std::vector<int> left(n, 0);
+  for (uint32_t v : out.raw_ij) {
+    ++left[v & 0xff];
+    ++left[(v >> 8) & 0xff];
+  }
+  std::vector<int> rem(P);
+  std::iota(rem.begin(), rem.end(), 0);
+  std::vector<uint32_t> ij;
+  std::vector<float4> coef;
+  int groups_used = 0;
+  while (!rem.empty()) {
+    std::stable_sort(rem.begin(), rem.end(), [&](int x, int y) {
+      const uint32_t a = out.raw_ij[x], b = out.raw_ij[y];
+      return left[a & 0xff] + left[(a >> 8) & 0xff] > left[b & 0xff] + left[(b >> 8) & 0xff];
+    });
+    std::vector<int> slot(kWave, -1);
+    std::vector<uint64_t> used(2 * K, 0);
+    std::vector<int> fill(K);
+    for (int g = 0; g < K; ++g) fill[g] = g * m;
+    std::vector<int> next;
+    for (int p : rem) {
+      const int i = out.raw_ij[p] & 0xff, j = (out.raw_ij[p] >> 8) & 0xff;
+      bool placed = false;
+      for (int g = 0; g < K && !placed; ++g) {
+        const int end = std::min(kWave, (g + 1) * m);
+        const bool bi = (used[2 * g + (i >> 6)] >> (i & 63)) & 1u;
+        const bool bj = (used[2 * g + (j >> 6)] >> (j & 63)) & 1u;
+        if (fill[g] < end && !bi && !bj) {
+          slot[fill[g]++] = p;
+          used[2 * g + (i >> 6)] |= 1ull << (i & 63);
+          used[2 * g + (j >> 6)] |= 1ull << (j & 63);
+          --left[i];
+          --left[j];
+          groups_used = std::max(groups_used, g + 1);
+          placed = true;
+        }
+      }
+      if (!placed) next.push_back(p);
+    }
+    const uint32_t pad = kPairPad | (uint32_t)n | ((uint32_t)n << 8);
+    for (int l = 0; l < kWave; ++l) {
+      ij.push_back(slot[l] < 0 ? pad : out.raw_ij[slot[l]]);
+      coef.push_back(slot[l] < 0 ? make_float4(0.f, 0.f, 0.f, 0.f) : out.raw_coef[slot[l]]);
+    }
+    rem.swap(next);
+  }
+  out.n_pairs = P;
+  out.n_rows = (int)(ij.size() / kWave);
+  out.pair_ij.swap(ij);
+  out.pair_coef.swap(coef);
+  out.group_lanes = m;
+  out.n_copies = groups_used;
+  out.plan = pp;
+  const size_t budget = (size_t)std::max(pp.lds_budget, 0);
+  const size_t waves = (size_t)kWavesPerBlock * lds_wave_bytes(n, out.n_copies, A);
+  int pr = out.n_rows;
+  while (pr > 0 && waves + lds_pairs_bytes(pr) > budget) --pr;
+  out.pl_rows = pr;
+  out.lds_bytes = (int)(waves + lds_pairs_bytes(pr));
 }
 
 }  // namespace mdock

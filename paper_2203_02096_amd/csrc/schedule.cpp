@@ -1,0 +1,154 @@
+// Per-generation launch schedule of the job-table GA kernels, shared by md_dock_batch and the
+// docking server, and its capture as a HIP graph.
+//
+// Ligands of very different sizes go through the same generation (the paper's screening
+// workflow docks a heterogeneous ligand stream; its discussion of heterogeneously sized
+// ligands makes load balance part of the problem).  Two choices here keep one large ligand
+// from setting the cost of many small ones:
+//  * size classes: jobs are grouped by atoms per lane and by how many blocks of their LDS
+//    plan fit on a compute unit, and each group is one launch with that group's LDS size, so
+//    a small ligand never runs with a large ligand's LDS reservation (and lower occupancy);
+//  * longest first: inside a launch, the blocks of the most expensive jobs come first, so the
+//    long waves start early and the short ones fill the tail.
+// One generation (selection/crossover/mutation + evaluation, local-search picks, local search,
+// epilogue) reads everything it needs from the device job table, so the same sequence of
+// launches serves every generation and is captured once and replayed.
+#include <algorithm>
+#include <map>
+#include <numeric>
+
+#include "internal.h"
+#include "mdock.h"
+
+namespace mdock {
+
+namespace {
+
+constexpr int kLdsPerCu = 160 * 1024;
+
+int occupancy_class(int lds) { return lds <= 0 ? 64 : std::min(64, kLdsPerCu / lds); }
+
+// Relative cost of one evaluation (pair slots dominate; atoms and torsions add the rest).
+double eval_cost(const LigDev& L) {
+  return (double)L.n_rows * kWave + 8.0 * L.n_atoms + 16.0 * L.n_tors + 64.0;
+}
+
+}  // namespace
+
+void build_schedule(const std::vector<SchedJob>& jobs, GenSchedule& out) {
+  out = GenSchedule();
+  // bucket key: (atoms per lane, occupancy class); larger occupancy classes first
+  std::map<std::pair<int, int>, std::vector<int>> pop_b, ls_b;
+  for (int k = 0; k < (int)jobs.size(); ++k) {
+    const SchedJob& j = jobs[k];
+    const int A = j.L->n_atoms > kWave ? 2 : 1;
+    const std::pair<int, int> key(A, -occupancy_class(j.L->lds_bytes));
+    pop_b[key].push_back(k);
+    if (j.n_ls > 0) ls_b[key].push_back(k);
+  }
+  auto emit = [&](std::map<std::pair<int, int>, std::vector<int>>& buckets, bool ls,
+                  std::vector<PhaseLaunch>& launches) {
+    for (auto& kv : buckets) {
+      std::vector<int>& members = kv.second;
+      std::vector<double> cost(jobs.size(), 0.0);
+      for (int k : members) {
+        const SchedJob& j = jobs[k];
+        cost[k] = eval_cost(*j.L) * (ls ? (double)j.ls_iters : 1.0);
+      }
+      std::stable_sort(members.begin(), members.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+      PhaseLaunch pl;
+      pl.A = kv.first.first;
+      pl.lds = 0;
+      pl.first = (int)out.blocks.size();
+      for (int k : members) {
+        const SchedJob& j = jobs[k];
+        const long long waves = ls ? (long long)j.n_runs * j.n_ls : (long long)j.n_runs * j.pop_size;
+        for (long long w = 0; w < waves; w += kWavesPerBlock) out.blocks.push_back(make_int2(j.slot, (int)w));
+        pl.lds = std::max(pl.lds, j.L->lds_bytes);
+      }
+      pl.count = (int)out.blocks.size() - pl.first;
+      if (pl.count > 0) launches.push_back(pl);
+    }
+  };
+  emit(pop_b, false, out.pop);
+  emit(ls_b, true, out.ls);
+  out.run_first = (int)out.blocks.size();
+  for (const SchedJob& j : jobs)
+    if (j.n_ls > 0)
+      for (int r = 0; r < j.n_runs; r += kWavesPerBlock) out.blocks.push_back(make_int2(j.slot, r));
+  out.run_count = (int)out.blocks.size() - out.run_first;
+}
+
+hipError_t launch_init_phase(const GenSchedule& g, JobDev* table, const int2* d_blocks, const RecDev& R,
+                             hipStream_t s, const LaunchHook* hook) {
+  hipError_t e = hipSuccess;
+  for (const PhaseLaunch& pl : g.pop) {
+    auto f = [&] { return launch_ga_init(table, d_blocks + pl.first, pl.count, pl.A, pl.lds, R, s); };
+    e = hook ? (*hook)(MD_K_INIT_POPULATION, f) : f();
+    if (e != hipSuccess) return e;
+  }
+  return e;
+}
+
+hipError_t launch_generation_phase(const GenSchedule& g, JobDev* table, int n_table, const int2* d_blocks,
+                                   const RecDev& R, hipStream_t s, const LaunchHook* hook) {
+  hipError_t e = hipSuccess;
+  auto run = [&](int kind, const std::function<hipError_t()>& f) { return hook ? (*hook)(kind, f) : f(); };
+  for (const PhaseLaunch& pl : g.pop) {
+    e = run(MD_K_GENERATION,
+            [&] { return launch_ga_generation(table, d_blocks + pl.first, pl.count, pl.A, pl.lds, R, s); });
+    if (e != hipSuccess) return e;
+  }
+  if (g.run_count > 0) {
+    e = run(MD_K_LS_PICK, [&] { return launch_ga_ls_pick(table, d_blocks + g.run_first, g.run_count, s); });
+    if (e != hipSuccess) return e;
+  }
+  for (const PhaseLaunch& pl : g.ls) {
+    e = run(MD_K_LOCAL_SEARCH,
+            [&] { return launch_ga_local_search(table, d_blocks + pl.first, pl.count, pl.A, pl.lds, R, s); });
+    if (e != hipSuccess) return e;
+  }
+  return run(MD_K_SUM_EVALS, [&] { return launch_ga_advance(table, n_table, s); });
+}
+
+// ------------------------------------------------------------------ captured generation
+hipError_t GenGraph::capture(const GenSchedule& g, JobDev* table, int n_table, const int2* d_blocks,
+                             const RecDev& R) {
+  reset();
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t el = launch_generation_phase(g, table, n_table, d_blocks, R, cs, nullptr);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    if (e == hipSuccess) e = el;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec_, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess && exec_) {
+      (void)hipGraphExecDestroy(exec_);
+      exec_ = nullptr;
+    }
+  }
+  (void)hipStreamDestroy(cs);
+  return e;
+}
+
+hipError_t GenGraph::launch(hipStream_t s) const {
+  return exec_ ? hipGraphLaunch(exec_, s) : hipErrorInvalidValue;
+}
+
+void GenGraph::reset() {
+  if (exec_) (void)hipGraphExecDestroy(exec_);
+  exec_ = nullptr;
+}
+
+namespace {
+bool g_use_graphs = true;
+}
+
+bool use_graphs() { return g_use_graphs; }
+void set_use_graphs(bool on) { g_use_graphs = on; }
+
+}  // namespace mdock

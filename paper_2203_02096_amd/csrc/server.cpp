@@ -120,6 +120,11 @@ struct md_server {
   int2* d_blocks = nullptr;
   size_t blocks_cap = 0;
   std::vector<std::shared_ptr<Request>> slots;   // resident request per slot (or null)
+  // launch schedule of the resident set; rebuilt (and the captured generation dropped) when
+  // the set changes
+  bool resident_changed = true;
+  GenSchedule sched;
+  GenGraph graph;
 
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -200,55 +205,45 @@ JobDev make_job(md_server* s, const Request& r) {
 
 // One tick: every resident request advances by one phase sequence.  Returns the HIP status.
 hipError_t run_tick(md_server* s, bool any_init, bool any_running) {
-  std::vector<int2> pop[2], ls[2], run;
-  int lds_pop[2] = {0, 0}, lds_ls[2] = {0, 0};
   const int n_slots = (int)s->slots.size();
-  for (int j = 0; j < n_slots; ++j) {
-    const auto& r = s->slots[j];
-    if (!r) continue;
-    const LigDev& L = r->lig->dev;
-    const md_dock_params& p = r->params;
-    const int b = L.n_atoms > kWave ? 1 : 0;
-    const long long rows = (long long)p.n_runs * p.pop_size;
-    const int n_ls = n_local_search_of(&p);
-    for (long long w = 0; w < rows; w += kWavesPerBlock) pop[b].push_back(make_int2(j, (int)w));
-    for (long long w = 0; w < (long long)p.n_runs * n_ls; w += kWavesPerBlock) ls[b].push_back(make_int2(j, (int)w));
-    for (int q = 0; q < p.n_runs; q += kWavesPerBlock) run.push_back(make_int2(j, q));
-    lds_pop[b] = std::max(lds_pop[b], L.lds_bytes);
-    if (n_ls > 0) lds_ls[b] = std::max(lds_ls[b], L.lds_bytes);
-  }
-  std::vector<int2> all;
-  size_t bo[6];
-  bo[0] = 0;
-  all.insert(all.end(), pop[0].begin(), pop[0].end()); bo[1] = all.size();
-  all.insert(all.end(), pop[1].begin(), pop[1].end()); bo[2] = all.size();
-  all.insert(all.end(), ls[0].begin(), ls[0].end()); bo[3] = all.size();
-  all.insert(all.end(), ls[1].begin(), ls[1].end()); bo[4] = all.size();
-  all.insert(all.end(), run.begin(), run.end()); bo[5] = all.size();
   hipError_t e = hipSuccess;
-  if (all.size() > s->blocks_cap) {
-    if (s->d_blocks) (void)hipFree(s->d_blocks);
-    s->blocks_cap = std::max<size_t>(all.size(), 2 * s->blocks_cap);
-    e = hipMalloc(&s->d_blocks, s->blocks_cap * sizeof(int2));
-    if (e != hipSuccess) {
-      s->d_blocks = nullptr;
-      s->blocks_cap = 0;
-      return e;
+  if (s->resident_changed) {
+    std::vector<SchedJob> jobs;
+    for (int j = 0; j < n_slots; ++j) {
+      const auto& r = s->slots[j];
+      if (!r) continue;
+      const md_dock_params& p = r->params;
+      jobs.push_back(SchedJob{j, &r->lig->dev, p.n_runs, p.pop_size, n_local_search_of(&p), p.ls_iters});
+    }
+    build_schedule(jobs, s->sched);
+    s->graph.reset();
+    const size_t nb = s->sched.blocks.size();
+    if (nb > s->blocks_cap) {
+      if (s->d_blocks) (void)hipFree(s->d_blocks);
+      s->blocks_cap = std::max<size_t>(nb, 2 * s->blocks_cap);
+      e = hipMalloc(&s->d_blocks, s->blocks_cap * sizeof(int2));
+      if (e != hipSuccess) {
+        s->d_blocks = nullptr;
+        s->blocks_cap = 0;
+        return e;
+      }
+    }
+    if (nb) e = hipMemcpyAsync(s->d_blocks, s->sched.blocks.data(), nb * sizeof(int2), hipMemcpyHostToDevice, s->stream);
+    if (e != hipSuccess) return e;
+    s->resident_changed = false;
+  }
+  const RecDev& R = s->rec->dev;
+  if (any_init) e = launch_init_phase(s->sched, s->d_table, s->d_blocks, R, s->stream, nullptr);
+  if (e == hipSuccess) {
+    if (!any_running) {
+      e = launch_ga_advance(s->d_table, n_slots, s->stream);
+    } else if (s->params.use_graphs && use_graphs()) {
+      if (!s->graph.ready()) e = s->graph.capture(s->sched, s->d_table, n_slots, s->d_blocks, R);
+      if (e == hipSuccess) e = s->graph.launch(s->stream);
+    } else {
+      e = launch_generation_phase(s->sched, s->d_table, n_slots, s->d_blocks, R, s->stream, nullptr);
     }
   }
-  if (!all.empty()) e = hipMemcpyAsync(s->d_blocks, all.data(), all.size() * sizeof(int2), hipMemcpyHostToDevice, s->stream);
-  const RecDev& R = s->rec->dev;
-  for (int b = 0; b < 2 && e == hipSuccess && any_init; ++b)
-    e = launch_ga_init(s->d_table, s->d_blocks + bo[b], (int)(bo[b + 1] - bo[b]), b + 1, lds_pop[b], R, s->stream);
-  if (any_running) {
-    for (int b = 0; b < 2 && e == hipSuccess; ++b)
-      e = launch_ga_generation(s->d_table, s->d_blocks + bo[b], (int)(bo[b + 1] - bo[b]), b + 1, lds_pop[b], R, s->stream);
-    if (e == hipSuccess) e = launch_ga_ls_pick(s->d_table, s->d_blocks + bo[4], (int)(bo[5] - bo[4]), s->stream);
-    for (int b = 0; b < 2 && e == hipSuccess; ++b)
-      e = launch_ga_local_search(s->d_table, s->d_blocks + bo[2 + b], (int)(bo[3 + b] - bo[2 + b]), b + 1,
-                                 lds_ls[b], R, s->stream);
-  }
-  if (e == hipSuccess) e = launch_ga_advance(s->d_table, n_slots, s->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(s->h_table, s->d_table, sizeof(JobDev) * n_slots, hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
@@ -305,6 +300,7 @@ void worker_loop(md_server* s) {
       r->state = kResident;
       r->t_start = now_s();
       s->slots[j] = r;
+      s->resident_changed = true;
       s->h_table[j] = make_job(s, *r);
       admitted.push_back(j);
     }
@@ -365,6 +361,7 @@ void worker_loop(md_server* s) {
       }
       s->pool->release(r->off, r->bytes);
       s->slots[r->slot] = nullptr;
+      s->resident_changed = true;
       s->h_table[r->slot].state = kJobEmpty;
     }
     // requests canceled while resident: drop them from their slots (device entry marked empty)
@@ -408,6 +405,7 @@ md_status md_server_create(const md_receptor* rec, const md_server_params* p, md
   if (!rec || !p || !out) return server_fail(MD_EINVAL, "md_server_create: null argument");
   if (p->max_slots < 1 || p->max_slots > 4096) return server_fail(MD_ERANGE, "md_server_create: max_slots must be in [1, 4096]");
   if (p->hbm_budget_bytes < (1u << 20)) return server_fail(MD_EINVAL, "md_server_create: hbm_budget_bytes must be >= 1 MiB");
+  if (p->use_graphs != 0 && p->use_graphs != 1) return server_fail(MD_EINVAL, "md_server_create: use_graphs must be 0 or 1");
   auto* s = new (std::nothrow) md_server();
   if (!s) return server_fail(MD_ENOMEM, "md_server_create: out of host memory");
   s->rec = rec;

@@ -55,7 +55,7 @@ class DockResult(C.Structure):
 
 
 class ServerParams(C.Structure):
-    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int)]
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int), ("use_graphs", C.c_int)]
 
 
 class ServerStats(C.Structure):
@@ -99,6 +99,8 @@ SIGNATURES = {
     "md_profile_enable": (C.c_int, [C.c_int]),
     "md_profile_reset": (C.c_int, []),
     "md_profile_read": (C.c_int, [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
+    "md_set_graphs": (C.c_int, [C.c_int]),
+    "md_graphs_enabled": (C.c_int, []),
     "md_last_error": (C.c_char_p, []),
     "md_version": (C.c_char_p, []),
 }
@@ -319,6 +321,15 @@ def md_profile_reset():
     _check(lib().md_profile_reset(), "md_profile_reset")
 
 
+def md_set_graphs(on=True):
+    """Capture and replay each LGA generation as a HIP graph (default on)."""
+    _check(lib().md_set_graphs(int(bool(on))), "md_set_graphs")
+
+
+def md_graphs_enabled():
+    return bool(lib().md_graphs_enabled())
+
+
 def md_profile_read(kind):
     ms, n = C.c_double(), C.c_longlong()
     _check(lib().md_profile_read(KERNELS.get(kind, kind), C.byref(ms), C.byref(n)), "md_profile_read")
@@ -329,9 +340,9 @@ class Server:
     """Continuous-batching docking server (md_server_*).  Keep the receptor and every submitted
     Ligand alive while the server runs."""
 
-    def __init__(self, rec: Receptor, hbm_budget_bytes=1 << 30, max_slots=64):
+    def __init__(self, rec: Receptor, hbm_budget_bytes=1 << 30, max_slots=64, use_graphs=True):
         h = C.c_void_p()
-        p = ServerParams(int(hbm_budget_bytes), int(max_slots))
+        p = ServerParams(int(hbm_budget_bytes), int(max_slots), int(bool(use_graphs)))
         _check(lib().md_server_create(rec.handle, C.byref(p), C.byref(h)), "md_server_create")
         self.handle = h
         self._rec = rec

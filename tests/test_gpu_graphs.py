@@ -1,0 +1,100 @@
+"""HIP-graph generations: md_dock / md_dock_batch capture one LGA generation and replay it, and
+the server captures its tick once per change of the resident set.  Every result must equal the
+kernel-by-kernel launch order bitwise, after any number of replays, with eager device work and
+synchronisations between calls."""
+import sys
+
+import numpy as np
+import pytest
+
+from workload import configs, synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+KEYS = ("best_energy", "best_genes", "best_xyz", "run_index", "evals", "generations")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def md():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    import paper_2203_02096_amd as m
+    m.lib()
+    yield m
+    m.md_set_graphs(True)
+
+
+@pytest.fixture(scope="module")
+def receptor(md):
+    rec = synth.make_receptor(64, 102)
+    return rec, md.Receptor(rec.maps, rec.origin, rec.spacing)
+
+
+def _dock(md, drec, lig, P, graphs):
+    md.md_set_graphs(graphs)
+    try:
+        return md.md_dock(drec, lig, P)
+    finally:
+        md.md_set_graphs(True)
+
+
+@pytest.mark.parametrize("gens", [2, 3, 7])
+def test_dock_graph_replays_equal_eager(md, receptor, gens):
+    rec, drec = receptor
+    lig = md.Ligand.from_synth(synth.make_ligand(30, 6, 901, configs.type_params()))
+    P = md.dock_params(**configs.search_params("serving_fp16", n_runs=4, pop_size=40, max_generations=gens,
+                                               ls_rate=0.25, ls_iters=25, seed=31 + gens))
+    _say(f"[graphs] md_dock 30 atoms, {gens} generations: eager then graph")
+    eager = _dock(md, drec, lig, P, False)
+    x = torch.randn(1 << 20, device="cuda")       # unrelated eager work between the calls
+    (x * 2).sum().item()
+    graph = _dock(md, drec, lig, P, True)
+    torch.cuda.synchronize()
+    again = _dock(md, drec, lig, P, True)
+    for k in KEYS:
+        assert np.array_equal(eager[k], graph[k]), k
+        assert np.array_equal(graph[k], again[k]), k
+    assert int(eager["generations"][0]) == gens
+
+
+def test_dock_batch_graph_equals_eager(md, receptor):
+    """Mixed sizes across the size classes (one and two atoms per lane, several LDS classes)."""
+    rec, drec = receptor
+    sizes = [(12, 2), (40, 8), (70, 16), (25, 4), (100, 20), (55, 10)]
+    ligs = [md.Ligand.from_synth(synth.make_ligand(n, t, 910 + k, configs.type_params()))
+            for k, (n, t) in enumerate(sizes)]
+    Ps = [md.dock_params(**configs.search_params("serving_fp16", n_runs=3, pop_size=30, max_generations=4,
+                                                 ls_rate=0.2, ls_iters=20, seed=40 + k)) for k in range(len(ligs))]
+    _say("[graphs] md_dock_batch of 6 ligands, eager then graph")
+    md.md_set_graphs(False)
+    eager = md.md_dock_batch(drec, list(zip(ligs, Ps)))
+    md.md_set_graphs(True)
+    graph = md.md_dock_batch(drec, list(zip(ligs, Ps)))
+    for k in range(len(ligs)):
+        for key in KEYS:
+            assert np.array_equal(eager[k][key], graph[k][key]), (k, key)
+
+
+@pytest.mark.parametrize("use_graphs", [True, False])
+def test_server_graphs_equal_alone(md, receptor, use_graphs):
+    rec, drec = receptor
+    sizes = [(20, 3), (66, 14), (35, 6), (90, 20)]
+    ligs = [md.Ligand.from_synth(synth.make_ligand(n, t, 930 + k, configs.type_params()))
+            for k, (n, t) in enumerate(sizes)]
+    Ps = [md.dock_params(**configs.search_params("serving_fp16", n_runs=2, pop_size=30, max_generations=3 + k,
+                                                 ls_rate=0.2, ls_iters=15, seed=60 + k)) for k in range(len(ligs))]
+    _say(f"[graphs] server use_graphs={use_graphs}, 4 requests")
+    srv = md.Server(drec, hbm_budget_bytes=64 << 20, max_slots=2, use_graphs=use_graphs)
+    tickets = [srv.submit(l, p) for l, p in zip(ligs, Ps)]
+    results = [srv.wait(t, timeout_s=120) for t in tickets]
+    srv.close()
+    for k, (l, p) in enumerate(zip(ligs, Ps)):
+        alone = _dock(md, drec, l, p, False)
+        for key in KEYS:
+            assert np.array_equal(results[k][key], alone[key]), (k, key)
