@@ -123,6 +123,54 @@ int md_ligand_num_pairs(const md_ligand* lig);     /* intramolecular pairs */
 md_status md_ligand_info(const md_ligand* lig, int* n_atoms, int* n_torsions, int* n_pairs,
                          int* sum_moving);
 
+/* ------------------------------------------------------------------ launch plan and autotuner
+ * A ligand's launch plan: the evaluation kernels run `waves_per_block` poses per block; each
+ * block takes at most `lds_budget` bytes of LDS, which stages the first `staged_rows` of the
+ * ligand's `total_rows` rows of 64 intramolecular pair slots (the rest are read from global
+ * memory); the lanes of a pair row form conflict-free groups of about n_atoms / group_div lanes.
+ * A plan changes speed and the order of floating-point sums, not the method: results stay
+ * within the parity tolerance of each other and are reproducible for a fixed plan.
+ * Defaults: lds_budget 65536, group_div 3, waves_per_block 4.  Read-only on input to
+ * md_ligand_set_plan: lds_bytes, staged_rows, total_rows. */
+typedef struct {
+  int lds_budget;       /* 0..163840 (gfx950: a block may take the whole 160 KiB LDS of a CU) */
+  int group_div;        /* 2..8 */
+  int waves_per_block;  /* 1, 2, 4 or 8 */
+  int lds_bytes, staged_rows, total_rows;   /* outputs: the resulting layout */
+} md_plan;
+md_status md_ligand_get_plan(const md_ligand* lig, md_plan* out);
+/* Re-plans the ligand (host work + one upload; waits for the device to be idle).  The ligand
+ * must not be in use by another call.  Errors: MD_EINVAL, MD_ERANGE, MD_EDEVICE. */
+md_status md_ligand_set_plan(md_ligand* lig, const md_plan* plan);
+
+enum { MD_TUNE_FORCE = 1 };   /* time candidates even if the size class is already tuned */
+typedef struct {
+  md_plan plan;                /* the plan now in the ligand */
+  double us_per_eval;          /* its time per local-search evaluation in the tuning launches */
+  double default_us_per_eval;  /* the default plan's (0 when taken from the table) */
+  int candidates;              /* distinct plans timed */
+  int from_table;              /* 1: the class was tuned before; its plan was applied untimed */
+} md_tune_info;
+/* Autotuner: times the local-search kernel on `rec` (8192 random starts inside the box, a few
+ * ADADELTA steps each, best of three launches) for candidate plans -- waves per block {4, 8} x
+ * LDS budget {32, 48, 64, 96, 128, 160} KiB, then lane-group sizes N/2 and N/4 for the best --
+ * applies the fastest to `lig` and records it for the ligand's size class (atoms per lane and
+ * pair count within a quarter octave), which md_ligand_create then uses for later ligands of
+ * that class.  Runs on `hip_stream`, synchronously.  The ligand must not be in use by another
+ * call.  info may be NULL.  Errors: MD_EINVAL, MD_EDEVICE. */
+md_status md_ligand_autotune(const md_receptor* rec, md_ligand* lig, int flags, void* hip_stream,
+                             md_tune_info* info);
+/* Host only (no device needed): the pair schedule that `plan` gives the ligand `d`, for tests and
+ * inspection.  On input plan->lds_budget / group_div / waves_per_block; on output the layout
+ * fields.  pair_slots (may be NULL) receives min(capacity, total_rows*64) slots, row-major, each
+ * i | j << 8 | hbond << 16, with bit 17 set for an empty slot (which names atom n_atoms at both
+ * ends); *group_lanes (may be NULL) the lanes per conflict-free group.  Errors as
+ * md_ligand_create, plus MD_ERANGE for a bad plan. */
+md_status md_schedule_preview(const md_ligand_desc* d, md_plan* plan, unsigned* pair_slots, int capacity,
+                              int* group_lanes);
+md_status md_tune_table_clear(void);   /* forget every tuned size class */
+int md_tune_table_size(void);          /* number of tuned size classes */
+
 /* ------------------------------------------------------------------ hot path, one pose
  * Energy and analytic gradient of n_poses genotypes.  Energy = grid part + pair part:
  *  grid part, per atom at grid coordinate g = (x - origin)/spacing: if every

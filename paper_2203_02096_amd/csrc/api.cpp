@@ -96,6 +96,73 @@ struct LaunchTimer {
   }
 };
 
+}  // namespace
+
+namespace mdock {
+
+// One device allocation per ligand holding every constant the kernels read; *L gets views into it.
+hipError_t upload_ligand(const LigHost& h, void** d_buf, LigDev* L) {
+  const size_t N = h.n_atoms, T = h.n_tors, S = h.pair_ij.size();   // S: scheduled slots
+  size_t off = 0;
+  const size_t o_p0q = off; off = align16(off + N * sizeof(float4));
+  const size_t o_type = off; off = align16(off + N * sizeof(int));
+  const size_t o_mask = off; off = align16(off + N * sizeof(uint32_t));
+  const size_t o_axis = off; off = align16(off + T * sizeof(float4));
+  const size_t o_piv = off; off = align16(off + T * sizeof(float4));
+  const size_t o_ab = off; off = align16(off + T * sizeof(int2));
+  const size_t o_gene = off; off = align16(off + T * sizeof(int));
+  const size_t o_ij = off; off = align16(off + S * sizeof(uint32_t));
+  const size_t o_coef = off; off = align16(off + S * sizeof(float4));
+  std::vector<char> buf(std::max<size_t>(off, 16), 0);
+  auto put = [&](size_t o, const void* p, size_t n) { if (n) std::memcpy(buf.data() + o, p, n); };
+  put(o_p0q, h.atom_p0q.data(), N * sizeof(float4));
+  put(o_type, h.atom_type.data(), N * sizeof(int));
+  put(o_mask, h.atom_mask.data(), N * sizeof(uint32_t));
+  put(o_axis, h.tor_axis.data(), T * sizeof(float4));
+  put(o_piv, h.tor_pivot.data(), T * sizeof(float4));
+  put(o_ab, h.tor_ab.data(), T * sizeof(int2));
+  put(o_gene, h.tor_gene.data(), T * sizeof(int));
+  put(o_ij, h.pair_ij.data(), S * sizeof(uint32_t));
+  put(o_coef, h.pair_coef.data(), S * sizeof(float4));
+  void* d = nullptr;
+  hipError_t e = hipMalloc(&d, buf.size());
+  if (e == hipSuccess) e = hipMemcpy(d, buf.data(), buf.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (d) (void)hipFree(d);
+    return e;
+  }
+  char* b = static_cast<char*>(d);
+  LigDev& l = *L;
+  l.n_atoms = (int)N;
+  l.n_tors = (int)T;
+  l.n_pairs = h.n_pairs;
+  l.n_genes = h.n_genes;
+  l.atom_p0q = reinterpret_cast<const float4*>(b + o_p0q);
+  l.atom_type = reinterpret_cast<const int*>(b + o_type);
+  l.atom_mask = reinterpret_cast<const uint32_t*>(b + o_mask);
+  l.tor_axis = reinterpret_cast<const float4*>(b + o_axis);
+  l.tor_pivot = reinterpret_cast<const float4*>(b + o_piv);
+  l.tor_ab = reinterpret_cast<const int2*>(b + o_ab);
+  l.tor_gene = reinterpret_cast<const int*>(b + o_gene);
+  l.pair_ij = reinterpret_cast<const uint32_t*>(b + o_ij);
+  l.pair_coef = reinterpret_cast<const float4*>(b + o_coef);
+  l.n_rows = h.n_rows;
+  l.pl_rows = h.pl_rows;
+  l.group_lanes = h.group_lanes;
+  l.n_copies = h.n_copies;
+  l.wpb = h.wpb;
+  l.lds_bytes = h.lds_bytes;
+  *d_buf = d;
+  return hipSuccess;
+}
+
+md_status api_fail(md_status st, const std::string& msg) { return fail(st, msg); }
+md_status api_hip_fail(hipError_t e, const std::string& what) { return hip_fail(e, what.c_str()); }
+
+}  // namespace mdock
+
+namespace {
+
 int n_local_search(const md_dock_params* p) {
   double v = std::ceil((double)p->ls_rate * (double)p->pop_size - 1e-4);
   return (int)std::max(0.0, std::min((double)p->pop_size, v));
@@ -184,57 +251,15 @@ md_status md_ligand_create(const md_ligand_desc* d, md_ligand** out) {
     delete l;
     return fail(range ? MD_ERANGE : MD_EINVAL, "md_ligand_create: " + err);
   }
-  const LigHost& h = l->host;
-  const size_t N = h.n_atoms, T = h.n_tors, S = h.pair_ij.size();   // S: scheduled slots
-  size_t off = 0;
-  const size_t o_p0q = off; off = align16(off + N * sizeof(float4));
-  const size_t o_type = off; off = align16(off + N * sizeof(int));
-  const size_t o_mask = off; off = align16(off + N * sizeof(uint32_t));
-  const size_t o_axis = off; off = align16(off + T * sizeof(float4));
-  const size_t o_piv = off; off = align16(off + T * sizeof(float4));
-  const size_t o_ab = off; off = align16(off + T * sizeof(int2));
-  const size_t o_gene = off; off = align16(off + T * sizeof(int));
-  const size_t o_ij = off; off = align16(off + S * sizeof(uint32_t));
-  const size_t o_coef = off; off = align16(off + S * sizeof(float4));
-  std::vector<char> buf(std::max<size_t>(off, 16), 0);
-  auto put = [&](size_t o, const void* p, size_t n) { if (n) std::memcpy(buf.data() + o, p, n); };
-  put(o_p0q, h.atom_p0q.data(), N * sizeof(float4));
-  put(o_type, h.atom_type.data(), N * sizeof(int));
-  put(o_mask, h.atom_mask.data(), N * sizeof(uint32_t));
-  put(o_axis, h.tor_axis.data(), T * sizeof(float4));
-  put(o_piv, h.tor_pivot.data(), T * sizeof(float4));
-  put(o_ab, h.tor_ab.data(), T * sizeof(int2));
-  put(o_gene, h.tor_gene.data(), T * sizeof(int));
-  put(o_ij, h.pair_ij.data(), S * sizeof(uint32_t));
-  put(o_coef, h.pair_coef.data(), S * sizeof(float4));
+  PlanParams tuned;
+  if (tuned_plan_for(l->host, &tuned)) plan_ligand(l->host, tuned);
   hipError_t e = hipGetDevice(&l->device);
-  if (e == hipSuccess) e = hipMalloc(&l->d_buf, buf.size());
-  if (e == hipSuccess) e = hipMemcpy(l->d_buf, buf.data(), buf.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = enable_large_lds();
+  if (e == hipSuccess) e = upload_ligand(l->host, &l->d_buf, &l->dev);
   if (e != hipSuccess) {
-    if (l->d_buf) (void)hipFree(l->d_buf);
     delete l;
     return hip_fail(e, "md_ligand_create");
   }
-  char* b = static_cast<char*>(l->d_buf);
-  LigDev& L = l->dev;
-  L.n_atoms = (int)N;
-  L.n_tors = (int)T;
-  L.n_pairs = h.n_pairs;
-  L.n_genes = h.n_genes;
-  L.atom_p0q = reinterpret_cast<const float4*>(b + o_p0q);
-  L.atom_type = reinterpret_cast<const int*>(b + o_type);
-  L.atom_mask = reinterpret_cast<const uint32_t*>(b + o_mask);
-  L.tor_axis = reinterpret_cast<const float4*>(b + o_axis);
-  L.tor_pivot = reinterpret_cast<const float4*>(b + o_piv);
-  L.tor_ab = reinterpret_cast<const int2*>(b + o_ab);
-  L.tor_gene = reinterpret_cast<const int*>(b + o_gene);
-  L.pair_ij = reinterpret_cast<const uint32_t*>(b + o_ij);
-  L.pair_coef = reinterpret_cast<const float4*>(b + o_coef);
-  L.n_rows = h.n_rows;
-  L.pl_rows = h.pl_rows;
-  L.group_lanes = h.group_lanes;
-  L.n_copies = h.n_copies;
-  L.lds_bytes = h.lds_bytes;
   *out = l;
   return MD_OK;
 }

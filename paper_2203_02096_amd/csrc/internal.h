@@ -16,8 +16,11 @@ constexpr int kMaxTorsions = 32;
 constexpr int kMaxGenes = 7 + kMaxTorsions;
 constexpr int kTypes = 7;
 constexpr int kMaps = kTypes + 2;
-constexpr int kWavesPerBlock = 4;
+constexpr int kWavesPerBlock = 4;                  // blocks of the kernels without a ligand plan
 constexpr int kBlock = kWave * kWavesPerBlock;
+constexpr int kMaxWavesPerBlock = 8;               // evaluation kernels: the plan's waves per block
+constexpr int kMaxBlock = kWave * kMaxWavesPerBlock;
+constexpr int kMaxLdsPerBlock = 160 * 1024;        // gfx950: all of a compute unit's LDS
 // Pair schedule of a ligand: the intramolecular pairs are laid out in rows of 64 (one pair per
 // lane).  The lanes of a row form groups of `group_lanes` consecutive lanes, and within a group
 // no atom occurs twice in a row, so every lane can add its pair's force into its group's copy of
@@ -66,6 +69,7 @@ struct LigDev {
   int pl_rows;                // rows staged in LDS (a prefix)
   int group_lanes;            // lanes per conflict-free group
   int n_copies;               // force-array copies (groups in use)
+  int wpb;                    // waves (poses) per block of the evaluation kernels
   int lds_bytes;              // dynamic LDS of one block
 };
 
@@ -110,8 +114,9 @@ struct JobDev {
 
 // Tunable choices of a ligand's plan (see plan_ligand).
 struct PlanParams {
-  int lds_budget = (int)kLdsBudget;   // dynamic LDS of one block, bytes
+  int lds_budget = (int)kLdsBudget;   // dynamic LDS of one block, bytes (<= kMaxLdsPerBlock)
   int group_div = 3;                  // lanes per conflict-free group ~ n_atoms / group_div
+  int wpb = kWavesPerBlock;           // waves per block (1..kMaxWavesPerBlock)
 };
 
 // Host-side ligand after preprocessing (arrays in internal torsion order).
@@ -127,7 +132,8 @@ struct LigHost {
   std::vector<float4> raw_coef;
   std::vector<uint32_t> pair_ij;   // scheduled rows, padded (see LigDev)
   std::vector<float4> pair_coef;
-  int n_pairs = 0, n_rows = 0, pl_rows = 0, group_lanes = 64, n_copies = 1, lds_bytes = 0;
+  int n_pairs = 0, n_rows = 0, pl_rows = 0, group_lanes = 64, n_copies = 1, wpb = kWavesPerBlock;
+  int lds_bytes = 0;
   PlanParams plan;
 };
 
@@ -157,13 +163,15 @@ hipError_t launch_local_search(const LigDev& L, const RecDev& R, int n, const fl
                                float* trace, hipStream_t s);
 // GA phases over a job table.  blocks: [n_blocks] (job, first wave of the block within the
 // job's work for this phase).  A: atoms per lane of every job in the table; lds: dynamic LDS.
-hipError_t launch_ga_init(JobDev* jobs, const int2* blocks, int n_blocks, int A, int lds,
+hipError_t launch_ga_init(JobDev* jobs, const int2* blocks, int n_blocks, int A, int wpb, int lds,
                           const RecDev& R, hipStream_t s);
-hipError_t launch_ga_generation(JobDev* jobs, const int2* blocks, int n_blocks, int A, int lds,
+hipError_t launch_ga_generation(JobDev* jobs, const int2* blocks, int n_blocks, int A, int wpb, int lds,
                                 const RecDev& R, hipStream_t s);
 hipError_t launch_ga_ls_pick(JobDev* jobs, const int2* blocks, int n_blocks, hipStream_t s);
-hipError_t launch_ga_local_search(JobDev* jobs, const int2* blocks, int n_blocks, int A, int lds,
+hipError_t launch_ga_local_search(JobDev* jobs, const int2* blocks, int n_blocks, int A, int wpb, int lds,
                                   const RecDev& R, hipStream_t s);
+// Lets every evaluation kernel take up to kMaxLdsPerBlock of dynamic LDS (once per device).
+hipError_t enable_large_lds();
 hipError_t launch_ga_advance(JobDev* jobs, int n_jobs, hipStream_t s);
 
 // Per-generation launch schedule over a job table (schedule.cpp).
@@ -173,7 +181,7 @@ struct SchedJob {
   int n_runs, pop_size, n_ls, ls_iters;
 };
 struct PhaseLaunch {
-  int A, lds, first, count;   // atoms per lane, dynamic LDS, range in the block array
+  int A, wpb, lds, first, count;   // atoms per lane, waves per block, dynamic LDS, block range
 };
 struct GenSchedule {
   std::vector<int2> blocks;   // (slot, first wave) of every block of every launch
@@ -220,3 +228,10 @@ struct md_ligand {
   mdock::LigHost host;
   int device = 0;
 };
+
+namespace mdock {
+// Uploads a prepared ligand (api.cpp): one device allocation, *L gets views into it.
+hipError_t upload_ligand(const LigHost& h, void** d_buf, LigDev* L);
+// Autotuner table (autotune.cpp): the tuned plan of this ligand's size class, if any.
+bool tuned_plan_for(const LigHost& h, PlanParams* out);
+}  // namespace mdock

@@ -15,6 +15,9 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <set>
+
 #include "internal.h"
 
 namespace mdock {
@@ -586,10 +589,10 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, 
 
 // ------------------------------------------------------------------ kernels
 template <int A, int PREC>
-__global__ __launch_bounds__(kBlock) void k_eval(LigDev L, RecDev R, int n, const float* __restrict__ genes,
+__global__ __launch_bounds__(kMaxBlock) void k_eval(LigDev L, RecDev R, int n, const float* __restrict__ genes,
                                                  float* __restrict__ energy, float* __restrict__ grad) {
   const BlockLds b = stage_block<A>(L);
-  const int pose = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  const int pose = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (pose >= n) return;
   AtomRegs<A> at;
   load_ligand<A>(L, at);
@@ -709,13 +712,13 @@ __device__ float local_search_wave(const LigDev& L, const RecDev& R, const Block
 
 // Standalone local search: one wave per start genotype.
 template <int A, int PREC>
-__global__ __launch_bounds__(kBlock) void k_local_search(LigDev L, RecDev R, int n,
+__global__ __launch_bounds__(kMaxBlock) void k_local_search(LigDev L, RecDev R, int n,
                                                          const float* genes_in, float* genes_out,
                                                          float* __restrict__ energy_out,
                                                          int iters, float rho, float eps,
                                                          float* __restrict__ trace) {
   const BlockLds b = stage_block<A>(L);
-  const int job = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  const int job = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (job >= n) return;
   AtomRegs<A> at;
   load_ligand<A>(L, at);
@@ -846,7 +849,7 @@ __device__ float offspring_gene(const GaDev& P, const float* __restrict__ genes_
 // not in the phase's state leaves before staging anything (uniform per block).
 
 template <int A, int PREC>
-__global__ __launch_bounds__(kBlock) void k_ga_init(JobDev* __restrict__ jobs, const int2* __restrict__ blocks,
+__global__ __launch_bounds__(kMaxBlock) void k_ga_init(JobDev* __restrict__ jobs, const int2* __restrict__ blocks,
                                                     RecDev R) {
   const int2 bt = blocks[blockIdx.x];
   JobDev& J = jobs[bt.x];
@@ -873,7 +876,7 @@ __global__ __launch_bounds__(kBlock) void k_ga_init(JobDev* __restrict__ jobs, c
 }
 
 template <int A, int PREC>
-__global__ __launch_bounds__(kBlock) void k_ga_generation(JobDev* __restrict__ jobs,
+__global__ __launch_bounds__(kMaxBlock) void k_ga_generation(JobDev* __restrict__ jobs,
                                                           const int2* __restrict__ blocks, RecDev R) {
   const int2 bt = blocks[blockIdx.x];
   JobDev& J = jobs[bt.x];
@@ -940,7 +943,7 @@ __global__ __launch_bounds__(kBlock) void k_ga_ls_pick(JobDev* __restrict__ jobs
 }
 
 template <int A, int PREC>
-__global__ __launch_bounds__(kBlock) void k_ga_local_search(JobDev* __restrict__ jobs,
+__global__ __launch_bounds__(kMaxBlock) void k_ga_local_search(JobDev* __restrict__ jobs,
                                                             const int2* __restrict__ blocks, RecDev R) {
   const int2 bt = blocks[blockIdx.x];
   JobDev& J = jobs[bt.x];
@@ -1009,8 +1012,8 @@ __global__ __launch_bounds__(kBlock) void k_ga_advance(JobDev* __restrict__ jobs
   }
 }
 
-inline unsigned blocks_for(long long waves) {
-  return (unsigned)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+inline unsigned blocks_for(long long waves, int wpb = kWavesPerBlock) {
+  return (unsigned)((waves + wpb - 1) / wpb);
 }
 
 }  // namespace
@@ -1019,21 +1022,52 @@ inline unsigned blocks_for(long long waves) {
   do {                                                                                             \
     const bool two = L.n_atoms > kWave;                                                            \
     const size_t sm = (size_t)L.lds_bytes;                                                         \
+    const dim3 blk(kWave * L.wpb);                                                                    \
     switch (R.precision * 2 + (two ? 1 : 0)) {                                                     \
-      case 0: hipLaunchKernelGGL((KERNEL<1, 0>), GRID, dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
-      case 1: hipLaunchKernelGGL((KERNEL<2, 0>), GRID, dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
-      case 2: hipLaunchKernelGGL((KERNEL<1, 1>), GRID, dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
-      case 3: hipLaunchKernelGGL((KERNEL<2, 1>), GRID, dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
-      case 4: hipLaunchKernelGGL((KERNEL<1, 2>), GRID, dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
-      default: hipLaunchKernelGGL((KERNEL<2, 2>), GRID, dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
+      case 0: hipLaunchKernelGGL((KERNEL<1, 0>), GRID, blk, sm, STREAM, __VA_ARGS__); break; \
+      case 1: hipLaunchKernelGGL((KERNEL<2, 0>), GRID, blk, sm, STREAM, __VA_ARGS__); break; \
+      case 2: hipLaunchKernelGGL((KERNEL<1, 1>), GRID, blk, sm, STREAM, __VA_ARGS__); break; \
+      case 3: hipLaunchKernelGGL((KERNEL<2, 1>), GRID, blk, sm, STREAM, __VA_ARGS__); break; \
+      case 4: hipLaunchKernelGGL((KERNEL<1, 2>), GRID, blk, sm, STREAM, __VA_ARGS__); break; \
+      default: hipLaunchKernelGGL((KERNEL<2, 2>), GRID, blk, sm, STREAM, __VA_ARGS__); break; \
     }                                                                                              \
   } while (0)
 
 
+hipError_t enable_large_lds() {
+  static std::mutex mu;
+  static std::set<int> done;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  if (done.count(dev)) return hipSuccess;
+  const void* fns[] = {
+      (const void*)k_eval<1, 0>, (const void*)k_eval<2, 0>, (const void*)k_eval<1, 1>,
+      (const void*)k_eval<2, 1>, (const void*)k_eval<1, 2>, (const void*)k_eval<2, 2>,
+      (const void*)k_local_search<1, 0>, (const void*)k_local_search<2, 0>,
+      (const void*)k_local_search<1, 1>, (const void*)k_local_search<2, 1>,
+      (const void*)k_local_search<1, 2>, (const void*)k_local_search<2, 2>,
+      (const void*)k_ga_init<1, 0>, (const void*)k_ga_init<2, 0>, (const void*)k_ga_init<1, 1>,
+      (const void*)k_ga_init<2, 1>, (const void*)k_ga_init<1, 2>, (const void*)k_ga_init<2, 2>,
+      (const void*)k_ga_generation<1, 0>, (const void*)k_ga_generation<2, 0>,
+      (const void*)k_ga_generation<1, 1>, (const void*)k_ga_generation<2, 1>,
+      (const void*)k_ga_generation<1, 2>, (const void*)k_ga_generation<2, 2>,
+      (const void*)k_ga_local_search<1, 0>, (const void*)k_ga_local_search<2, 0>,
+      (const void*)k_ga_local_search<1, 1>, (const void*)k_ga_local_search<2, 1>,
+      (const void*)k_ga_local_search<1, 2>, (const void*)k_ga_local_search<2, 2>};
+  for (const void* f : fns) {
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsPerBlock);
+    if (e != hipSuccess) return e;
+  }
+  done.insert(dev);
+  return hipSuccess;
+}
+
 hipError_t launch_eval(const LigDev& L, const RecDev& R, int n, const float* genes, float* energy,
                        float* grad, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  MDOCK_DISPATCH(k_eval, dim3(blocks_for(n)), s, L, R, n, genes, energy, grad);
+  MDOCK_DISPATCH(k_eval, dim3(blocks_for(n, L.wpb)), s, L, R, n, genes, energy, grad);
   return hipGetLastError();
 }
 
@@ -1050,35 +1084,36 @@ hipError_t launch_local_search(const LigDev& L, const RecDev& R, int n, const fl
                                float* genes_out, float* energy_out, int iters, float rho, float eps,
                                float* trace, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  MDOCK_DISPATCH(k_local_search, dim3(blocks_for(n)), s, L, R, n, genes_in, genes_out, energy_out,
+  MDOCK_DISPATCH(k_local_search, dim3(blocks_for(n, L.wpb)), s, L, R, n, genes_in, genes_out, energy_out,
                  iters, rho, eps, trace);
   return hipGetLastError();
 }
 
-#define MDOCK_GA_DISPATCH(KERNEL, A, LDS, NB, STREAM, ...)                                          \
+#define MDOCK_GA_DISPATCH(KERNEL, A, WPB, LDS, NB, STREAM, ...)                                     \
   do {                                                                                             \
     const size_t sm = (size_t)(LDS);                                                               \
+    const dim3 blk(kWave * (WPB));                                                                    \
     switch (R.precision * 2 + ((A) == 2 ? 1 : 0)) {                                               \
-      case 0: hipLaunchKernelGGL((KERNEL<1, 0>), dim3(NB), dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
-      case 1: hipLaunchKernelGGL((KERNEL<2, 0>), dim3(NB), dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
-      case 2: hipLaunchKernelGGL((KERNEL<1, 1>), dim3(NB), dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
-      case 3: hipLaunchKernelGGL((KERNEL<2, 1>), dim3(NB), dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
-      case 4: hipLaunchKernelGGL((KERNEL<1, 2>), dim3(NB), dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
-      default: hipLaunchKernelGGL((KERNEL<2, 2>), dim3(NB), dim3(kBlock), sm, STREAM, __VA_ARGS__); break; \
+      case 0: hipLaunchKernelGGL((KERNEL<1, 0>), dim3(NB), blk, sm, STREAM, __VA_ARGS__); break; \
+      case 1: hipLaunchKernelGGL((KERNEL<2, 0>), dim3(NB), blk, sm, STREAM, __VA_ARGS__); break; \
+      case 2: hipLaunchKernelGGL((KERNEL<1, 1>), dim3(NB), blk, sm, STREAM, __VA_ARGS__); break; \
+      case 3: hipLaunchKernelGGL((KERNEL<2, 1>), dim3(NB), blk, sm, STREAM, __VA_ARGS__); break; \
+      case 4: hipLaunchKernelGGL((KERNEL<1, 2>), dim3(NB), blk, sm, STREAM, __VA_ARGS__); break; \
+      default: hipLaunchKernelGGL((KERNEL<2, 2>), dim3(NB), blk, sm, STREAM, __VA_ARGS__); break; \
     }                                                                                              \
   } while (0)
 
-hipError_t launch_ga_init(JobDev* jobs, const int2* blocks, int n_blocks, int A, int lds, const RecDev& R,
-                          hipStream_t s) {
+hipError_t launch_ga_init(JobDev* jobs, const int2* blocks, int n_blocks, int A, int wpb, int lds,
+                          const RecDev& R, hipStream_t s) {
   if (n_blocks <= 0) return hipSuccess;
-  MDOCK_GA_DISPATCH(k_ga_init, A, lds, n_blocks, s, jobs, blocks, R);
+  MDOCK_GA_DISPATCH(k_ga_init, A, wpb, lds, n_blocks, s, jobs, blocks, R);
   return hipGetLastError();
 }
 
-hipError_t launch_ga_generation(JobDev* jobs, const int2* blocks, int n_blocks, int A, int lds,
+hipError_t launch_ga_generation(JobDev* jobs, const int2* blocks, int n_blocks, int A, int wpb, int lds,
                                 const RecDev& R, hipStream_t s) {
   if (n_blocks <= 0) return hipSuccess;
-  MDOCK_GA_DISPATCH(k_ga_generation, A, lds, n_blocks, s, jobs, blocks, R);
+  MDOCK_GA_DISPATCH(k_ga_generation, A, wpb, lds, n_blocks, s, jobs, blocks, R);
   return hipGetLastError();
 }
 
@@ -1088,10 +1123,10 @@ hipError_t launch_ga_ls_pick(JobDev* jobs, const int2* blocks, int n_blocks, hip
   return hipGetLastError();
 }
 
-hipError_t launch_ga_local_search(JobDev* jobs, const int2* blocks, int n_blocks, int A, int lds,
+hipError_t launch_ga_local_search(JobDev* jobs, const int2* blocks, int n_blocks, int A, int wpb, int lds,
                                   const RecDev& R, hipStream_t s) {
   if (n_blocks <= 0) return hipSuccess;
-  MDOCK_GA_DISPATCH(k_ga_local_search, A, lds, n_blocks, s, jobs, blocks, R);
+  MDOCK_GA_DISPATCH(k_ga_local_search, A, wpb, lds, n_blocks, s, jobs, blocks, R);
   return hipGetLastError();
 }
 

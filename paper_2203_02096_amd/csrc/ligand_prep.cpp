@@ -252,8 +252,9 @@ void plan_ligand(LigHost& out, const PlanParams& pp) {
   out.group_lanes = m;
   out.n_copies = groups_used;
   out.plan = pp;
-  const size_t budget = (size_t)std::max(pp.lds_budget, 0);
-  const size_t waves = (size_t)kWavesPerBlock * lds_wave_bytes(n, out.n_copies, A);
+  out.wpb = std::max(1, std::min(kMaxWavesPerBlock, pp.wpb));
+  const size_t budget = (size_t)std::max(0, std::min(pp.lds_budget, kMaxLdsPerBlock));
+  const size_t waves = (size_t)out.wpb * lds_wave_bytes(n, out.n_copies, A);
   int pr = out.n_rows;
   while (pr > 0 && waves + lds_pairs_bytes(pr) > budget) --pr;
   out.pl_rows = pr;

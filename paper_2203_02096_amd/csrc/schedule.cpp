@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <map>
 #include <numeric>
+#include <tuple>
 
 #include "internal.h"
 #include "mdock.h"
@@ -26,6 +27,7 @@ namespace {
 
 constexpr int kLdsPerCu = 160 * 1024;
 
+// blocks of this LDS size that fit on one compute unit
 int occupancy_class(int lds) { return lds <= 0 ? 64 : std::min(64, kLdsPerCu / lds); }
 
 // Relative cost of one evaluation (pair slots dominate; atoms and torsions add the rest).
@@ -37,17 +39,17 @@ double eval_cost(const LigDev& L) {
 
 void build_schedule(const std::vector<SchedJob>& jobs, GenSchedule& out) {
   out = GenSchedule();
-  // bucket key: (atoms per lane, occupancy class); larger occupancy classes first
-  std::map<std::pair<int, int>, std::vector<int>> pop_b, ls_b;
+  // bucket key: (atoms per lane, waves per block, occupancy class); larger classes first
+  using Key = std::tuple<int, int, int>;
+  std::map<Key, std::vector<int>> pop_b, ls_b;
   for (int k = 0; k < (int)jobs.size(); ++k) {
     const SchedJob& j = jobs[k];
     const int A = j.L->n_atoms > kWave ? 2 : 1;
-    const std::pair<int, int> key(A, -occupancy_class(j.L->lds_bytes));
+    const Key key(A, j.L->wpb, -occupancy_class(j.L->lds_bytes) * j.L->wpb);
     pop_b[key].push_back(k);
     if (j.n_ls > 0) ls_b[key].push_back(k);
   }
-  auto emit = [&](std::map<std::pair<int, int>, std::vector<int>>& buckets, bool ls,
-                  std::vector<PhaseLaunch>& launches) {
+  auto emit = [&](std::map<Key, std::vector<int>>& buckets, bool ls, std::vector<PhaseLaunch>& launches) {
     for (auto& kv : buckets) {
       std::vector<int>& members = kv.second;
       std::vector<double> cost(jobs.size(), 0.0);
@@ -57,13 +59,14 @@ void build_schedule(const std::vector<SchedJob>& jobs, GenSchedule& out) {
       }
       std::stable_sort(members.begin(), members.end(), [&](int a, int b) { return cost[a] > cost[b]; });
       PhaseLaunch pl;
-      pl.A = kv.first.first;
+      pl.A = std::get<0>(kv.first);
+      pl.wpb = std::get<1>(kv.first);
       pl.lds = 0;
       pl.first = (int)out.blocks.size();
       for (int k : members) {
         const SchedJob& j = jobs[k];
         const long long waves = ls ? (long long)j.n_runs * j.n_ls : (long long)j.n_runs * j.pop_size;
-        for (long long w = 0; w < waves; w += kWavesPerBlock) out.blocks.push_back(make_int2(j.slot, (int)w));
+        for (long long w = 0; w < waves; w += pl.wpb) out.blocks.push_back(make_int2(j.slot, (int)w));
         pl.lds = std::max(pl.lds, j.L->lds_bytes);
       }
       pl.count = (int)out.blocks.size() - pl.first;
@@ -83,7 +86,7 @@ hipError_t launch_init_phase(const GenSchedule& g, JobDev* table, const int2* d_
                              hipStream_t s, const LaunchHook* hook) {
   hipError_t e = hipSuccess;
   for (const PhaseLaunch& pl : g.pop) {
-    auto f = [&] { return launch_ga_init(table, d_blocks + pl.first, pl.count, pl.A, pl.lds, R, s); };
+    auto f = [&] { return launch_ga_init(table, d_blocks + pl.first, pl.count, pl.A, pl.wpb, pl.lds, R, s); };
     e = hook ? (*hook)(MD_K_INIT_POPULATION, f) : f();
     if (e != hipSuccess) return e;
   }
@@ -96,7 +99,7 @@ hipError_t launch_generation_phase(const GenSchedule& g, JobDev* table, int n_ta
   auto run = [&](int kind, const std::function<hipError_t()>& f) { return hook ? (*hook)(kind, f) : f(); };
   for (const PhaseLaunch& pl : g.pop) {
     e = run(MD_K_GENERATION,
-            [&] { return launch_ga_generation(table, d_blocks + pl.first, pl.count, pl.A, pl.lds, R, s); });
+            [&] { return launch_ga_generation(table, d_blocks + pl.first, pl.count, pl.A, pl.wpb, pl.lds, R, s); });
     if (e != hipSuccess) return e;
   }
   if (g.run_count > 0) {
@@ -105,7 +108,7 @@ hipError_t launch_generation_phase(const GenSchedule& g, JobDev* table, int n_ta
   }
   for (const PhaseLaunch& pl : g.ls) {
     e = run(MD_K_LOCAL_SEARCH,
-            [&] { return launch_ga_local_search(table, d_blocks + pl.first, pl.count, pl.A, pl.lds, R, s); });
+            [&] { return launch_ga_local_search(table, d_blocks + pl.first, pl.count, pl.A, pl.wpb, pl.lds, R, s); });
     if (e != hipSuccess) return e;
   }
   return run(MD_K_SUM_EVALS, [&] { return launch_ga_advance(table, n_table, s); });

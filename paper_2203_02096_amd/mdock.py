@@ -63,6 +63,16 @@ class ServerStats(C.Structure):
                 ("resident", C.c_int), ("pool_used_bytes", C.c_size_t), ("busy_seconds", C.c_double)]
 
 
+class Plan(C.Structure):
+    _fields_ = [("lds_budget", C.c_int), ("group_div", C.c_int), ("waves_per_block", C.c_int),
+                ("lds_bytes", C.c_int), ("staged_rows", C.c_int), ("total_rows", C.c_int)]
+
+
+class TuneInfo(C.Structure):
+    _fields_ = [("plan", Plan), ("us_per_eval", C.c_double), ("default_us_per_eval", C.c_double),
+                ("candidates", C.c_int), ("from_table", C.c_int)]
+
+
 class DockJob(C.Structure):
     _fields_ = [("ligand", C.c_void_p), ("params", DockParams), ("result", C.POINTER(DockResult))]
 
@@ -100,6 +110,13 @@ SIGNATURES = {
     "md_profile_reset": (C.c_int, []),
     "md_profile_read": (C.c_int, [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]),
     "md_set_graphs": (C.c_int, [C.c_int]),
+    "md_ligand_get_plan": (C.c_int, [C.c_void_p, C.POINTER(Plan)]),
+    "md_ligand_set_plan": (C.c_int, [C.c_void_p, C.POINTER(Plan)]),
+    "md_ligand_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.POINTER(TuneInfo)]),
+    "md_tune_table_clear": (C.c_int, []),
+    "md_schedule_preview": (C.c_int, [C.POINTER(LigandDesc), C.POINTER(Plan), C.POINTER(C.c_uint), C.c_int,
+                                      C.POINTER(C.c_int)]),
+    "md_tune_table_size": (C.c_int, []),
     "md_graphs_enabled": (C.c_int, []),
     "md_last_error": (C.c_char_p, []),
     "md_version": (C.c_char_p, []),
@@ -319,6 +336,61 @@ def md_profile_enable(on=True):
 
 def md_profile_reset():
     _check(lib().md_profile_reset(), "md_profile_reset")
+
+
+def _plan_dict(p: Plan):
+    return {k: getattr(p, k) for k, _ in Plan._fields_}
+
+
+def md_ligand_get_plan(lig: Ligand):
+    p = Plan()
+    _check(lib().md_ligand_get_plan(lig.handle, C.byref(p)), "md_ligand_get_plan")
+    return _plan_dict(p)
+
+
+def md_ligand_set_plan(lig: Ligand, lds_budget=65536, group_div=3, waves_per_block=4):
+    p = Plan(int(lds_budget), int(group_div), int(waves_per_block), 0, 0, 0)
+    _check(lib().md_ligand_set_plan(lig.handle, C.byref(p)), "md_ligand_set_plan")
+    return md_ligand_get_plan(lig)
+
+
+def md_ligand_autotune(rec: Receptor, lig: Ligand, force=False, stream=None):
+    """Times candidate launch plans of the ligand on this receptor and keeps the fastest."""
+    info = TuneInfo()
+    _check(lib().md_ligand_autotune(rec.handle, lig.handle, 1 if force else 0, _stream_ptr(stream),
+                                    C.byref(info)), "md_ligand_autotune")
+    return dict(plan=_plan_dict(info.plan), us_per_eval=info.us_per_eval,
+                default_us_per_eval=info.default_us_per_eval, candidates=info.candidates,
+                from_table=bool(info.from_table))
+
+
+def md_schedule_preview(lig, lds_budget=65536, group_div=3, waves_per_block=4):
+    """Host only: the pair schedule (slots i | j<<8 | hb<<16 | empty<<17, row-major) that a plan
+    gives a ligand described like workload.synth.Ligand; returns (plan dict, slots, group_lanes)."""
+    xyz = np.ascontiguousarray(lig.xyz, dtype=np.float32).reshape(-1, 3)
+    types = np.ascontiguousarray(lig.types, dtype=np.int32).reshape(-1)
+    q = np.ascontiguousarray(lig.charges, dtype=np.float32).reshape(-1)
+    bonds = np.ascontiguousarray(lig.bonds, dtype=np.int32).reshape(-1, 2)
+    tors = np.ascontiguousarray(lig.torsions, dtype=np.int32).reshape(-1)
+    tp = np.ascontiguousarray(lig.type_params, dtype=np.float32).reshape(-1, 7)
+    d = LigandDesc(xyz.shape[0], _fptr(xyz), _iptr(types), _fptr(q), bonds.shape[0], _iptr(bonds),
+                   tors.shape[0], _iptr(tors), int(getattr(lig, "root", 0)), tp.shape[0], _fptr(tp))
+    p = Plan(int(lds_budget), int(group_div), int(waves_per_block), 0, 0, 0)
+    gl = C.c_int()
+    _check(lib().md_schedule_preview(C.byref(d), C.byref(p), None, 0, C.byref(gl)), "md_schedule_preview")
+    slots = np.zeros(p.total_rows * 64, dtype=np.uint32)
+    p2 = Plan(int(lds_budget), int(group_div), int(waves_per_block), 0, 0, 0)
+    _check(lib().md_schedule_preview(C.byref(d), C.byref(p2), slots.ctypes.data_as(C.POINTER(C.c_uint)),
+                                     slots.size, C.byref(gl)), "md_schedule_preview")
+    return _plan_dict(p2), slots, gl.value
+
+
+def md_tune_table_clear():
+    _check(lib().md_tune_table_clear(), "md_tune_table_clear")
+
+
+def md_tune_table_size():
+    return int(lib().md_tune_table_size())
 
 
 def md_set_graphs(on=True):

@@ -104,6 +104,21 @@ def test_null_handles_rejected(md):
     assert lib.md_local_search(None, None, 1, None, None, None, 10, 0.8, 0.01, None, None) == -1
     assert lib.md_dock(None, None, None, None, None) == -1
     assert lib.md_ligand_num_genes(None) == -1
+    plan = md.mdock.Plan(65536, 3, 4, 0, 0, 0)
+    assert lib.md_ligand_get_plan(None, C.byref(plan)) == -1
+    assert lib.md_ligand_set_plan(None, C.byref(plan)) == -1
+    assert lib.md_ligand_autotune(None, None, 0, None, None) == -1
+    assert lib.md_schedule_preview(None, C.byref(plan), None, 0, None) == -1
+    assert lib.md_server_create(None, None, None) == -1
+
+
+def test_host_only_settings(md):
+    lib = md.lib()
+    assert lib.md_tune_table_clear() == 0
+    assert lib.md_tune_table_size() == 0
+    assert lib.md_graphs_enabled() == 1
+    assert lib.md_set_graphs(0) == 0 and lib.md_graphs_enabled() == 0
+    assert lib.md_set_graphs(1) == 0 and lib.md_graphs_enabled() == 1
 
 
 def test_planned_generations_closed_form(md):

@@ -1,0 +1,77 @@
+"""Host-side pair schedule of the library (md_schedule_preview; no GPU needed).
+
+The evaluation kernel adds each pair's force into its lane group's force copy without atomics,
+which is only correct if no atom occurs twice within a group's part of a row.  These tests
+check that invariant, and that the schedule holds exactly the oracle's intramolecular pair list
+(built independently, in Python), for many ligands and plans."""
+import numpy as np
+import pytest
+
+from oracle import ligand as OL
+from workload import configs, synth
+
+md = pytest.importorskip("paper_2203_02096_amd")
+
+CASES = [(4, 1), (6, 2), (10, 3), (20, 4), (33, 7), (40, 8), (64, 12), (65, 12), (90, 20), (128, 32)]
+PLANS = [dict(), dict(group_div=2), dict(group_div=4), dict(group_div=8, waves_per_block=1),
+         dict(lds_budget=0), dict(lds_budget=160 * 1024, waves_per_block=8), dict(lds_budget=20000)]
+
+
+def _lib_available():
+    try:
+        md.lib()
+        return True
+    except Exception:
+        return False
+
+
+pytestmark = pytest.mark.skipif(not _lib_available(), reason="libmdock.so not built")
+
+
+@pytest.mark.parametrize("n,t", CASES)
+@pytest.mark.parametrize("plan", range(len(PLANS)))
+def test_schedule_invariants(n, t, plan):
+    lig = synth.make_ligand(n, t, 5000 + 7 * n + t, configs.type_params())
+    info, slots, m = md.md_schedule_preview(lig, **PLANS[plan])
+    ol = OL.from_synth(lig)
+    rows = info["total_rows"]
+    assert slots.size == rows * 64
+    empty = (slots >> 17) & 1
+    i = slots & 0xFF
+    j = (slots >> 8) & 0xFF
+    # empty slots name atom N at both ends; real slots hold the oracle's pairs, each exactly once
+    assert np.all(i[empty == 1] == n) and np.all(j[empty == 1] == n)
+    real = np.stack([i[empty == 0], j[empty == 0]], 1)
+    assert real.shape[0] == len(ol.pairs)
+    assert np.all(real[:, 0] < real[:, 1]) and np.all(real[:, 1] < n)
+    got = sorted(map(tuple, real.tolist()))
+    want = sorted(map(tuple, np.asarray(ol.pairs).reshape(-1, 2).tolist()))
+    assert got == want
+    # no atom twice within a lane group's part of a row
+    assert 1 <= m <= 64
+    for r in range(rows):
+        for g0 in range(0, 64, m):
+            seg = slice(r * 64 + g0, r * 64 + min(64, g0 + m))
+            atoms = np.concatenate([i[seg][empty[seg] == 0], j[seg][empty[seg] == 0]])
+            assert len(np.unique(atoms)) == len(atoms), (r, g0)
+    # close to the minimum number of rows
+    assert rows >= -(-len(ol.pairs) // 64)
+    assert rows * 64 <= 1.2 * len(ol.pairs) + 128
+    # LDS: staged rows within the budget, and as many as fit
+    budget = PLANS[plan].get("lds_budget", 65536)
+    assert 0 <= info["staged_rows"] <= rows
+    per_row = 64 * 20
+    fixed = info["lds_bytes"] - info["staged_rows"] * per_row
+    assert fixed > 0
+    if info["staged_rows"] > 0:
+        assert info["lds_bytes"] <= budget
+    if info["staged_rows"] < rows:
+        assert info["lds_bytes"] + per_row > budget
+
+
+def test_schedule_preview_rejects_bad_plans():
+    lig = synth.make_ligand(20, 4, 77, configs.type_params())
+    for bad in (dict(group_div=1), dict(group_div=9), dict(waves_per_block=3), dict(lds_budget=-1),
+                dict(lds_budget=160 * 1024 + 1)):
+        with pytest.raises(md.MdockError):
+            md.md_schedule_preview(lig, **bad)
