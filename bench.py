@@ -135,6 +135,9 @@ def main():
     ap.add_argument("--rates", default="50,100,200,350,500",
                     help="serving_fp16: arrival rates (ligands/s)")
     ap.add_argument("--requests", type=int, default=300, help="serving_fp16: requests per rate")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch plans (else every ligand size class is autotuned "
+                         "on the receptor before the timed region)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the docking path has "
@@ -167,6 +170,9 @@ def main():
     P = md.dock_params(**sp)
     gens = md.md_dock_planned_generations(P)
     n_ls = max(0, min(P.pop_size, math.ceil(sp["ls_rate"] * P.pop_size - 1e-4)))
+    # tune the launch plan for this dock's local-search launches (n_runs x n_ls searches)
+    tune = None if args.no_autotune else md.md_ligand_autotune(drec, dlig, n_starts=P.n_runs * n_ls)
+    plan = md.md_ligand_get_plan(dlig)
     ls_evals = P.n_runs * gens * n_ls * P.ls_iters
     total_evals = P.n_runs * (P.pop_size + gens * ((P.pop_size - P.elitism) + n_ls * P.ls_iters))
     stream = torch.cuda.current_stream()
@@ -215,6 +221,7 @@ def main():
                    "n_pairs": info["n_pairs"], "n_runs": P.n_runs, "pop_size": P.pop_size,
                    "max_evals_per_run": P.max_evals_per_run, "generations": gens,
                    "ls_rate": sp["ls_rate"], "ls_iters": P.ls_iters},
+        "launch_plan": {**plan, "autotuned": tune is not None},
         "ligands_per_s": 1.0 / (elapsed / args.steps),
         "total_evals_per_s": total_evals / (elapsed / args.steps),
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
@@ -262,6 +269,9 @@ def bench_batched(args):
     drec = md.Receptor(rec.maps, rec.origin, rec.spacing, "fp32")
     ligs = configs.batched_ligands(name)
     dligs = [md.Ligand.from_synth(l) for l in ligs]
+    t_tune = time.perf_counter()
+    tuned = [] if args.no_autotune else [md.md_ligand_autotune(drec, d) for d in dligs]
+    t_tune = time.perf_counter() - t_tune
     sp = configs.search_params(name, seed=args.seed, max_generations=args.generations)
     P = md.dock_params(**sp)
     jobs = [(d, P) for d in dligs]
@@ -272,13 +282,16 @@ def bench_batched(args):
     ls_evals = len(jobs) * P.n_runs * gens * n_ls * P.ls_iters
     md.md_dock_batch(drec, jobs[:8], want_xyz=False)      # warm-up
     torch.cuda.synchronize()
-    md.md_profile_reset()
-    md.md_profile_enable(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        md.md_dock_batch(drec, jobs, want_xyz=False)
+        md.md_dock_batch(drec, jobs, want_xyz=False)     # each generation one captured graph
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    # one more batch, launched kernel by kernel with HIP events, for the per-kernel breakdown
+    md.md_profile_reset()
+    md.md_profile_enable(True)
+    md.md_dock_batch(drec, jobs, want_xyz=False)
+    torch.cuda.synchronize()
     md.md_profile_enable(False)
     full = configs.search_params(name)
     full_gens = md.md_dock_planned_generations(md.dock_params(**full))
@@ -295,7 +308,11 @@ def bench_batched(args):
            "ligands_per_s_projected": rate / evals_per_ligand_full,
            "projection": f"total evals/s / {evals_per_ligand_full} evals per ligand at the full budget "
                          f"({full_gens} generations)",
-           "kernel_ms_per_step": {k: md.md_profile_read(k)[0] / args.steps for k in md.mdock.KERNELS}}
+           "autotune": {"ligands": len(tuned), "classes_timed": sum(1 for t in tuned if not t["from_table"]),
+                        "seconds": t_tune},
+           "kernel_ms_per_step": {k: md.md_profile_read(k)[0] for k in md.mdock.KERNELS},
+           "kernel_ms_note": "one extra batch launched kernel by kernel (HIP events); the timed batches "
+                             "replay each generation as a HIP graph"}
     print(json.dumps(out), flush=True)
 
 
@@ -315,6 +332,9 @@ def bench_serving(args):
     sizes = configs.serving_sizes(args.requests, seed=205)
     ligs = [md.Ligand.from_synth(synth.make_ligand(n, t, 9000 + k, configs.type_params()))
             for k, (n, t) in enumerate(sizes)]
+    t_tune = time.perf_counter()
+    tuned = [] if args.no_autotune else [md.md_ligand_autotune(drec, d) for d in ligs]
+    t_tune = time.perf_counter() - t_tune
     sp = configs.search_params(name, seed=args.seed)
     P = md.dock_params(**sp)
     n_ls = max(0, min(P.pop_size, math.ceil(sp["ls_rate"] * P.pop_size - 1e-4)))
@@ -348,7 +368,7 @@ def bench_serving(args):
                         "p99_ms": float(np.percentile(steady, 99)),
                         "ligands_per_s": len(tickets) / (max(done) - first),
                         "evals_per_s": len(tickets) * evals_per_req / (max(done) - first),
-                        "wall_s": t_end - t_start, "ticks": st["ticks"]})
+                        "wall_s": t_end - t_start, "ticks": st["ticks"], "busy_s": st["busy_seconds"]})
         print(json.dumps({"partial": results[-1]}), file=sys.stderr, flush=True)
     best = max(results, key=lambda r: r["ligands_per_s"])
     out = {"metric": "ligands docked/s (serving)", "value": best["ligands_per_s"], "unit": "ligands/s",
@@ -357,6 +377,8 @@ def bench_serving(args):
            "config": {"workload": name, "grid": "96^3 x 9 maps FP16", "requests_per_rate": len(ligs),
                       "n_runs": P.n_runs, "pop_size": P.pop_size, "generations": gens,
                       "evals_per_request": evals_per_req, "median_atoms": float(np.median([n for n, _ in sizes]))},
+           "autotune": {"ligands": len(tuned), "classes_timed": sum(1 for t in tuned if not t["from_table"]),
+                        "seconds": t_tune},
            "rates": results}
     print(json.dumps(out), flush=True)
 

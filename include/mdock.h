@@ -151,21 +151,26 @@ typedef struct {
   int candidates;              /* distinct plans timed */
   int from_table;              /* 1: the class was tuned before; its plan was applied untimed */
 } md_tune_info;
-/* Autotuner: times the local-search kernel on `rec` (8192 random starts inside the box, a few
- * ADADELTA steps each, best of three launches) for candidate plans -- waves per block {4, 8} x
- * LDS budget {32, 48, 64, 96, 128, 160} KiB, then lane-group sizes N/2 and N/4 for the best --
- * applies the fastest to `lig` and records it for the ligand's size class (atoms per lane and
- * pair count within a quarter octave), which md_ligand_create then uses for later ligands of
- * that class.  Runs on `hip_stream`, synchronously.  The ligand must not be in use by another
- * call.  info may be NULL.  Errors: MD_EINVAL, MD_EDEVICE. */
-md_status md_ligand_autotune(const md_receptor* rec, md_ligand* lig, int flags, void* hip_stream,
-                             md_tune_info* info);
+/* Autotuner: times the local-search kernel on `rec` for candidate plans -- waves per block
+ * {4, 8} x LDS budget {32, 48, 64, 96, 128, 160} KiB, then lane-group sizes N/2 and N/4 for the
+ * best -- and applies the fastest to `lig`.  n_starts is the number of local searches one launch
+ * will run (md_dock: n_runs x ceil(ls_rate x pop_size)); the candidates are timed on that many
+ * random starts inside the box (a few ADADELTA steps each, best of three launches), since the
+ * best plan depends on how well the launch fills the device.  n_starts = 0 (or >= 8192) tunes
+ * for launches that fill the device many times over (batches, servers): that plan is also
+ * recorded for the ligand's size class (atoms per lane and pair count within a quarter octave),
+ * which md_ligand_create then uses for later ligands of that class, and which a later call for
+ * such a class applies without timing (unless MD_TUNE_FORCE).  Runs on `hip_stream`,
+ * synchronously.  The ligand must not be in use by another call.  info may be NULL.
+ * Errors: MD_EINVAL, MD_ERANGE (n_starts > 2^20), MD_EDEVICE. */
+md_status md_ligand_autotune(const md_receptor* rec, md_ligand* lig, int n_starts, int flags,
+                             void* hip_stream, md_tune_info* info);
 /* Host only (no device needed): the pair schedule that `plan` gives the ligand `d`, for tests and
  * inspection.  On input plan->lds_budget / group_div / waves_per_block; on output the layout
  * fields.  pair_slots (may be NULL) receives min(capacity, total_rows*64) slots, row-major, each
- * i | j << 8 | hbond << 16, with bit 17 set for an empty slot (which names atom n_atoms at both
- * ends); *group_lanes (may be NULL) the lanes per conflict-free group.  Errors as
- * md_ligand_create, plus MD_ERANGE for a bad plan. */
+ * i | j << 8 | hbond << 16 in the library's internal atom order, with bit 17 set for an empty
+ * slot (which names atom n_atoms at both ends); *group_lanes (may be NULL) the lanes per
+ * conflict-free group.  Errors as md_ligand_create, plus MD_ERANGE for a bad plan. */
 md_status md_schedule_preview(const md_ligand_desc* d, md_plan* plan, unsigned* pair_slots, int capacity,
                               int* group_lanes);
 md_status md_tune_table_clear(void);   /* forget every tuned size class */

@@ -111,6 +111,7 @@ hipError_t upload_ligand(const LigHost& h, void** d_buf, LigDev* L) {
   const size_t o_piv = off; off = align16(off + T * sizeof(float4));
   const size_t o_ab = off; off = align16(off + T * sizeof(int2));
   const size_t o_gene = off; off = align16(off + T * sizeof(int));
+  const size_t o_gtor = off; off = align16(off + T * sizeof(int));
   const size_t o_ij = off; off = align16(off + S * sizeof(uint32_t));
   const size_t o_coef = off; off = align16(off + S * sizeof(float4));
   std::vector<char> buf(std::max<size_t>(off, 16), 0);
@@ -122,6 +123,7 @@ hipError_t upload_ligand(const LigHost& h, void** d_buf, LigDev* L) {
   put(o_piv, h.tor_pivot.data(), T * sizeof(float4));
   put(o_ab, h.tor_ab.data(), T * sizeof(int2));
   put(o_gene, h.tor_gene.data(), T * sizeof(int));
+  put(o_gtor, h.gene_tor.data(), T * sizeof(int));
   put(o_ij, h.pair_ij.data(), S * sizeof(uint32_t));
   put(o_coef, h.pair_coef.data(), S * sizeof(float4));
   void* d = nullptr;
@@ -144,6 +146,7 @@ hipError_t upload_ligand(const LigHost& h, void** d_buf, LigDev* L) {
   l.tor_pivot = reinterpret_cast<const float4*>(b + o_piv);
   l.tor_ab = reinterpret_cast<const int2*>(b + o_ab);
   l.tor_gene = reinterpret_cast<const int*>(b + o_gene);
+  l.gene_tor = reinterpret_cast<const int*>(b + o_gtor);
   l.pair_ij = reinterpret_cast<const uint32_t*>(b + o_ij);
   l.pair_coef = reinterpret_cast<const float4*>(b + o_coef);
   l.n_rows = h.n_rows;

@@ -32,6 +32,8 @@ using namespace mdock;
 
 namespace {
 
+constexpr int kFillStarts = 8192;   // local searches that fill the device several times over
+
 // Size class: atoms per lane and a quarter-octave bucket of the pair count.
 std::pair<int, int> size_class(const LigHost& h) {
   const int A = h.n_atoms > kWave ? 2 : 1;
@@ -208,13 +210,17 @@ int md_tune_table_size(void) {
   return (int)g_table.size();
 }
 
-md_status md_ligand_autotune(const md_receptor* rec, md_ligand* lig, int flags, void* hip_stream,
-                             md_tune_info* info) {
+md_status md_ligand_autotune(const md_receptor* rec, md_ligand* lig, int n_starts, int flags,
+                             void* hip_stream, md_tune_info* info) {
   if (!rec || !lig) return api_fail(MD_EINVAL, "md_ligand_autotune: null handle");
   if (flags & ~MD_TUNE_FORCE) return api_fail(MD_EINVAL, "md_ligand_autotune: unknown flags");
+  if (n_starts < 0 || n_starts > (1 << 20)) return api_fail(MD_ERANGE, "md_ligand_autotune: n_starts in [0, 2^20]");
   md_tune_info out{};
   const std::pair<int, int> cls = size_class(lig->host);
-  if (!(flags & MD_TUNE_FORCE)) {
+  // the table holds plans for full-device launches (batches and servers); a plan for a given,
+  // smaller launch is tuned for that launch and kept in the ligand only
+  const bool fill = n_starts == 0 || n_starts >= kFillStarts;
+  if (fill && !(flags & MD_TUNE_FORCE)) {
     TuneEntry hit{};
     bool found = false;
     {
@@ -238,10 +244,10 @@ md_status md_ligand_autotune(const md_receptor* rec, md_ligand* lig, int flags, 
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const RecDev& R = rec->dev;
   const LigHost base = lig->host;
-  // enough poses to fill every compute unit several times; enough steps for ~0.5 ms per launch
-  const int n = 8192;
+  // the launch size to tune for; enough steps for ~0.5 ms per launch
+  const int n = fill ? kFillStarts : n_starts;
   const double slots = (double)base.n_rows * kWave + 64.0;
-  const int iters = (int)std::max(2.0, std::min(50.0, std::round(4e7 / (n * slots))));
+  const int iters = (int)std::max(2.0, std::min(300.0, std::round(4e7 / (n * slots))));
   const std::vector<float> g = tuning_genes(R, base.n_genes, n);
   Bench bench{&R, s, n, iters, nullptr, nullptr, nullptr, nullptr, nullptr};
   const size_t gb = g.size() * sizeof(float);
@@ -327,7 +333,7 @@ md_status md_ligand_autotune(const md_receptor* rec, md_ligand* lig, int flags, 
   if (e != hipSuccess) return api_hip_fail(e, "md_ligand_autotune");
   e = apply_plan(lig, best);
   if (e != hipSuccess) return api_hip_fail(e, "md_ligand_autotune");
-  {
+  if (fill) {
     std::lock_guard<std::mutex> lk(g_table_mu);
     g_table[cls] = TuneEntry{best, best_us};
   }

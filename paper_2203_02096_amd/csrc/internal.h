@@ -62,6 +62,7 @@ struct LigDev {
   const float4* tor_pivot;    // [T] reference position of the root-side atom a
   const int2* tor_ab;         // [T] atoms (a, b)
   const int* tor_gene;        // [T] gene index (7 + caller's torsion index)
+  const int* gene_tor;        // [T] internal torsion of gene 7 + j
   const uint32_t* pair_ij;    // [n_rows*64] i | j << 8 | hbond << 16 (| kPairPad)
   const float4* pair_coef;    // [n_rows*64] weighted C12, weighted C6 or C10, W_el*332*qi*qj,
                               //     W_ds*(S_i V_j + S_j V_i); zero in empty slots
@@ -128,6 +129,7 @@ struct LigHost {
   std::vector<float4> tor_axis, tor_pivot;
   std::vector<int2> tor_ab;
   std::vector<int> tor_gene;
+  std::vector<int> gene_tor;
   std::vector<uint32_t> raw_ij;    // pair list before scheduling
   std::vector<float4> raw_coef;
   std::vector<uint32_t> pair_ij;   // scheduled rows, padded (see LigDev)
@@ -140,9 +142,10 @@ struct LigHost {
 // LDS layout helpers shared by the host plan and the kernels.
 __host__ __device__ inline size_t lds_align16(size_t v) { return (v + 15) & ~size_t(15); }
 // per wave: posed coordinates [64*A + 1] and the force-array copies [n_copies][n_atoms + 1],
-// float4 each (the last entry of each is the spare one that empty slots name)
-__host__ __device__ inline size_t lds_wave_bytes(int n_atoms, int n_copies, int A) {
-  return (size_t)16 * (kWave * A + 1) + (size_t)16 * n_copies * (n_atoms + 1);
+// float4 each (the last entry of each is the spare one that empty slots name), then the torsion
+// table [3*n_tors] float4 (per-pose rotations, later posed axes and pivots)
+__host__ __device__ inline size_t lds_wave_bytes(int n_atoms, int n_copies, int A, int n_tors) {
+  return (size_t)16 * (kWave * A + 1) + (size_t)16 * n_copies * (n_atoms + 1) + (size_t)48 * n_tors;
 }
 __host__ __device__ inline size_t lds_pairs_bytes(int rows) { return (size_t)rows * kWave * (16 + 4); }
 

@@ -106,6 +106,7 @@ struct BlockLds {
   float4* x;                 // this wave: [64*A + 1] posed x, y, z
   float4* f;                 // this wave: [n_copies][n_atoms + 1] intramolecular forces
   float4* fg;                // this lane's group copy
+  float4* tor;               // this wave: [3*n_tors] torsion table (see eval_pose)
 };
 
 extern __shared__ __align__(16) unsigned char g_lds[];
@@ -126,12 +127,14 @@ __device__ __forceinline__ BlockLds stage_block(const LigDev& L) {
   }
   const int w = threadIdx.x / kWave;
   const int lane = lane_id();
-  cur += (size_t)w * lds_wave_bytes(L.n_atoms, L.n_copies, A);
+  cur += (size_t)w * lds_wave_bytes(L.n_atoms, L.n_copies, A, L.n_tors);
   b.pair_coef = pc;
   b.pair_ij = pij;
   b.x = reinterpret_cast<float4*>(cur);
   cur += (size_t)16 * (kWave * A + 1);
   b.f = reinterpret_cast<float4*>(cur);
+  cur += (size_t)16 * L.n_copies * (L.n_atoms + 1);
+  b.tor = reinterpret_cast<float4*>(cur);
   const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
   if (lane == 0) b.x[kWave * A] = z;
   const int nf = L.n_copies * (L.n_atoms + 1);
@@ -152,6 +155,7 @@ struct AtomRegs {
   uint32_t mask[A];
   bool valid[A];
   int gene_of_tor;
+  int tor_of_gene;           // lanes 7 .. G-1: internal torsion of gene `lane`
   float tux, tuy, tuz, tpx, tpy, tpz;
   int ta, tb;
 };
@@ -172,6 +176,7 @@ __device__ __forceinline__ void load_ligand(const LigDev& L, AtomRegs<A>& at) {
     at.mask[a] = at.valid[a] ? L.atom_mask[i] : 0u;
   }
   at.gene_of_tor = 0;
+  at.tor_of_gene = (lane >= 7 && lane < L.n_genes) ? L.gene_tor[lane - 7] : 0;
   at.tux = at.tuy = at.tuz = at.tpx = at.tpy = at.tpz = 0.f;
   at.ta = at.tb = 0;
   if (lane < L.n_tors) {
@@ -411,6 +416,59 @@ __device__ __forceinline__ float pair_rows(const LigDev& L, const BlockLds& b) {
   return e;
 }
 
+// Torsion gradients: for torsion k (posed axis u_k and pivot p_k, held in lane k) the sum over
+// the atoms it moves of u_k . ((x - p_k) x F).  Torsions go in batches of four: each lane forms
+// its atoms' terms for the batch's torsions kb..kb+3, then a reduce-scatter with gfx950's
+// register-half swaps (no lane addresses, no LDS) leaves the 16 lanes of row r holding parts of
+// torsion kb + r's sum -- v_permlane32_swap pairs torsions (kb, kb+2) and (kb+1, kb+3) across the
+// wave halves, v_permlane16_swap pairs the results across rows -- and the row's DPP sum (the
+// first four steps of wave_sum) completes it.  Gene lane L (torsion tk) reads its torsion's row.
+template <int A>
+__device__ __forceinline__ float torsion_gradients(const AtomRegs<A>& at, int T, float3 tu, float3 tp,
+                                                   const float* x, const float* y, const float* z,
+                                                   const float* Fx, const float* Fy, const float* Fz) {
+  const int tk = at.tor_of_gene;
+  float g = 0.f;
+  for (int kb = 0; kb < T; kb += 4) {
+    float c[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = kb + j;
+      c[j] = 0.f;
+      if (k < T) {
+        const float ux = readlane(tu.x, k), uy = readlane(tu.y, k), uz = readlane(tu.z, k);
+        const float px = readlane(tp.x, k), py = readlane(tp.y, k), pz = readlane(tp.z, k);
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+          if ((at.mask[a] >> k) & 1u) {
+            const float rx = x[a] - px, ry = y[a] - py, rz = z[a] - pz;
+            const float cx = ry * Fz[a] - rz * Fy[a];
+            const float cy = rz * Fx[a] - rx * Fz[a];
+            const float cz = rx * Fy[a] - ry * Fx[a];
+            c[j] += ux * cx + uy * cy + uz * cz;
+          }
+        }
+      }
+    }
+    // lanes 0-31 end with torsion kb (h0) / kb+1 (h1) summed over both halves, lanes 32-63
+    // with kb+2 / kb+3
+    const auto s0 = __builtin_amdgcn_permlane32_swap(__float_as_uint(c[0]), __float_as_uint(c[2]), false, false);
+    const auto s1 = __builtin_amdgcn_permlane32_swap(__float_as_uint(c[1]), __float_as_uint(c[3]), false, false);
+    const float h0 = __uint_as_float(s0[0]) + __uint_as_float(s0[1]);
+    const float h1 = __uint_as_float(s1[0]) + __uint_as_float(s1[1]);
+    // rows 0, 1, 2, 3 end with torsions kb, kb+1, kb+2, kb+3
+    const auto s2 = __builtin_amdgcn_permlane16_swap(__float_as_uint(h0), __float_as_uint(h1), false, false);
+    float v = __uint_as_float(s2[0]) + __uint_as_float(s2[1]);
+    v += dpp<0xb1, 0xf>(v);    // quad_perm [1,0,3,2]
+    v += dpp<0x4e, 0xf>(v);    // quad_perm [2,3,0,1]
+    v += dpp<0x141, 0xf>(v);   // row_half_mirror
+    v += dpp<0x140, 0xf>(v);   // row_mirror
+    const float mine = __shfl(v, ((tk - kb) & 3) * 16, kWave);
+    if (tk >= kb && tk < kb + 4) g = mine;
+  }
+  return g;
+}
+
 // ------------------------------------------------------------------ one pose
 // Energy (returned, identical in every lane) and, with GRAD, the gradient component of
 // gene `lane` (lanes >= n_genes get 0).  xg: gene `lane` of the pose (lanes < n_genes).
@@ -445,8 +503,23 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, 
     tcs = __builtin_amdgcn_cosf(rev);
   }
 
-  // pose: torsions from the deepest to the root-most, each about its reference-frame axis,
-  // applied by every lane whose atom it moves; then orientation and translation.
+  // pose: torsions from the deepest to the root-most, each a rotation about its reference-frame
+  // axis through its reference pivot, applied by every lane whose atom it moves; then
+  // orientation and translation.  Lane k builds torsion k's rotation as x -> M x + t (Rodrigues:
+  // M = c I + s [u]x + (1 - c) u u^T, t = p - M p) in the wave's torsion table, from which the
+  // atom loop reads it with broadcast loads.
+  if (lane < T) {
+    const float c = tcs, sn = tsn, oc = 1.f - tcs;
+    const float ux = at.tux, uy = at.tuy, uz = at.tuz;
+    const float m00 = oc * ux * ux + c, m01 = oc * ux * uy - sn * uz, m02 = oc * ux * uz + sn * uy;
+    const float m10 = oc * uy * ux + sn * uz, m11 = oc * uy * uy + c, m12 = oc * uy * uz - sn * ux;
+    const float m20 = oc * uz * ux - sn * uy, m21 = oc * uz * uy + sn * ux, m22 = oc * uz * uz + c;
+    const float vx = at.tpx, vy = at.tpy, vz = at.tpz;
+    b.tor[3 * lane + 0] = make_float4(m00, m01, m02, vx - (m00 * vx + m01 * vy + m02 * vz));
+    b.tor[3 * lane + 1] = make_float4(m10, m11, m12, vy - (m10 * vx + m11 * vy + m12 * vz));
+    b.tor[3 * lane + 2] = make_float4(m20, m21, m22, vz - (m20 * vx + m21 * vy + m22 * vz));
+  }
+  wave_sync();
   float px[A], py[A], pz[A];
 #pragma unroll
   for (int a = 0; a < A; ++a) {
@@ -455,19 +528,14 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, 
     pz[a] = at.pz[a];
   }
   for (int k = T - 1; k >= 0; --k) {
-    const float ux = readlane(at.tux, k), uy = readlane(at.tuy, k), uz = readlane(at.tuz, k);
-    const float vpx = readlane(at.tpx, k), vpy = readlane(at.tpy, k), vpz = readlane(at.tpz, k);
-    const float cs = readlane(tcs, k), sn = readlane(tsn, k);
+    const float4 m0 = b.tor[3 * k + 0], m1 = b.tor[3 * k + 1], m2 = b.tor[3 * k + 2];
 #pragma unroll
     for (int a = 0; a < A; ++a) {
       if ((at.mask[a] >> k) & 1u) {
-        const float vx = px[a] - vpx, vy = py[a] - vpy, vz = pz[a] - vpz;
-        const float ud = ux * vx + uy * vy + uz * vz;
-        const float cx = uy * vz - uz * vy, cy = uz * vx - ux * vz, cz = ux * vy - uy * vx;
-        const float omc = (1.f - cs) * ud;
-        px[a] = vpx + vx * cs + cx * sn + ux * omc;
-        py[a] = vpy + vy * cs + cy * sn + uy * omc;
-        pz[a] = vpz + vz * cs + cz * sn + uz * omc;
+        const float ox = px[a], oy = py[a], oz = pz[a];
+        px[a] = m0.x * ox + m0.y * oy + m0.z * oz + m0.w;
+        py[a] = m1.x * ox + m1.y * oy + m1.z * oz + m1.w;
+        pz[a] = m2.x * ox + m2.y * oy + m2.z * oz + m2.w;
       }
     }
   }
@@ -550,38 +618,20 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, 
   if (lane == 5) g = 2.f * (qw * tqy - (qz * tqx - qx * tqz)) * iqn;
   if (lane == 6) g = 2.f * (qw * tqz - (qx * tqy - qy * tqx)) * iqn;
 
-  // torsions: lane k forms the posed axis and pivot of torsion k; then for each k every lane
-  // adds axis . (arm x force) of its atoms moved by k
-  float aux = 0.f, auy = 0.f, auz = 0.f, apx = 0.f, apy = 0.f, apz = 0.f;
-  if (lane < T) {
-    const float4 xa = b.x[at.ta], xb = b.x[at.tb];
-    aux = xb.x - xa.x;
-    auy = xb.y - xa.y;
-    auz = xb.z - xa.z;
-    const float il = __builtin_amdgcn_rsqf(aux * aux + auy * auy + auz * auz);
-    aux *= il;
-    auy *= il;
-    auz *= il;
-    apx = xa.x;
-    apy = xa.y;
-    apz = xa.z;
-  }
-  for (int k = 0; k < T; ++k) {
-    const float ux = readlane(aux, k), uy = readlane(auy, k), uz = readlane(auz, k);
-    const float pax = readlane(apx, k), pay = readlane(apy, k), paz = readlane(apz, k);
-    float c = 0.f;
-#pragma unroll
-    for (int a = 0; a < A; ++a) {
-      if ((at.mask[a] >> k) & 1u) {
-        const float rx = x[a] - pax, ry = y[a] - pay, rz = z[a] - paz;
-        const float cx = ry * Fz[a] - rz * Fy[a];
-        const float cy = rz * Fx[a] - rx * Fz[a];
-        const float cz = rx * Fy[a] - ry * Fx[a];
-        c += ux * cx + uy * cy + uz * cz;
-      }
+  // torsions: lane k forms the posed axis and pivot of torsion k; every lane then forms, for
+  // every torsion k, axis . (arm x force) of its atoms that k moves, and reduce-scatters across
+  // the wave sum four torsions at a time.
+  if (T > 0) {
+    float3 tu = make_float3(0.f, 0.f, 0.f), tp = make_float3(0.f, 0.f, 0.f);
+    if (lane < T) {
+      const float4 xa = b.x[at.ta], xb = b.x[at.tb];
+      const float ux = xb.x - xa.x, uy = xb.y - xa.y, uz = xb.z - xa.z;
+      const float il = __builtin_amdgcn_rsqf(ux * ux + uy * uy + uz * uz);
+      tu = make_float3(ux * il, uy * il, uz * il);
+      tp = make_float3(xa.x, xa.y, xa.z);
     }
-    c = wave_sum(c);
-    if (lane == readlane_i(at.gene_of_tor, k)) g = c;
+    const float gk = torsion_gradients<A>(at, T, tu, tp, x, y, z, Fx, Fy, Fz);
+    if (lane >= 7 && lane < L.n_genes) g = gk;
   }
   g_out = g;
   return E;

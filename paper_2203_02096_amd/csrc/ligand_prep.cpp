@@ -179,6 +179,8 @@ std::string prepare_ligand(int n, const float* xyz, const int* type, const float
       out.pair_coef.push_back(make_float4((float)c12, (float)cn, (float)qq, (float)ds));
     }
   }
+  out.gene_tor.assign(out.n_tors, 0);
+  for (int k = 0; k < out.n_tors; ++k) out.gene_tor[out.tor_gene[k] - 7] = k;
   out.raw_ij = out.pair_ij;
   out.raw_coef = out.pair_coef;
   plan_ligand(out, PlanParams());
@@ -254,7 +256,7 @@ void plan_ligand(LigHost& out, const PlanParams& pp) {
   out.plan = pp;
   out.wpb = std::max(1, std::min(kMaxWavesPerBlock, pp.wpb));
   const size_t budget = (size_t)std::max(0, std::min(pp.lds_budget, kMaxLdsPerBlock));
-  const size_t waves = (size_t)out.wpb * lds_wave_bytes(n, out.n_copies, A);
+  const size_t waves = (size_t)out.wpb * lds_wave_bytes(n, out.n_copies, A, out.n_tors);
   int pr = out.n_rows;
   while (pr > 0 && waves + lds_pairs_bytes(pr) > budget) --pr;
   out.pl_rows = pr;

@@ -112,7 +112,7 @@ SIGNATURES = {
     "md_set_graphs": (C.c_int, [C.c_int]),
     "md_ligand_get_plan": (C.c_int, [C.c_void_p, C.POINTER(Plan)]),
     "md_ligand_set_plan": (C.c_int, [C.c_void_p, C.POINTER(Plan)]),
-    "md_ligand_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.POINTER(TuneInfo)]),
+    "md_ligand_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.POINTER(TuneInfo)]),
     "md_tune_table_clear": (C.c_int, []),
     "md_schedule_preview": (C.c_int, [C.POINTER(LigandDesc), C.POINTER(Plan), C.POINTER(C.c_uint), C.c_int,
                                       C.POINTER(C.c_int)]),
@@ -354,11 +354,12 @@ def md_ligand_set_plan(lig: Ligand, lds_budget=65536, group_div=3, waves_per_blo
     return md_ligand_get_plan(lig)
 
 
-def md_ligand_autotune(rec: Receptor, lig: Ligand, force=False, stream=None):
-    """Times candidate launch plans of the ligand on this receptor and keeps the fastest."""
+def md_ligand_autotune(rec: Receptor, lig: Ligand, n_starts=0, force=False, stream=None):
+    """Times candidate launch plans of the ligand on this receptor for launches of n_starts local
+    searches (0: launches that fill the device) and keeps the fastest."""
     info = TuneInfo()
-    _check(lib().md_ligand_autotune(rec.handle, lig.handle, 1 if force else 0, _stream_ptr(stream),
-                                    C.byref(info)), "md_ligand_autotune")
+    _check(lib().md_ligand_autotune(rec.handle, lig.handle, int(n_starts), 1 if force else 0,
+                                    _stream_ptr(stream), C.byref(info)), "md_ligand_autotune")
     return dict(plan=_plan_dict(info.plan), us_per_eval=info.us_per_eval,
                 default_us_per_eval=info.default_us_per_eval, candidates=info.candidates,
                 from_table=bool(info.from_table))

@@ -107,7 +107,7 @@ def test_null_handles_rejected(md):
     plan = md.mdock.Plan(65536, 3, 4, 0, 0, 0)
     assert lib.md_ligand_get_plan(None, C.byref(plan)) == -1
     assert lib.md_ligand_set_plan(None, C.byref(plan)) == -1
-    assert lib.md_ligand_autotune(None, None, 0, None, None) == -1
+    assert lib.md_ligand_autotune(None, None, 0, 0, None, None) == -1
     assert lib.md_schedule_preview(None, C.byref(plan), None, 0, None) == -1
     assert lib.md_server_create(None, None, None) == -1
 
