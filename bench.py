@@ -37,19 +37,23 @@ PROFILE = os.path.join(ROOT, "profiles", "k_local_search_plain_fp32_production.t
 KERNEL_SRC = os.path.join(ROOT, "paper_2203_02096_amd", "csrc", "kernels.hip")
 
 
-def measured_traffic():
-    """HBM bytes per local-search launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary, or None when the kernel source has changed since those counters were taken."""
+def measured_profile():
+    """Figures from the committed rocprofv3 summary of the local-search kernel: HBM bytes per
+    launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's counts) and VALU issue utilisation
+    (SQ_INSTS_VALU); None for each when the kernel source has changed since they were taken."""
     import hashlib
+    none = {"traffic": None, "valu_issue_utilisation": None, "valu_instructions_per_eval": None}
     try:
         text = open(PROFILE).read()
         sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
     except OSError:
-        return None
+        return none
     vals = dict(l.split(": ", 1) for l in text.splitlines() if ": " in l and not l.startswith(" "))
     if vals.get("kernel_source_sha256", "").strip() != sha:
-        return None
-    return float(vals["traffic_bytes_per_launch"])
+        return none
+    return {"traffic": float(vals["traffic_bytes_per_launch"]),
+            "valu_issue_utilisation": float(vals["valu_issue_utilisation"]),
+            "valu_instructions_per_eval": float(vals["valu_instructions_per_eval"])}
 
 
 def flop_model(n_atoms, n_torsions, n_pairs, sum_moving):
@@ -203,6 +207,7 @@ def main():
     achieved_tflops = flops_eval * evals_per_ls_launch / avg_ls_s / 1e12
     hbm_gbs = bytes_model(info["n_atoms"]) * evals_per_ls_launch / avg_ls_s / 1e9
     lat_ms = np.array(lat) * 1e3
+    prof = measured_profile()
     out = {
         "metric": "energy+gradient evals/s",
         "value": value,
@@ -227,7 +232,10 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_VALU_TFLOPS,
-                     "traffic": measured_traffic(), "kernel": "k_local_search",
+                     "traffic": prof["traffic"], "kernel": "k_ga_local_search",
+                     "frac_of_nonpacked_fp32": achieved_tflops / (PEAK_FP32_VALU_TFLOPS / 2),
+                     "valu_issue_utilisation": prof["valu_issue_utilisation"],
+                     "valu_instructions_per_eval": prof["valu_instructions_per_eval"],
                      "flop_per_eval": flops_eval, "evals_per_launch": evals_per_ls_launch,
                      "avg_launch_ms": avg_ls_s * 1e3, "launches": ls_n,
                      "hbm_algorithmic_GBs": hbm_gbs, "hbm_frac": hbm_gbs / PEAK_HBM_GBS},
