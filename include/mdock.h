@@ -268,6 +268,31 @@ typedef struct {
 } md_dock_job;
 md_status md_dock_batch(const md_receptor* rec, int n_jobs, const md_dock_job* jobs, void* hip_stream);
 
+/* Batch autotuner.  In a batch, ligands of different sizes share launches (one per size class
+ * and GA phase, as parallel branches of the captured generation), so the plan that is fastest
+ * for a ligand alone on the whole device need not be fastest in the mix.  This times whole-batch
+ * plan policies on the batch itself -- md_dock_batch of these ligands and parameters, run to
+ * generations/3 and to `generations` generations, the per-generation time being the difference
+ * over the extra generations (which leaves out per-call costs) -- and applies the fastest policy
+ * to every ligand: MD_POLICY_DEFAULT (every ligand on the default plan),
+ * MD_POLICY_TUNED_ALONE (md_ligand_autotune for full-device launches, per size class),
+ * MD_POLICY_LDS_ALL (LDS budget 160 KiB: all pair rows staged), MD_POLICY_WIDE_BLOCKS (8 waves
+ * per block), MD_POLICY_SMALL_GROUPS (lane groups of about N/2).  The ligands must not be in use
+ * by another call.  Blocking.  info may be NULL.  Errors: MD_EINVAL, MD_ERANGE
+ * (generations outside [2, 1000]), and md_dock_batch's. */
+enum {
+  MD_POLICY_DEFAULT = 0, MD_POLICY_TUNED_ALONE = 1, MD_POLICY_LDS_ALL = 2, MD_POLICY_WIDE_BLOCKS = 3,
+  MD_POLICY_SMALL_GROUPS = 4, MD_BATCH_POLICIES = 5
+};
+typedef struct {
+  int policy;                     /* the policy applied */
+  int n_policies;
+  double ms_per_generation[8];    /* measured per policy (index = policy) */
+} md_batch_tune_info;
+md_status md_batch_autotune(const md_receptor* rec, int n, md_ligand* const* ligands,
+                            const md_dock_params* params, int generations, void* hip_stream,
+                            md_batch_tune_info* info);
+
 /* Number of generations md_dock runs for these parameters (all runs share it). */
 int md_dock_planned_generations(const md_dock_params* params);
 

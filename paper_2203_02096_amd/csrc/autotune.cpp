@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -346,4 +347,96 @@ md_status md_ligand_autotune(const md_receptor* rec, md_ligand* lig, int n_start
   return MD_OK;
 }
 
+// Batch autotuner.  A batch mixes ligand sizes in shared launches (one per size class and phase,
+// in parallel graph branches), so the plan that is fastest for a ligand alone on the whole device
+// need not be fastest in the mix.  Here whole-batch plan policies are timed on the batch itself,
+// for a few generations each, and the fastest is applied to every ligand.
+md_status md_batch_autotune(const md_receptor* rec, int n, md_ligand* const* ligands,
+                            const md_dock_params* params, int generations, void* hip_stream,
+                            md_batch_tune_info* info) {
+  if (!rec || n < 1 || !ligands || !params) return api_fail(MD_EINVAL, "md_batch_autotune: null argument");
+  if (generations < 2 || generations > 1000) return api_fail(MD_ERANGE, "md_batch_autotune: generations in [2, 1000]");
+  for (int k = 0; k < n; ++k)
+    if (!ligands[k]) return api_fail(MD_EINVAL, "md_batch_autotune: null ligand");
+  // scratch results and shortened searches: each policy is timed at g1 and at g2 generations and
+  // charged (t2 - t1) / (g2 - g1) per generation, which leaves out the per-call costs
+  // (workspace, schedule, graph capture, initial population)
+  const int g2 = std::max(2, generations), g1 = std::max(1, g2 / 3);
+  std::vector<md_dock_params> P(params, params + n);
+  for (auto& p : P) p.max_evals_per_run = (long long)1 << 62;
+  std::vector<std::vector<float>> be(n), bg(n);
+  std::vector<md_dock_result> res(n);
+  std::vector<md_dock_job> jobs(n);
+  for (int k = 0; k < n; ++k) {
+    be[k].resize(P[k].n_runs);
+    bg[k].resize((size_t)P[k].n_runs * ligands[k]->dev.n_genes);
+    res[k] = md_dock_result{};
+    res[k].n_runs = P[k].n_runs;
+    res[k].n_genes = ligands[k]->dev.n_genes;
+    res[k].n_atoms = ligands[k]->dev.n_atoms;
+    res[k].best_energy = be[k].data();
+    res[k].best_genes = bg[k].data();
+    jobs[k] = md_dock_job{ligands[k], P[k], &res[k]};
+  }
+  auto apply_all = [&](const std::vector<PlanParams>& plans) -> md_status {
+    for (int k = 0; k < n; ++k) {
+      LigHost probe = ligands[k]->host;
+      plan_ligand(probe, plans[k]);
+      if (probe.lds_bytes > kMaxLdsPerBlock) continue;   // keep the ligand's current plan
+      hipError_t e = apply_plan(ligands[k], plans[k]);
+      if (e != hipSuccess) return api_hip_fail(e, "md_batch_autotune");
+    }
+    return MD_OK;
+  };
+  auto run = [&](int gens, double* ms) -> md_status {
+    for (int k = 0; k < n; ++k) jobs[k].params.max_generations = gens;
+    const auto t0 = std::chrono::steady_clock::now();
+    const md_status st = md_dock_batch(rec, n, jobs.data(), hip_stream);
+    *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return st;
+  };
+  auto time_batch = [&](double* ms) -> md_status {
+    double t1 = 0.0, t2 = 0.0;
+    md_status st = run(g1, &t1);                  // warm-up (first use of the plans)
+    if (st == MD_OK) st = run(g1, &t1);
+    if (st == MD_OK) st = run(g2, &t2);
+    *ms = std::max(t2 - t1, 1e-6) / (g2 - g1);
+    return st;
+  };
+  const int n_pol = MD_BATCH_POLICIES;
+  std::vector<std::vector<PlanParams>> plans(n_pol, std::vector<PlanParams>(n));
+  for (int k = 0; k < n; ++k) {
+    plans[MD_POLICY_LDS_ALL][k].lds_budget = kMaxLdsPerBlock;
+    plans[MD_POLICY_WIDE_BLOCKS][k].wpb = 8;
+    plans[MD_POLICY_SMALL_GROUPS][k].group_div = 2;
+  }
+  md_batch_tune_info out{};
+  out.n_policies = n_pol;
+  double best = 1e300;
+  for (int pol = 0; pol < n_pol; ++pol) {
+    md_status st = MD_OK;
+    if (pol == MD_POLICY_TUNED_ALONE) {
+      for (int k = 0; k < n && st == MD_OK; ++k) {
+        st = md_ligand_autotune(rec, ligands[k], 0, 0, hip_stream, nullptr);
+        plans[pol][k] = ligands[k]->host.plan;
+      }
+    } else {
+      st = apply_all(plans[pol]);
+    }
+    double ms = 0.0;
+    if (st == MD_OK) st = time_batch(&ms);
+    if (st != MD_OK) return st;
+    out.ms_per_generation[pol] = ms;
+    if (ms < best) {
+      best = ms;
+      out.policy = pol;
+    }
+  }
+  md_status st = apply_all(plans[out.policy]);
+  if (st != MD_OK) return st;
+  if (info) *info = out;
+  return MD_OK;
+}
+
 }  // extern "C"
+

@@ -196,8 +196,11 @@ using LaunchHook = std::function<hipError_t(int, const std::function<hipError_t(
 void build_schedule(const std::vector<SchedJob>& jobs, GenSchedule& out);
 hipError_t launch_init_phase(const GenSchedule& g, JobDev* table, const int2* d_blocks, const RecDev& R,
                              hipStream_t s, const LaunchHook* hook);
+// side: optional streams across which a phase's size-class launches are forked (used while
+// capturing a graph, where they become parallel branches).
 hipError_t launch_generation_phase(const GenSchedule& g, JobDev* table, int n_table, const int2* d_blocks,
-                                   const RecDev& R, hipStream_t s, const LaunchHook* hook);
+                                   const RecDev& R, hipStream_t s, const LaunchHook* hook,
+                                   const std::vector<hipStream_t>* side = nullptr);
 // One generation captured as a HIP graph (on a private stream) and replayed on any stream.
 class GenGraph {
  public:

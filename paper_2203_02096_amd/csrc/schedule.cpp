@@ -26,6 +26,7 @@ namespace mdock {
 namespace {
 
 constexpr int kLdsPerCu = 160 * 1024;
+constexpr size_t kGraphBranches = 4;   // concurrent size-class launches in a captured phase
 
 // blocks of this LDS size that fit on one compute unit
 int occupancy_class(int lds) { return lds <= 0 ? 64 : std::min(64, kLdsPerCu / lds); }
@@ -93,24 +94,58 @@ hipError_t launch_init_phase(const GenSchedule& g, JobDev* table, const int2* d_
   return e;
 }
 
-hipError_t launch_generation_phase(const GenSchedule& g, JobDev* table, int n_table, const int2* d_blocks,
-                                   const RecDev& R, hipStream_t s, const LaunchHook* hook) {
+namespace {
+
+// Launches the phase's size-class launches one after another on s, or, with side streams,
+// forked across s and the side streams (joined back into s before returning): during graph
+// capture that makes them parallel branches, so one class's tail overlaps another's work.
+hipError_t launch_phase(const std::vector<PhaseLaunch>& launches, hipStream_t s,
+                        const std::vector<hipStream_t>* side, int kind, const LaunchHook* hook,
+                        const std::function<hipError_t(const PhaseLaunch&, hipStream_t)>& one) {
   hipError_t e = hipSuccess;
-  auto run = [&](int kind, const std::function<hipError_t()>& f) { return hook ? (*hook)(kind, f) : f(); };
-  for (const PhaseLaunch& pl : g.pop) {
-    e = run(MD_K_GENERATION,
-            [&] { return launch_ga_generation(table, d_blocks + pl.first, pl.count, pl.A, pl.wpb, pl.lds, R, s); });
-    if (e != hipSuccess) return e;
+  if (!side || side->empty() || launches.size() < 2) {
+    for (const PhaseLaunch& pl : launches) {
+      auto f = [&] { return one(pl, s); };
+      e = hook ? (*hook)(kind, f) : f();
+      if (e != hipSuccess) return e;
+    }
+    return e;
   }
+  const size_t n_side = std::min(side->size(), launches.size() - 1);
+  std::vector<hipEvent_t> ev(1 + n_side, nullptr);
+  for (hipEvent_t& x : ev) {
+    e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
+    if (e != hipSuccess) break;
+  }
+  if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+  for (size_t k = 0; k < n_side && e == hipSuccess; ++k) e = hipStreamWaitEvent((*side)[k], ev[0], 0);
+  for (size_t i = 0; i < launches.size() && e == hipSuccess; ++i)
+    e = one(launches[i], i == 0 ? s : (*side)[(i - 1) % n_side]);
+  for (size_t k = 0; k < n_side && e == hipSuccess; ++k) e = hipEventRecord(ev[1 + k], (*side)[k]);
+  for (size_t k = 0; k < n_side && e == hipSuccess; ++k) e = hipStreamWaitEvent(s, ev[1 + k], 0);
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  return e;
+}
+
+}  // namespace
+
+hipError_t launch_generation_phase(const GenSchedule& g, JobDev* table, int n_table, const int2* d_blocks,
+                                   const RecDev& R, hipStream_t s, const LaunchHook* hook,
+                                   const std::vector<hipStream_t>* side) {
+  hipError_t e = launch_phase(g.pop, s, side, MD_K_GENERATION, hook, [&](const PhaseLaunch& pl, hipStream_t st) {
+    return launch_ga_generation(table, d_blocks + pl.first, pl.count, pl.A, pl.wpb, pl.lds, R, st);
+  });
+  if (e != hipSuccess) return e;
+  auto run = [&](int kind, const std::function<hipError_t()>& f) { return hook ? (*hook)(kind, f) : f(); };
   if (g.run_count > 0) {
     e = run(MD_K_LS_PICK, [&] { return launch_ga_ls_pick(table, d_blocks + g.run_first, g.run_count, s); });
     if (e != hipSuccess) return e;
   }
-  for (const PhaseLaunch& pl : g.ls) {
-    e = run(MD_K_LOCAL_SEARCH,
-            [&] { return launch_ga_local_search(table, d_blocks + pl.first, pl.count, pl.A, pl.wpb, pl.lds, R, s); });
-    if (e != hipSuccess) return e;
-  }
+  e = launch_phase(g.ls, s, side, MD_K_LOCAL_SEARCH, hook, [&](const PhaseLaunch& pl, hipStream_t st) {
+    return launch_ga_local_search(table, d_blocks + pl.first, pl.count, pl.A, pl.wpb, pl.lds, R, st);
+  });
+  if (e != hipSuccess) return e;
   return run(MD_K_SUM_EVALS, [&] { return launch_ga_advance(table, n_table, s); });
 }
 
@@ -121,9 +156,18 @@ hipError_t GenGraph::capture(const GenSchedule& g, JobDev* table, int n_table, c
   hipStream_t cs = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e != hipSuccess) return e;
-  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  // side streams for the parallel branches of the phases with several size-class launches
+  std::vector<hipStream_t> side;
+  size_t width = 1;
+  for (const auto* v : {&g.pop, &g.ls}) width = std::max(width, v->size());
+  for (size_t k = 0; k + 1 < std::min<size_t>(width, kGraphBranches) && e == hipSuccess; ++k) {
+    hipStream_t x = nullptr;
+    e = hipStreamCreateWithFlags(&x, hipStreamNonBlocking);
+    if (e == hipSuccess) side.push_back(x);
+  }
+  if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    hipError_t el = launch_generation_phase(g, table, n_table, d_blocks, R, cs, nullptr);
+    hipError_t el = launch_generation_phase(g, table, n_table, d_blocks, R, cs, nullptr, &side);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cs, &graph);
     if (e == hipSuccess) e = el;
@@ -134,6 +178,7 @@ hipError_t GenGraph::capture(const GenSchedule& g, JobDev* table, int n_table, c
       exec_ = nullptr;
     }
   }
+  for (hipStream_t x : side) (void)hipStreamDestroy(x);
   (void)hipStreamDestroy(cs);
   return e;
 }

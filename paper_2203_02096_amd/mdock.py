@@ -73,6 +73,13 @@ class TuneInfo(C.Structure):
                 ("candidates", C.c_int), ("from_table", C.c_int)]
 
 
+class BatchTuneInfo(C.Structure):
+    _fields_ = [("policy", C.c_int), ("n_policies", C.c_int), ("ms_per_generation", C.c_double * 8)]
+
+
+BATCH_POLICIES = ["default", "tuned_alone", "lds_all", "wide_blocks", "small_groups"]
+
+
 class DockJob(C.Structure):
     _fields_ = [("ligand", C.c_void_p), ("params", DockParams), ("result", C.POINTER(DockResult))]
 
@@ -114,6 +121,8 @@ SIGNATURES = {
     "md_ligand_set_plan": (C.c_int, [C.c_void_p, C.POINTER(Plan)]),
     "md_ligand_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.POINTER(TuneInfo)]),
     "md_tune_table_clear": (C.c_int, []),
+    "md_batch_autotune": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_void_p), C.POINTER(DockParams), C.c_int,
+                                    C.c_void_p, C.POINTER(BatchTuneInfo)]),
     "md_schedule_preview": (C.c_int, [C.POINTER(LigandDesc), C.POINTER(Plan), C.POINTER(C.c_uint), C.c_int,
                                       C.POINTER(C.c_int)]),
     "md_tune_table_size": (C.c_int, []),
@@ -384,6 +393,20 @@ def md_schedule_preview(lig, lds_budget=65536, group_div=3, waves_per_block=4):
     _check(lib().md_schedule_preview(C.byref(d), C.byref(p2), slots.ctypes.data_as(C.POINTER(C.c_uint)),
                                      slots.size, C.byref(gl)), "md_schedule_preview")
     return _plan_dict(p2), slots, gl.value
+
+
+def md_batch_autotune(rec: Receptor, jobs, generations=6, stream=None):
+    """Times whole-batch launch-plan policies on the batch itself (jobs: (Ligand, DockParams)
+    pairs, run to generations/3 and to `generations` generations) and applies the fastest to
+    every ligand."""
+    jobs = list(jobs)
+    ligs = (C.c_void_p * len(jobs))(*[l.handle.value for l, _ in jobs])
+    params = (DockParams * len(jobs))(*[p for _, p in jobs])
+    info = BatchTuneInfo()
+    _check(lib().md_batch_autotune(rec.handle, len(jobs), ligs, params, int(generations), _stream_ptr(stream),
+                                   C.byref(info)), "md_batch_autotune")
+    return dict(policy=BATCH_POLICIES[info.policy],
+                ms_per_generation={BATCH_POLICIES[k]: info.ms_per_generation[k] for k in range(info.n_policies)})
 
 
 def md_tune_table_clear():

@@ -125,3 +125,28 @@ def test_autotune_and_table(md, receptor):
         assert np.array_equal(a[k], b[k]), k
     md.md_tune_table_clear()
     assert md.md_tune_table_size() == 0
+
+
+def test_batch_autotune(md, receptor):
+    """The batch tuner times every policy on the batch, applies one, and afterwards a batch's
+    results still equal each ligand docked alone; best energies re-scored by the oracle agree."""
+    from oracle import scoring as S
+    rec, drec = receptor
+    sizes = [(14, 2), (36, 7), (70, 15), (52, 9), (95, 24), (25, 4)]
+    ligs = [synth.make_ligand(n, t, 1500 + k, configs.type_params()) for k, (n, t) in enumerate(sizes)]
+    dligs = [md.Ligand.from_synth(l) for l in ligs]
+    Ps = [md.dock_params(**configs.search_params("serving_fp16", n_runs=3, pop_size=40, max_generations=4,
+                                                 ls_rate=0.2, ls_iters=20, seed=70 + k)) for k in range(len(ligs))]
+    info = md.md_batch_autotune(drec, list(zip(dligs, Ps)), generations=4)
+    _say(f"[batch autotune] {info}")
+    assert info["policy"] in md.mdock.BATCH_POLICIES
+    assert all(v > 0 for v in info["ms_per_generation"].values())
+    batch = md.md_dock_batch(drec, list(zip(dligs, Ps)))
+    grid = oracle_grid(rec)
+    for k, (dl, P) in enumerate(zip(dligs, Ps)):
+        alone = md.md_dock(drec, dl, P)
+        for key in ("best_energy", "best_genes", "evals"):
+            assert np.array_equal(batch[k][key], alone[key]), (k, key)
+        r = S.energy_and_gradient(grid, oracle_ligand(ligs[k]), batch[k]["best_genes"][0].astype(np.float64))
+        assert abs(float(batch[k]["best_energy"][0]) - r.energy) <= 1e-4 * max(abs(r.energy), r.scale_energy)
+    md.md_tune_table_clear()
