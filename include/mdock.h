@@ -301,8 +301,10 @@ int md_dock_planned_generations(const md_dock_params* params);
  * high-throughput screening workflow over many heterogeneous ligands; introduction and its
  * workflow figure).  A worker thread admits queued requests (FIFO) into free slots while their
  * device buffers (populations, counters, results) fit in a pool of hbm_budget_bytes, advances
- * every resident request by one generation per tick with the batched GA kernels, and retires
- * finished requests at once, freeing their slot and memory for the next admission.  A
+ * every resident request with the batched GA kernels -- with graphs, each size class of
+ * resident ligands by as many generations per tick (up to 8) as fit in the time the most
+ * expensive class takes for one; without, one generation per tick -- and retires finished
+ * requests at once, freeing their slot and memory for the next admission.  A
  * request's result equals md_dock of the same ligand and parameters.
  * The receptor and every submitted ligand must stay alive until the server is destroyed (or
  * the request is released).  Calls are thread-safe.  md_server_destroy drops queued requests,

@@ -52,6 +52,9 @@ uint16_t f32_to_f16_rne(float f) {
 
 size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
+// Generations per captured graph of md_dock_batch: fewer joins of the size classes' branches.
+constexpr int kBatchGraphGenerations = 4;
+
 // Optional per-kernel timing of md_dock's launches (HIP events on the dock's stream).
 struct Profiler {
   bool on = false;
@@ -455,7 +458,7 @@ md_status md_dock_batch(const md_receptor* rec, int n_jobs, const md_dock_job* j
     max_planned = std::max(max_planned, md_dock_planned_generations(&p));
   }
   GenSchedule sched;
-  build_schedule(sched_jobs, sched);
+  build_schedule(sched_jobs, sched, 0, kBatchGraphGenerations);
   const size_t o_blocks = cv.take(sizeof(int2) * std::max<size_t>(sched.blocks.size(), 1));
   const size_t o_results = cv.off;
   for (int j = 0; j < n_jobs; ++j) {
@@ -524,11 +527,14 @@ md_status md_dock_batch(const md_receptor* rec, int n_jobs, const md_dock_job* j
   if (e == hipSuccess) e = timer.run(MD_K_SUM_EVALS, [&] { return launch_ga_advance(d_table, n_jobs, s); });
   if (g_prof.on || !use_graphs() || max_planned < 2) {
     for (int g = 1; g <= max_planned && e == hipSuccess; ++g)
-      e = launch_generation_phase(sched, d_table, n_jobs, d_blocks, R, s, &hook);
+      e = launch_generation_phase(sched, d_table, d_blocks, R, s, &hook);
   } else {
+    // each replay runs kBatchGraphGenerations generations of every class (the classes as
+    // parallel branches); generations past a job's plan are skipped on the device
     GenGraph graph;
-    if (e == hipSuccess) e = graph.capture(sched, d_table, n_jobs, d_blocks, R);
-    for (int g = 1; g <= max_planned && e == hipSuccess; ++g) e = graph.launch(s);
+    if (e == hipSuccess) e = graph.capture(sched, d_table, d_blocks, R);
+    const int replays = (max_planned + kBatchGraphGenerations - 1) / kBatchGraphGenerations;
+    for (int g = 0; g < replays && e == hipSuccess; ++g) e = graph.launch(s);
     // the graph's launches read the workspace: finish them before the graph is destroyed
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   }

@@ -176,6 +176,8 @@ hipError_t launch_ga_local_search(JobDev* jobs, const int2* blocks, int n_blocks
 // Lets every evaluation kernel take up to kMaxLdsPerBlock of dynamic LDS (once per device).
 hipError_t enable_large_lds();
 hipError_t launch_ga_advance(JobDev* jobs, int n_jobs, hipStream_t s);
+// the epilogue for the jobs list[k].x, k < n
+hipError_t launch_ga_advance_list(JobDev* jobs, const int2* list, int n, hipStream_t s);
 
 // Per-generation launch schedule over a job table (schedule.cpp).
 struct SchedJob {
@@ -183,32 +185,38 @@ struct SchedJob {
   const LigDev* L;
   int n_runs, pop_size, n_ls, ls_iters;
 };
-struct PhaseLaunch {
-  int A, wpb, lds, first, count;   // atoms per lane, waves per block, dynamic LDS, block range
+// One size class's generation chain: GA generation (+ initial population), local-search picks,
+// local search, epilogue -- each a range of the block array (pick blocks cover four runs each,
+// epilogue entries name one job each) -- repeated `reps` times per captured phase.
+struct ClassChain {
+  int A, wpb, lds;
+  int pop_first, pop_count, ls_first, ls_count, run_first, run_count, adv_first, adv_count;
+  int reps;
+  double latency;             // relative serial cost of one generation of the class's slowest job
 };
 struct GenSchedule {
-  std::vector<int2> blocks;   // (slot, first wave) of every block of every launch
-  std::vector<PhaseLaunch> pop, ls;
-  int run_first = 0, run_count = 0;
+  std::vector<int2> blocks;   // (slot, first wave) of every block; (slot, 0) epilogue entries
+  std::vector<ClassChain> classes;
 };
 // Optional wrapper around each launch (kind: md_kernel_kind), e.g. for timing.
 using LaunchHook = std::function<hipError_t(int, const std::function<hipError_t()>&)>;
-void build_schedule(const std::vector<SchedJob>& jobs, GenSchedule& out);
+// max_reps: 0 -> every class runs `uniform_reps` generations per phase; else each class runs
+// about (slowest class's latency / its latency) generations, at most max_reps.
+void build_schedule(const std::vector<SchedJob>& jobs, GenSchedule& out, int max_reps = 0, int uniform_reps = 1);
 hipError_t launch_init_phase(const GenSchedule& g, JobDev* table, const int2* d_blocks, const RecDev& R,
                              hipStream_t s, const LaunchHook* hook);
-// side: optional streams across which a phase's size-class launches are forked (used while
-// capturing a graph, where they become parallel branches).
-hipError_t launch_generation_phase(const GenSchedule& g, JobDev* table, int n_table, const int2* d_blocks,
-                                   const RecDev& R, hipStream_t s, const LaunchHook* hook,
-                                   const std::vector<hipStream_t>* side = nullptr);
-// One generation captured as a HIP graph (on a private stream) and replayed on any stream.
+// One generation of every class, kernel by kernel on s (reps ignored).
+hipError_t launch_generation_phase(const GenSchedule& g, JobDev* table, const int2* d_blocks,
+                                   const RecDev& R, hipStream_t s, const LaunchHook* hook);
+// Generations captured as a HIP graph (on private streams) and replayed on any stream.
 class GenGraph {
  public:
   GenGraph() = default;
   GenGraph(const GenGraph&) = delete;
   GenGraph& operator=(const GenGraph&) = delete;
   ~GenGraph() { reset(); }
-  hipError_t capture(const GenSchedule& g, JobDev* table, int n_table, const int2* d_blocks, const RecDev& R);
+  // each class's chain `reps` times, classes as parallel branches joined at the end
+  hipError_t capture(const GenSchedule& g, JobDev* table, const int2* d_blocks, const RecDev& R);
   hipError_t launch(hipStream_t s) const;
   bool ready() const { return exec_ != nullptr; }
   void reset();

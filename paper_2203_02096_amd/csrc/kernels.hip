@@ -1018,11 +1018,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_ga_local_search(JobDev* __restric
 // Generation epilogue, one wave per job: the per-run evaluation sum (the miniapp's
 // sum_evals), then the job's state advances -- a freshly initialised job starts running, a
 // running job swaps its population buffers and moves to the next generation -- and a job whose
-// planned generations are done gets its best individual per run.
-__global__ __launch_bounds__(kBlock) void k_ga_advance(JobDev* __restrict__ jobs, int n_jobs) {
-  const int j = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-  if (j >= n_jobs) return;
-  JobDev& J = jobs[j];
+// planned generations are done gets its best individual per run.  list: NULL (jobs 0..n-1) or
+// [n] entries whose .x is the job.
+__global__ __launch_bounds__(kBlock) void k_ga_advance(JobDev* __restrict__ jobs, const int2* __restrict__ list,
+                                                       int n_jobs) {
+  const int w = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  if (w >= n_jobs) return;
+  JobDev& J = jobs[list ? list[w].x : w];
   const int state = J.state;
   if (state != kJobInit && state != kJobRunning) return;
   const GaDev P = J.P;
@@ -1182,7 +1184,13 @@ hipError_t launch_ga_local_search(JobDev* jobs, const int2* blocks, int n_blocks
 
 hipError_t launch_ga_advance(JobDev* jobs, int n_jobs, hipStream_t s) {
   if (n_jobs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ga_advance, dim3(blocks_for(n_jobs)), dim3(kBlock), 0, s, jobs, n_jobs);
+  hipLaunchKernelGGL(k_ga_advance, dim3(blocks_for(n_jobs)), dim3(kBlock), 0, s, jobs, (const int2*)nullptr, n_jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_ga_advance_list(JobDev* jobs, const int2* list, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ga_advance, dim3(blocks_for(n)), dim3(kBlock), 0, s, jobs, list, n);
   return hipGetLastError();
 }
 

@@ -1,18 +1,21 @@
 // Per-generation launch schedule of the job-table GA kernels, shared by md_dock_batch and the
 // docking server, and its capture as a HIP graph.
 //
-// Ligands of very different sizes go through the same generation (the paper's screening
+// Ligands of very different sizes go through the same launches (the paper's screening
 // workflow docks a heterogeneous ligand stream; its discussion of heterogeneously sized
-// ligands makes load balance part of the problem).  Two choices here keep one large ligand
-// from setting the cost of many small ones:
-//  * size classes: jobs are grouped by atoms per lane and by how many blocks of their LDS
-//    plan fit on a compute unit, and each group is one launch with that group's LDS size, so
-//    a small ligand never runs with a large ligand's LDS reservation (and lower occupancy);
+// ligands makes load balance part of the problem).  Three choices here keep large ligands from
+// setting the pace of small ones:
+//  * size classes: jobs are grouped by atoms per lane, waves per block and how many blocks of
+//    their LDS plan fit on a compute unit; each class has its own chain of launches with the
+//    class's LDS size, so a small ligand never runs with a large ligand's LDS reservation;
 //  * longest first: inside a launch, the blocks of the most expensive jobs come first, so the
-//    long waves start early and the short ones fill the tail.
-// One generation (selection/crossover/mutation + evaluation, local-search picks, local search,
-// epilogue) reads everything it needs from the device job table, so the same sequence of
-// launches serves every generation and is captured once and replayed.
+//    long waves start early and the short ones fill the tail;
+//  * independent chains: a class's generation (selection/crossover/mutation + evaluation,
+//    local-search picks, local search, epilogue) depends only on its own jobs, so in a captured
+//    phase the classes are parallel graph branches, and a cheap class may run several
+//    generations while an expensive one runs one.
+// Every kernel reads what it needs from the device job table (a finished job's work is skipped
+// on the device), so the same captured phase serves every generation and is replayed.
 #include <algorithm>
 #include <map>
 #include <numeric>
@@ -26,7 +29,7 @@ namespace mdock {
 namespace {
 
 constexpr int kLdsPerCu = 160 * 1024;
-constexpr size_t kGraphBranches = 4;   // concurrent size-class launches in a captured phase
+constexpr size_t kGraphBranches = 4;   // streams for the classes' parallel branches
 
 // blocks of this LDS size that fit on one compute unit
 int occupancy_class(int lds) { return lds <= 0 ? 64 : std::min(64, kLdsPerCu / lds); }
@@ -38,136 +41,138 @@ double eval_cost(const LigDev& L) {
 
 }  // namespace
 
-void build_schedule(const std::vector<SchedJob>& jobs, GenSchedule& out) {
+void build_schedule(const std::vector<SchedJob>& jobs, GenSchedule& out, int max_reps, int uniform_reps) {
   out = GenSchedule();
-  // bucket key: (atoms per lane, waves per block, occupancy class); larger classes first
+  // class key: (atoms per lane, waves per block, -(waves per CU)); denser classes first
   using Key = std::tuple<int, int, int>;
-  std::map<Key, std::vector<int>> pop_b, ls_b;
+  std::map<Key, std::vector<int>> cls;
   for (int k = 0; k < (int)jobs.size(); ++k) {
     const SchedJob& j = jobs[k];
     const int A = j.L->n_atoms > kWave ? 2 : 1;
-    const Key key(A, j.L->wpb, -occupancy_class(j.L->lds_bytes) * j.L->wpb);
-    pop_b[key].push_back(k);
-    if (j.n_ls > 0) ls_b[key].push_back(k);
+    cls[Key(A, j.L->wpb, -occupancy_class(j.L->lds_bytes) * j.L->wpb)].push_back(k);
   }
-  auto emit = [&](std::map<Key, std::vector<int>>& buckets, bool ls, std::vector<PhaseLaunch>& launches) {
-    for (auto& kv : buckets) {
-      std::vector<int>& members = kv.second;
-      std::vector<double> cost(jobs.size(), 0.0);
-      for (int k : members) {
-        const SchedJob& j = jobs[k];
-        cost[k] = eval_cost(*j.L) * (ls ? (double)j.ls_iters : 1.0);
-      }
-      std::stable_sort(members.begin(), members.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-      PhaseLaunch pl;
-      pl.A = std::get<0>(kv.first);
-      pl.wpb = std::get<1>(kv.first);
-      pl.lds = 0;
-      pl.first = (int)out.blocks.size();
-      for (int k : members) {
-        const SchedJob& j = jobs[k];
-        const long long waves = ls ? (long long)j.n_runs * j.n_ls : (long long)j.n_runs * j.pop_size;
-        for (long long w = 0; w < waves; w += pl.wpb) out.blocks.push_back(make_int2(j.slot, (int)w));
-        pl.lds = std::max(pl.lds, j.L->lds_bytes);
-      }
-      pl.count = (int)out.blocks.size() - pl.first;
-      if (pl.count > 0) launches.push_back(pl);
+  std::vector<double> cost(jobs.size());
+  for (size_t k = 0; k < jobs.size(); ++k) {
+    const SchedJob& j = jobs[k];
+    cost[k] = eval_cost(*j.L) * (1.0 + (j.n_ls > 0 ? (double)j.ls_iters : 0.0));
+  }
+  for (auto& kv : cls) {
+    std::vector<int>& m = kv.second;
+    std::stable_sort(m.begin(), m.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    ClassChain c{};
+    c.A = std::get<0>(kv.first);
+    c.wpb = std::get<1>(kv.first);
+    c.pop_first = (int)out.blocks.size();
+    for (int k : m) {
+      const SchedJob& j = jobs[k];
+      const long long waves = (long long)j.n_runs * j.pop_size;
+      for (long long w = 0; w < waves; w += c.wpb) out.blocks.push_back(make_int2(j.slot, (int)w));
+      c.lds = std::max(c.lds, j.L->lds_bytes);
+      c.latency = std::max(c.latency, cost[k]);
     }
-  };
-  emit(pop_b, false, out.pop);
-  emit(ls_b, true, out.ls);
-  out.run_first = (int)out.blocks.size();
-  for (const SchedJob& j : jobs)
-    if (j.n_ls > 0)
-      for (int r = 0; r < j.n_runs; r += kWavesPerBlock) out.blocks.push_back(make_int2(j.slot, r));
-  out.run_count = (int)out.blocks.size() - out.run_first;
+    c.pop_count = (int)out.blocks.size() - c.pop_first;
+    c.ls_first = (int)out.blocks.size();
+    for (int k : m) {
+      const SchedJob& j = jobs[k];
+      const long long waves = (long long)j.n_runs * j.n_ls;
+      for (long long w = 0; w < waves; w += c.wpb) out.blocks.push_back(make_int2(j.slot, (int)w));
+    }
+    c.ls_count = (int)out.blocks.size() - c.ls_first;
+    c.run_first = (int)out.blocks.size();
+    for (int k : m) {
+      const SchedJob& j = jobs[k];
+      if (j.n_ls > 0)
+        for (int r = 0; r < j.n_runs; r += kWavesPerBlock) out.blocks.push_back(make_int2(j.slot, r));
+    }
+    c.run_count = (int)out.blocks.size() - c.run_first;
+    c.adv_first = (int)out.blocks.size();
+    for (int k : m) out.blocks.push_back(make_int2(jobs[k].slot, 0));
+    c.adv_count = (int)out.blocks.size() - c.adv_first;
+    out.classes.push_back(c);
+  }
+  double slowest = 0.0;
+  for (const ClassChain& c : out.classes) slowest = std::max(slowest, c.latency);
+  for (ClassChain& c : out.classes) {
+    if (max_reps <= 0) {
+      c.reps = std::max(1, uniform_reps);
+    } else {
+      const double r = c.latency > 0.0 ? std::floor(slowest / c.latency) : 1.0;
+      c.reps = (int)std::max(1.0, std::min((double)max_reps, r));
+    }
+  }
 }
 
 hipError_t launch_init_phase(const GenSchedule& g, JobDev* table, const int2* d_blocks, const RecDev& R,
                              hipStream_t s, const LaunchHook* hook) {
-  hipError_t e = hipSuccess;
-  for (const PhaseLaunch& pl : g.pop) {
-    auto f = [&] { return launch_ga_init(table, d_blocks + pl.first, pl.count, pl.A, pl.wpb, pl.lds, R, s); };
-    e = hook ? (*hook)(MD_K_INIT_POPULATION, f) : f();
+  for (const ClassChain& c : g.classes) {
+    auto f = [&] { return launch_ga_init(table, d_blocks + c.pop_first, c.pop_count, c.A, c.wpb, c.lds, R, s); };
+    const hipError_t e = hook ? (*hook)(MD_K_INIT_POPULATION, f) : f();
     if (e != hipSuccess) return e;
   }
-  return e;
+  return hipSuccess;
 }
 
 namespace {
 
-// Launches the phase's size-class launches one after another on s, or, with side streams,
-// forked across s and the side streams (joined back into s before returning): during graph
-// capture that makes them parallel branches, so one class's tail overlaps another's work.
-hipError_t launch_phase(const std::vector<PhaseLaunch>& launches, hipStream_t s,
-                        const std::vector<hipStream_t>* side, int kind, const LaunchHook* hook,
-                        const std::function<hipError_t(const PhaseLaunch&, hipStream_t)>& one) {
-  hipError_t e = hipSuccess;
-  if (!side || side->empty() || launches.size() < 2) {
-    for (const PhaseLaunch& pl : launches) {
-      auto f = [&] { return one(pl, s); };
-      e = hook ? (*hook)(kind, f) : f();
-      if (e != hipSuccess) return e;
-    }
-    return e;
-  }
-  const size_t n_side = std::min(side->size(), launches.size() - 1);
-  std::vector<hipEvent_t> ev(1 + n_side, nullptr);
-  for (hipEvent_t& x : ev) {
-    e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
-    if (e != hipSuccess) break;
-  }
-  if (e == hipSuccess) e = hipEventRecord(ev[0], s);
-  for (size_t k = 0; k < n_side && e == hipSuccess; ++k) e = hipStreamWaitEvent((*side)[k], ev[0], 0);
-  for (size_t i = 0; i < launches.size() && e == hipSuccess; ++i)
-    e = one(launches[i], i == 0 ? s : (*side)[(i - 1) % n_side]);
-  for (size_t k = 0; k < n_side && e == hipSuccess; ++k) e = hipEventRecord(ev[1 + k], (*side)[k]);
-  for (size_t k = 0; k < n_side && e == hipSuccess; ++k) e = hipStreamWaitEvent(s, ev[1 + k], 0);
-  for (hipEvent_t x : ev)
-    if (x) (void)hipEventDestroy(x);
+// One generation of one class on stream st.
+hipError_t launch_chain(const ClassChain& c, JobDev* table, const int2* d_blocks, const RecDev& R, hipStream_t st,
+                        const LaunchHook* hook) {
+  auto run = [&](int kind, const std::function<hipError_t()>& f) { return hook ? (*hook)(kind, f) : f(); };
+  hipError_t e = run(MD_K_GENERATION, [&] {
+    return launch_ga_generation(table, d_blocks + c.pop_first, c.pop_count, c.A, c.wpb, c.lds, R, st);
+  });
+  if (e == hipSuccess && c.run_count > 0)
+    e = run(MD_K_LS_PICK, [&] { return launch_ga_ls_pick(table, d_blocks + c.run_first, c.run_count, st); });
+  if (e == hipSuccess && c.ls_count > 0)
+    e = run(MD_K_LOCAL_SEARCH, [&] {
+      return launch_ga_local_search(table, d_blocks + c.ls_first, c.ls_count, c.A, c.wpb, c.lds, R, st);
+    });
+  if (e == hipSuccess)
+    e = run(MD_K_SUM_EVALS, [&] { return launch_ga_advance_list(table, d_blocks + c.adv_first, c.adv_count, st); });
   return e;
 }
 
 }  // namespace
 
-hipError_t launch_generation_phase(const GenSchedule& g, JobDev* table, int n_table, const int2* d_blocks,
-                                   const RecDev& R, hipStream_t s, const LaunchHook* hook,
-                                   const std::vector<hipStream_t>* side) {
-  hipError_t e = launch_phase(g.pop, s, side, MD_K_GENERATION, hook, [&](const PhaseLaunch& pl, hipStream_t st) {
-    return launch_ga_generation(table, d_blocks + pl.first, pl.count, pl.A, pl.wpb, pl.lds, R, st);
-  });
-  if (e != hipSuccess) return e;
-  auto run = [&](int kind, const std::function<hipError_t()>& f) { return hook ? (*hook)(kind, f) : f(); };
-  if (g.run_count > 0) {
-    e = run(MD_K_LS_PICK, [&] { return launch_ga_ls_pick(table, d_blocks + g.run_first, g.run_count, s); });
+hipError_t launch_generation_phase(const GenSchedule& g, JobDev* table, const int2* d_blocks,
+                                   const RecDev& R, hipStream_t s, const LaunchHook* hook) {
+  for (const ClassChain& c : g.classes) {
+    const hipError_t e = launch_chain(c, table, d_blocks, R, s, hook);
     if (e != hipSuccess) return e;
   }
-  e = launch_phase(g.ls, s, side, MD_K_LOCAL_SEARCH, hook, [&](const PhaseLaunch& pl, hipStream_t st) {
-    return launch_ga_local_search(table, d_blocks + pl.first, pl.count, pl.A, pl.wpb, pl.lds, R, st);
-  });
-  if (e != hipSuccess) return e;
-  return run(MD_K_SUM_EVALS, [&] { return launch_ga_advance(table, n_table, s); });
+  return hipSuccess;
 }
 
-// ------------------------------------------------------------------ captured generation
-hipError_t GenGraph::capture(const GenSchedule& g, JobDev* table, int n_table, const int2* d_blocks,
-                             const RecDev& R) {
+// ------------------------------------------------------------------ captured generations
+hipError_t GenGraph::capture(const GenSchedule& g, JobDev* table, const int2* d_blocks, const RecDev& R) {
   reset();
   hipStream_t cs = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e != hipSuccess) return e;
-  // side streams for the parallel branches of the phases with several size-class launches
+  // side streams for the classes' parallel branches
   std::vector<hipStream_t> side;
-  size_t width = 1;
-  for (const auto* v : {&g.pop, &g.ls}) width = std::max(width, v->size());
-  for (size_t k = 0; k + 1 < std::min<size_t>(width, kGraphBranches) && e == hipSuccess; ++k) {
+  const size_t width = std::min(g.classes.size(), kGraphBranches);
+  for (size_t k = 0; k + 1 < width && e == hipSuccess; ++k) {
     hipStream_t x = nullptr;
     e = hipStreamCreateWithFlags(&x, hipStreamNonBlocking);
     if (e == hipSuccess) side.push_back(x);
   }
+  std::vector<hipEvent_t> ev(1 + side.size(), nullptr);
+  for (hipEvent_t& x : ev)
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    hipError_t el = launch_generation_phase(g, table, n_table, d_blocks, R, cs, nullptr, &side);
+    // fork: every side stream waits for the start of the capture; class i runs on stream
+    // i mod width (0 = the capture stream); then every side stream joins back
+    hipError_t el = hipEventRecord(ev[0], cs);
+    for (size_t k = 0; k < side.size() && el == hipSuccess; ++k) el = hipStreamWaitEvent(side[k], ev[0], 0);
+    for (size_t i = 0; i < g.classes.size() && el == hipSuccess; ++i) {
+      const ClassChain& c = g.classes[i];
+      hipStream_t st = (i % width == 0) ? cs : side[i % width - 1];
+      for (int r = 0; r < c.reps && el == hipSuccess; ++r) el = launch_chain(c, table, d_blocks, R, st, nullptr);
+    }
+    for (size_t k = 0; k < side.size() && el == hipSuccess; ++k) el = hipEventRecord(ev[1 + k], side[k]);
+    for (size_t k = 0; k < side.size() && el == hipSuccess; ++k) el = hipStreamWaitEvent(cs, ev[1 + k], 0);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cs, &graph);
     if (e == hipSuccess) e = el;
@@ -178,6 +183,8 @@ hipError_t GenGraph::capture(const GenSchedule& g, JobDev* table, int n_table, c
       exec_ = nullptr;
     }
   }
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
   for (hipStream_t x : side) (void)hipStreamDestroy(x);
   (void)hipStreamDestroy(cs);
   return e;

@@ -44,6 +44,10 @@ double now_s() {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// With graphs, a tick advances each size class by up to this many generations: cheap classes
+// run several while the most expensive runs one, so the device stays busy through its tail.
+constexpr int kTickMaxGenerations = 8;
+
 // First-fit allocator over one device pool (offsets only).
 class Pool {
  public:
@@ -215,7 +219,7 @@ hipError_t run_tick(md_server* s, bool any_init, bool any_running) {
       const md_dock_params& p = r->params;
       jobs.push_back(SchedJob{j, &r->lig->dev, p.n_runs, p.pop_size, n_local_search_of(&p), p.ls_iters});
     }
-    build_schedule(jobs, s->sched);
+    build_schedule(jobs, s->sched, (s->params.use_graphs && use_graphs()) ? kTickMaxGenerations : 0, 1);
     s->graph.reset();
     const size_t nb = s->sched.blocks.size();
     if (nb > s->blocks_cap) {
@@ -238,10 +242,10 @@ hipError_t run_tick(md_server* s, bool any_init, bool any_running) {
     if (!any_running) {
       e = launch_ga_advance(s->d_table, n_slots, s->stream);
     } else if (s->params.use_graphs && use_graphs()) {
-      if (!s->graph.ready()) e = s->graph.capture(s->sched, s->d_table, n_slots, s->d_blocks, R);
+      if (!s->graph.ready()) e = s->graph.capture(s->sched, s->d_table, s->d_blocks, R);
       if (e == hipSuccess) e = s->graph.launch(s->stream);
     } else {
-      e = launch_generation_phase(s->sched, s->d_table, n_slots, s->d_blocks, R, s->stream, nullptr);
+      e = launch_generation_phase(s->sched, s->d_table, s->d_blocks, R, s->stream, nullptr);
     }
   }
   if (e == hipSuccess)
