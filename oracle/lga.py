@@ -26,7 +26,10 @@ unpinned beyond the invariants the tests check):
     wrapped to (-pi, pi];
   * local search on ceil(ls_rate * pop) distinct individuals: those whose random
     key (ties to the lower index) ranks lowest;
-  * evaluation budget: each GA evaluation counts 1, each ADADELTA step 1; the
+  * local optimiser: ADADELTA (`adadelta`, the default) or Solis-Wets (`solis_wets`,
+    ls_method="solis_wets"), which the paper names; either spends exactly ls_iters
+    evaluations per searched individual;
+  * evaluation budget: each GA evaluation counts 1, each local-search evaluation 1; the
     budget is checked at generation boundaries (the last generation may overshoot).
 Random numbers: `rng` (a counter-based draw per decision).
 """
@@ -39,6 +42,7 @@ import numpy as np
 
 from . import rng as R
 from .adadelta import local_search
+from .solis_wets import local_search_sw
 from .pose import quat_mul, wrap_angle
 from .scoring import energy
 
@@ -61,6 +65,7 @@ class DockParams:
     mut_rot: float = math.pi / 2
     mut_tors: float = math.pi
     seed: int = 7
+    ls_method: str = "adadelta"
 
 
 def n_local_search(p: DockParams) -> int:
@@ -208,7 +213,10 @@ def run_lga(grid, lig, p: DockParams, run: int, trace=None):
             counts[j] += 1
         if n_ls:
             for i in local_search_picks(p, run, gen):
-                bx, be = local_search(grid, lig, new[i], p.ls_iters, p.rho, p.eps)
+                if p.ls_method == "solis_wets":
+                    bx, be = local_search_sw(grid, lig, new[i], p.ls_iters, p.seed, run, gen, i)
+                else:
+                    bx, be = local_search(grid, lig, new[i], p.ls_iters, p.rho, p.eps)
                 new[i], newE[i] = bx, be
                 counts[i] += p.ls_iters
         evals += int(counts.sum())

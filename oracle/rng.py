@@ -22,6 +22,7 @@ P_TOURNAMENT = 2
 P_CROSSOVER = 3
 P_MUTATION = 4
 P_LS_PICK = 5
+P_LS_SW = 6
 
 
 def splitmix64(x: int) -> int:
