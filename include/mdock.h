@@ -212,6 +212,26 @@ md_status md_local_search(const md_receptor* rec, const md_ligand* lig, int n,
                           float* energy_out_dev, int n_iters, float rho, float eps,
                           float* trace_dev, void* hip_stream);
 
+/* Solis-Wets random search (Solis and Wets, Math. Oper. Res. 6(1), 1981; the local optimiser
+ * the paper names in Background, "Design and Structure of MiniMDock") from each start
+ * genotype.  From x with energy E: xi ~ N(b, (rho sigma)^2) per gene (sigma 0.5 A for the
+ * translation, 0.05 per quaternion component, 0.25 rad per torsion); x + xi is taken if its
+ * energy is lower, else x - xi if that is lower; b <- 0.2 b + 0.4 xi after a + success,
+ * b - 0.4 xi after a - success, b / 2 after a double failure; rho (from 1) doubles after 4
+ * successes in a row, at most 4, and halves after 4 failures in a row, at least 0.01.  Moved
+ * genotypes get a renormalised quaternion and torsions wrapped to (-pi, pi].  Exactly n_evals
+ * energy evaluations: the start point, then one or two per step (a step cut short by the
+ * budget tries x + xi only).  Normals: Box-Muller z = sqrt(-2 ln u1) cos(2 pi u2) with
+ * u1 = (k1 + 1) / 2^24, u2 = k2 / 2^24 from the counter-based draws (seed, 0, 0, start k,
+ * purpose 6, index 2m) and (..., 2m + 1), m = 64 step + gene.  Outputs the final genotype
+ * (the lowest energy evaluated) and its energy.
+ * genes_in_dev/genes_out_dev [n][n_genes] (may alias), energy_out_dev [n];
+ * trace_dev: NULL or [n][n_evals] energies of every evaluation.
+ * Errors: MD_EINVAL (null, n < 0, n_evals < 1), MD_ERANGE (n_evals > 2^24), MD_EDEVICE. */
+md_status md_local_search_sw(const md_receptor* rec, const md_ligand* lig, int n,
+                             const float* genes_in_dev, float* genes_out_dev, float* energy_out_dev,
+                             int n_evals, unsigned long long seed, float* trace_dev, void* hip_stream);
+
 /* ------------------------------------------------------------------ docking
  * Lamarckian GA (Background, "Design and Structure of MiniMDock"): n_runs independent runs
  * of pop_size individuals.  Initial individuals: translation uniform in the grid box,
@@ -221,8 +241,10 @@ md_status md_local_search(const md_receptor* rec, const md_ligand* lig, int n,
  * with crossover_rate, per-unit mutation with mutation_rate (t += U(-mut_trans,
  * mut_trans), q <- normalise(r (x) q) with r a rotation by U(-mut_rot, mut_rot) about a
  * uniform axis, theta += U(-mut_tors, mut_tors)), energy of the new individuals, then
- * ADADELTA (ls_iters steps, rho, eps) on ceil(ls_rate * pop_size) distinct random
- * individuals, written back.  Evaluations are counted per individual and summed per run
+ * a local search of ls_iters evaluations on ceil(ls_rate * pop_size) distinct random
+ * individuals, written back: ADADELTA (rho, eps; md_local_search) or Solis-Wets
+ * (md_local_search_sw, individual i of run r in generation g drawing from (seed, r, g, i)),
+ * chosen by ls_method.  Evaluations are counted per individual and summed per run
  * (sum_evals); a run stops at the first generation boundary where its count reaches
  * max_evals_per_run or max_generations generations have run.  Random numbers:
  * SplitMix64 counter hash of (seed, run, generation, individual, purpose, index).
@@ -238,7 +260,9 @@ typedef struct {
   int elitism;                 /* 0 or 1 */
   float mut_trans, mut_rot, mut_tors;
   unsigned long long seed;
+  int ls_method;               /* MD_LS_ADADELTA or MD_LS_SOLIS_WETS (ls_iters <= 2^24) */
 } md_dock_params;
+enum { MD_LS_ADADELTA = 0, MD_LS_SOLIS_WETS = 1 };
 
 typedef struct {
   int n_runs, n_genes, n_atoms;   /* capacities set by the caller (>= the problem's) */

@@ -110,9 +110,14 @@ def solis_wets(f, x0, n_evals, normal, sigma, project=lambda x: x, record=None):
     return x, e, trace
 
 
-def local_search_sw(grid, lig, genes0, n_evals, seed, run=0, gen=0, indiv=0, trace=False):
-    """Solis-Wets on a ligand's genotype; returns (genes, energy[, energies of every evaluation])."""
-    x, e, tr = solis_wets(lambda g: energy(grid, lig, g), genes0, n_evals,
+def local_search_sw(grid, lig, genes0, n_evals, seed, run=0, gen=0, indiv=0, trace=False, points=None):
+    """Solis-Wets on a ligand's genotype; returns (genes, energy[, energies of every evaluation]).
+    points (a list) receives every evaluated genotype, in order."""
+    def f(g):
+        if points is not None:
+            points.append(g.copy())
+        return energy(grid, lig, g)
+    x, e, tr = solis_wets(f, genes0, n_evals,
                           counter_normals(seed, run, gen, indiv), sigmas(lig.n_genes),
                           project=lambda g: project_genes(g, lig.n_torsions))
     if trace:

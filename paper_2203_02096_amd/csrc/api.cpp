@@ -358,6 +358,21 @@ md_status md_local_search(const md_receptor* rec, const md_ligand* lig, int n, c
   return MD_OK;
 }
 
+md_status md_local_search_sw(const md_receptor* rec, const md_ligand* lig, int n, const float* genes_in,
+                             float* genes_out, float* energy_out, int n_evals, unsigned long long seed,
+                             float* trace, void* hip_stream) {
+  if (!rec || !lig) return fail(MD_EINVAL, "md_local_search_sw: null handle");
+  if (n < 0) return fail(MD_EINVAL, "md_local_search_sw: n < 0");
+  if (n_evals < 1) return fail(MD_EINVAL, "md_local_search_sw: n_evals must be >= 1");
+  if (n_evals > (1 << 24)) return fail(MD_ERANGE, "md_local_search_sw: n_evals must be <= 2^24");
+  if (n == 0) return MD_OK;
+  if (!genes_in || !genes_out || !energy_out) return fail(MD_EINVAL, "md_local_search_sw: null buffer");
+  MD_HIP(launch_solis_wets(lig->dev, rec->dev, n, genes_in, genes_out, energy_out, n_evals, seed, trace,
+                           static_cast<hipStream_t>(hip_stream)),
+         "md_local_search_sw launch");
+  return MD_OK;
+}
+
 int md_dock_planned_generations(const md_dock_params* p) {
   if (!p || p->pop_size < 1) return -1;
   const long long per = (long long)(p->pop_size - (p->elitism ? 1 : 0)) +
@@ -384,6 +399,8 @@ std::string check_params(const md_dock_params* p) {
   if (p->max_generations < 0 || p->max_evals_per_run < 0) return "negative budget";
   if (!(p->ls_rate >= 0.f && p->ls_rate <= 1.f)) return "ls_rate must be in [0,1]";
   if (n_local_search(p) > 0 && p->ls_iters < 1) return "ls_iters must be >= 1";
+  if (p->ls_method != MD_LS_ADADELTA && p->ls_method != MD_LS_SOLIS_WETS) return "unknown ls_method";
+  if (p->ls_method == MD_LS_SOLIS_WETS && p->ls_iters > (1 << 24)) return "Solis-Wets ls_iters must be <= 2^24";
   if (!(p->rho >= 0.f && p->rho < 1.f) || !(p->eps > 0.f)) return "bad rho/eps";
   const float rates[3] = {p->crossover_rate, p->mutation_rate, p->tournament_rate};
   for (float r : rates)
@@ -454,7 +471,7 @@ md_status md_dock_batch(const md_receptor* rec, int n_jobs, const md_dock_job* j
     o.ev = cv.take(rows * 4);
     o.lsr = cv.take((size_t)p.n_runs * std::max(n_ls, 1) * 4);
     o.br = cv.take((size_t)p.n_runs * 4);
-    sched_jobs[j] = SchedJob{j, &jobs[j].ligand->dev, p.n_runs, p.pop_size, n_ls, p.ls_iters};
+    sched_jobs[j] = SchedJob{j, &jobs[j].ligand->dev, p.n_runs, p.pop_size, n_ls, p.ls_iters, p.ls_method};
     max_planned = std::max(max_planned, md_dock_planned_generations(&p));
   }
   GenSchedule sched;
@@ -485,6 +502,7 @@ md_status md_dock_batch(const md_receptor* rec, int n_jobs, const md_dock_job* j
     P.n_genes = J.L.n_genes;
     P.n_ls = n_local_search(&p);
     P.ls_iters = p.ls_iters;
+    P.ls_method = p.ls_method;
     P.elitism = p.elitism;
     P.rho = p.rho;
     P.eps = p.eps;

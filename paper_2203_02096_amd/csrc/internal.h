@@ -84,8 +84,11 @@ struct RecDev {
 };
 
 // GA parameters as the kernels see them.
+// local optimisers (md_dock_params.ls_method)
+enum : int { kLsAdadelta = 0, kLsSolisWets = 1 };
+
 struct GaDev {
-  int n_runs, pop_size, n_genes, n_ls, ls_iters, elitism;
+  int n_runs, pop_size, n_genes, n_ls, ls_iters, elitism, ls_method;
   float rho, eps;
   float crossover_rate, mutation_rate, tournament_rate;
   float mut_trans, mut_rot, mut_tors;
@@ -164,6 +167,8 @@ hipError_t launch_pose(const LigDev& L, int n, const float* genes, float* xyz, h
 hipError_t launch_local_search(const LigDev& L, const RecDev& R, int n, const float* genes_in,
                                float* genes_out, float* energy_out, int iters, float rho, float eps,
                                float* trace, hipStream_t s);
+hipError_t launch_solis_wets(const LigDev& L, const RecDev& R, int n, const float* genes_in, float* genes_out,
+                             float* energy_out, int n_evals, unsigned long long seed, float* trace, hipStream_t s);
 // GA phases over a job table.  blocks: [n_blocks] (job, first wave of the block within the
 // job's work for this phase).  A: atoms per lane of every job in the table; lds: dynamic LDS.
 hipError_t launch_ga_init(JobDev* jobs, const int2* blocks, int n_blocks, int A, int wpb, int lds,
@@ -172,7 +177,7 @@ hipError_t launch_ga_generation(JobDev* jobs, const int2* blocks, int n_blocks, 
                                 const RecDev& R, hipStream_t s);
 hipError_t launch_ga_ls_pick(JobDev* jobs, const int2* blocks, int n_blocks, hipStream_t s);
 hipError_t launch_ga_local_search(JobDev* jobs, const int2* blocks, int n_blocks, int A, int wpb, int lds,
-                                  const RecDev& R, hipStream_t s);
+                                  int ls_method, const RecDev& R, hipStream_t s);
 // Lets every evaluation kernel take up to kMaxLdsPerBlock of dynamic LDS (once per device).
 hipError_t enable_large_lds();
 hipError_t launch_ga_advance(JobDev* jobs, int n_jobs, hipStream_t s);
@@ -183,13 +188,13 @@ hipError_t launch_ga_advance_list(JobDev* jobs, const int2* list, int n, hipStre
 struct SchedJob {
   int slot;                   // index in the job table
   const LigDev* L;
-  int n_runs, pop_size, n_ls, ls_iters;
+  int n_runs, pop_size, n_ls, ls_iters, ls_method;
 };
 // One size class's generation chain: GA generation (+ initial population), local-search picks,
 // local search, epilogue -- each a range of the block array (pick blocks cover four runs each,
 // epilogue entries name one job each) -- repeated `reps` times per captured phase.
 struct ClassChain {
-  int A, wpb, lds;
+  int A, wpb, lds, ls_method;
   int pop_first, pop_count, ls_first, ls_count, run_first, run_count, adv_first, adv_count;
   int reps;
   double latency;             // relative serial cost of one generation of the class's slowest job

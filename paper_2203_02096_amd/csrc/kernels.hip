@@ -1,5 +1,5 @@
-// gfx950 kernels of libmdock: pose, energy and genotype gradient, ADADELTA local search,
-// GA generation, evaluation accounting and best-of-runs.
+// gfx950 kernels of libmdock: pose, energy and genotype gradient, ADADELTA and Solis-Wets
+// local searches, GA generation, evaluation accounting and best-of-runs.
 //
 // Mapping: one 64-lane wavefront owns one pose (genotype).  Lanes hold atoms (atom l and,
 // for ligands above 64 atoms, l + 64), then stride over the intramolecular pair list; the
@@ -69,7 +69,7 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
   return z ^ (z >> 31);
 }
 
-enum : uint32_t { kPInit = 1, kPTournament = 2, kPCrossover = 3, kPMutation = 4, kPLsPick = 5 };
+enum : uint32_t { kPInit = 1, kPTournament = 2, kPCrossover = 3, kPMutation = 4, kPLsPick = 5, kPLsSw = 6 };
 
 __device__ __forceinline__ uint32_t draw_u24(uint64_t seed, uint32_t run, uint32_t gen,
                                              uint32_t indiv, uint32_t purpose, uint32_t index) {
@@ -80,6 +80,21 @@ __device__ __forceinline__ uint32_t draw_u24(uint64_t seed, uint32_t run, uint32
   h = splitmix64(h ^ purpose);
   h = splitmix64(h ^ index);
   return (uint32_t)(h >> 40);
+}
+
+// The hash state after the first five coordinates; draw_from(prefix, index) then equals
+// draw_u24(seed, run, gen, indiv, purpose, index) at one mixing round per draw.
+__device__ __forceinline__ uint64_t draw_prefix(uint64_t seed, uint32_t run, uint32_t gen, uint32_t indiv,
+                                                uint32_t purpose) {
+  uint64_t h = seed;
+  h = splitmix64(h ^ run);
+  h = splitmix64(h ^ gen);
+  h = splitmix64(h ^ indiv);
+  return splitmix64(h ^ purpose);
+}
+
+__device__ __forceinline__ uint32_t draw_from(uint64_t prefix, uint32_t index) {
+  return (uint32_t)(splitmix64(prefix ^ index) >> 40);
 }
 
 __device__ __forceinline__ float draw_uniform(uint64_t seed, uint32_t run, uint32_t gen,
@@ -715,8 +730,18 @@ __global__ __launch_bounds__(kBlock) void k_pose(LigDev L, int n, const float* _
   }
 }
 
-// ADADELTA step on the gene held by this lane, then quaternion renormalisation and torsion
-// wrapping.  Returns the new gene.
+// A moved genotype back on its domain: the quaternion (lanes 3..6) renormalised, the torsions
+// wrapped to (-pi, pi].
+__device__ __forceinline__ float project_gene(float nx, int G) {
+  const int lane = lane_id();
+  const float q0 = readlane(nx, 3), q1 = readlane(nx, 4), q2 = readlane(nx, 5), q3 = readlane(nx, 6);
+  const float qn = __builtin_sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+  if (lane >= 3 && lane < 7) nx = nx / qn;
+  if (lane >= 7 && lane < G) nx = wrap_angle(nx);
+  return nx;
+}
+
+// ADADELTA step on the gene held by this lane, then the projection.  Returns the new gene.
 __device__ __forceinline__ float adadelta_update(float x, float g, float& eg2, float& edx2,
                                                  float rho, float eps, int G) {
   const int lane = lane_id();
@@ -727,11 +752,7 @@ __device__ __forceinline__ float adadelta_update(float x, float g, float& eg2, f
     edx2 = rho * edx2 + (1.f - rho) * dx * dx;
     nx = x + dx;
   }
-  const float q0 = readlane(nx, 3), q1 = readlane(nx, 4), q2 = readlane(nx, 5), q3 = readlane(nx, 6);
-  const float qn = __builtin_sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
-  if (lane >= 3 && lane < 7) nx = nx / qn;
-  if (lane >= 7 && lane < G) nx = wrap_angle(nx);
-  return nx;
+  return project_gene(nx, G);
 }
 
 // ADADELTA from genes_in[row_in] for `iters` steps; the best genotype goes to genes_out[row_out]
@@ -774,6 +795,108 @@ __global__ __launch_bounds__(kMaxBlock) void k_local_search(LigDev L, RecDev R, 
   load_ligand<A>(L, at);
   const float E = local_search_wave<A, PREC>(L, R, b, at, genes_in, job, genes_out, job, iters, rho, eps,
                                              trace ? trace + (long long)job * iters : nullptr);
+  if (lane_id() == 0) energy_out[job] = E;
+}
+
+// ------------------------------------------------------------------ Solis-Wets
+// Solis and Wets' adaptive random search (Math. Oper. Res. 6(1), 1981), the local optimiser
+// the paper names.  From x with energy E: draw xi ~ N(b, (rho sigma)^2) per gene; move to
+// x + xi if its energy is lower, else to x - xi if that is lower.  The bias b becomes
+// 0.2 b + 0.4 xi after a + success, b - 0.4 xi after a - success, b / 2 after a double failure;
+// rho doubles after 4 successes in a row (at most 4) and halves after 4 failures in a row (at
+// least 0.01).  sigma: 0.5 A for translation, 0.05 per quaternion component, 0.25 rad per
+// torsion.  Exactly n_evals energy evaluations: the start point, then one or two per step (a
+// step the budget cuts short tries x + xi only).  Each step's normals come from Box-Muller on
+// two counter-based 24-bit draws per gene, indices 2m and 2m + 1 with m = 64 step + gene.
+constexpr float kSwSigmaTrans = 0.5f, kSwSigmaQuat = 0.05f, kSwSigmaTors = 0.25f;
+constexpr float kSwRho0 = 1.f, kSwRhoMin = 0.01f, kSwRhoMax = 4.f;
+constexpr int kSwExpandAfter = 4, kSwContractAfter = 4;
+constexpr int kSwMaxEvals = 1 << 24;   // keeps the draw indices below 2^31
+
+__device__ __forceinline__ float box_muller(uint32_t k1, uint32_t k2) {
+  const float u1 = (float)(k1 + 1u) * (1.0f / 16777216.0f);   // (0, 1], exact
+  const float u2 = (float)k2 * (1.0f / 16777216.0f);          // [0, 1), exact
+  return __builtin_sqrtf(-2.f * logf(u1)) * cospif(2.f * u2);
+}
+
+// One wave's search from genes_in[row_in]; the final genotype goes to genes_out[row_out] and
+// its energy is returned (wave-uniform).  key: draw_prefix of the search's coordinates.
+// trace: NULL or [n_evals] energies of every evaluation.
+template <int A, int PREC>
+__device__ float solis_wets_wave(const LigDev& L, const RecDev& R, const BlockLds& b, const AtomRegs<A>& at,
+                                 const float* genes_in, long long row_in, float* genes_out, long long row_out,
+                                 int n_evals, uint64_t key, float* trace) {
+  const int lane = lane_id();
+  const int G = L.n_genes;
+  const bool gene = lane < G;
+  const float sigma = lane < 3 ? kSwSigmaTrans : (lane < 7 ? kSwSigmaQuat : kSwSigmaTors);
+  float x = gene ? genes_in[row_in * G + lane] : 0.f;
+  float g;
+  float e = eval_pose<A, PREC, false>(L, R, b, at, x, g);
+  if (trace && lane == 0) trace[0] = e;
+  int used = 1;
+  float bias = 0.f, rho = kSwRho0;
+  int succ = 0, fail = 0;
+  for (uint32_t step = 0; used < n_evals; ++step) {
+    const uint32_t m = 64u * step + (uint32_t)lane;
+    const float z = box_muller(draw_from(key, 2u * m), draw_from(key, 2u * m + 1u));
+    const float xi = gene ? bias + rho * sigma * z : 0.f;
+    const float x1 = project_gene(x + xi, G);
+    const float e1 = eval_pose<A, PREC, false>(L, R, b, at, x1, g);
+    if (trace && lane == 0) trace[used] = e1;
+    ++used;
+    bool moved = true;
+    if (e1 < e) {
+      x = x1;
+      e = e1;
+      bias = 0.2f * bias + 0.4f * xi;
+    } else if (used < n_evals) {
+      const float x2 = project_gene(x - xi, G);
+      const float e2 = eval_pose<A, PREC, false>(L, R, b, at, x2, g);
+      if (trace && lane == 0) trace[used] = e2;
+      ++used;
+      if (e2 < e) {
+        x = x2;
+        e = e2;
+        bias = bias - 0.4f * xi;
+      } else {
+        bias = 0.5f * bias;
+        moved = false;
+      }
+    } else {
+      bias = 0.5f * bias;
+      moved = false;
+    }
+    succ = moved ? succ + 1 : 0;
+    fail = moved ? 0 : fail + 1;
+    if (succ >= kSwExpandAfter) {
+      rho = fminf(kSwRhoMax, 2.f * rho);
+      succ = 0;
+    }
+    if (fail >= kSwContractAfter) {
+      rho = fmaxf(kSwRhoMin, 0.5f * rho);
+      fail = 0;
+    }
+  }
+  if (gene) genes_out[row_out * G + lane] = x;
+  return e;
+}
+
+// Standalone Solis-Wets: one wave per start genotype; start k draws from coordinates
+// (seed, 0, 0, k).
+template <int A, int PREC>
+__global__ __launch_bounds__(kMaxBlock) void k_solis_wets(LigDev L, RecDev R, int n, const float* genes_in,
+                                                       float* genes_out, float* __restrict__ energy_out,
+                                                       int n_evals, unsigned long long seed,
+                                                       float* __restrict__ trace) {
+  const BlockLds b = stage_block<A>(L);
+  const int job = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (job >= n) return;
+  AtomRegs<A> at;
+  load_ligand<A>(L, at);
+  const uint64_t key = draw_prefix(seed, 0u, 0u, (uint32_t)job, kPLsSw);
+  const float E = solis_wets_wave<A, PREC>(L, R, b, at, genes_in, job, genes_out, job, n_evals, key,
+                                           trace ? trace + (long long)job * n_evals : nullptr);
   if (lane_id() == 0) energy_out[job] = E;
 }
 
@@ -1015,6 +1138,33 @@ __global__ __launch_bounds__(kMaxBlock) void k_ga_local_search(JobDev* __restric
   }
 }
 
+// Solis-Wets on the picked individuals (Lamarckian write-back); the search of individual i of
+// run r in generation g draws from coordinates (seed, r, g, i).
+template <int A, int PREC>
+__global__ __launch_bounds__(kMaxBlock) void k_ga_solis_wets(JobDev* __restrict__ jobs,
+                                                          const int2* __restrict__ blocks, RecDev R) {
+  const int2 bt = blocks[blockIdx.x];
+  JobDev& J = jobs[bt.x];
+  if (J.state != kJobRunning) return;
+  const LigDev L = J.L;
+  const GaDev P = J.P;
+  const int cur = J.cur, gen = J.gen;
+  const BlockLds b = stage_block<A>(L);
+  const int w = bt.y + threadIdx.x / kWave;
+  if (w >= P.n_runs * P.n_ls) return;
+  AtomRegs<A> at;
+  load_ligand<A>(L, at);
+  const int row = J.ls_rows[w];
+  const uint64_t key = draw_prefix(P.seed, (uint32_t)(row / P.pop_size), (uint32_t)gen,
+                                   (uint32_t)(row % P.pop_size), kPLsSw);
+  float* pop = J.genes[cur ^ 1];
+  const float E = solis_wets_wave<A, PREC>(L, R, b, at, pop, row, pop, row, P.ls_iters, key, nullptr);
+  if (lane_id() == 0) {
+    J.energy[cur ^ 1][row] = E;
+    J.evals[row] += P.ls_iters;
+  }
+}
+
 // Generation epilogue, one wave per job: the per-run evaluation sum (the miniapp's
 // sum_evals), then the job's state advances -- a freshly initialised job starts running, a
 // running job swaps its population buffers and moves to the next generation -- and a job whose
@@ -1107,7 +1257,13 @@ hipError_t enable_large_lds() {
       (const void*)k_ga_generation<1, 2>, (const void*)k_ga_generation<2, 2>,
       (const void*)k_ga_local_search<1, 0>, (const void*)k_ga_local_search<2, 0>,
       (const void*)k_ga_local_search<1, 1>, (const void*)k_ga_local_search<2, 1>,
-      (const void*)k_ga_local_search<1, 2>, (const void*)k_ga_local_search<2, 2>};
+      (const void*)k_ga_local_search<1, 2>, (const void*)k_ga_local_search<2, 2>,
+      (const void*)k_solis_wets<1, 0>, (const void*)k_solis_wets<2, 0>,
+      (const void*)k_solis_wets<1, 1>, (const void*)k_solis_wets<2, 1>,
+      (const void*)k_solis_wets<1, 2>, (const void*)k_solis_wets<2, 2>,
+      (const void*)k_ga_solis_wets<1, 0>, (const void*)k_ga_solis_wets<2, 0>,
+      (const void*)k_ga_solis_wets<1, 1>, (const void*)k_ga_solis_wets<2, 1>,
+      (const void*)k_ga_solis_wets<1, 2>, (const void*)k_ga_solis_wets<2, 2>};
   for (const void* f : fns) {
     e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsPerBlock);
     if (e != hipSuccess) return e;
@@ -1138,6 +1294,15 @@ hipError_t launch_local_search(const LigDev& L, const RecDev& R, int n, const fl
   if (n <= 0) return hipSuccess;
   MDOCK_DISPATCH(k_local_search, dim3(blocks_for(n, L.wpb)), s, L, R, n, genes_in, genes_out, energy_out,
                  iters, rho, eps, trace);
+  return hipGetLastError();
+}
+
+hipError_t launch_solis_wets(const LigDev& L, const RecDev& R, int n, const float* genes_in, float* genes_out,
+                             float* energy_out, int n_evals, unsigned long long seed, float* trace, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (n_evals < 1 || n_evals > kSwMaxEvals) return hipErrorInvalidValue;
+  MDOCK_DISPATCH(k_solis_wets, dim3(blocks_for(n, L.wpb)), s, L, R, n, genes_in, genes_out, energy_out,
+                 n_evals, seed, trace);
   return hipGetLastError();
 }
 
@@ -1176,9 +1341,12 @@ hipError_t launch_ga_ls_pick(JobDev* jobs, const int2* blocks, int n_blocks, hip
 }
 
 hipError_t launch_ga_local_search(JobDev* jobs, const int2* blocks, int n_blocks, int A, int wpb, int lds,
-                                  const RecDev& R, hipStream_t s) {
+                                  int ls_method, const RecDev& R, hipStream_t s) {
   if (n_blocks <= 0) return hipSuccess;
-  MDOCK_GA_DISPATCH(k_ga_local_search, A, wpb, lds, n_blocks, s, jobs, blocks, R);
+  if (ls_method == kLsSolisWets)
+    MDOCK_GA_DISPATCH(k_ga_solis_wets, A, wpb, lds, n_blocks, s, jobs, blocks, R);
+  else
+    MDOCK_GA_DISPATCH(k_ga_local_search, A, wpb, lds, n_blocks, s, jobs, blocks, R);
   return hipGetLastError();
 }
 

@@ -31,6 +31,9 @@ namespace {
 constexpr int kLdsPerCu = 160 * 1024;
 constexpr size_t kGraphBranches = 4;   // streams for the classes' parallel branches
 
+// a Solis-Wets evaluation (energy only) relative to an ADADELTA step (energy and gradient)
+constexpr double kEnergyOnlyCost = 0.6;
+
 // blocks of this LDS size that fit on one compute unit
 int occupancy_class(int lds) { return lds <= 0 ? 64 : std::min(64, kLdsPerCu / lds); }
 
@@ -43,18 +46,20 @@ double eval_cost(const LigDev& L) {
 
 void build_schedule(const std::vector<SchedJob>& jobs, GenSchedule& out, int max_reps, int uniform_reps) {
   out = GenSchedule();
-  // class key: (atoms per lane, waves per block, -(waves per CU)); denser classes first
-  using Key = std::tuple<int, int, int>;
+  // class key: (atoms per lane, waves per block, -(waves per CU), local optimiser); denser
+  // classes first
+  using Key = std::tuple<int, int, int, int>;
   std::map<Key, std::vector<int>> cls;
   for (int k = 0; k < (int)jobs.size(); ++k) {
     const SchedJob& j = jobs[k];
     const int A = j.L->n_atoms > kWave ? 2 : 1;
-    cls[Key(A, j.L->wpb, -occupancy_class(j.L->lds_bytes) * j.L->wpb)].push_back(k);
+    cls[Key(A, j.L->wpb, -occupancy_class(j.L->lds_bytes) * j.L->wpb, j.ls_method)].push_back(k);
   }
   std::vector<double> cost(jobs.size());
   for (size_t k = 0; k < jobs.size(); ++k) {
     const SchedJob& j = jobs[k];
-    cost[k] = eval_cost(*j.L) * (1.0 + (j.n_ls > 0 ? (double)j.ls_iters : 0.0));
+    const double ls_eval = j.ls_method == kLsSolisWets ? kEnergyOnlyCost : 1.0;
+    cost[k] = eval_cost(*j.L) * (1.0 + (j.n_ls > 0 ? ls_eval * (double)j.ls_iters : 0.0));
   }
   for (auto& kv : cls) {
     std::vector<int>& m = kv.second;
@@ -62,6 +67,7 @@ void build_schedule(const std::vector<SchedJob>& jobs, GenSchedule& out, int max
     ClassChain c{};
     c.A = std::get<0>(kv.first);
     c.wpb = std::get<1>(kv.first);
+    c.ls_method = std::get<3>(kv.first);
     c.pop_first = (int)out.blocks.size();
     for (int k : m) {
       const SchedJob& j = jobs[k];
@@ -125,7 +131,8 @@ hipError_t launch_chain(const ClassChain& c, JobDev* table, const int2* d_blocks
     e = run(MD_K_LS_PICK, [&] { return launch_ga_ls_pick(table, d_blocks + c.run_first, c.run_count, st); });
   if (e == hipSuccess && c.ls_count > 0)
     e = run(MD_K_LOCAL_SEARCH, [&] {
-      return launch_ga_local_search(table, d_blocks + c.ls_first, c.ls_count, c.A, c.wpb, c.lds, R, st);
+      return launch_ga_local_search(table, d_blocks + c.ls_first, c.ls_count, c.A, c.wpb, c.lds, c.ls_method, R,
+                                    st);
     });
   if (e == hipSuccess)
     e = run(MD_K_SUM_EVALS, [&] { return launch_ga_advance_list(table, d_blocks + c.adv_first, c.adv_count, st); });

@@ -180,6 +180,7 @@ JobDev make_job(md_server* s, const Request& r) {
   P.n_genes = J.L.n_genes;
   P.n_ls = n_local_search_of(&p);
   P.ls_iters = p.ls_iters;
+  P.ls_method = p.ls_method;
   P.elitism = p.elitism;
   P.rho = p.rho;
   P.eps = p.eps;
@@ -217,7 +218,8 @@ hipError_t run_tick(md_server* s, bool any_init, bool any_running) {
       const auto& r = s->slots[j];
       if (!r) continue;
       const md_dock_params& p = r->params;
-      jobs.push_back(SchedJob{j, &r->lig->dev, p.n_runs, p.pop_size, n_local_search_of(&p), p.ls_iters});
+      jobs.push_back(SchedJob{j, &r->lig->dev, p.n_runs, p.pop_size, n_local_search_of(&p), p.ls_iters,
+                              p.ls_method});
     }
     build_schedule(jobs, s->sched, (s->params.use_graphs && use_graphs()) ? kTickMaxGenerations : 0, 1);
     s->graph.reset();

@@ -44,7 +44,10 @@ class DockParams(C.Structure):
                 ("rho", C.c_float), ("eps", C.c_float), ("crossover_rate", C.c_float),
                 ("mutation_rate", C.c_float), ("tournament_rate", C.c_float), ("elitism", C.c_int),
                 ("mut_trans", C.c_float), ("mut_rot", C.c_float), ("mut_tors", C.c_float),
-                ("seed", C.c_ulonglong)]
+                ("seed", C.c_ulonglong), ("ls_method", C.c_int)]
+
+
+LS_METHODS = {"adadelta": 0, "solis_wets": 1}
 
 
 class DockResult(C.Structure):
@@ -98,6 +101,8 @@ SIGNATURES = {
     "md_pose": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "md_local_search": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_int, C.c_float, C.c_float, C.c_void_p, C.c_void_p]),
+    "md_local_search_sw": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_int, C.c_ulonglong, C.c_void_p, C.c_void_p]),
     "md_dock": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(DockParams), C.POINTER(DockResult), C.c_void_p]),
     "md_dock_batch": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(DockJob), C.c_void_p]),
     "md_dock_planned_generations": (C.c_int, [C.POINTER(DockParams)]),
@@ -278,13 +283,29 @@ def md_local_search(rec: Receptor, lig: Ligand, genes_in, genes_out, energy_out,
            "md_local_search")
 
 
+def md_local_search_sw(rec: Receptor, lig: Ligand, genes_in, genes_out, energy_out, n_evals=300,
+                       seed=7, trace=None, stream=None):
+    import torch
+    n = genes_in.shape[0]
+    tp = _dev_ptr(trace, "trace", (n, n_evals), torch.float32) if trace is not None else None
+    _check(lib().md_local_search_sw(rec.handle, lig.handle, n,
+                                    _dev_ptr(genes_in, "genes_in", (n, lig.n_genes), torch.float32),
+                                    _dev_ptr(genes_out, "genes_out", (n, lig.n_genes), torch.float32),
+                                    _dev_ptr(energy_out, "energy_out", (n,), torch.float32),
+                                    int(n_evals), int(seed), tp, _stream_ptr(stream)),
+           "md_local_search_sw")
+
+
 def dock_params(**kw) -> DockParams:
+    """md_dock_params with the library's defaults; ls_method may be given by name."""
     p = DockParams()
     defaults = dict(n_runs=1, pop_size=150, max_evals_per_run=2_500_000, max_generations=27000,
                     ls_rate=0.06, ls_iters=300, rho=0.8, eps=1e-2, crossover_rate=0.8,
                     mutation_rate=0.02, tournament_rate=0.6, elitism=1, mut_trans=2.0,
-                    mut_rot=float(np.pi / 2), mut_tors=float(np.pi), seed=7)
+                    mut_rot=float(np.pi / 2), mut_tors=float(np.pi), seed=7, ls_method=0)
     defaults.update(kw)
+    if isinstance(defaults["ls_method"], str):
+        defaults["ls_method"] = LS_METHODS[defaults["ls_method"]]
     for k, v in defaults.items():
         setattr(p, k, v)
     return p

@@ -102,6 +102,7 @@ def test_null_handles_rejected(md):
     lib = md.lib()
     assert lib.md_eval(None, None, 1, None, None, None, None) == -1
     assert lib.md_local_search(None, None, 1, None, None, None, 10, 0.8, 0.01, None, None) == -1
+    assert lib.md_local_search_sw(None, None, 1, None, None, None, 10, 7, None, None) == -1
     assert lib.md_dock(None, None, None, None, None) == -1
     assert lib.md_ligand_num_genes(None) == -1
     plan = md.mdock.Plan(65536, 3, 4, 0, 0, 0)
@@ -127,3 +128,6 @@ def test_planned_generations_closed_form(md):
     assert md.md_dock_planned_generations(p) == 10
     p = md.dock_params(**configs.search_params("plain_fp32_production"))
     assert md.md_dock_planned_generations(p) == 56
+    # the local optimiser does not change the budget: both spend ls_iters evaluations
+    p = md.dock_params(**configs.search_params("plain_fp32_production", ls_method="solis_wets"))
+    assert p.ls_method == 1 and md.md_dock_planned_generations(p) == 56
