@@ -14,6 +14,10 @@ oracle's energy+gradient evaluations per second on the host cores, on a bounded 
 random poses of the same ligand and grid.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--ls adadelta|solis_wets] [--workload plain_fp32_production|batched_fp32|serving_fp16]
+
+--ls solis_wets runs the same dock with the Solis-Wets local search (same evaluation budget);
+its value counts the energy-only evaluations of the searches.
 """
 from __future__ import annotations
 
@@ -33,18 +37,19 @@ PEAK_FP32_VALU_TFLOPS = 157.3     # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
 
 
-PROFILE = os.path.join(ROOT, "profiles", "k_local_search_plain_fp32_production.txt")
+PROFILES = {"adadelta": os.path.join(ROOT, "profiles", "k_local_search_plain_fp32_production.txt"),
+            "solis_wets": os.path.join(ROOT, "profiles", "k_ga_solis_wets_plain_fp32_production.txt")}
 KERNEL_SRC = os.path.join(ROOT, "paper_2203_02096_amd", "csrc", "kernels.hip")
 
 
-def measured_profile():
+def measured_profile(ls="adadelta"):
     """Figures from the committed rocprofv3 summary of the local-search kernel: HBM bytes per
     launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's counts) and VALU issue utilisation
     (SQ_INSTS_VALU); None for each when the kernel source has changed since they were taken."""
     import hashlib
     none = {"traffic": None, "valu_issue_utilisation": None, "valu_instructions_per_eval": None}
     try:
-        text = open(PROFILE).read()
+        text = open(PROFILES[ls]).read()
         sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
     except OSError:
         return none
@@ -61,6 +66,13 @@ def flop_model(n_atoms, n_torsions, n_pairs, sum_moving):
     pose 24*sum_M + 21*N + 25*T + 30, grid 170*N, pairs 75*P, reductions 12*sum_M + 12*N + 10*T."""
     N, T, P, M = n_atoms, n_torsions, n_pairs, sum_moving
     return (24 * M + 21 * N + 25 * T + 30) + 170 * N + 75 * P + (12 * M + 12 * N + 10 * T)
+
+
+def flop_model_energy(n_atoms, n_torsions, n_pairs, sum_moving):
+    """Algorithmic flop-equivalents of one energy-only evaluation (a Solis-Wets trial point):
+    pose 24*sum_M + 21*N + 25*T + 30, grid value 62*N, pair energies 53*P, energy sum N."""
+    N, T, P, M = n_atoms, n_torsions, n_pairs, sum_moving
+    return (24 * M + 21 * N + 25 * T + 30) + 62 * N + 53 * P + N
 
 
 def bytes_model(n_atoms, map_bytes=4):
@@ -139,6 +151,9 @@ def main():
     ap.add_argument("--rates", default="50,100,200,350,500",
                     help="serving_fp16: arrival rates (ligands/s)")
     ap.add_argument("--requests", type=int, default=300, help="serving_fp16: requests per rate")
+    ap.add_argument("--ls", default="adadelta", choices=["adadelta", "solis_wets"],
+                    help="local optimiser of the production dock (default adadelta, the headline; "
+                         "solis_wets reports energy-only evaluations per second)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch plans (else every ligand size class is autotuned "
                          "on the receptor before the timed region)")
@@ -170,7 +185,8 @@ def main():
     drec = md.Receptor(rec.maps, rec.origin, rec.spacing, "fp32")
     dlig = md.Ligand.from_synth(lig)
     info = md.md_ligand_info(dlig)
-    sp = configs.search_params(WORKLOAD, seed=args.seed)
+    sw = args.ls == "solis_wets"
+    sp = configs.search_params(WORKLOAD, seed=args.seed, ls_method=args.ls)
     P = md.dock_params(**sp)
     gens = md.md_dock_planned_generations(P)
     n_ls = max(0, min(P.pop_size, math.ceil(sp["ls_rate"] * P.pop_size - 1e-4)))
@@ -202,14 +218,15 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
     value = ls_evals / (elapsed / args.steps)
     evals_per_ls_launch = P.n_runs * n_ls * P.ls_iters
-    flops_eval = flop_model(info["n_atoms"], info["n_torsions"], info["n_pairs"], info["sum_moving"])
+    fm = flop_model_energy if sw else flop_model
+    flops_eval = fm(info["n_atoms"], info["n_torsions"], info["n_pairs"], info["sum_moving"])
     avg_ls_s = ls_ms / 1e3 / max(ls_n, 1)
     achieved_tflops = flops_eval * evals_per_ls_launch / avg_ls_s / 1e12
     hbm_gbs = bytes_model(info["n_atoms"]) * evals_per_ls_launch / avg_ls_s / 1e9
     lat_ms = np.array(lat) * 1e3
-    prof = measured_profile()
+    prof = measured_profile(args.ls)
     out = {
-        "metric": "energy+gradient evals/s",
+        "metric": "energy evals/s (Solis-Wets)" if sw else "energy+gradient evals/s",
         "value": value,
         "unit": "evals/s",
         "n_gpus": 1,
@@ -225,14 +242,14 @@ def main():
                    "n_atoms": info["n_atoms"], "n_torsions": info["n_torsions"],
                    "n_pairs": info["n_pairs"], "n_runs": P.n_runs, "pop_size": P.pop_size,
                    "max_evals_per_run": P.max_evals_per_run, "generations": gens,
-                   "ls_rate": sp["ls_rate"], "ls_iters": P.ls_iters},
+                   "ls_rate": sp["ls_rate"], "ls_iters": P.ls_iters, "local_search": args.ls},
         "launch_plan": {**plan, "autotuned": tune is not None},
         "ligands_per_s": 1.0 / (elapsed / args.steps),
         "total_evals_per_s": total_evals / (elapsed / args.steps),
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP32_VALU_TFLOPS,
-                     "traffic": prof["traffic"], "kernel": "k_ga_local_search",
+                     "traffic": prof["traffic"], "kernel": "k_ga_solis_wets" if sw else "k_ga_local_search",
                      "frac_of_nonpacked_fp32": achieved_tflops / (PEAK_FP32_VALU_TFLOPS / 2),
                      "valu_issue_utilisation": prof["valu_issue_utilisation"],
                      "valu_instructions_per_eval": prof["valu_instructions_per_eval"],
