@@ -143,9 +143,11 @@ def main():
                     help="after the timed region, one plain device copy of this size (a known-size "
                          "dispatch for calibrating byte counters under a profiler)")
     ap.add_argument("--workload", default=WORKLOAD,
-                    choices=[WORKLOAD, "batched_fp32", "serving_fp16"],
+                    choices=[WORKLOAD, "batched_fp32", "serving_fp16", "paper_inputs"],
                     help="plain_fp32_production (default): one ligand, 20 runs; batched_fp32: 256 "
-                         "ligands in one batch; serving_fp16: Poisson arrivals into the server")
+                         "ligands in one batch; serving_fp16: Poisson arrivals into the server; "
+                         "paper_inputs: the paper's three input sizes at 10 and 100 runs, docked "
+                         "with each block size")
     ap.add_argument("--generations", type=int, default=50,
                     help="batched_fp32: generations per timed batch (the full budget takes ~878)")
     ap.add_argument("--rates", default="50,100,200,350,500",
@@ -166,6 +168,8 @@ def main():
         return bench_batched(args)
     if args.workload == "serving_fp16":
         return bench_serving(args)
+    if args.workload == "paper_inputs":
+        return bench_paper_inputs(args)
 
     # the oracle baseline runs first, in spawned processes, before this process touches the GPU
     base = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)
@@ -276,6 +280,100 @@ def _common(md):
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     md.lib()
+
+
+def bench_paper_inputs(args):
+    """The paper's three inputs (synthetic ligands of 21, 43 and 108 atoms with 2, 15 and 31
+    rotatable bonds) docked with 10 and 100 runs, once per block size -- 1, 2, 4 and 8 waves per
+    block, i.e. 64 to 512 threads per workgroup, one pose per wave (the paper swept 32 to 256
+    threads per workgroup for its large input; one pose per 64-lane wave rules out 32) -- once
+    per pose size -- 2 and 4 waves sharing each local-search pose, i.e. 128 and 256 threads per
+    pose, the counterpart of the paper's threads per individual -- and once with the autotuned
+    plan.  Each case is the median of --steps docks after --warmup; value is the local-search
+    evaluations per second summed over the six (input, runs) cases at the best plan of each."""
+    import numpy as np
+    import torch
+
+    import paper_2203_02096_amd as md
+    from workload import configs
+    _common(md)
+    name = "paper_inputs"
+    rec = configs.receptor(name)
+    drec = md.Receptor(rec.maps, rec.origin, rec.spacing, "fp32")
+    stream = torch.cuda.current_stream()
+    cases = []
+    total_ls, total_s = 0, 0.0
+    for size in configs.PAPER_INPUT_SIZES:
+        lig = configs.paper_ligand(size)
+        dlig = md.Ligand.from_synth(lig)
+        info = md.md_ligand_info(dlig)
+        default = md.md_ligand_get_plan(dlig)
+        for nruns in configs.PAPER_NRUNS:
+            sp = configs.search_params(name, seed=args.seed, n_runs=nruns, ls_method=args.ls)
+            P = md.dock_params(**sp)
+            gens = md.md_dock_planned_generations(P)
+            n_ls = max(0, min(P.pop_size, math.ceil(sp["ls_rate"] * P.pop_size - 1e-4)))
+            ls_evals = nruns * gens * n_ls * P.ls_iters
+
+            def timed():
+                for _ in range(args.warmup):
+                    md.md_dock(drec, dlig, P, stream=stream, want_xyz=False)
+                ts = []
+                for _ in range(args.steps):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    md.md_dock(drec, dlig, P, stream=stream, want_xyz=False)
+                    ts.append(time.perf_counter() - t0)
+                return float(np.median(ts))
+
+            per_wpb, per_wpp = {}, {}
+            for wpb in (1, 2, 4, 8):
+                try:
+                    md.md_ligand_set_plan(dlig, default["lds_budget"], default["group_div"], wpb)
+                except md.MdockError:
+                    per_wpb[64 * wpb] = None        # the plan does not fit in LDS
+                    continue
+                per_wpb[64 * wpb] = timed()
+            per_wpp[64] = per_wpb[64]
+            for wpp in (2, 4):
+                try:
+                    md.md_ligand_set_plan(dlig, default["lds_budget"], default["group_div"], wpp, wpp)
+                except md.MdockError:
+                    per_wpp[64 * wpp] = None
+                    continue
+                per_wpp[64 * wpp] = timed()
+            md.md_ligand_set_plan(dlig, default["lds_budget"], default["group_div"], default["waves_per_block"])
+            tune = md.md_ligand_autotune(drec, dlig, n_starts=nruns * n_ls, force=True)
+            t_tuned = timed()
+            md.md_ligand_set_plan(dlig, default["lds_budget"], default["group_div"], default["waves_per_block"])
+            ok = [t for t in per_wpb.values() if t is not None]
+            best = min(ok + [t for t in per_wpp.values() if t is not None] + [t_tuned])
+            total_ls += ls_evals
+            total_s += best
+            cases.append({"input": size, "n_atoms": info["n_atoms"], "n_torsions": info["n_torsions"],
+                          "n_pairs": info["n_pairs"], "n_runs": nruns, "generations": gens,
+                          "seconds_by_threads_per_block": per_wpb, "seconds_by_threads_per_pose": per_wpp,
+                          "seconds_tuned": t_tuned,
+                          "tuned_plan": tune["plan"], "worst_over_best": max(ok) / min(ok),
+                          "ls_evals_per_s_best": ls_evals / best})
+            print(f"[paper_inputs] {size} nruns {nruns}: threads per block " +
+                  ", ".join(f"{k}: {v:.3f} s" if v is not None else f"{k}: n/a" for k, v in per_wpb.items()) +
+                  "; threads per pose " +
+                  ", ".join(f"{k}: {v:.3f} s" if v is not None else f"{k}: n/a" for k, v in per_wpp.items()) +
+                  f"; tuned {t_tuned:.3f} s {tune['plan']}", file=sys.stderr, flush=True)
+    out = {
+        "metric": ("energy evals/s (Solis-Wets)" if args.ls == "solis_wets" else "energy+gradient evals/s"),
+        "value": total_ls / total_s,
+        "unit": "evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * total_s, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": name, "grid": "64^3 x 9 maps FP32", "pop_size": 150,
+                   "max_evals_per_run": 2_500_000, "ls_rate": 0.06, "ls_iters": 300,
+                   "local_search": args.ls},
+        "cases": cases,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def bench_batched(args):

@@ -128,15 +128,22 @@ md_status md_ligand_info(const md_ligand* lig, int* n_atoms, int* n_torsions, in
  * block takes at most `lds_budget` bytes of LDS, which stages the first `staged_rows` of the
  * ligand's `total_rows` rows of 64 intramolecular pair slots (the rest are read from global
  * memory); the lanes of a pair row form conflict-free groups of about n_atoms / group_div lanes.
+ * waves_per_pose > 1 (2 or 4) lets that many waves evaluate one pose together in the local
+ * searches (md_local_search, md_local_search_sw, md_eval and the docking searches): each takes a
+ * share of the pair rows, and their partial forces and energies meet in LDS once per evaluation
+ * (one block barrier).  It shortens a search when there are too few searches to fill the device
+ * (few runs, large ligands); a block then holds one pose, so waves_per_block becomes
+ * waves_per_pose.  The GA's own evaluations keep one wave per pose.
  * A plan changes speed and the order of floating-point sums, not the method: results stay
  * within the parity tolerance of each other and are reproducible for a fixed plan.
- * Defaults: lds_budget 65536, group_div 3, waves_per_block 4.  Read-only on input to
- * md_ligand_set_plan: lds_bytes, staged_rows, total_rows. */
+ * Defaults: lds_budget 65536, group_div 3, waves_per_block 4, waves_per_pose 1.  Read-only on
+ * input to md_ligand_set_plan: lds_bytes, staged_rows, total_rows. */
 typedef struct {
   int lds_budget;       /* 0..163840 (gfx950: a block may take the whole 160 KiB LDS of a CU) */
   int group_div;        /* 2..8 */
   int waves_per_block;  /* 1, 2, 4 or 8 */
   int lds_bytes, staged_rows, total_rows;   /* outputs: the resulting layout */
+  int waves_per_pose;   /* 1 (or 0), 2 or 4 */
 } md_plan;
 md_status md_ligand_get_plan(const md_ligand* lig, md_plan* out);
 /* Re-plans the ligand (host work + one upload; waits for the device to be idle).  The ligand
@@ -152,8 +159,8 @@ typedef struct {
   int from_table;              /* 1: the class was tuned before; its plan was applied untimed */
 } md_tune_info;
 /* Autotuner: times the local-search kernel on `rec` for candidate plans -- waves per block
- * {4, 8} x LDS budget {32, 48, 64, 96, 128, 160} KiB, then lane-group sizes N/2 and N/4 for the
- * best -- and applies the fastest to `lig`.  n_starts is the number of local searches one launch
+ * {4, 8} x LDS budget {32, 48, 64, 96, 128, 160} KiB, waves per pose {2, 4} x LDS budget {64,
+ * 160} KiB, then lane-group sizes N/2 and N/4 for the best -- and applies the fastest to `lig`.  n_starts is the number of local searches one launch
  * will run (md_dock: n_runs x ceil(ls_rate x pop_size)); the candidates are timed on that many
  * random starts inside the box (a few ADADELTA steps each, best of three launches), since the
  * best plan depends on how well the launch fills the device.  n_starts = 0 (or >= 8192) tunes

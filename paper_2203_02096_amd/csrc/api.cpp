@@ -157,6 +157,7 @@ hipError_t upload_ligand(const LigHost& h, void** d_buf, LigDev* L) {
   l.group_lanes = h.group_lanes;
   l.n_copies = h.n_copies;
   l.wpb = h.wpb;
+  l.wpp = h.wpp;
   l.lds_bytes = h.lds_bytes;
   *d_buf = d;
   return hipSuccess;

@@ -52,7 +52,8 @@ std::map<std::pair<int, int>, TuneEntry> g_table;
 bool valid_plan(const md_plan& p) {
   return p.lds_budget >= 0 && p.lds_budget <= kMaxLdsPerBlock && p.group_div >= 2 && p.group_div <= 8 &&
          (p.waves_per_block == 1 || p.waves_per_block == 2 || p.waves_per_block == 4 ||
-          p.waves_per_block == 8);
+          p.waves_per_block == 8) &&
+         (p.waves_per_pose == 0 || p.waves_per_pose == 1 || p.waves_per_pose == 2 || p.waves_per_pose == 4);
 }
 
 PlanParams to_params(const md_plan& p) {
@@ -60,6 +61,7 @@ PlanParams to_params(const md_plan& p) {
   pp.lds_budget = p.lds_budget;
   pp.group_div = p.group_div;
   pp.wpb = p.waves_per_block;
+  pp.wpp = std::max(1, p.waves_per_pose);
   return pp;
 }
 
@@ -67,6 +69,7 @@ void describe(const LigHost& h, md_plan* out) {
   out->lds_budget = h.plan.lds_budget;
   out->group_div = h.plan.group_div;
   out->waves_per_block = h.wpb;
+  out->waves_per_pose = h.wpp;
   out->lds_bytes = h.lds_bytes;
   out->staged_rows = h.pl_rows;
   out->total_rows = h.n_rows;
@@ -166,7 +169,7 @@ md_status md_ligand_set_plan(md_ligand* lig, const md_plan* plan) {
   if (!lig || !plan) return api_fail(MD_EINVAL, "md_ligand_set_plan: null argument");
   if (!valid_plan(*plan))
     return api_fail(MD_ERANGE, "md_ligand_set_plan: lds_budget in [0, 163840], group_div in [2, 8], "
-                               "waves_per_block in {1, 2, 4, 8}");
+                               "waves_per_block in {1, 2, 4, 8}, waves_per_pose in {1, 2, 4}");
   LigHost probe = lig->host;
   plan_ligand(probe, to_params(*plan));
   if (probe.lds_bytes > kMaxLdsPerBlock)
@@ -181,7 +184,7 @@ md_status md_schedule_preview(const md_ligand_desc* d, md_plan* plan, unsigned* 
   if (!d || !plan) return api_fail(MD_EINVAL, "md_schedule_preview: null argument");
   if (!valid_plan(*plan))
     return api_fail(MD_ERANGE, "md_schedule_preview: lds_budget in [0, 163840], group_div in [2, 8], "
-                               "waves_per_block in {1, 2, 4, 8}");
+                               "waves_per_block in {1, 2, 4, 8}, waves_per_pose in {1, 2, 4}");
   LigHost h;
   bool range = false;
   const std::string err = prepare_ligand(d->n_atoms, d->xyz, d->type, d->charge, d->n_bonds, d->bonds,
@@ -267,7 +270,8 @@ md_status md_ligand_autotune(const md_receptor* rec, md_ligand* lig, int n_start
   };
   std::vector<Cand> tried;
   auto same_plan = [](const LigHost& x, const LigHost& y) {
-    return x.wpb == y.wpb && x.pl_rows == y.pl_rows && x.group_lanes == y.group_lanes && x.lds_bytes == y.lds_bytes;
+    return x.wpb == y.wpb && x.wpp == y.wpp && x.pl_rows == y.pl_rows && x.group_lanes == y.group_lanes &&
+           x.lds_bytes == y.lds_bytes;
   };
   std::vector<LigHost> plans_seen;
   auto try_plan = [&](const PlanParams& pp) -> double {
@@ -309,6 +313,19 @@ md_status md_ligand_autotune(const md_receptor* rec, md_ligand* lig, int n_start
       if (e != hipSuccess) break;
       PlanParams pp;
       pp.wpb = wpb;
+      pp.lds_budget = budget;
+      const double us = try_plan(pp);
+      if (us > 0 && us < best_us) {
+        best_us = us;
+        best = pp;
+      }
+    }
+  for (int wpp : {2, 4})
+    for (int budget : {64 * 1024, kMaxLdsPerBlock}) {
+      if (e != hipSuccess) break;
+      PlanParams pp;
+      pp.wpp = wpp;
+      pp.wpb = wpp;
       pp.lds_budget = budget;
       const double us = try_plan(pp);
       if (us > 0 && us < best_us) {

@@ -20,6 +20,10 @@ constexpr int kWavesPerBlock = 4;                  // blocks of the kernels with
 constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kMaxWavesPerBlock = 8;               // evaluation kernels: the plan's waves per block
 constexpr int kMaxBlock = kWave * kMaxWavesPerBlock;
+// Waves that share one pose in the local-search kernels (1, 2 or 4): the pair rows are split
+// between them and their partial forces and energies meet in LDS once per evaluation.  A block
+// whose waves share a pose holds exactly that one pose.
+constexpr int kMaxWavesPerPose = 4;
 constexpr int kMaxLdsPerBlock = 160 * 1024;        // gfx950: all of a compute unit's LDS
 // Pair schedule of a ligand: the intramolecular pairs are laid out in rows of 64 (one pair per
 // lane).  The lanes of a row form groups of `group_lanes` consecutive lanes, and within a group
@@ -70,7 +74,8 @@ struct LigDev {
   int pl_rows;                // rows staged in LDS (a prefix)
   int group_lanes;            // lanes per conflict-free group
   int n_copies;               // force-array copies (groups in use)
-  int wpb;                    // waves (poses) per block of the evaluation kernels
+  int wpb;                    // waves per block of the evaluation kernels
+  int wpp;                    // waves per pose of the local-search kernels (1, 2, 4; > 1: wpb == wpp)
   int lds_bytes;              // dynamic LDS of one block
 };
 
@@ -121,6 +126,7 @@ struct PlanParams {
   int lds_budget = (int)kLdsBudget;   // dynamic LDS of one block, bytes (<= kMaxLdsPerBlock)
   int group_div = 3;                  // lanes per conflict-free group ~ n_atoms / group_div
   int wpb = kWavesPerBlock;           // waves per block (1..kMaxWavesPerBlock)
+  int wpp = 1;                        // waves per pose in the local searches (1, 2, 4; > 1 sets wpb)
 };
 
 // Host-side ligand after preprocessing (arrays in internal torsion order).
@@ -138,6 +144,7 @@ struct LigHost {
   std::vector<uint32_t> pair_ij;   // scheduled rows, padded (see LigDev)
   std::vector<float4> pair_coef;
   int n_pairs = 0, n_rows = 0, pl_rows = 0, group_lanes = 64, n_copies = 1, wpb = kWavesPerBlock;
+  int wpp = 1;
   int lds_bytes = 0;
   PlanParams plan;
 };
@@ -151,6 +158,12 @@ __host__ __device__ inline size_t lds_wave_bytes(int n_atoms, int n_copies, int 
   return (size_t)16 * (kWave * A + 1) + (size_t)16 * n_copies * (n_atoms + 1) + (size_t)48 * n_tors;
 }
 __host__ __device__ inline size_t lds_pairs_bytes(int rows) { return (size_t)rows * kWave * (16 + 4); }
+// waves sharing a pose (W > 1): two alternating sets (even and odd evaluations) of the per-wave
+// intramolecular force partials [W][n_atoms + 1], the grid forces [n_atoms + 1] (float4 each)
+// and the per-wave energy partials [W] (one float4 slot each)
+__host__ __device__ inline size_t lds_pose_share_bytes(int n_atoms, int W) {
+  return W > 1 ? (size_t)2 * 16 * ((size_t)(W + 1) * (n_atoms + 1) + W) : 0;
+}
 
 // Returns an empty string on success, else a message; `range_error` tells MD_ERANGE apart.
 std::string prepare_ligand(int n_atoms, const float* xyz, const int* type, const float* charge,
@@ -176,8 +189,9 @@ hipError_t launch_ga_init(JobDev* jobs, const int2* blocks, int n_blocks, int A,
 hipError_t launch_ga_generation(JobDev* jobs, const int2* blocks, int n_blocks, int A, int wpb, int lds,
                                 const RecDev& R, hipStream_t s);
 hipError_t launch_ga_ls_pick(JobDev* jobs, const int2* blocks, int n_blocks, hipStream_t s);
-hipError_t launch_ga_local_search(JobDev* jobs, const int2* blocks, int n_blocks, int A, int wpb, int lds,
-                                  int ls_method, const RecDev& R, hipStream_t s);
+// wpp: waves per search (1, 2, 4); a block holds wpb / wpp searches
+hipError_t launch_ga_local_search(JobDev* jobs, const int2* blocks, int n_blocks, int A, int wpb, int wpp,
+                                  int lds, int ls_method, const RecDev& R, hipStream_t s);
 // Lets every evaluation kernel take up to kMaxLdsPerBlock of dynamic LDS (once per device).
 hipError_t enable_large_lds();
 hipError_t launch_ga_advance(JobDev* jobs, int n_jobs, hipStream_t s);
@@ -194,7 +208,7 @@ struct SchedJob {
 // local search, epilogue -- each a range of the block array (pick blocks cover four runs each,
 // epilogue entries name one job each) -- repeated `reps` times per captured phase.
 struct ClassChain {
-  int A, wpb, lds, ls_method;
+  int A, wpb, wpp, lds, ls_method;
   int pop_first, pop_count, ls_first, ls_count, run_first, run_count, adv_first, adv_count;
   int reps;
   double latency;             // relative serial cost of one generation of the class's slowest job

@@ -15,6 +15,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <mutex>
 #include <set>
 
@@ -114,7 +115,8 @@ __device__ __forceinline__ float wrap_angle(float th) {
 // ------------------------------------------------------------------ LDS layout
 // Dynamic LDS of a block (sizes from the ligand's plan): the staged pair rows, shared by the
 // block's waves; then per wave the posed coordinates and the force-array copies, one per lane
-// group of the pair schedule.
+// group of the pair schedule; then, when the block's waves share one pose, the share sets
+// (partial forces and energies, see eval_pose).
 struct BlockLds {
   const float4* pair_coef;   // [pl_rows*64]
   const uint32_t* pair_ij;   // [pl_rows*64]
@@ -122,6 +124,15 @@ struct BlockLds {
   float4* f;                 // this wave: [n_copies][n_atoms + 1] intramolecular forces
   float4* fg;                // this lane's group copy
   float4* tor;               // this wave: [3*n_tors] torsion table (see eval_pose)
+  float4* share;             // waves sharing a pose: two sets of [W + 1][n_atoms + 1] + [W]
+};
+
+// Which of the waves sharing a pose this one is, and which share set its next evaluation uses
+// (sets alternate, so one barrier per evaluation suffices: a wave can rewrite a set only after
+// every wave has passed the next evaluation's barrier, i.e. has finished reading it).
+struct PoseShare {
+  int w;
+  int par;
 };
 
 extern __shared__ __align__(16) unsigned char g_lds[];
@@ -142,7 +153,9 @@ __device__ __forceinline__ BlockLds stage_block(const LigDev& L) {
   }
   const int w = threadIdx.x / kWave;
   const int lane = lane_id();
-  cur += (size_t)w * lds_wave_bytes(L.n_atoms, L.n_copies, A, L.n_tors);
+  const size_t wave_bytes = lds_wave_bytes(L.n_atoms, L.n_copies, A, L.n_tors);
+  b.share = reinterpret_cast<float4*>(cur + (size_t)L.wpb * wave_bytes);
+  cur += (size_t)w * wave_bytes;
   b.pair_coef = pc;
   b.pair_ij = pij;
   b.x = reinterpret_cast<float4*>(cur);
@@ -423,12 +436,37 @@ __device__ __forceinline__ void pair_span(const LigDev& L, const BlockLds& b, in
   }
 }
 
+// Pair rows [r0, r1): the staged prefix from LDS, the rest from global memory.
 template <bool GRAD>
-__device__ __forceinline__ float pair_rows(const LigDev& L, const BlockLds& b) {
+__device__ __forceinline__ float pair_rows(const LigDev& L, const BlockLds& b, int r0, int r1) {
   float e = 0.f;
-  pair_span<GRAD, true>(L, b, 0, L.pl_rows, e);
-  pair_span<GRAD, false>(L, b, L.pl_rows, L.n_rows, e);
+  pair_span<GRAD, true>(L, b, r0, min(r1, L.pl_rows), e);
+  pair_span<GRAD, false>(L, b, max(r0, L.pl_rows), r1, e);
   return e;
+}
+
+// The pair rows [r0, r1) of wave w of the W waves sharing a pose.  Wave a < A also finishes grid
+// slot a (atoms 64a + lane), worth about kGridSlotRows rows, so it takes that many fewer rows;
+// the last wave takes what remains.  W = 1: all rows.
+constexpr int kGridSlotRows = 2;
+
+template <int A, int W>
+__device__ __forceinline__ void share_rows(int n_rows, int w, int& r0, int& r1) {
+  r0 = 0;
+  r1 = n_rows;
+  if (W == 1) return;
+  const int target = (n_rows + kGridSlotRows * A + W - 1) / W;
+  int start = 0;
+#pragma unroll
+  for (int v = 0; v < W; ++v) {
+    const int take = v == W - 1 ? n_rows - start
+                                : min(max(target - (v < A ? kGridSlotRows : 0), 0), n_rows - start);
+    if (v == w) {
+      r0 = start;
+      r1 = start + take;
+    }
+    start += take;
+  }
 }
 
 // Torsion gradients: for torsion k (posed axis u_k and pivot p_k, held in lane k) the sum over
@@ -487,9 +525,14 @@ __device__ __forceinline__ float torsion_gradients(const AtomRegs<A>& at, int T,
 // ------------------------------------------------------------------ one pose
 // Energy (returned, identical in every lane) and, with GRAD, the gradient component of
 // gene `lane` (lanes >= n_genes get 0).  xg: gene `lane` of the pose (lanes < n_genes).
-template <int A, int PREC, bool GRAD>
+// W > 1 waves (the whole block) evaluate one pose together: each poses all atoms, wave w runs
+// its share of the pair rows and wave a < A the grid slot a; the partial forces and energies
+// meet in the share set after one block barrier, and every wave then forms the same energy and
+// gradient from them (same data, same order), so the waves stay in step without a second
+// exchange.  Every wave of the block must make the same sequence of calls.
+template <int A, int PREC, bool GRAD, int W>
 __device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, const AtomRegs<A>& at,
-                           float xg, float& g_out) {
+                           float xg, float& g_out, PoseShare& ps) {
   const int lane = lane_id();
   const int T = L.n_tors;
   // rigid-body genes (wave-uniform)
@@ -564,14 +607,19 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, 
     b.x[i] = make_float4(x[a], y[a], z[a], 0.f);
   }
 
-  // grid term: issue the corner loads now, finish after the pair term
+  // grid term: issue the corner loads now, finish after the pair term (the slots this wave owns)
+  bool gv[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) gv[a] = at.valid[a] && (W == 1 || a == ps.w);
   GridFetch gf[A];
 #pragma unroll
-  for (int a = 0; a < A; ++a) grid_fetch<PREC>(R, x[a], y[a], z[a], at.type[a], at.q[a], at.valid[a], gf[a]);
+  for (int a = 0; a < A; ++a) grid_fetch<PREC>(R, x[a], y[a], z[a], at.type[a], at.q[a], gv[a], gf[a]);
   wave_sync();
 
   // intramolecular pairs; with GRAD each atom then sums (and clears) its force copies
-  float e_lane = pair_rows<GRAD>(L, b);
+  int r0, r1;
+  share_rows<A, W>(L.n_rows, ps.w, r0, r1);
+  float e_lane = pair_rows<GRAD>(L, b, r0, r1);
   float Fx[A], Fy[A], Fz[A];
 #pragma unroll
   for (int a = 0; a < A; ++a) Fx[a] = Fy[a] = Fz[a] = 0.f;
@@ -595,8 +643,53 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, 
 
   float gfx[A], gfy[A], gfz[A];
 #pragma unroll
-  for (int a = 0; a < A; ++a) e_lane += grid_finish(R, gf[a], at.valid[a], gfx[a], gfy[a], gfz[a]);
-  const float E = wave_sum(e_lane);
+  for (int a = 0; a < A; ++a) e_lane += grid_finish(R, gf[a], gv[a], gfx[a], gfy[a], gfz[a]);
+  float E = wave_sum(e_lane);
+  if constexpr (W > 1) {
+    // publish this wave's partials, meet, and take every wave's
+    const int N = L.n_atoms;
+    float4* set = b.share + (size_t)ps.par * ((size_t)(W + 1) * (N + 1) + W);
+    float4* fx = set;                               // [W][N + 1] intramolecular force partials
+    float4* gx = set + (size_t)W * (N + 1);         // [N + 1] grid forces
+    float4* ew = set + (size_t)(W + 1) * (N + 1);   // [W] energy partials
+    if (GRAD) {
+#pragma unroll
+      for (int a = 0; a < A; ++a) {
+        const int i = lane + kWave * a;
+        if (at.valid[a]) fx[ps.w * (N + 1) + i] = make_float4(Fx[a], Fy[a], Fz[a], 0.f);
+        if (gv[a]) gx[i] = make_float4(gfx[a], gfy[a], gfz[a], 0.f);
+      }
+    }
+    if (lane == 0) ew[ps.w] = make_float4(E, 0.f, 0.f, 0.f);
+    __syncthreads();
+    E = ew[0].x;
+#pragma unroll
+    for (int v = 1; v < W; ++v) E += ew[v].x;
+    if (GRAD) {
+#pragma unroll
+      for (int a = 0; a < A; ++a) {
+        if (at.valid[a]) {
+          const int i = lane + kWave * a;
+          float4 f = fx[i];
+#pragma unroll
+          for (int v = 1; v < W; ++v) {
+            const float4 fv = fx[v * (N + 1) + i];
+            f.x += fv.x;
+            f.y += fv.y;
+            f.z += fv.z;
+          }
+          Fx[a] = f.x;
+          Fy[a] = f.y;
+          Fz[a] = f.z;
+          const float4 gg = gx[i];
+          gfx[a] = gg.x;
+          gfy[a] = gg.y;
+          gfz[a] = gg.z;
+        }
+      }
+    }
+    ps.par ^= 1;
+  }
   if (!GRAD) return E;
   wave_sync();
 
@@ -653,11 +746,21 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, 
 }
 
 // ------------------------------------------------------------------ kernels
-template <int A, int PREC>
+// One block = blockDim / (64 W) poses; W > 1: the block's waves share its one pose.
+template <int W>
+__device__ __forceinline__ int block_pose(PoseShare& ps) {
+  const int wave = threadIdx.x / kWave;
+  ps.w = wave % W;
+  ps.par = 0;
+  return blockIdx.x * (blockDim.x / (kWave * W)) + wave / W;
+}
+
+template <int A, int PREC, int W>
 __global__ __launch_bounds__(kMaxBlock) void k_eval(LigDev L, RecDev R, int n, const float* __restrict__ genes,
                                                  float* __restrict__ energy, float* __restrict__ grad) {
   const BlockLds b = stage_block<A>(L);
-  const int pose = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  PoseShare ps;
+  const int pose = block_pose<W>(ps);
   if (pose >= n) return;
   AtomRegs<A> at;
   load_ligand<A>(L, at);
@@ -667,12 +770,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_eval(LigDev L, RecDev R, int n, c
   float g = 0.f;
   float E;
   if (grad) {
-    E = eval_pose<A, PREC, true>(L, R, b, at, xg, g);
-    if (lane < G) grad[(long long)pose * G + lane] = g;
+    E = eval_pose<A, PREC, true, W>(L, R, b, at, xg, g, ps);
+    if (lane < G && ps.w == 0) grad[(long long)pose * G + lane] = g;
   } else {
-    E = eval_pose<A, PREC, false>(L, R, b, at, xg, g);
+    E = eval_pose<A, PREC, false, W>(L, R, b, at, xg, g, ps);
   }
-  if (lane == 0) energy[pose] = E;
+  if (lane == 0 && ps.w == 0) energy[pose] = E;
 }
 
 template <int A>
@@ -757,10 +860,11 @@ __device__ __forceinline__ float adadelta_update(float x, float g, float& eg2, f
 
 // ADADELTA from genes_in[row_in] for `iters` steps; the best genotype goes to genes_out[row_out]
 // and its energy is returned (wave-uniform).  trace: NULL or [iters] energies of every step.
-template <int A, int PREC>
+template <int A, int PREC, int W>
 __device__ float local_search_wave(const LigDev& L, const RecDev& R, const BlockLds& b, const AtomRegs<A>& at,
                                    const float* genes_in, long long row_in, float* genes_out,
-                                   long long row_out, int iters, float rho, float eps, float* trace) {
+                                   long long row_out, int iters, float rho, float eps, float* trace,
+                                   PoseShare& ps) {
   const int lane = lane_id();
   const int G = L.n_genes;
   float x = lane < G ? genes_in[row_in * G + lane] : 0.f;
@@ -769,33 +873,34 @@ __device__ float local_search_wave(const LigDev& L, const RecDev& R, const Block
   float best_e = __builtin_huge_valf();
   for (int it = 0; it < iters; ++it) {
     float g = 0.f;
-    const float E = eval_pose<A, PREC, true>(L, R, b, at, x, g);
-    if (trace && lane == 0) trace[it] = E;
+    const float E = eval_pose<A, PREC, true, W>(L, R, b, at, x, g, ps);
+    if (trace && lane == 0 && ps.w == 0) trace[it] = E;
     if (E < best_e) {
       best_e = E;
       best_x = x;
     }
     x = adadelta_update(x, g, eg2, edx2, rho, eps, G);
   }
-  if (lane < G) genes_out[row_out * G + lane] = best_x;
+  if (lane < G && ps.w == 0) genes_out[row_out * G + lane] = best_x;
   return best_e;
 }
 
-// Standalone local search: one wave per start genotype.
-template <int A, int PREC>
+// Standalone local search: one pose (W waves) per start genotype.
+template <int A, int PREC, int W>
 __global__ __launch_bounds__(kMaxBlock) void k_local_search(LigDev L, RecDev R, int n,
                                                          const float* genes_in, float* genes_out,
                                                          float* __restrict__ energy_out,
                                                          int iters, float rho, float eps,
                                                          float* __restrict__ trace) {
   const BlockLds b = stage_block<A>(L);
-  const int job = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  PoseShare ps;
+  const int job = block_pose<W>(ps);
   if (job >= n) return;
   AtomRegs<A> at;
   load_ligand<A>(L, at);
-  const float E = local_search_wave<A, PREC>(L, R, b, at, genes_in, job, genes_out, job, iters, rho, eps,
-                                             trace ? trace + (long long)job * iters : nullptr);
-  if (lane_id() == 0) energy_out[job] = E;
+  const float E = local_search_wave<A, PREC, W>(L, R, b, at, genes_in, job, genes_out, job, iters, rho, eps,
+                                                trace ? trace + (long long)job * iters : nullptr, ps);
+  if (lane_id() == 0 && ps.w == 0) energy_out[job] = E;
 }
 
 // ------------------------------------------------------------------ Solis-Wets
@@ -822,18 +927,19 @@ __device__ __forceinline__ float box_muller(uint32_t k1, uint32_t k2) {
 // One wave's search from genes_in[row_in]; the final genotype goes to genes_out[row_out] and
 // its energy is returned (wave-uniform).  key: draw_prefix of the search's coordinates.
 // trace: NULL or [n_evals] energies of every evaluation.
-template <int A, int PREC>
+template <int A, int PREC, int W>
 __device__ float solis_wets_wave(const LigDev& L, const RecDev& R, const BlockLds& b, const AtomRegs<A>& at,
                                  const float* genes_in, long long row_in, float* genes_out, long long row_out,
-                                 int n_evals, uint64_t key, float* trace) {
+                                 int n_evals, uint64_t key, float* trace, PoseShare& ps) {
   const int lane = lane_id();
   const int G = L.n_genes;
   const bool gene = lane < G;
   const float sigma = lane < 3 ? kSwSigmaTrans : (lane < 7 ? kSwSigmaQuat : kSwSigmaTors);
   float x = gene ? genes_in[row_in * G + lane] : 0.f;
   float g;
-  float e = eval_pose<A, PREC, false>(L, R, b, at, x, g);
-  if (trace && lane == 0) trace[0] = e;
+  const bool out = ps.w == 0;
+  float e = eval_pose<A, PREC, false, W>(L, R, b, at, x, g, ps);
+  if (trace && lane == 0 && out) trace[0] = e;
   int used = 1;
   float bias = 0.f, rho = kSwRho0;
   int succ = 0, fail = 0;
@@ -842,8 +948,8 @@ __device__ float solis_wets_wave(const LigDev& L, const RecDev& R, const BlockLd
     const float z = box_muller(draw_from(key, 2u * m), draw_from(key, 2u * m + 1u));
     const float xi = gene ? bias + rho * sigma * z : 0.f;
     const float x1 = project_gene(x + xi, G);
-    const float e1 = eval_pose<A, PREC, false>(L, R, b, at, x1, g);
-    if (trace && lane == 0) trace[used] = e1;
+    const float e1 = eval_pose<A, PREC, false, W>(L, R, b, at, x1, g, ps);
+    if (trace && lane == 0 && out) trace[used] = e1;
     ++used;
     bool moved = true;
     if (e1 < e) {
@@ -852,8 +958,8 @@ __device__ float solis_wets_wave(const LigDev& L, const RecDev& R, const BlockLd
       bias = 0.2f * bias + 0.4f * xi;
     } else if (used < n_evals) {
       const float x2 = project_gene(x - xi, G);
-      const float e2 = eval_pose<A, PREC, false>(L, R, b, at, x2, g);
-      if (trace && lane == 0) trace[used] = e2;
+      const float e2 = eval_pose<A, PREC, false, W>(L, R, b, at, x2, g, ps);
+      if (trace && lane == 0 && out) trace[used] = e2;
       ++used;
       if (e2 < e) {
         x = x2;
@@ -878,26 +984,27 @@ __device__ float solis_wets_wave(const LigDev& L, const RecDev& R, const BlockLd
       fail = 0;
     }
   }
-  if (gene) genes_out[row_out * G + lane] = x;
+  if (gene && out) genes_out[row_out * G + lane] = x;
   return e;
 }
 
 // Standalone Solis-Wets: one wave per start genotype; start k draws from coordinates
 // (seed, 0, 0, k).
-template <int A, int PREC>
+template <int A, int PREC, int W>
 __global__ __launch_bounds__(kMaxBlock) void k_solis_wets(LigDev L, RecDev R, int n, const float* genes_in,
                                                        float* genes_out, float* __restrict__ energy_out,
                                                        int n_evals, unsigned long long seed,
                                                        float* __restrict__ trace) {
   const BlockLds b = stage_block<A>(L);
-  const int job = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  PoseShare ps;
+  const int job = block_pose<W>(ps);
   if (job >= n) return;
   AtomRegs<A> at;
   load_ligand<A>(L, at);
   const uint64_t key = draw_prefix(seed, 0u, 0u, (uint32_t)job, kPLsSw);
-  const float E = solis_wets_wave<A, PREC>(L, R, b, at, genes_in, job, genes_out, job, n_evals, key,
-                                           trace ? trace + (long long)job * n_evals : nullptr);
-  if (lane_id() == 0) energy_out[job] = E;
+  const float E = solis_wets_wave<A, PREC, W>(L, R, b, at, genes_in, job, genes_out, job, n_evals, key,
+                                              trace ? trace + (long long)job * n_evals : nullptr, ps);
+  if (lane_id() == 0 && ps.w == 0) energy_out[job] = E;
 }
 
 // Initial individual `indiv` of run `run` in the lane-per-gene layout.
@@ -1039,7 +1146,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_ga_init(JobDev* __restrict__ jobs
   const int run = w / P.pop_size, indiv = w % P.pop_size;
   const float x = initial_gene(R, P, run, indiv);
   float g;
-  const float E = eval_pose<A, PREC, false>(L, R, b, at, x, g);
+  PoseShare ps{0, 0};
+  const float E = eval_pose<A, PREC, false, 1>(L, R, b, at, x, g, ps);
   float* genes = J.genes[J.cur];
   if (lane < G) genes[(long long)w * G + lane] = x;
   if (lane == 0) {
@@ -1081,7 +1189,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_ga_generation(JobDev* __restrict_
   load_ligand<A>(L, at);
   const float x = offspring_gene(P, genes_in, E, rbase, G, L.n_tors, run, gen, slot);
   float g;
-  const float Enew = eval_pose<A, PREC, false>(L, R, b, at, x, g);
+  PoseShare ps{0, 0};
+  const float Enew = eval_pose<A, PREC, false, 1>(L, R, b, at, x, g, ps);
   if (lane < G) genes_out[(long long)w * G + lane] = x;
   if (lane == 0) {
     energy_out[w] = Enew;
@@ -1115,7 +1224,9 @@ __global__ __launch_bounds__(kBlock) void k_ga_ls_pick(JobDev* __restrict__ jobs
   }
 }
 
-template <int A, int PREC>
+// Local search on the picked individuals; a block holds blockDim / (64 W) searches from
+// (job, first search) of its block-table entry.
+template <int A, int PREC, int W>
 __global__ __launch_bounds__(kMaxBlock) void k_ga_local_search(JobDev* __restrict__ jobs,
                                                             const int2* __restrict__ blocks, RecDev R) {
   const int2 bt = blocks[blockIdx.x];
@@ -1125,14 +1236,16 @@ __global__ __launch_bounds__(kMaxBlock) void k_ga_local_search(JobDev* __restric
   const GaDev P = J.P;
   const int cur = J.cur;
   const BlockLds b = stage_block<A>(L);
-  const int w = bt.y + threadIdx.x / kWave;
+  PoseShare ps{(int)(threadIdx.x / kWave) % W, 0};
+  const int w = bt.y + (int)(threadIdx.x / kWave) / W;
   if (w >= P.n_runs * P.n_ls) return;
   AtomRegs<A> at;
   load_ligand<A>(L, at);
   const long long row = J.ls_rows[w];
   float* pop = J.genes[cur ^ 1];
-  const float E = local_search_wave<A, PREC>(L, R, b, at, pop, row, pop, row, P.ls_iters, P.rho, P.eps, nullptr);
-  if (lane_id() == 0) {
+  const float E = local_search_wave<A, PREC, W>(L, R, b, at, pop, row, pop, row, P.ls_iters, P.rho, P.eps,
+                                                nullptr, ps);
+  if (lane_id() == 0 && ps.w == 0) {
     J.energy[cur ^ 1][row] = E;
     J.evals[row] += P.ls_iters;
   }
@@ -1140,7 +1253,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_ga_local_search(JobDev* __restric
 
 // Solis-Wets on the picked individuals (Lamarckian write-back); the search of individual i of
 // run r in generation g draws from coordinates (seed, r, g, i).
-template <int A, int PREC>
+template <int A, int PREC, int W>
 __global__ __launch_bounds__(kMaxBlock) void k_ga_solis_wets(JobDev* __restrict__ jobs,
                                                           const int2* __restrict__ blocks, RecDev R) {
   const int2 bt = blocks[blockIdx.x];
@@ -1150,7 +1263,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_ga_solis_wets(JobDev* __restrict_
   const GaDev P = J.P;
   const int cur = J.cur, gen = J.gen;
   const BlockLds b = stage_block<A>(L);
-  const int w = bt.y + threadIdx.x / kWave;
+  PoseShare ps{(int)(threadIdx.x / kWave) % W, 0};
+  const int w = bt.y + (int)(threadIdx.x / kWave) / W;
   if (w >= P.n_runs * P.n_ls) return;
   AtomRegs<A> at;
   load_ligand<A>(L, at);
@@ -1158,8 +1272,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_ga_solis_wets(JobDev* __restrict_
   const uint64_t key = draw_prefix(P.seed, (uint32_t)(row / P.pop_size), (uint32_t)gen,
                                    (uint32_t)(row % P.pop_size), kPLsSw);
   float* pop = J.genes[cur ^ 1];
-  const float E = solis_wets_wave<A, PREC>(L, R, b, at, pop, row, pop, row, P.ls_iters, key, nullptr);
-  if (lane_id() == 0) {
+  const float E = solis_wets_wave<A, PREC, W>(L, R, b, at, pop, row, pop, row, P.ls_iters, key, nullptr, ps);
+  if (lane_id() == 0 && ps.w == 0) {
     J.energy[cur ^ 1][row] = E;
     J.evals[row] += P.ls_iters;
   }
@@ -1220,21 +1334,46 @@ inline unsigned blocks_for(long long waves, int wpb = kWavesPerBlock) {
 
 }  // namespace
 
-#define MDOCK_DISPATCH(KERNEL, GRID, STREAM, ...)                                                   \
-  do {                                                                                             \
-    const bool two = L.n_atoms > kWave;                                                            \
-    const size_t sm = (size_t)L.lds_bytes;                                                         \
-    const dim3 blk(kWave * L.wpb);                                                                    \
-    switch (R.precision * 2 + (two ? 1 : 0)) {                                                     \
-      case 0: hipLaunchKernelGGL((KERNEL<1, 0>), GRID, blk, sm, STREAM, __VA_ARGS__); break; \
-      case 1: hipLaunchKernelGGL((KERNEL<2, 0>), GRID, blk, sm, STREAM, __VA_ARGS__); break; \
-      case 2: hipLaunchKernelGGL((KERNEL<1, 1>), GRID, blk, sm, STREAM, __VA_ARGS__); break; \
-      case 3: hipLaunchKernelGGL((KERNEL<2, 1>), GRID, blk, sm, STREAM, __VA_ARGS__); break; \
-      case 4: hipLaunchKernelGGL((KERNEL<1, 2>), GRID, blk, sm, STREAM, __VA_ARGS__); break; \
-      default: hipLaunchKernelGGL((KERNEL<2, 2>), GRID, blk, sm, STREAM, __VA_ARGS__); break; \
-    }                                                                                              \
+// KERNEL<A, PREC> or KERNEL<A, PREC, W> for a ligand of A atoms per lane, maps of precision
+// PREC (0 fp32, 1 fp16, 2 bf16) and W waves per pose.
+#define MDOCK_LAUNCH_W(KERNEL, A_, P_, W_, GRID, BLK, SM, STREAM, ...)                              \
+  switch (W_) {                                                                                   \
+    case 2: hipLaunchKernelGGL((KERNEL<A_, P_, 2>), GRID, BLK, SM, STREAM, __VA_ARGS__); break;   \
+    case 4: hipLaunchKernelGGL((KERNEL<A_, P_, 4>), GRID, BLK, SM, STREAM, __VA_ARGS__); break;   \
+    default: hipLaunchKernelGGL((KERNEL<A_, P_, 1>), GRID, BLK, SM, STREAM, __VA_ARGS__); break;  \
+  }
+
+#define MDOCK_DISPATCH_W(KERNEL, A, PREC, W, GRID, BLK, SM, STREAM, ...)                           \
+  do {                                                                                            \
+    switch ((PREC) * 2 + ((A) == 2 ? 1 : 0)) {                                                    \
+      case 0: MDOCK_LAUNCH_W(KERNEL, 1, 0, W, GRID, BLK, SM, STREAM, __VA_ARGS__) break;           \
+      case 1: MDOCK_LAUNCH_W(KERNEL, 2, 0, W, GRID, BLK, SM, STREAM, __VA_ARGS__) break;           \
+      case 2: MDOCK_LAUNCH_W(KERNEL, 1, 1, W, GRID, BLK, SM, STREAM, __VA_ARGS__) break;           \
+      case 3: MDOCK_LAUNCH_W(KERNEL, 2, 1, W, GRID, BLK, SM, STREAM, __VA_ARGS__) break;           \
+      case 4: MDOCK_LAUNCH_W(KERNEL, 1, 2, W, GRID, BLK, SM, STREAM, __VA_ARGS__) break;           \
+      default: MDOCK_LAUNCH_W(KERNEL, 2, 2, W, GRID, BLK, SM, STREAM, __VA_ARGS__) break;          \
+    }                                                                                             \
   } while (0)
 
+#define MDOCK_DISPATCH(KERNEL, A, PREC, GRID, BLK, SM, STREAM, ...)                                \
+  do {                                                                                            \
+    switch ((PREC) * 2 + ((A) == 2 ? 1 : 0)) {                                                    \
+      case 0: hipLaunchKernelGGL((KERNEL<1, 0>), GRID, BLK, SM, STREAM, __VA_ARGS__); break;      \
+      case 1: hipLaunchKernelGGL((KERNEL<2, 0>), GRID, BLK, SM, STREAM, __VA_ARGS__); break;      \
+      case 2: hipLaunchKernelGGL((KERNEL<1, 1>), GRID, BLK, SM, STREAM, __VA_ARGS__); break;      \
+      case 3: hipLaunchKernelGGL((KERNEL<2, 1>), GRID, BLK, SM, STREAM, __VA_ARGS__); break;      \
+      case 4: hipLaunchKernelGGL((KERNEL<1, 2>), GRID, BLK, SM, STREAM, __VA_ARGS__); break;      \
+      default: hipLaunchKernelGGL((KERNEL<2, 2>), GRID, BLK, SM, STREAM, __VA_ARGS__); break;     \
+    }                                                                                             \
+  } while (0)
+
+#define MDOCK_FN_W(K, A, P) (const void*)K<A, P, 1>, (const void*)K<A, P, 2>, (const void*)K<A, P, 4>
+#define MDOCK_FNS_W(K)                                                                            \
+  MDOCK_FN_W(K, 1, 0), MDOCK_FN_W(K, 2, 0), MDOCK_FN_W(K, 1, 1), MDOCK_FN_W(K, 2, 1),              \
+      MDOCK_FN_W(K, 1, 2), MDOCK_FN_W(K, 2, 2)
+#define MDOCK_FNS(K)                                                                              \
+  (const void*)K<1, 0>, (const void*)K<2, 0>, (const void*)K<1, 1>, (const void*)K<2, 1>,          \
+      (const void*)K<1, 2>, (const void*)K<2, 2>
 
 hipError_t enable_large_lds() {
   static std::mutex mu;
@@ -1244,26 +1383,9 @@ hipError_t enable_large_lds() {
   if (e != hipSuccess) return e;
   std::lock_guard<std::mutex> lk(mu);
   if (done.count(dev)) return hipSuccess;
-  const void* fns[] = {
-      (const void*)k_eval<1, 0>, (const void*)k_eval<2, 0>, (const void*)k_eval<1, 1>,
-      (const void*)k_eval<2, 1>, (const void*)k_eval<1, 2>, (const void*)k_eval<2, 2>,
-      (const void*)k_local_search<1, 0>, (const void*)k_local_search<2, 0>,
-      (const void*)k_local_search<1, 1>, (const void*)k_local_search<2, 1>,
-      (const void*)k_local_search<1, 2>, (const void*)k_local_search<2, 2>,
-      (const void*)k_ga_init<1, 0>, (const void*)k_ga_init<2, 0>, (const void*)k_ga_init<1, 1>,
-      (const void*)k_ga_init<2, 1>, (const void*)k_ga_init<1, 2>, (const void*)k_ga_init<2, 2>,
-      (const void*)k_ga_generation<1, 0>, (const void*)k_ga_generation<2, 0>,
-      (const void*)k_ga_generation<1, 1>, (const void*)k_ga_generation<2, 1>,
-      (const void*)k_ga_generation<1, 2>, (const void*)k_ga_generation<2, 2>,
-      (const void*)k_ga_local_search<1, 0>, (const void*)k_ga_local_search<2, 0>,
-      (const void*)k_ga_local_search<1, 1>, (const void*)k_ga_local_search<2, 1>,
-      (const void*)k_ga_local_search<1, 2>, (const void*)k_ga_local_search<2, 2>,
-      (const void*)k_solis_wets<1, 0>, (const void*)k_solis_wets<2, 0>,
-      (const void*)k_solis_wets<1, 1>, (const void*)k_solis_wets<2, 1>,
-      (const void*)k_solis_wets<1, 2>, (const void*)k_solis_wets<2, 2>,
-      (const void*)k_ga_solis_wets<1, 0>, (const void*)k_ga_solis_wets<2, 0>,
-      (const void*)k_ga_solis_wets<1, 1>, (const void*)k_ga_solis_wets<2, 1>,
-      (const void*)k_ga_solis_wets<1, 2>, (const void*)k_ga_solis_wets<2, 2>};
+  const void* fns[] = {MDOCK_FNS_W(k_eval),          MDOCK_FNS_W(k_local_search),  MDOCK_FNS_W(k_solis_wets),
+                       MDOCK_FNS_W(k_ga_local_search), MDOCK_FNS_W(k_ga_solis_wets), MDOCK_FNS(k_ga_init),
+                       MDOCK_FNS(k_ga_generation)};
   for (const void* f : fns) {
     e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsPerBlock);
     if (e != hipSuccess) return e;
@@ -1272,10 +1394,15 @@ hipError_t enable_large_lds() {
   return hipSuccess;
 }
 
+// searches (poses) per block of the ligand's plan
+inline int poses_per_block(const LigDev& L) { return std::max(1, L.wpb / std::max(1, L.wpp)); }
+
 hipError_t launch_eval(const LigDev& L, const RecDev& R, int n, const float* genes, float* energy,
                        float* grad, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  MDOCK_DISPATCH(k_eval, dim3(blocks_for(n, L.wpb)), s, L, R, n, genes, energy, grad);
+  const int A = L.n_atoms > kWave ? 2 : 1;
+  MDOCK_DISPATCH_W(k_eval, A, R.precision, L.wpp, dim3(blocks_for(n, poses_per_block(L))), dim3(kWave * L.wpb),
+                   (size_t)L.lds_bytes, s, L, R, n, genes, energy, grad);
   return hipGetLastError();
 }
 
@@ -1292,8 +1419,10 @@ hipError_t launch_local_search(const LigDev& L, const RecDev& R, int n, const fl
                                float* genes_out, float* energy_out, int iters, float rho, float eps,
                                float* trace, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  MDOCK_DISPATCH(k_local_search, dim3(blocks_for(n, L.wpb)), s, L, R, n, genes_in, genes_out, energy_out,
-                 iters, rho, eps, trace);
+  const int A = L.n_atoms > kWave ? 2 : 1;
+  MDOCK_DISPATCH_W(k_local_search, A, R.precision, L.wpp, dim3(blocks_for(n, poses_per_block(L))),
+                   dim3(kWave * L.wpb), (size_t)L.lds_bytes, s, L, R, n, genes_in, genes_out, energy_out, iters,
+                   rho, eps, trace);
   return hipGetLastError();
 }
 
@@ -1301,36 +1430,25 @@ hipError_t launch_solis_wets(const LigDev& L, const RecDev& R, int n, const floa
                              float* energy_out, int n_evals, unsigned long long seed, float* trace, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (n_evals < 1 || n_evals > kSwMaxEvals) return hipErrorInvalidValue;
-  MDOCK_DISPATCH(k_solis_wets, dim3(blocks_for(n, L.wpb)), s, L, R, n, genes_in, genes_out, energy_out,
-                 n_evals, seed, trace);
+  const int A = L.n_atoms > kWave ? 2 : 1;
+  MDOCK_DISPATCH_W(k_solis_wets, A, R.precision, L.wpp, dim3(blocks_for(n, poses_per_block(L))),
+                   dim3(kWave * L.wpb), (size_t)L.lds_bytes, s, L, R, n, genes_in, genes_out, energy_out, n_evals,
+                   seed, trace);
   return hipGetLastError();
 }
-
-#define MDOCK_GA_DISPATCH(KERNEL, A, WPB, LDS, NB, STREAM, ...)                                     \
-  do {                                                                                             \
-    const size_t sm = (size_t)(LDS);                                                               \
-    const dim3 blk(kWave * (WPB));                                                                    \
-    switch (R.precision * 2 + ((A) == 2 ? 1 : 0)) {                                               \
-      case 0: hipLaunchKernelGGL((KERNEL<1, 0>), dim3(NB), blk, sm, STREAM, __VA_ARGS__); break; \
-      case 1: hipLaunchKernelGGL((KERNEL<2, 0>), dim3(NB), blk, sm, STREAM, __VA_ARGS__); break; \
-      case 2: hipLaunchKernelGGL((KERNEL<1, 1>), dim3(NB), blk, sm, STREAM, __VA_ARGS__); break; \
-      case 3: hipLaunchKernelGGL((KERNEL<2, 1>), dim3(NB), blk, sm, STREAM, __VA_ARGS__); break; \
-      case 4: hipLaunchKernelGGL((KERNEL<1, 2>), dim3(NB), blk, sm, STREAM, __VA_ARGS__); break; \
-      default: hipLaunchKernelGGL((KERNEL<2, 2>), dim3(NB), blk, sm, STREAM, __VA_ARGS__); break; \
-    }                                                                                              \
-  } while (0)
 
 hipError_t launch_ga_init(JobDev* jobs, const int2* blocks, int n_blocks, int A, int wpb, int lds,
                           const RecDev& R, hipStream_t s) {
   if (n_blocks <= 0) return hipSuccess;
-  MDOCK_GA_DISPATCH(k_ga_init, A, wpb, lds, n_blocks, s, jobs, blocks, R);
+  MDOCK_DISPATCH(k_ga_init, A, R.precision, dim3(n_blocks), dim3(kWave * wpb), (size_t)lds, s, jobs, blocks, R);
   return hipGetLastError();
 }
 
 hipError_t launch_ga_generation(JobDev* jobs, const int2* blocks, int n_blocks, int A, int wpb, int lds,
                                 const RecDev& R, hipStream_t s) {
   if (n_blocks <= 0) return hipSuccess;
-  MDOCK_GA_DISPATCH(k_ga_generation, A, wpb, lds, n_blocks, s, jobs, blocks, R);
+  MDOCK_DISPATCH(k_ga_generation, A, R.precision, dim3(n_blocks), dim3(kWave * wpb), (size_t)lds, s, jobs, blocks,
+                 R);
   return hipGetLastError();
 }
 
@@ -1340,13 +1458,15 @@ hipError_t launch_ga_ls_pick(JobDev* jobs, const int2* blocks, int n_blocks, hip
   return hipGetLastError();
 }
 
-hipError_t launch_ga_local_search(JobDev* jobs, const int2* blocks, int n_blocks, int A, int wpb, int lds,
-                                  int ls_method, const RecDev& R, hipStream_t s) {
+hipError_t launch_ga_local_search(JobDev* jobs, const int2* blocks, int n_blocks, int A, int wpb, int wpp,
+                                  int lds, int ls_method, const RecDev& R, hipStream_t s) {
   if (n_blocks <= 0) return hipSuccess;
   if (ls_method == kLsSolisWets)
-    MDOCK_GA_DISPATCH(k_ga_solis_wets, A, wpb, lds, n_blocks, s, jobs, blocks, R);
+    MDOCK_DISPATCH_W(k_ga_solis_wets, A, R.precision, wpp, dim3(n_blocks), dim3(kWave * wpb), (size_t)lds, s, jobs,
+                     blocks, R);
   else
-    MDOCK_GA_DISPATCH(k_ga_local_search, A, wpb, lds, n_blocks, s, jobs, blocks, R);
+    MDOCK_DISPATCH_W(k_ga_local_search, A, R.precision, wpp, dim3(n_blocks), dim3(kWave * wpb), (size_t)lds, s,
+                     jobs, blocks, R);
   return hipGetLastError();
 }
 

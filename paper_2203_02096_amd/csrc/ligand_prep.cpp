@@ -254,9 +254,11 @@ void plan_ligand(LigHost& out, const PlanParams& pp) {
   out.group_lanes = m;
   out.n_copies = groups_used;
   out.plan = pp;
-  out.wpb = std::max(1, std::min(kMaxWavesPerBlock, pp.wpb));
+  out.wpp = (pp.wpp == 2 || pp.wpp == 4) ? pp.wpp : 1;
+  out.wpb = out.wpp > 1 ? out.wpp : std::max(1, std::min(kMaxWavesPerBlock, pp.wpb));
   const size_t budget = (size_t)std::max(0, std::min(pp.lds_budget, kMaxLdsPerBlock));
-  const size_t waves = (size_t)out.wpb * lds_wave_bytes(n, out.n_copies, A, out.n_tors);
+  const size_t waves = (size_t)out.wpb * lds_wave_bytes(n, out.n_copies, A, out.n_tors) +
+                       lds_pose_share_bytes(n, out.wpp);
   int pr = out.n_rows;
   while (pr > 0 && waves + lds_pairs_bytes(pr) > budget) --pr;
   out.pl_rows = pr;

@@ -46,19 +46,21 @@ double eval_cost(const LigDev& L) {
 
 void build_schedule(const std::vector<SchedJob>& jobs, GenSchedule& out, int max_reps, int uniform_reps) {
   out = GenSchedule();
-  // class key: (atoms per lane, waves per block, -(waves per CU), local optimiser); denser
-  // classes first
-  using Key = std::tuple<int, int, int, int>;
+  // class key: (atoms per lane, waves per block, -(waves per CU), local optimiser, waves per
+  // search); denser classes first
+  using Key = std::tuple<int, int, int, int, int>;
   std::map<Key, std::vector<int>> cls;
   for (int k = 0; k < (int)jobs.size(); ++k) {
     const SchedJob& j = jobs[k];
     const int A = j.L->n_atoms > kWave ? 2 : 1;
-    cls[Key(A, j.L->wpb, -occupancy_class(j.L->lds_bytes) * j.L->wpb, j.ls_method)].push_back(k);
+    cls[Key(A, j.L->wpb, -occupancy_class(j.L->lds_bytes) * j.L->wpb, j.ls_method, std::max(1, j.L->wpp))]
+        .push_back(k);
   }
   std::vector<double> cost(jobs.size());
   for (size_t k = 0; k < jobs.size(); ++k) {
     const SchedJob& j = jobs[k];
-    const double ls_eval = j.ls_method == kLsSolisWets ? kEnergyOnlyCost : 1.0;
+    // a search whose pose is shared by wpp waves takes about 1/wpp of the time
+    const double ls_eval = (j.ls_method == kLsSolisWets ? kEnergyOnlyCost : 1.0) / std::max(1, j.L->wpp);
     cost[k] = eval_cost(*j.L) * (1.0 + (j.n_ls > 0 ? ls_eval * (double)j.ls_iters : 0.0));
   }
   for (auto& kv : cls) {
@@ -68,6 +70,7 @@ void build_schedule(const std::vector<SchedJob>& jobs, GenSchedule& out, int max
     c.A = std::get<0>(kv.first);
     c.wpb = std::get<1>(kv.first);
     c.ls_method = std::get<3>(kv.first);
+    c.wpp = std::get<4>(kv.first);
     c.pop_first = (int)out.blocks.size();
     for (int k : m) {
       const SchedJob& j = jobs[k];
@@ -78,10 +81,11 @@ void build_schedule(const std::vector<SchedJob>& jobs, GenSchedule& out, int max
     }
     c.pop_count = (int)out.blocks.size() - c.pop_first;
     c.ls_first = (int)out.blocks.size();
+    const int searches_per_block = std::max(1, c.wpb / c.wpp);
     for (int k : m) {
       const SchedJob& j = jobs[k];
-      const long long waves = (long long)j.n_runs * j.n_ls;
-      for (long long w = 0; w < waves; w += c.wpb) out.blocks.push_back(make_int2(j.slot, (int)w));
+      const long long searches = (long long)j.n_runs * j.n_ls;
+      for (long long w = 0; w < searches; w += searches_per_block) out.blocks.push_back(make_int2(j.slot, (int)w));
     }
     c.ls_count = (int)out.blocks.size() - c.ls_first;
     c.run_first = (int)out.blocks.size();
@@ -131,8 +135,8 @@ hipError_t launch_chain(const ClassChain& c, JobDev* table, const int2* d_blocks
     e = run(MD_K_LS_PICK, [&] { return launch_ga_ls_pick(table, d_blocks + c.run_first, c.run_count, st); });
   if (e == hipSuccess && c.ls_count > 0)
     e = run(MD_K_LOCAL_SEARCH, [&] {
-      return launch_ga_local_search(table, d_blocks + c.ls_first, c.ls_count, c.A, c.wpb, c.lds, c.ls_method, R,
-                                    st);
+      return launch_ga_local_search(table, d_blocks + c.ls_first, c.ls_count, c.A, c.wpb, c.wpp, c.lds, c.ls_method,
+                                    R, st);
     });
   if (e == hipSuccess)
     e = run(MD_K_SUM_EVALS, [&] { return launch_ga_advance_list(table, d_blocks + c.adv_first, c.adv_count, st); });

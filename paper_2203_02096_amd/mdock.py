@@ -68,7 +68,8 @@ class ServerStats(C.Structure):
 
 class Plan(C.Structure):
     _fields_ = [("lds_budget", C.c_int), ("group_div", C.c_int), ("waves_per_block", C.c_int),
-                ("lds_bytes", C.c_int), ("staged_rows", C.c_int), ("total_rows", C.c_int)]
+                ("lds_bytes", C.c_int), ("staged_rows", C.c_int), ("total_rows", C.c_int),
+                ("waves_per_pose", C.c_int)]
 
 
 class TuneInfo(C.Structure):
@@ -378,8 +379,8 @@ def md_ligand_get_plan(lig: Ligand):
     return _plan_dict(p)
 
 
-def md_ligand_set_plan(lig: Ligand, lds_budget=65536, group_div=3, waves_per_block=4):
-    p = Plan(int(lds_budget), int(group_div), int(waves_per_block), 0, 0, 0)
+def md_ligand_set_plan(lig: Ligand, lds_budget=65536, group_div=3, waves_per_block=4, waves_per_pose=1):
+    p = Plan(int(lds_budget), int(group_div), int(waves_per_block), 0, 0, 0, int(waves_per_pose))
     _check(lib().md_ligand_set_plan(lig.handle, C.byref(p)), "md_ligand_set_plan")
     return md_ligand_get_plan(lig)
 
@@ -395,7 +396,7 @@ def md_ligand_autotune(rec: Receptor, lig: Ligand, n_starts=0, force=False, stre
                 from_table=bool(info.from_table))
 
 
-def md_schedule_preview(lig, lds_budget=65536, group_div=3, waves_per_block=4):
+def md_schedule_preview(lig, lds_budget=65536, group_div=3, waves_per_block=4, waves_per_pose=1):
     """Host only: the pair schedule (slots i | j<<8 | hb<<16 | empty<<17, row-major) that a plan
     gives a ligand described like workload.synth.Ligand; returns (plan dict, slots, group_lanes)."""
     xyz = np.ascontiguousarray(lig.xyz, dtype=np.float32).reshape(-1, 3)
@@ -406,11 +407,11 @@ def md_schedule_preview(lig, lds_budget=65536, group_div=3, waves_per_block=4):
     tp = np.ascontiguousarray(lig.type_params, dtype=np.float32).reshape(-1, 7)
     d = LigandDesc(xyz.shape[0], _fptr(xyz), _iptr(types), _fptr(q), bonds.shape[0], _iptr(bonds),
                    tors.shape[0], _iptr(tors), int(getattr(lig, "root", 0)), tp.shape[0], _fptr(tp))
-    p = Plan(int(lds_budget), int(group_div), int(waves_per_block), 0, 0, 0)
+    p = Plan(int(lds_budget), int(group_div), int(waves_per_block), 0, 0, 0, int(waves_per_pose))
     gl = C.c_int()
     _check(lib().md_schedule_preview(C.byref(d), C.byref(p), None, 0, C.byref(gl)), "md_schedule_preview")
     slots = np.zeros(p.total_rows * 64, dtype=np.uint32)
-    p2 = Plan(int(lds_budget), int(group_div), int(waves_per_block), 0, 0, 0)
+    p2 = Plan(int(lds_budget), int(group_div), int(waves_per_block), 0, 0, 0, int(waves_per_pose))
     _check(lib().md_schedule_preview(C.byref(d), C.byref(p2), slots.ctypes.data_as(C.POINTER(C.c_uint)),
                                      slots.size, C.byref(gl)), "md_schedule_preview")
     return _plan_dict(p2), slots, gl.value

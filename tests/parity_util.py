@@ -18,6 +18,8 @@ posed coordinate in these boxes (|x| <= 20 A: 8 ulp ~ 1.5e-5 A ~ 4e-5 grid units
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 from oracle import ligand as OL
@@ -70,3 +72,42 @@ def compare(ref, e_gpu, g_gpu=None):
                  median_plain_rel_energy=float(np.median(plain_e)) if plain_e else 0.0)
     assert not fails, (fails[:5], stats)
     return stats
+
+
+def check_sw_start(grid, ol, start, g_out, e_out, tr_gpu, n_evals, seed, k):
+    """Solis-Wets from one start (standalone key (seed, 0, 0, k)): compares the library's energy
+    trace tr_gpu with the oracle's element by element; the first disagreement must follow a near
+    tie (two compared oracle energies within the sum of their tolerances) or a kink.  Checks the
+    returned genotype and energy.  Returns (evaluations that agree, cause of the first
+    disagreement)."""
+    from oracle import scoring as S
+    from oracle import solis_wets as OSW
+    pts = []
+    _, _, tr = OSW.local_search_sw(grid, ol, start.astype(np.float64), n_evals, seed, 0, 0, k,
+                                   trace=True, points=pts)
+    evs = [S.energy_and_gradient(grid, ol, x) for x in pts]
+    tol = [E_TOL * max(abs(r.energy), r.scale_energy) for r in evs]
+    d = next((i for i in range(n_evals) if evs[i].margin_energy >= KINK and abs(tr_gpu[i] - tr[i]) > tol[i]),
+             n_evals)
+    if d < n_evals:
+        cause = None
+        run_min = tr[0]
+        for i in range(1, d + 1):
+            if evs[i].margin_energy < KINK:
+                cause = f"kink at evaluation {i}"
+                break
+            if i < d and abs(tr[i] - run_min) <= tol[i] + tol[int(np.argmin(tr[:i]))]:
+                cause = f"near tie at evaluation {i} (|dE| {abs(tr[i] - run_min):.2e})"
+                break
+            run_min = min(run_min, tr[i])
+        assert cause is not None, (k, d, tr_gpu[d], tr[d])
+    else:
+        cause = "none"
+    # the result is the lowest energy the GPU evaluated, at a valid genotype that re-evaluates to it
+    assert e_out == tr_gpu.min()
+    re = S.energy_and_gradient(grid, ol, g_out.astype(np.float64))
+    if re.margin_energy >= KINK:
+        assert abs(re.energy - e_out) <= E_TOL * max(abs(re.energy), re.scale_energy)
+    assert abs(np.linalg.norm(g_out[3:7]) - 1) < 1e-5
+    assert np.all(g_out[7:] > -math.pi - 1e-6) and np.all(g_out[7:] <= math.pi + 1e-6)
+    return d, cause

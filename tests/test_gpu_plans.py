@@ -1,5 +1,6 @@
-"""Launch plans and the autotuner: every plan (waves per block, LDS budget -- from all pair rows
-read from global memory to all staged in up to 160 KiB of LDS -- and lane-group size) gives
+"""Launch plans and the autotuner: every plan (waves per block, waves per pose, LDS budget -- from
+all pair rows read from global memory to all staged in up to 160 KiB of LDS -- and lane-group
+size) gives
 energies and gradients within the parity tolerance of the FP64 oracle, with the energy-only and
 gradient paths bitwise equal; the autotuner picks one of them, records it for the size class,
 and a dock with a tuned plan is reproducible."""
@@ -41,7 +42,11 @@ PLANS = [dict(lds_budget=0, group_div=3, waves_per_block=4),
          dict(lds_budget=160 * 1024, group_div=3, waves_per_block=8),
          dict(lds_budget=32 * 1024, group_div=2, waves_per_block=1),
          dict(lds_budget=96 * 1024, group_div=4, waves_per_block=2),
-         dict(lds_budget=65536, group_div=8, waves_per_block=8)]
+         dict(lds_budget=65536, group_div=8, waves_per_block=8),
+         # waves sharing a pose (the block holds one pose)
+         dict(lds_budget=65536, group_div=3, waves_per_block=2, waves_per_pose=2),
+         dict(lds_budget=160 * 1024, group_div=3, waves_per_block=4, waves_per_pose=4),
+         dict(lds_budget=0, group_div=2, waves_per_block=4, waves_per_pose=4)]
 
 
 @pytest.mark.parametrize("na,nt", [(22, 4), (66, 14), (110, 30)])
@@ -77,7 +82,7 @@ def test_local_search_consistent_across_plans(md, receptor):
     n = 96
     genes = torch.from_numpy(synth.random_genes(lig, rec, n, seed=5, margin=3.0)).cuda()
     outs = []
-    for plan in (PLANS[0], PLANS[1]):
+    for plan in (PLANS[0], PLANS[1], PLANS[6]):
         md.md_ligand_set_plan(dlig, **plan)
         go = torch.empty_like(genes)
         eo = torch.empty(n, device="cuda")
@@ -88,8 +93,9 @@ def test_local_search_consistent_across_plans(md, receptor):
         assert np.array_equal(eo.cpu().numpy(), ee.cpu().numpy()), plan
         outs.append(eo.cpu().numpy())
     # the two searches follow the same iteration up to summation order: most end close together
-    rel = np.abs(outs[0] - outs[1]) / np.maximum(1.0, np.abs(outs[1]))
-    assert np.median(rel) < 1e-2
+    for other in outs[1:]:
+        rel = np.abs(outs[0] - other) / np.maximum(1.0, np.abs(other))
+        assert np.median(rel) < 1e-2
 
 
 def test_autotune_and_table(md, receptor):

@@ -10,13 +10,12 @@ only where the oracle's two energies are within twice that tolerance of each oth
 tie), or where an evaluated point sits within KINK of a place where the energy jumps.  The
 parity test therefore compares every evaluation element by element up to the first
 disagreement and requires that disagreement to follow a near tie or a kink."""
-import math
 import sys
 
 import numpy as np
 import pytest
 
-from parity_util import E_TOL, KINK, oracle_grid, oracle_ligand
+from parity_util import E_TOL, check_sw_start, oracle_grid, oracle_ligand
 from workload import configs, synth
 
 pytestmark = pytest.mark.gpu
@@ -57,42 +56,6 @@ def _run_gpu(md, drec, dlig, genes, n_evals, seed):
     return gout.cpu().numpy(), eout.cpu().numpy(), trace.cpu().numpy()
 
 
-def _check_start(grid, ol, start, g_out, e_out, tr_gpu, n_evals, seed, k):
-    """Element-by-element comparison of one start's evaluations; returns the number of leading
-    evaluations that agree."""
-    from oracle import scoring as S
-    from oracle import solis_wets as OSW
-    pts = []
-    _, _, tr = OSW.local_search_sw(grid, ol, start.astype(np.float64), n_evals, seed, 0, 0, k,
-                                   trace=True, points=pts)
-    evs = [S.energy_and_gradient(grid, ol, x) for x in pts]
-    tol = [E_TOL * max(abs(r.energy), r.scale_energy) for r in evs]
-    d = next((i for i in range(n_evals) if evs[i].margin_energy >= KINK and abs(tr_gpu[i] - tr[i]) > tol[i]),
-             n_evals)
-    if d < n_evals:
-        cause = None
-        run_min = tr[0]
-        for i in range(1, d + 1):
-            if evs[i].margin_energy < KINK:
-                cause = f"kink at evaluation {i}"
-                break
-            if i < d and abs(tr[i] - run_min) <= tol[i] + tol[int(np.argmin(tr[:i]))]:
-                cause = f"near tie at evaluation {i} (|dE| {abs(tr[i] - run_min):.2e})"
-                break
-            run_min = min(run_min, tr[i])
-        assert cause is not None, (k, d, tr_gpu[d], tr[d])
-    else:
-        cause = "none"
-    # the result is the lowest energy the GPU evaluated, at a valid genotype that re-evaluates to it
-    assert e_out == tr_gpu.min()
-    re = S.energy_and_gradient(grid, ol, g_out.astype(np.float64))
-    if re.margin_energy >= KINK:
-        assert abs(re.energy - e_out) <= E_TOL * max(abs(re.energy), re.scale_energy)
-    assert abs(np.linalg.norm(g_out[3:7]) - 1) < 1e-5
-    assert np.all(g_out[7:] > -math.pi - 1e-6) and np.all(g_out[7:] <= math.pi + 1e-6)
-    return d, cause
-
-
 # (name, grid, map seed, atoms, torsions, ligand seed, starts, evaluations)
 SW_CASES = [
     ("small_20a_4t", 40, 101, 20, 4, 201, 13, 200),
@@ -115,7 +78,7 @@ def test_solis_wets_parity(md, case):
     grid, ol = oracle_grid(rec), oracle_ligand(lig)
     agree = []
     for k in range(n):
-        d, cause = _check_start(grid, ol, genes[k], G[k], E[k], T[k], n_evals, seed, k)
+        d, cause = check_sw_start(grid, ol, genes[k], G[k], E[k], T[k], n_evals, seed, k)
         agree.append(d)
         _say(f"[sw parity] {name} start {k}: {d}/{n_evals} evaluations agree (first cause: {cause}); "
              f"E {T[k, 0]:.5g} -> {E[k]:.5g}")

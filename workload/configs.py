@@ -10,6 +10,11 @@ batched_fp32          one 64^3 map set, 256 ligands (10-100 atoms, 0-32 rotatabl
                       bonds), 10 runs x 150 each.
 serving_fp16          96^3 map set, ligands of log-normal size (median 35, 10-120
                       atoms), 10 runs x 150, 250k evaluations per run.
+paper_inputs          the paper's three input sizes (small / medium / large ligands of 21, 43
+                      and 108 atoms with 2, 15 and 31 rotatable bonds; Background, "Design and
+                      Structure of MiniMDock") as synthetic ligands on the 64^3 map set, run
+                      with 10 and 100 runs (its threads-per-workgroup study, Section "Results"),
+                      2.5M evaluations per run, 6 % local search x 300.
 """
 from __future__ import annotations
 
@@ -34,7 +39,14 @@ WORKLOADS = {
     "serving_fp16": dict(grid=96, map_seed=105, lig_seed=205,
                          n_runs=10, pop_size=150, max_generations=10**6,
                          max_evals_per_run=250_000, ls_rate=0.06, ls_iters=300),
+    "paper_inputs": dict(grid=64, map_seed=102, lig_seed=206,
+                         n_runs=10, pop_size=150, max_generations=10**6,
+                         max_evals_per_run=2_500_000, ls_rate=0.06, ls_iters=300),
 }
+
+# the paper's three inputs: (atoms, rotatable bonds)
+PAPER_INPUT_SIZES = {"small": (21, 2), "medium": (43, 15), "large": (108, 31)}
+PAPER_NRUNS = (10, 100)
 
 # search constants shared by every workload (ADADELTA and LGA operator rates)
 SEARCH_DEFAULTS = dict(rho=0.8, eps=1e-2, crossover_rate=0.8, mutation_rate=0.02,
@@ -54,6 +66,13 @@ def receptor(name: str) -> synth.Receptor:
 def ligand(name: str) -> synth.Ligand:
     w = WORKLOADS[name]
     return synth.make_ligand(w["n_atoms"], w["n_torsions"], w["lig_seed"], type_params())
+
+
+def paper_ligand(size: str) -> synth.Ligand:
+    """Synthetic stand-in for one of the paper's three inputs ("small", "medium", "large")."""
+    n, t = PAPER_INPUT_SIZES[size]
+    k = list(PAPER_INPUT_SIZES).index(size)
+    return synth.make_ligand(n, t, WORKLOADS["paper_inputs"]["lig_seed"] * 10 + k, type_params())
 
 
 def batched_ligands(name: str = "batched_fp32", count: int | None = None):
