@@ -463,13 +463,19 @@ def bench_serving(args):
         tuned = md.md_batch_autotune(drec, [(l, md.dock_params(**sp)) for l in ligs[:96]], generations=9)
         if tuned["policy"] != "default":
             pol = {"tuned_alone": None, "lds_all": dict(lds_budget=160 * 1024), "wide_blocks": dict(waves_per_block=8),
-                   "small_groups": dict(group_div=2)}[tuned["policy"]]
+                   "small_groups": dict(group_div=2),
+                   "shared_large": dict(waves_per_block=4, waves_per_pose=4)}[tuned["policy"]]
             for l in ligs[96:]:
                 if pol is None:
                     md.md_ligand_autotune(drec, l)
-                else:
+                elif tuned["policy"] != "shared_large" or l.n_atoms > 64:
                     md.md_ligand_set_plan(l, **{"lds_budget": 65536, "group_div": 3, "waves_per_block": 4, **pol})
     t_tune = time.perf_counter() - t_tune
+    plan_mix = {}
+    for l in ligs:
+        pl = md.md_ligand_get_plan(l)
+        key = f"wpb{pl['waves_per_block']}_wpp{pl['waves_per_pose']}_lds{pl['lds_budget'] // 1024}k"
+        plan_mix[key] = plan_mix.get(key, 0) + 1
     P = md.dock_params(**sp)
     n_ls = max(0, min(P.pop_size, math.ceil(sp["ls_rate"] * P.pop_size - 1e-4)))
     gens = md.md_dock_planned_generations(P)
@@ -511,7 +517,7 @@ def bench_serving(args):
            "config": {"workload": name, "grid": "96^3 x 9 maps FP16", "requests_per_rate": len(ligs),
                       "n_runs": P.n_runs, "pop_size": P.pop_size, "generations": gens,
                       "evals_per_request": evals_per_req, "median_atoms": float(np.median([n for n, _ in sizes]))},
-           "autotune": {**(tuned or {"policy": "default (not tuned)"}), "seconds": t_tune},
+           "autotune": {**(tuned or {"policy": "default (not tuned)"}), "seconds": t_tune, "plan_mix": plan_mix},
            "rates": results}
     print(json.dumps(out), flush=True)
 

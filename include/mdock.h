@@ -308,12 +308,14 @@ md_status md_dock_batch(const md_receptor* rec, int n_jobs, const md_dock_job* j
  * to every ligand: MD_POLICY_DEFAULT (every ligand on the default plan),
  * MD_POLICY_TUNED_ALONE (md_ligand_autotune for full-device launches, per size class),
  * MD_POLICY_LDS_ALL (LDS budget 160 KiB: all pair rows staged), MD_POLICY_WIDE_BLOCKS (8 waves
- * per block), MD_POLICY_SMALL_GROUPS (lane groups of about N/2).  The ligands must not be in use
+ * per block), MD_POLICY_SMALL_GROUPS (lane groups of about N/2), MD_POLICY_SHARED_LARGE (ligands of
+ * more than 64 atoms search with 4 waves per pose, the rest with the default plan: shorter
+ * generations for the largest ligands, whose searches set the pace).  The ligands must not be in use
  * by another call.  Blocking.  info may be NULL.  Errors: MD_EINVAL, MD_ERANGE
  * (generations outside [2, 1000]), and md_dock_batch's. */
 enum {
   MD_POLICY_DEFAULT = 0, MD_POLICY_TUNED_ALONE = 1, MD_POLICY_LDS_ALL = 2, MD_POLICY_WIDE_BLOCKS = 3,
-  MD_POLICY_SMALL_GROUPS = 4, MD_BATCH_POLICIES = 5
+  MD_POLICY_SMALL_GROUPS = 4, MD_POLICY_SHARED_LARGE = 5, MD_BATCH_POLICIES = 6
 };
 typedef struct {
   int policy;                     /* the policy applied */

@@ -426,6 +426,10 @@ md_status md_batch_autotune(const md_receptor* rec, int n, md_ligand* const* lig
     plans[MD_POLICY_LDS_ALL][k].lds_budget = kMaxLdsPerBlock;
     plans[MD_POLICY_WIDE_BLOCKS][k].wpb = 8;
     plans[MD_POLICY_SMALL_GROUPS][k].group_div = 2;
+    if (ligands[k]->host.n_atoms > kWave) {
+      plans[MD_POLICY_SHARED_LARGE][k].wpp = 4;
+      plans[MD_POLICY_SHARED_LARGE][k].wpb = 4;
+    }
   }
   md_batch_tune_info out{};
   out.n_policies = n_pol;

@@ -81,7 +81,7 @@ class BatchTuneInfo(C.Structure):
     _fields_ = [("policy", C.c_int), ("n_policies", C.c_int), ("ms_per_generation", C.c_double * 8)]
 
 
-BATCH_POLICIES = ["default", "tuned_alone", "lds_all", "wide_blocks", "small_groups"]
+BATCH_POLICIES = ["default", "tuned_alone", "lds_all", "wide_blocks", "small_groups", "shared_large"]
 
 
 class DockJob(C.Structure):
