@@ -14,7 +14,8 @@ md = pytest.importorskip("paper_2203_02096_amd")
 
 CASES = [(4, 1), (6, 2), (10, 3), (20, 4), (33, 7), (40, 8), (64, 12), (65, 12), (90, 20), (128, 32)]
 PLANS = [dict(), dict(group_div=2), dict(group_div=4), dict(group_div=8, waves_per_block=1),
-         dict(lds_budget=0), dict(lds_budget=160 * 1024, waves_per_block=8), dict(lds_budget=20000)]
+         dict(lds_budget=0), dict(lds_budget=160 * 1024, waves_per_block=8), dict(lds_budget=20000),
+         dict(waves_per_block=4, waves_per_pose=4), dict(lds_budget=160 * 1024, waves_per_block=8, waves_per_pose=2)]
 
 
 def _lib_available():
@@ -72,6 +73,23 @@ def test_schedule_invariants(n, t, plan):
 def test_schedule_preview_rejects_bad_plans():
     lig = synth.make_ligand(20, 4, 77, configs.type_params())
     for bad in (dict(group_div=1), dict(group_div=9), dict(waves_per_block=3), dict(lds_budget=-1),
-                dict(lds_budget=160 * 1024 + 1)):
+                dict(lds_budget=160 * 1024 + 1), dict(waves_per_pose=3), dict(waves_per_pose=8)):
         with pytest.raises(md.MdockError):
             md.md_schedule_preview(lig, **bad)
+
+
+@pytest.mark.parametrize("n,t", [(20, 4), (65, 12), (128, 32)])
+@pytest.mark.parametrize("wpp", [2, 4])
+def test_shared_pose_layout(n, t, wpp):
+    """A plan whose waves share a pose holds one pose per block (waves_per_block = waves_per_pose)
+    and adds to the W waves' own LDS exactly the two share sets the kernel addresses:
+    2 x 16 x ((W + 1)(N + 1) + W) bytes."""
+    lig = synth.make_ligand(n, t, 6000 + n, configs.type_params())
+    shared, s1, _ = md.md_schedule_preview(lig, lds_budget=0, waves_per_block=8, waves_per_pose=wpp)
+    alone, s2, _ = md.md_schedule_preview(lig, lds_budget=0, waves_per_block=wpp)
+    assert shared["waves_per_block"] == wpp and shared["waves_per_pose"] == wpp
+    assert alone["waves_per_pose"] == 1
+    assert np.array_equal(s1, s2)                       # the pair schedule itself is unchanged
+    assert shared["staged_rows"] == alone["staged_rows"] == 0
+    assert shared["lds_bytes"] - alone["lds_bytes"] == 2 * 16 * ((wpp + 1) * (n + 1) + wpp)
+
