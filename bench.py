@@ -47,7 +47,8 @@ def measured_profile(ls="adadelta"):
     launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's counts) and VALU issue utilisation
     (SQ_INSTS_VALU); None for each when the kernel source has changed since they were taken."""
     import hashlib
-    none = {"traffic": None, "valu_issue_utilisation": None, "valu_instructions_per_eval": None}
+    none = {"traffic": None, "valu_issue_utilisation": None, "valu_instructions_per_eval": None,
+            "l2_read_bytes_per_launch": None, "l2_hit_rate": None}
     try:
         text = open(PROFILES[ls]).read()
         sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
@@ -56,9 +57,12 @@ def measured_profile(ls="adadelta"):
     vals = dict(l.split(": ", 1) for l in text.splitlines() if ": " in l and not l.startswith(" "))
     if vals.get("kernel_source_sha256", "").strip() != sha:
         return none
-    return {"traffic": float(vals["traffic_bytes_per_launch"]),
-            "valu_issue_utilisation": float(vals["valu_issue_utilisation"]),
-            "valu_instructions_per_eval": float(vals["valu_instructions_per_eval"])}
+    out = {"traffic": float(vals["traffic_bytes_per_launch"]),
+           "valu_issue_utilisation": float(vals["valu_issue_utilisation"]),
+           "valu_instructions_per_eval": float(vals["valu_instructions_per_eval"])}
+    for k in ("l2_read_bytes_per_launch", "l2_hit_rate"):
+        out[k] = float(vals[k]) if k in vals else None
+    return out
 
 
 def flop_model(n_atoms, n_torsions, n_pairs, sum_moving):
@@ -78,6 +82,46 @@ def flop_model_energy(n_atoms, n_torsions, n_pairs, sum_moving):
 def bytes_model(n_atoms, map_bytes=4):
     """Algorithmic bytes of one evaluation: 8 corners x 3 maps per atom."""
     return 24 * map_bytes * n_atoms
+
+
+def mix_roofline(md, dligs, ls_evals_each, seconds, map_bytes):
+    """Roofline of a mix of ligands: the local searches' algorithmic flops (flop_model) and map
+    bytes (bytes_model) summed over the ligands, over the wall time.  The bound is the VALU (as
+    for the single ligand); the HBM fraction is stated beside it."""
+    flops = byts = 0.0
+    for d, n in zip(dligs, ls_evals_each):
+        info = md.md_ligand_info(d)
+        flops += n * flop_model(info["n_atoms"], info["n_torsions"], info["n_pairs"], info["sum_moving"])
+        byts += n * bytes_model(info["n_atoms"], map_bytes)
+    tf = flops / seconds / 1e12
+    gbs = byts / seconds / 1e9
+    return {"bound": "alu", "achieved": tf, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+            "frac": tf / PEAK_FP32_VALU_TFLOPS, "traffic": None,
+            "frac_of_nonpacked_fp32": tf / (PEAK_FP32_VALU_TFLOPS / 2),
+            "hbm_algorithmic_GBs": gbs, "hbm_peak_GBs": PEAK_HBM_GBS, "hbm_frac": gbs / PEAK_HBM_GBS,
+            "scope": "whole job: every local-search evaluation over the wall time"}
+
+
+def single_ligand_path(md, drec, dligs, params, sample):
+    """The plain single-ligand path on the same GPU: md_dock of `sample` ligands (spread over the
+    list) one after another with the same parameters.  Returns (local-search evals/s, ligands/s,
+    indices)."""
+    import torch
+    idx = sorted(set(int(round(k)) for k in
+                     [i * (len(dligs) - 1) / max(1, sample - 1) for i in range(sample)]))
+    ls = 0
+    md.md_dock(drec, dligs[idx[0]], params[idx[0]], want_xyz=False)       # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in idx:
+        P = params[k]
+        gens = md.md_dock_planned_generations(P)
+        n_ls = max(0, min(P.pop_size, math.ceil(P.ls_rate * P.pop_size - 1e-4)))
+        md.md_dock(drec, dligs[k], P, want_xyz=False)
+        ls += P.n_runs * gens * n_ls * P.ls_iters
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return ls / dt, len(idx) / dt, idx
 
 
 # ------------------------------------------------------------------ CPU baseline (oracle)
@@ -259,7 +303,10 @@ def main():
                      "valu_instructions_per_eval": prof["valu_instructions_per_eval"],
                      "flop_per_eval": flops_eval, "evals_per_launch": evals_per_ls_launch,
                      "avg_launch_ms": avg_ls_s * 1e3, "launches": ls_n,
-                     "hbm_algorithmic_GBs": hbm_gbs, "hbm_frac": hbm_gbs / PEAK_HBM_GBS},
+                     "hbm_algorithmic_GBs": hbm_gbs, "hbm_frac": hbm_gbs / PEAK_HBM_GBS,
+                     "l2_read_GBs": (prof["l2_read_bytes_per_launch"] / avg_ls_s / 1e9
+                                     if prof["l2_read_bytes_per_launch"] else None),
+                     "l2_hit_rate": prof["l2_hit_rate"]},
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kern.items()},
         "best_energy": float(res["best_energy"][0]),
         "cpu_baseline": base,
@@ -417,11 +464,14 @@ def bench_batched(args):
     md.md_dock_batch(drec, jobs, want_xyz=False)
     torch.cuda.synchronize()
     md.md_profile_enable(False)
+    kern = {k: md.md_profile_read(k)[0] for k in md.mdock.KERNELS}
     full = configs.search_params(name)
     full_gens = md.md_dock_planned_generations(md.dock_params(**full))
     evals_per_ligand_full = P.n_runs * (P.pop_size + full_gens * per_gen)
     rate = total_evals / dt
     sizes = np.array([l.n_atoms for l in ligs])
+    roof = mix_roofline(md, dligs, [ls_evals // len(jobs)] * len(jobs), dt, 4)
+    single_eps, single_lps, idx = single_ligand_path(md, drec, dligs, [P] * len(dligs), 16)
     out = {"metric": "energy+gradient evals/s", "value": ls_evals / dt, "unit": "evals/s", "n_gpus": 1,
            "steps": args.steps, "warmup": 1, "ms_per_step": dt * 1e3, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -433,7 +483,12 @@ def bench_batched(args):
            "projection": f"total evals/s / {evals_per_ligand_full} evals per ligand at the full budget "
                          f"({full_gens} generations)",
            "autotune": {**(tuned or {"policy": "default (not tuned)"}), "seconds": t_tune},
-           "kernel_ms_per_step": {k: md.md_profile_read(k)[0] for k in md.mdock.KERNELS},
+           "roofline": roof,
+           "single_ligand_path": {"evals_per_s": single_eps, "speedup_of_batch": (ls_evals / dt) / single_eps,
+                                  "ligands": len(idx),
+                                  "what": "md_dock of 16 of the batch's ligands one after another, same "
+                                          "parameters and plans, same GPU"},
+           "kernel_ms_per_step": kern,
            "kernel_ms_note": "one extra batch launched kernel by kernel (HIP events); the timed batches "
                              "replay each generation as a HIP graph"}
     print(json.dumps(out), flush=True)
@@ -508,9 +563,14 @@ def bench_serving(args):
                         "p99_ms": float(np.percentile(steady, 99)),
                         "ligands_per_s": len(tickets) / (max(done) - first),
                         "evals_per_s": len(tickets) * evals_per_req / (max(done) - first),
-                        "wall_s": t_end - t_start, "ticks": st["ticks"], "busy_s": st["busy_seconds"]})
+                        "wall_s": t_end - t_start, "span_s": max(done) - first, "ticks": st["ticks"],
+                        "busy_s": st["busy_seconds"]})
         print(json.dumps({"partial": results[-1]}), file=sys.stderr, flush=True)
     best = max(results, key=lambda r: r["ligands_per_s"])
+    ls_per_req = P.n_runs * gens * n_ls * P.ls_iters
+    roof = mix_roofline(md, ligs, [ls_per_req] * len(ligs), best["span_s"], 2)
+    single_eps, single_lps, idx = single_ligand_path(
+        md, drec, ligs, [md.dock_params(**{**sp, "seed": args.seed * 1000 + k}) for k in range(len(ligs))], 16)
     out = {"metric": "ligands docked/s (serving)", "value": best["ligands_per_s"], "unit": "ligands/s",
            "n_gpus": 1, "steps": len(results), "warmup": 0, "ms_per_step": None, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -518,6 +578,13 @@ def bench_serving(args):
                       "n_runs": P.n_runs, "pop_size": P.pop_size, "generations": gens,
                       "evals_per_request": evals_per_req, "median_atoms": float(np.median([n for n, _ in sizes]))},
            "autotune": {**(tuned or {"policy": "default (not tuned)"}), "seconds": t_tune, "plan_mix": plan_mix},
+           "roofline": {**roof, "scope": f"the {best['rate']:g}/s run: every local-search evaluation over the "
+                                          f"span from the first arrival to the last completion"},
+           "ls_evals_per_s": len(ligs) * ls_per_req / best["span_s"],
+           "single_ligand_path": {"ligands_per_s": single_lps, "evals_per_s": single_eps,
+                                  "speedup_of_serving": best["ligands_per_s"] / single_lps, "ligands": len(idx),
+                                  "what": "md_dock of 16 of the requests one after another, same parameters "
+                                          "and plans, same GPU"},
            "rates": results}
     print(json.dumps(out), flush=True)
 

@@ -158,11 +158,15 @@ __host__ __device__ inline size_t lds_wave_bytes(int n_atoms, int n_copies, int 
   return (size_t)16 * (kWave * A + 1) + (size_t)16 * n_copies * (n_atoms + 1) + (size_t)48 * n_tors;
 }
 __host__ __device__ inline size_t lds_pairs_bytes(int rows) { return (size_t)rows * kWave * (16 + 4); }
-// waves sharing a pose (W > 1): two alternating sets (even and odd evaluations) of the per-wave
+// waves sharing a pose (W > 1): the pose's coordinates [64A + 1] (float4), its torsion gradients
+// by gene lane [64] (float), then two alternating sets (even and odd evaluations) of the per-wave
 // intramolecular force partials [W][n_atoms + 1], the grid forces [n_atoms + 1] (float4 each)
 // and the per-wave energy partials [W] (one float4 slot each)
 __host__ __device__ inline size_t lds_pose_share_bytes(int n_atoms, int W) {
-  return W > 1 ? (size_t)2 * 16 * ((size_t)(W + 1) * (n_atoms + 1) + W) : 0;
+  const int A = n_atoms > kWave ? 2 : 1;
+  return W > 1 ? (size_t)16 * (kWave * A + 1) + (size_t)4 * kWave +
+                     (size_t)2 * 16 * ((size_t)(W + 1) * (n_atoms + 1) + W)
+               : 0;
 }
 
 // Returns an empty string on success, else a message; `range_error` tells MD_ERANGE apart.

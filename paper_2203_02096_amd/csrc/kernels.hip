@@ -165,6 +165,7 @@ __device__ __forceinline__ BlockLds stage_block(const LigDev& L) {
   b.tor = reinterpret_cast<float4*>(cur);
   const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
   if (lane == 0) b.x[kWave * A] = z;
+  if (L.wpp > 1 && threadIdx.x == 0) b.share[kWave * A] = z;   // spare entry of the shared pose
   const int nf = L.n_copies * (L.n_atoms + 1);
   for (int k = lane; k < nf; k += kWave) b.f[k] = z;
   const int g = min(lane / L.group_lanes, max(L.n_copies - 1, 0));
@@ -479,10 +480,11 @@ __device__ __forceinline__ void share_rows(int n_rows, int w, int& r0, int& r1) 
 template <int A>
 __device__ __forceinline__ float torsion_gradients(const AtomRegs<A>& at, int T, float3 tu, float3 tp,
                                                    const float* x, const float* y, const float* z,
-                                                   const float* Fx, const float* Fy, const float* Fz) {
+                                                   const float* Fx, const float* Fy, const float* Fz,
+                                                   int kb0 = 0, int kb_step = 4) {
   const int tk = at.tor_of_gene;
   float g = 0.f;
-  for (int kb = 0; kb < T; kb += 4) {
+  for (int kb = kb0; kb < T; kb += kb_step) {
     float c[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -525,14 +527,10 @@ __device__ __forceinline__ float torsion_gradients(const AtomRegs<A>& at, int T,
 // ------------------------------------------------------------------ one pose
 // Energy (returned, identical in every lane) and, with GRAD, the gradient component of
 // gene `lane` (lanes >= n_genes get 0).  xg: gene `lane` of the pose (lanes < n_genes).
-// W > 1 waves (the whole block) evaluate one pose together: each poses all atoms, wave w runs
-// its share of the pair rows and wave a < A the grid slot a; the partial forces and energies
-// meet in the share set after one block barrier, and every wave then forms the same energy and
-// gradient from them (same data, same order), so the waves stay in step without a second
-// exchange.  Every wave of the block must make the same sequence of calls.
-template <int A, int PREC, bool GRAD, int W>
-__device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, const AtomRegs<A>& at,
-                           float xg, float& g_out, PoseShare& ps) {
+// One wave evaluates the pose.
+template <int A, int PREC, bool GRAD>
+__device__ float eval_pose_one(const LigDev& L, const RecDev& R, const BlockLds& b, const AtomRegs<A>& at,
+                               float xg, float& g_out) {
   const int lane = lane_id();
   const int T = L.n_tors;
   // rigid-body genes (wave-uniform)
@@ -607,19 +605,17 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, 
     b.x[i] = make_float4(x[a], y[a], z[a], 0.f);
   }
 
-  // grid term: issue the corner loads now, finish after the pair term (the slots this wave owns)
+  // grid term: issue the corner loads now, finish after the pair term
   bool gv[A];
 #pragma unroll
-  for (int a = 0; a < A; ++a) gv[a] = at.valid[a] && (W == 1 || a == ps.w);
+  for (int a = 0; a < A; ++a) gv[a] = at.valid[a];
   GridFetch gf[A];
 #pragma unroll
   for (int a = 0; a < A; ++a) grid_fetch<PREC>(R, x[a], y[a], z[a], at.type[a], at.q[a], gv[a], gf[a]);
   wave_sync();
 
   // intramolecular pairs; with GRAD each atom then sums (and clears) its force copies
-  int r0, r1;
-  share_rows<A, W>(L.n_rows, ps.w, r0, r1);
-  float e_lane = pair_rows<GRAD>(L, b, r0, r1);
+  float e_lane = pair_rows<GRAD>(L, b, 0, L.n_rows);
   float Fx[A], Fy[A], Fz[A];
 #pragma unroll
   for (int a = 0; a < A; ++a) Fx[a] = Fy[a] = Fz[a] = 0.f;
@@ -644,52 +640,7 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, 
   float gfx[A], gfy[A], gfz[A];
 #pragma unroll
   for (int a = 0; a < A; ++a) e_lane += grid_finish(R, gf[a], gv[a], gfx[a], gfy[a], gfz[a]);
-  float E = wave_sum(e_lane);
-  if constexpr (W > 1) {
-    // publish this wave's partials, meet, and take every wave's
-    const int N = L.n_atoms;
-    float4* set = b.share + (size_t)ps.par * ((size_t)(W + 1) * (N + 1) + W);
-    float4* fx = set;                               // [W][N + 1] intramolecular force partials
-    float4* gx = set + (size_t)W * (N + 1);         // [N + 1] grid forces
-    float4* ew = set + (size_t)(W + 1) * (N + 1);   // [W] energy partials
-    if (GRAD) {
-#pragma unroll
-      for (int a = 0; a < A; ++a) {
-        const int i = lane + kWave * a;
-        if (at.valid[a]) fx[ps.w * (N + 1) + i] = make_float4(Fx[a], Fy[a], Fz[a], 0.f);
-        if (gv[a]) gx[i] = make_float4(gfx[a], gfy[a], gfz[a], 0.f);
-      }
-    }
-    if (lane == 0) ew[ps.w] = make_float4(E, 0.f, 0.f, 0.f);
-    __syncthreads();
-    E = ew[0].x;
-#pragma unroll
-    for (int v = 1; v < W; ++v) E += ew[v].x;
-    if (GRAD) {
-#pragma unroll
-      for (int a = 0; a < A; ++a) {
-        if (at.valid[a]) {
-          const int i = lane + kWave * a;
-          float4 f = fx[i];
-#pragma unroll
-          for (int v = 1; v < W; ++v) {
-            const float4 fv = fx[v * (N + 1) + i];
-            f.x += fv.x;
-            f.y += fv.y;
-            f.z += fv.z;
-          }
-          Fx[a] = f.x;
-          Fy[a] = f.y;
-          Fz[a] = f.z;
-          const float4 gg = gx[i];
-          gfx[a] = gg.x;
-          gfy[a] = gg.y;
-          gfz[a] = gg.z;
-        }
-      }
-    }
-    ps.par ^= 1;
-  }
+  const float E = wave_sum(e_lane);
   if (!GRAD) return E;
   wave_sync();
 
@@ -743,6 +694,235 @@ __device__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b, 
   }
   g_out = g;
   return E;
+}
+
+// The same for W > 1 waves (the whole block) sharing one pose; every wave of the block must
+// make the same sequence of calls.  Wave a < A poses atom slot a (atoms 64a + lane) into the
+// block's coordinate array and issues that slot's grid loads; after a block barrier every wave
+// takes its share of the pair rows (share_rows) and wave a finishes grid slot a.  The partial
+// forces and energies go to one of two alternating share sets; after a second barrier every
+// wave sums them in the same order.  With GRAD, wave w then forms the torsion gradients of the
+// torsion batches w, w + W, ... and publishes them by gene; after a third barrier every wave
+// holds the same gradient, so the waves take identical search steps.  Hazards: the coordinate
+// array and the torsion-gradient array are rewritten only after the barrier that follows their
+// last reads; the share sets alternate.
+template <int A, int PREC, bool GRAD, int W>
+__device__ float eval_pose_shared(const LigDev& L, const RecDev& R, const BlockLds& b, const AtomRegs<A>& at,
+                                  float xg, float& g_out, PoseShare& ps) {
+  const int lane = lane_id();
+  const int T = L.n_tors;
+  const int N = L.n_atoms;
+  float4* X = b.share;                                          // [64A + 1] posed coordinates
+  float* GG = reinterpret_cast<float*>(X + kWave * A + 1);      // [64] torsion gradients by gene lane
+  float4* sets = X + kWave * A + 1 + kWave / 4;                 // two share sets
+  const float tx = readlane(xg, 0), ty = readlane(xg, 1), tz = readlane(xg, 2);
+  float qw = readlane(xg, 3), qx = readlane(xg, 4), qy = readlane(xg, 5), qz = readlane(xg, 6);
+  const float qn = __builtin_sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+  const float iqn = 1.f / qn;
+  qw *= iqn;
+  qx *= iqn;
+  qy *= iqn;
+  qz *= iqn;
+
+  // pose of this wave's slot (waves >= A have none) and its grid loads
+  GridFetch gf[A];
+  bool gv[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) gv[a] = at.valid[a] && a == ps.w;
+  if (ps.w < A) {
+    const float r00 = 1.f - 2.f * (qy * qy + qz * qz), r01 = 2.f * (qx * qy - qw * qz),
+                r02 = 2.f * (qx * qz + qw * qy);
+    const float r10 = 2.f * (qx * qy + qw * qz), r11 = 1.f - 2.f * (qx * qx + qz * qz),
+                r12 = 2.f * (qy * qz - qw * qx);
+    const float r20 = 2.f * (qx * qz - qw * qy), r21 = 2.f * (qy * qz + qw * qx),
+                r22 = 1.f - 2.f * (qx * qx + qy * qy);
+    const float th = __shfl(xg, at.gene_of_tor, kWave);
+    if (lane < T) {
+      const float rev = th * 0.15915494309189535f;
+      const float sn = __builtin_amdgcn_sinf(rev), c = __builtin_amdgcn_cosf(rev), oc = 1.f - c;
+      const float ux = at.tux, uy = at.tuy, uz = at.tuz;
+      const float m00 = oc * ux * ux + c, m01 = oc * ux * uy - sn * uz, m02 = oc * ux * uz + sn * uy;
+      const float m10 = oc * uy * ux + sn * uz, m11 = oc * uy * uy + c, m12 = oc * uy * uz - sn * ux;
+      const float m20 = oc * uz * ux - sn * uy, m21 = oc * uz * uy + sn * ux, m22 = oc * uz * uz + c;
+      const float vx = at.tpx, vy = at.tpy, vz = at.tpz;
+      b.tor[3 * lane + 0] = make_float4(m00, m01, m02, vx - (m00 * vx + m01 * vy + m02 * vz));
+      b.tor[3 * lane + 1] = make_float4(m10, m11, m12, vy - (m10 * vx + m11 * vy + m12 * vz));
+      b.tor[3 * lane + 2] = make_float4(m20, m21, m22, vz - (m20 * vx + m21 * vy + m22 * vz));
+    }
+    wave_sync();
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+      if (a == ps.w) {
+        float px = at.px[a], py = at.py[a], pz = at.pz[a];
+        for (int k = T - 1; k >= 0; --k) {
+          const float4 m0 = b.tor[3 * k + 0], m1 = b.tor[3 * k + 1], m2 = b.tor[3 * k + 2];
+          if ((at.mask[a] >> k) & 1u) {
+            const float ox = px, oy = py, oz = pz;
+            px = m0.x * ox + m0.y * oy + m0.z * oz + m0.w;
+            py = m1.x * ox + m1.y * oy + m1.z * oz + m1.w;
+            pz = m2.x * ox + m2.y * oy + m2.z * oz + m2.w;
+          }
+        }
+        const float x = r00 * px + r01 * py + r02 * pz + tx;
+        const float y = r10 * px + r11 * py + r12 * pz + ty;
+        const float z = r20 * px + r21 * py + r22 * pz + tz;
+        X[lane + kWave * a] = make_float4(x, y, z, 0.f);
+        grid_fetch<PREC>(R, x, y, z, at.type[a], at.q[a], gv[a], gf[a]);
+      } else {
+        grid_fetch<PREC>(R, 0.f, 0.f, 0.f, at.type[a], at.q[a], false, gf[a]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < A; ++a) grid_fetch<PREC>(R, 0.f, 0.f, 0.f, at.type[a], at.q[a], false, gf[a]);
+  }
+  __syncthreads();
+
+  // every atom's posed coordinates (kept for the gradient), this wave's pair rows
+  float x[A], y[A], z[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) {
+    const float4 v = X[lane + kWave * a];
+    x[a] = v.x;
+    y[a] = v.y;
+    z[a] = v.z;
+  }
+  BlockLds bs = b;
+  bs.x = X;
+  int r0, r1;
+  share_rows<A, W>(L.n_rows, ps.w, r0, r1);
+  float e_lane = pair_rows<GRAD>(L, bs, r0, r1);
+  float Fx[A], Fy[A], Fz[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) Fx[a] = Fy[a] = Fz[a] = 0.f;
+  if (GRAD) {
+    wave_sync();
+    const int K = L.n_copies;
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+      if (at.valid[a]) {
+        const int i = lane + kWave * a;
+        for (int g = 0; g < K; ++g) {
+          const float4 v = b.f[g * (N + 1) + i];
+          Fx[a] += v.x;
+          Fy[a] += v.y;
+          Fz[a] += v.z;
+          b.f[g * (N + 1) + i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+      }
+    }
+  }
+  float gfx[A], gfy[A], gfz[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) e_lane += grid_finish(R, gf[a], gv[a], gfx[a], gfy[a], gfz[a]);
+  float E = wave_sum(e_lane);
+
+  // publish this wave's partials, meet, take every wave's
+  {
+    float4* set = sets + (size_t)ps.par * ((size_t)(W + 1) * (N + 1) + W);
+    float4* fx = set;                               // [W][N + 1] intramolecular force partials
+    float4* gx = set + (size_t)W * (N + 1);         // [N + 1] grid forces
+    float4* ew = set + (size_t)(W + 1) * (N + 1);   // [W] energy partials
+    if (GRAD) {
+#pragma unroll
+      for (int a = 0; a < A; ++a) {
+        const int i = lane + kWave * a;
+        if (at.valid[a]) fx[ps.w * (N + 1) + i] = make_float4(Fx[a], Fy[a], Fz[a], 0.f);
+        if (gv[a]) gx[i] = make_float4(gfx[a], gfy[a], gfz[a], 0.f);
+      }
+    }
+    if (lane == 0) ew[ps.w] = make_float4(E, 0.f, 0.f, 0.f);
+    __syncthreads();
+    E = ew[0].x;
+#pragma unroll
+    for (int v = 1; v < W; ++v) E += ew[v].x;
+    if (GRAD) {
+#pragma unroll
+      for (int a = 0; a < A; ++a) {
+        gfx[a] = gfy[a] = gfz[a] = 0.f;
+        if (at.valid[a]) {
+          const int i = lane + kWave * a;
+          float4 f = fx[i];
+#pragma unroll
+          for (int v = 1; v < W; ++v) {
+            const float4 fv = fx[v * (N + 1) + i];
+            f.x += fv.x;
+            f.y += fv.y;
+            f.z += fv.z;
+          }
+          Fx[a] = f.x;
+          Fy[a] = f.y;
+          Fz[a] = f.z;
+          const float4 gg = gx[i];
+          gfx[a] = gg.x;
+          gfy[a] = gg.y;
+          gfz[a] = gg.z;
+        }
+      }
+    }
+    ps.par ^= 1;
+  }
+  if (!GRAD) return E;
+
+  // rigid-body gradient from the grid forces (as in eval_pose_one), the same in every wave
+  float sfx = 0.f, sfy = 0.f, sfz = 0.f, tqx = 0.f, tqy = 0.f, tqz = 0.f;
+#pragma unroll
+  for (int a = 0; a < A; ++a) {
+    const float rx = x[a] - tx, ry = y[a] - ty, rz = z[a] - tz;
+    sfx += gfx[a];
+    sfy += gfy[a];
+    sfz += gfz[a];
+    tqx += ry * gfz[a] - rz * gfy[a];
+    tqy += rz * gfx[a] - rx * gfz[a];
+    tqz += rx * gfy[a] - ry * gfx[a];
+    Fx[a] += gfx[a];
+    Fy[a] += gfy[a];
+    Fz[a] += gfz[a];
+  }
+  sfx = wave_sum(sfx);
+  sfy = wave_sum(sfy);
+  sfz = wave_sum(sfz);
+  tqx = wave_sum(tqx);
+  tqy = wave_sum(tqy);
+  tqz = wave_sum(tqz);
+  float g = 0.f;
+  if (lane == 0) g = sfx;
+  if (lane == 1) g = sfy;
+  if (lane == 2) g = sfz;
+  if (lane == 3) g = -2.f * (tqx * qx + tqy * qy + tqz * qz) * iqn;
+  if (lane == 4) g = 2.f * (qw * tqx - (qy * tqz - qz * tqy)) * iqn;
+  if (lane == 5) g = 2.f * (qw * tqy - (qz * tqx - qx * tqz)) * iqn;
+  if (lane == 6) g = 2.f * (qw * tqz - (qx * tqy - qy * tqx)) * iqn;
+
+  // this wave's torsion batches, published by gene lane, then every wave reads all
+  if (T > 0) {
+    float3 tu = make_float3(0.f, 0.f, 0.f), tp = make_float3(0.f, 0.f, 0.f);
+    if (lane < T) {
+      const float4 xa = X[at.ta], xb = X[at.tb];
+      const float ux = xb.x - xa.x, uy = xb.y - xa.y, uz = xb.z - xa.z;
+      const float il = __builtin_amdgcn_rsqf(ux * ux + uy * uy + uz * uz);
+      tu = make_float3(ux * il, uy * il, uz * il);
+      tp = make_float3(xa.x, xa.y, xa.z);
+    }
+    const float gk = torsion_gradients<A>(at, T, tu, tp, x, y, z, Fx, Fy, Fz, 4 * ps.w, 4 * W);
+    const bool gene_t = lane >= 7 && lane < L.n_genes;
+    if (gene_t && ((at.tor_of_gene >> 2) % W) == ps.w) GG[lane] = gk;
+    __syncthreads();
+    if (gene_t) g = GG[lane];
+  }
+  g_out = g;
+  return E;
+}
+
+// Dispatch on the waves per pose.
+template <int A, int PREC, bool GRAD, int W>
+__device__ __forceinline__ float eval_pose(const LigDev& L, const RecDev& R, const BlockLds& b,
+                                           const AtomRegs<A>& at, float xg, float& g_out, PoseShare& ps) {
+  if constexpr (W == 1) {
+    return eval_pose_one<A, PREC, GRAD>(L, R, b, at, xg, g_out);
+  } else {
+    return eval_pose_shared<A, PREC, GRAD, W>(L, R, b, at, xg, g_out, ps);
+  }
 }
 
 // ------------------------------------------------------------------ kernels

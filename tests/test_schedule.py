@@ -82,7 +82,8 @@ def test_schedule_preview_rejects_bad_plans():
 @pytest.mark.parametrize("wpp", [2, 4])
 def test_shared_pose_layout(n, t, wpp):
     """A plan whose waves share a pose holds one pose per block (waves_per_block = waves_per_pose)
-    and adds to the W waves' own LDS exactly the two share sets the kernel addresses:
+    and adds to the W waves' own LDS exactly the shared arrays the kernel addresses: the pose's
+    coordinates 16 x (64A + 1), its torsion gradients 4 x 64 and two share sets
     2 x 16 x ((W + 1)(N + 1) + W) bytes."""
     lig = synth.make_ligand(n, t, 6000 + n, configs.type_params())
     shared, s1, _ = md.md_schedule_preview(lig, lds_budget=0, waves_per_block=8, waves_per_pose=wpp)
@@ -91,5 +92,6 @@ def test_shared_pose_layout(n, t, wpp):
     assert alone["waves_per_pose"] == 1
     assert np.array_equal(s1, s2)                       # the pair schedule itself is unchanged
     assert shared["staged_rows"] == alone["staged_rows"] == 0
-    assert shared["lds_bytes"] - alone["lds_bytes"] == 2 * 16 * ((wpp + 1) * (n + 1) + wpp)
+    A = 2 if n > 64 else 1
+    assert shared["lds_bytes"] - alone["lds_bytes"] == 16 * (64 * A + 1) + 4 * 64 + 2 * 16 * ((wpp + 1) * (n + 1) + wpp)
 
