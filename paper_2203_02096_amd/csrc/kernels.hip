@@ -525,57 +525,72 @@ __device__ __forceinline__ float torsion_gradients(const AtomRegs<A>& at, int T,
 }
 
 // ------------------------------------------------------------------ one pose
-// Energy (returned, identical in every lane) and, with GRAD, the gradient component of
-// gene `lane` (lanes >= n_genes get 0).  xg: gene `lane` of the pose (lanes < n_genes).
-// One wave evaluates the pose.
-template <int A, int PREC, bool GRAD>
-__device__ float eval_pose_one(const LigDev& L, const RecDev& R, const BlockLds& b, const AtomRegs<A>& at,
-                               float xg, float& g_out) {
-  const int lane = lane_id();
-  const int T = L.n_tors;
-  // rigid-body genes (wave-uniform)
-  const float tx = readlane(xg, 0), ty = readlane(xg, 1), tz = readlane(xg, 2);
+// Pieces of a pose evaluation shared by the one-wave and the shared-pose paths.
+
+// Rigid-body genes (wave-uniform): translation, unit quaternion, 1/|q| and the rotation matrix.
+struct Rigid {
+  float tx, ty, tz, qw, qx, qy, qz, iqn;
+  float r00, r01, r02, r10, r11, r12, r20, r21, r22;
+};
+
+__device__ __forceinline__ Rigid rigid_of(float xg) {
+  Rigid r;
+  r.tx = readlane(xg, 0);
+  r.ty = readlane(xg, 1);
+  r.tz = readlane(xg, 2);
   float qw = readlane(xg, 3), qx = readlane(xg, 4), qy = readlane(xg, 5), qz = readlane(xg, 6);
   const float qn = __builtin_sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
-  const float iqn = 1.f / qn;
-  qw *= iqn;
-  qx *= iqn;
-  qy *= iqn;
-  qz *= iqn;
-  const float r00 = 1.f - 2.f * (qy * qy + qz * qz), r01 = 2.f * (qx * qy - qw * qz),
-              r02 = 2.f * (qx * qz + qw * qy);
-  const float r10 = 2.f * (qx * qy + qw * qz), r11 = 1.f - 2.f * (qx * qx + qz * qz),
-              r12 = 2.f * (qy * qz - qw * qx);
-  const float r20 = 2.f * (qx * qz - qw * qy), r21 = 2.f * (qy * qz + qw * qx),
-              r22 = 1.f - 2.f * (qx * qx + qy * qy);
+  r.iqn = 1.f / qn;
+  qw *= r.iqn;
+  qx *= r.iqn;
+  qy *= r.iqn;
+  qz *= r.iqn;
+  r.qw = qw;
+  r.qx = qx;
+  r.qy = qy;
+  r.qz = qz;
+  r.r00 = 1.f - 2.f * (qy * qy + qz * qz);
+  r.r01 = 2.f * (qx * qy - qw * qz);
+  r.r02 = 2.f * (qx * qz + qw * qy);
+  r.r10 = 2.f * (qx * qy + qw * qz);
+  r.r11 = 1.f - 2.f * (qx * qx + qz * qz);
+  r.r12 = 2.f * (qy * qz - qw * qx);
+  r.r20 = 2.f * (qx * qz - qw * qy);
+  r.r21 = 2.f * (qy * qz + qw * qx);
+  r.r22 = 1.f - 2.f * (qx * qx + qy * qy);
+  return r;
+}
 
-  // torsion angle of torsion `lane` (internal order) -> cos, sin in that lane
+// Lane k < T writes torsion k's rotation about its reference-frame axis through its reference
+// pivot as x -> M x + t (Rodrigues: M = c I + s [u]x + (1 - c) u u^T, t = p - M p) into the wave's
+// torsion table, from which the atom loop reads it with broadcast loads.
+template <int A>
+__device__ __forceinline__ void build_torsion_table(const AtomRegs<A>& at, float4* tor, float xg, int T) {
+  const int lane = lane_id();
   const float th = __shfl(xg, at.gene_of_tor, kWave);
-  float tsn = 0.f, tcs = 1.f;
   if (lane < T) {
     // v_sin / v_cos take the angle in revolutions
     const float rev = th * 0.15915494309189535f;
-    tsn = __builtin_amdgcn_sinf(rev);
-    tcs = __builtin_amdgcn_cosf(rev);
-  }
-
-  // pose: torsions from the deepest to the root-most, each a rotation about its reference-frame
-  // axis through its reference pivot, applied by every lane whose atom it moves; then
-  // orientation and translation.  Lane k builds torsion k's rotation as x -> M x + t (Rodrigues:
-  // M = c I + s [u]x + (1 - c) u u^T, t = p - M p) in the wave's torsion table, from which the
-  // atom loop reads it with broadcast loads.
-  if (lane < T) {
-    const float c = tcs, sn = tsn, oc = 1.f - tcs;
+    const float sn = __builtin_amdgcn_sinf(rev);
+    const float c = __builtin_amdgcn_cosf(rev);
+    const float oc = 1.f - c;
     const float ux = at.tux, uy = at.tuy, uz = at.tuz;
     const float m00 = oc * ux * ux + c, m01 = oc * ux * uy - sn * uz, m02 = oc * ux * uz + sn * uy;
     const float m10 = oc * uy * ux + sn * uz, m11 = oc * uy * uy + c, m12 = oc * uy * uz - sn * ux;
     const float m20 = oc * uz * ux - sn * uy, m21 = oc * uz * uy + sn * ux, m22 = oc * uz * uz + c;
     const float vx = at.tpx, vy = at.tpy, vz = at.tpz;
-    b.tor[3 * lane + 0] = make_float4(m00, m01, m02, vx - (m00 * vx + m01 * vy + m02 * vz));
-    b.tor[3 * lane + 1] = make_float4(m10, m11, m12, vy - (m10 * vx + m11 * vy + m12 * vz));
-    b.tor[3 * lane + 2] = make_float4(m20, m21, m22, vz - (m20 * vx + m21 * vy + m22 * vz));
+    tor[3 * lane + 0] = make_float4(m00, m01, m02, vx - (m00 * vx + m01 * vy + m02 * vz));
+    tor[3 * lane + 1] = make_float4(m10, m11, m12, vy - (m10 * vx + m11 * vy + m12 * vz));
+    tor[3 * lane + 2] = make_float4(m20, m21, m22, vz - (m20 * vx + m21 * vy + m22 * vz));
   }
   wave_sync();
+}
+
+// Posed coordinates of this lane's atom slots a with use[a]: torsions from the deepest to the
+// root-most (each applied by the lanes whose atom it moves), then orientation and translation.
+template <int A>
+__device__ __forceinline__ void pose_slots(const AtomRegs<A>& at, const float4* tor, const Rigid& rb, int T,
+                                           const bool (&use)[A], float (&x)[A], float (&y)[A], float (&z)[A]) {
   float px[A], py[A], pz[A];
 #pragma unroll
   for (int a = 0; a < A; ++a) {
@@ -584,10 +599,10 @@ __device__ float eval_pose_one(const LigDev& L, const RecDev& R, const BlockLds&
     pz[a] = at.pz[a];
   }
   for (int k = T - 1; k >= 0; --k) {
-    const float4 m0 = b.tor[3 * k + 0], m1 = b.tor[3 * k + 1], m2 = b.tor[3 * k + 2];
+    const float4 m0 = tor[3 * k + 0], m1 = tor[3 * k + 1], m2 = tor[3 * k + 2];
 #pragma unroll
     for (int a = 0; a < A; ++a) {
-      if ((at.mask[a] >> k) & 1u) {
+      if (use[a] && ((at.mask[a] >> k) & 1u)) {
         const float ox = px[a], oy = py[a], oz = pz[a];
         px[a] = m0.x * ox + m0.y * oy + m0.z * oz + m0.w;
         py[a] = m1.x * ox + m1.y * oy + m1.z * oz + m1.w;
@@ -595,61 +610,48 @@ __device__ float eval_pose_one(const LigDev& L, const RecDev& R, const BlockLds&
       }
     }
   }
-  float x[A], y[A], z[A];
 #pragma unroll
   for (int a = 0; a < A; ++a) {
-    x[a] = r00 * px[a] + r01 * py[a] + r02 * pz[a] + tx;
-    y[a] = r10 * px[a] + r11 * py[a] + r12 * pz[a] + ty;
-    z[a] = r20 * px[a] + r21 * py[a] + r22 * pz[a] + tz;
-    const int i = lane + kWave * a;
-    b.x[i] = make_float4(x[a], y[a], z[a], 0.f);
+    x[a] = rb.r00 * px[a] + rb.r01 * py[a] + rb.r02 * pz[a] + rb.tx;
+    y[a] = rb.r10 * px[a] + rb.r11 * py[a] + rb.r12 * pz[a] + rb.ty;
+    z[a] = rb.r20 * px[a] + rb.r21 * py[a] + rb.r22 * pz[a] + rb.tz;
   }
+}
 
-  // grid term: issue the corner loads now, finish after the pair term
-  bool gv[A];
+// Sum (and clear) this wave's force copies for this lane's atoms.
+template <int A>
+__device__ __forceinline__ void sum_force_copies(const LigDev& L, const BlockLds& b, const AtomRegs<A>& at,
+                                                 float (&Fx)[A], float (&Fy)[A], float (&Fz)[A]) {
+  const int lane = lane_id();
+  const int N = L.n_atoms, K = L.n_copies;
 #pragma unroll
-  for (int a = 0; a < A; ++a) gv[a] = at.valid[a];
-  GridFetch gf[A];
-#pragma unroll
-  for (int a = 0; a < A; ++a) grid_fetch<PREC>(R, x[a], y[a], z[a], at.type[a], at.q[a], gv[a], gf[a]);
-  wave_sync();
-
-  // intramolecular pairs; with GRAD each atom then sums (and clears) its force copies
-  float e_lane = pair_rows<GRAD>(L, b, 0, L.n_rows);
-  float Fx[A], Fy[A], Fz[A];
-#pragma unroll
-  for (int a = 0; a < A; ++a) Fx[a] = Fy[a] = Fz[a] = 0.f;
-  if (GRAD) {
-    wave_sync();
-    const int N = L.n_atoms, K = L.n_copies;
-#pragma unroll
-    for (int a = 0; a < A; ++a) {
-      if (at.valid[a]) {
-        const int i = lane + kWave * a;
-        for (int g = 0; g < K; ++g) {
-          const float4 v = b.f[g * (N + 1) + i];
-          Fx[a] += v.x;
-          Fy[a] += v.y;
-          Fz[a] += v.z;
-          b.f[g * (N + 1) + i] = make_float4(0.f, 0.f, 0.f, 0.f);
-        }
+  for (int a = 0; a < A; ++a) {
+    if (at.valid[a]) {
+      const int i = lane + kWave * a;
+      for (int g = 0; g < K; ++g) {
+        const float4 v = b.f[g * (N + 1) + i];
+        Fx[a] += v.x;
+        Fy[a] += v.y;
+        Fz[a] += v.z;
+        b.f[g * (N + 1) + i] = make_float4(0.f, 0.f, 0.f, 0.f);
       }
     }
   }
+}
 
-  float gfx[A], gfy[A], gfz[A];
-#pragma unroll
-  for (int a = 0; a < A; ++a) e_lane += grid_finish(R, gf[a], gv[a], gfx[a], gfy[a], gfz[a]);
-  const float E = wave_sum(e_lane);
-  if (!GRAD) return E;
-  wave_sync();
-
-  // translation gradient and torque come from the grid forces alone: intramolecular
-  // forces are equal and opposite along each pair's line, so they add neither.
+// Gradient components of genes 0..6 (in those lanes, 0 elsewhere).  The translation gradient
+// and the torque come from the grid forces alone: intramolecular forces are equal and opposite
+// along each pair's line, so they add neither.  Adds the grid forces into F.
+template <int A>
+__device__ __forceinline__ float rigid_gradient(const Rigid& rb, const float (&x)[A], const float (&y)[A],
+                                                const float (&z)[A], const float (&gfx)[A], const float (&gfy)[A],
+                                                const float (&gfz)[A], float (&Fx)[A], float (&Fy)[A],
+                                                float (&Fz)[A]) {
+  const int lane = lane_id();
   float sfx = 0.f, sfy = 0.f, sfz = 0.f, tqx = 0.f, tqy = 0.f, tqz = 0.f;
 #pragma unroll
   for (int a = 0; a < A; ++a) {
-    const float rx = x[a] - tx, ry = y[a] - ty, rz = z[a] - tz;
+    const float rx = x[a] - rb.tx, ry = y[a] - rb.ty, rz = z[a] - rb.tz;
     sfx += gfx[a];
     sfy += gfy[a];
     sfz += gfz[a];
@@ -666,7 +668,7 @@ __device__ float eval_pose_one(const LigDev& L, const RecDev& R, const BlockLds&
   tqx = wave_sum(tqx);
   tqy = wave_sum(tqy);
   tqz = wave_sum(tqz);
-
+  const float qw = rb.qw, qx = rb.qx, qy = rb.qy, qz = rb.qz, iqn = rb.iqn;
   float g = 0.f;
   if (lane == 0) g = sfx;
   if (lane == 1) g = sfy;
@@ -676,19 +678,69 @@ __device__ float eval_pose_one(const LigDev& L, const RecDev& R, const BlockLds&
   if (lane == 4) g = 2.f * (qw * tqx - (qy * tqz - qz * tqy)) * iqn;
   if (lane == 5) g = 2.f * (qw * tqy - (qz * tqx - qx * tqz)) * iqn;
   if (lane == 6) g = 2.f * (qw * tqz - (qx * tqy - qy * tqx)) * iqn;
+  return g;
+}
 
-  // torsions: lane k forms the posed axis and pivot of torsion k; every lane then forms, for
-  // every torsion k, axis . (arm x force) of its atoms that k moves, and reduce-scatters across
-  // the wave sum four torsions at a time.
+// Lane k < T: the posed axis and pivot of torsion k, from the posed coordinates xs.
+template <int A>
+__device__ __forceinline__ void torsion_axes(const AtomRegs<A>& at, const float4* xs, int T, float3& tu, float3& tp) {
+  tu = make_float3(0.f, 0.f, 0.f);
+  tp = make_float3(0.f, 0.f, 0.f);
+  if (lane_id() < T) {
+    const float4 xa = xs[at.ta], xb = xs[at.tb];
+    const float ux = xb.x - xa.x, uy = xb.y - xa.y, uz = xb.z - xa.z;
+    const float il = __builtin_amdgcn_rsqf(ux * ux + uy * uy + uz * uz);
+    tu = make_float3(ux * il, uy * il, uz * il);
+    tp = make_float3(xa.x, xa.y, xa.z);
+  }
+}
+
+// Energy (returned, identical in every lane) and, with GRAD, the gradient component of
+// gene `lane` (lanes >= n_genes get 0).  xg: gene `lane` of the pose (lanes < n_genes).
+// One wave evaluates the pose.
+template <int A, int PREC, bool GRAD>
+__device__ float eval_pose_one(const LigDev& L, const RecDev& R, const BlockLds& b, const AtomRegs<A>& at,
+                               float xg, float& g_out) {
+  const int lane = lane_id();
+  const int T = L.n_tors;
+  const Rigid rb = rigid_of(xg);
+  build_torsion_table<A>(at, b.tor, xg, T);
+  bool all[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) all[a] = true;
+  float x[A], y[A], z[A];
+  pose_slots<A>(at, b.tor, rb, T, all, x, y, z);
+#pragma unroll
+  for (int a = 0; a < A; ++a) b.x[lane + kWave * a] = make_float4(x[a], y[a], z[a], 0.f);
+
+  // grid term: issue the corner loads now, finish after the pair term
+  GridFetch gf[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) grid_fetch<PREC>(R, x[a], y[a], z[a], at.type[a], at.q[a], at.valid[a], gf[a]);
+  wave_sync();
+
+  // intramolecular pairs; with GRAD each atom then sums (and clears) its force copies
+  float e_lane = pair_rows<GRAD>(L, b, 0, L.n_rows);
+  float Fx[A], Fy[A], Fz[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) Fx[a] = Fy[a] = Fz[a] = 0.f;
+  if (GRAD) {
+    wave_sync();
+    sum_force_copies<A>(L, b, at, Fx, Fy, Fz);
+  }
+  float gfx[A], gfy[A], gfz[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) e_lane += grid_finish(R, gf[a], at.valid[a], gfx[a], gfy[a], gfz[a]);
+  const float E = wave_sum(e_lane);
+  if (!GRAD) return E;
+  wave_sync();
+
+  float g = rigid_gradient<A>(rb, x, y, z, gfx, gfy, gfz, Fx, Fy, Fz);
+  // torsions: every lane forms, for every torsion k, axis . (arm x force) of its atoms that k
+  // moves, and reduce-scatters across the wave sum four torsions at a time
   if (T > 0) {
-    float3 tu = make_float3(0.f, 0.f, 0.f), tp = make_float3(0.f, 0.f, 0.f);
-    if (lane < T) {
-      const float4 xa = b.x[at.ta], xb = b.x[at.tb];
-      const float ux = xb.x - xa.x, uy = xb.y - xa.y, uz = xb.z - xa.z;
-      const float il = __builtin_amdgcn_rsqf(ux * ux + uy * uy + uz * uz);
-      tu = make_float3(ux * il, uy * il, uz * il);
-      tp = make_float3(xa.x, xa.y, xa.z);
-    }
+    float3 tu, tp;
+    torsion_axes<A>(at, b.x, T, tu, tp);
     const float gk = torsion_gradients<A>(at, T, tu, tp, x, y, z, Fx, Fy, Fz);
     if (lane >= 7 && lane < L.n_genes) g = gk;
   }
@@ -715,59 +767,25 @@ __device__ float eval_pose_shared(const LigDev& L, const RecDev& R, const BlockL
   float4* X = b.share;                                          // [64A + 1] posed coordinates
   float* GG = reinterpret_cast<float*>(X + kWave * A + 1);      // [64] torsion gradients by gene lane
   float4* sets = X + kWave * A + 1 + kWave / 4;                 // two share sets
-  const float tx = readlane(xg, 0), ty = readlane(xg, 1), tz = readlane(xg, 2);
-  float qw = readlane(xg, 3), qx = readlane(xg, 4), qy = readlane(xg, 5), qz = readlane(xg, 6);
-  const float qn = __builtin_sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
-  const float iqn = 1.f / qn;
-  qw *= iqn;
-  qx *= iqn;
-  qy *= iqn;
-  qz *= iqn;
+  const Rigid rb = rigid_of(xg);
 
   // pose of this wave's slot (waves >= A have none) and its grid loads
-  GridFetch gf[A];
-  bool gv[A];
+  bool mine[A], gv[A];
 #pragma unroll
-  for (int a = 0; a < A; ++a) gv[a] = at.valid[a] && a == ps.w;
+  for (int a = 0; a < A; ++a) {
+    mine[a] = a == ps.w;
+    gv[a] = at.valid[a] && mine[a];
+  }
+  GridFetch gf[A];
   if (ps.w < A) {
-    const float r00 = 1.f - 2.f * (qy * qy + qz * qz), r01 = 2.f * (qx * qy - qw * qz),
-                r02 = 2.f * (qx * qz + qw * qy);
-    const float r10 = 2.f * (qx * qy + qw * qz), r11 = 1.f - 2.f * (qx * qx + qz * qz),
-                r12 = 2.f * (qy * qz - qw * qx);
-    const float r20 = 2.f * (qx * qz - qw * qy), r21 = 2.f * (qy * qz + qw * qx),
-                r22 = 1.f - 2.f * (qx * qx + qy * qy);
-    const float th = __shfl(xg, at.gene_of_tor, kWave);
-    if (lane < T) {
-      const float rev = th * 0.15915494309189535f;
-      const float sn = __builtin_amdgcn_sinf(rev), c = __builtin_amdgcn_cosf(rev), oc = 1.f - c;
-      const float ux = at.tux, uy = at.tuy, uz = at.tuz;
-      const float m00 = oc * ux * ux + c, m01 = oc * ux * uy - sn * uz, m02 = oc * ux * uz + sn * uy;
-      const float m10 = oc * uy * ux + sn * uz, m11 = oc * uy * uy + c, m12 = oc * uy * uz - sn * ux;
-      const float m20 = oc * uz * ux - sn * uy, m21 = oc * uz * uy + sn * ux, m22 = oc * uz * uz + c;
-      const float vx = at.tpx, vy = at.tpy, vz = at.tpz;
-      b.tor[3 * lane + 0] = make_float4(m00, m01, m02, vx - (m00 * vx + m01 * vy + m02 * vz));
-      b.tor[3 * lane + 1] = make_float4(m10, m11, m12, vy - (m10 * vx + m11 * vy + m12 * vz));
-      b.tor[3 * lane + 2] = make_float4(m20, m21, m22, vz - (m20 * vx + m21 * vy + m22 * vz));
-    }
-    wave_sync();
+    build_torsion_table<A>(at, b.tor, xg, T);
+    float x[A], y[A], z[A];
+    pose_slots<A>(at, b.tor, rb, T, mine, x, y, z);
 #pragma unroll
     for (int a = 0; a < A; ++a) {
-      if (a == ps.w) {
-        float px = at.px[a], py = at.py[a], pz = at.pz[a];
-        for (int k = T - 1; k >= 0; --k) {
-          const float4 m0 = b.tor[3 * k + 0], m1 = b.tor[3 * k + 1], m2 = b.tor[3 * k + 2];
-          if ((at.mask[a] >> k) & 1u) {
-            const float ox = px, oy = py, oz = pz;
-            px = m0.x * ox + m0.y * oy + m0.z * oz + m0.w;
-            py = m1.x * ox + m1.y * oy + m1.z * oz + m1.w;
-            pz = m2.x * ox + m2.y * oy + m2.z * oz + m2.w;
-          }
-        }
-        const float x = r00 * px + r01 * py + r02 * pz + tx;
-        const float y = r10 * px + r11 * py + r12 * pz + ty;
-        const float z = r20 * px + r21 * py + r22 * pz + tz;
-        X[lane + kWave * a] = make_float4(x, y, z, 0.f);
-        grid_fetch<PREC>(R, x, y, z, at.type[a], at.q[a], gv[a], gf[a]);
+      if (mine[a]) {
+        X[lane + kWave * a] = make_float4(x[a], y[a], z[a], 0.f);
+        grid_fetch<PREC>(R, x[a], y[a], z[a], at.type[a], at.q[a], gv[a], gf[a]);
       } else {
         grid_fetch<PREC>(R, 0.f, 0.f, 0.f, at.type[a], at.q[a], false, gf[a]);
       }
@@ -797,20 +815,7 @@ __device__ float eval_pose_shared(const LigDev& L, const RecDev& R, const BlockL
   for (int a = 0; a < A; ++a) Fx[a] = Fy[a] = Fz[a] = 0.f;
   if (GRAD) {
     wave_sync();
-    const int K = L.n_copies;
-#pragma unroll
-    for (int a = 0; a < A; ++a) {
-      if (at.valid[a]) {
-        const int i = lane + kWave * a;
-        for (int g = 0; g < K; ++g) {
-          const float4 v = b.f[g * (N + 1) + i];
-          Fx[a] += v.x;
-          Fy[a] += v.y;
-          Fz[a] += v.z;
-          b.f[g * (N + 1) + i] = make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-      }
-    }
+    sum_force_copies<A>(L, b, at, Fx, Fy, Fz);
   }
   float gfx[A], gfy[A], gfz[A];
 #pragma unroll
@@ -864,46 +869,11 @@ __device__ float eval_pose_shared(const LigDev& L, const RecDev& R, const BlockL
   }
   if (!GRAD) return E;
 
-  // rigid-body gradient from the grid forces (as in eval_pose_one), the same in every wave
-  float sfx = 0.f, sfy = 0.f, sfz = 0.f, tqx = 0.f, tqy = 0.f, tqz = 0.f;
-#pragma unroll
-  for (int a = 0; a < A; ++a) {
-    const float rx = x[a] - tx, ry = y[a] - ty, rz = z[a] - tz;
-    sfx += gfx[a];
-    sfy += gfy[a];
-    sfz += gfz[a];
-    tqx += ry * gfz[a] - rz * gfy[a];
-    tqy += rz * gfx[a] - rx * gfz[a];
-    tqz += rx * gfy[a] - ry * gfx[a];
-    Fx[a] += gfx[a];
-    Fy[a] += gfy[a];
-    Fz[a] += gfz[a];
-  }
-  sfx = wave_sum(sfx);
-  sfy = wave_sum(sfy);
-  sfz = wave_sum(sfz);
-  tqx = wave_sum(tqx);
-  tqy = wave_sum(tqy);
-  tqz = wave_sum(tqz);
-  float g = 0.f;
-  if (lane == 0) g = sfx;
-  if (lane == 1) g = sfy;
-  if (lane == 2) g = sfz;
-  if (lane == 3) g = -2.f * (tqx * qx + tqy * qy + tqz * qz) * iqn;
-  if (lane == 4) g = 2.f * (qw * tqx - (qy * tqz - qz * tqy)) * iqn;
-  if (lane == 5) g = 2.f * (qw * tqy - (qz * tqx - qx * tqz)) * iqn;
-  if (lane == 6) g = 2.f * (qw * tqz - (qx * tqy - qy * tqx)) * iqn;
-
+  float g = rigid_gradient<A>(rb, x, y, z, gfx, gfy, gfz, Fx, Fy, Fz);
   // this wave's torsion batches, published by gene lane, then every wave reads all
   if (T > 0) {
-    float3 tu = make_float3(0.f, 0.f, 0.f), tp = make_float3(0.f, 0.f, 0.f);
-    if (lane < T) {
-      const float4 xa = X[at.ta], xb = X[at.tb];
-      const float ux = xb.x - xa.x, uy = xb.y - xa.y, uz = xb.z - xa.z;
-      const float il = __builtin_amdgcn_rsqf(ux * ux + uy * uy + uz * uz);
-      tu = make_float3(ux * il, uy * il, uz * il);
-      tp = make_float3(xa.x, xa.y, xa.z);
-    }
+    float3 tu, tp;
+    torsion_axes<A>(at, X, T, tu, tp);
     const float gk = torsion_gradients<A>(at, T, tu, tp, x, y, z, Fx, Fy, Fz, 4 * ps.w, 4 * W);
     const bool gene_t = lane >= 7 && lane < L.n_genes;
     if (gene_t && ((at.tor_of_gene >> 2) % W) == ps.w) GG[lane] = gk;
@@ -926,6 +896,10 @@ __device__ __forceinline__ float eval_pose(const LigDev& L, const RecDev& R, con
 }
 
 // ------------------------------------------------------------------ kernels
+// One-wave searches keep the register budget of 4 waves per SIMD (one atom per lane) or 3 (two):
+// each search is a long dependent chain, and those waves are what hides its latency.
+#define MDOCK_SEARCH_OCCUPANCY __attribute__((amdgpu_waves_per_eu(W == 1 ? (A == 1 ? 4 : 3) : 1)))
+
 // One block = blockDim / (64 W) poses; W > 1: the block's waves share its one pose.
 template <int W>
 __device__ __forceinline__ int block_pose(PoseShare& ps) {
@@ -1067,7 +1041,7 @@ __device__ float local_search_wave(const LigDev& L, const RecDev& R, const Block
 
 // Standalone local search: one pose (W waves) per start genotype.
 template <int A, int PREC, int W>
-__global__ __launch_bounds__(kMaxBlock) void k_local_search(LigDev L, RecDev R, int n,
+__global__ __launch_bounds__(kMaxBlock) MDOCK_SEARCH_OCCUPANCY void k_local_search(LigDev L, RecDev R, int n,
                                                          const float* genes_in, float* genes_out,
                                                          float* __restrict__ energy_out,
                                                          int iters, float rho, float eps,
@@ -1171,7 +1145,7 @@ __device__ float solis_wets_wave(const LigDev& L, const RecDev& R, const BlockLd
 // Standalone Solis-Wets: one wave per start genotype; start k draws from coordinates
 // (seed, 0, 0, k).
 template <int A, int PREC, int W>
-__global__ __launch_bounds__(kMaxBlock) void k_solis_wets(LigDev L, RecDev R, int n, const float* genes_in,
+__global__ __launch_bounds__(kMaxBlock) MDOCK_SEARCH_OCCUPANCY void k_solis_wets(LigDev L, RecDev R, int n, const float* genes_in,
                                                        float* genes_out, float* __restrict__ energy_out,
                                                        int n_evals, unsigned long long seed,
                                                        float* __restrict__ trace) {
@@ -1407,7 +1381,7 @@ __global__ __launch_bounds__(kBlock) void k_ga_ls_pick(JobDev* __restrict__ jobs
 // Local search on the picked individuals; a block holds blockDim / (64 W) searches from
 // (job, first search) of its block-table entry.
 template <int A, int PREC, int W>
-__global__ __launch_bounds__(kMaxBlock) void k_ga_local_search(JobDev* __restrict__ jobs,
+__global__ __launch_bounds__(kMaxBlock) MDOCK_SEARCH_OCCUPANCY void k_ga_local_search(JobDev* __restrict__ jobs,
                                                             const int2* __restrict__ blocks, RecDev R) {
   const int2 bt = blocks[blockIdx.x];
   JobDev& J = jobs[bt.x];
@@ -1434,7 +1408,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_ga_local_search(JobDev* __restric
 // Solis-Wets on the picked individuals (Lamarckian write-back); the search of individual i of
 // run r in generation g draws from coordinates (seed, r, g, i).
 template <int A, int PREC, int W>
-__global__ __launch_bounds__(kMaxBlock) void k_ga_solis_wets(JobDev* __restrict__ jobs,
+__global__ __launch_bounds__(kMaxBlock) MDOCK_SEARCH_OCCUPANCY void k_ga_solis_wets(JobDev* __restrict__ jobs,
                                                           const int2* __restrict__ blocks, RecDev R) {
   const int2 bt = blocks[blockIdx.x];
   JobDev& J = jobs[bt.x];
