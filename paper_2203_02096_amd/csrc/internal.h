@@ -237,15 +237,23 @@ class GenGraph {
   GenGraph() = default;
   GenGraph(const GenGraph&) = delete;
   GenGraph& operator=(const GenGraph&) = delete;
-  ~GenGraph() { reset(); }
+  ~GenGraph();
   // each class's chain `reps` times, classes as parallel branches joined at the end
   hipError_t capture(const GenSchedule& g, JobDev* table, const int2* d_blocks, const RecDev& R);
   hipError_t launch(hipStream_t s) const;
   bool ready() const { return exec_ != nullptr; }
+  // drops the executable graph (the capture streams stay for the next capture)
   void reset();
 
  private:
+  hipError_t make_streams();
   hipGraphExec_t exec_ = nullptr;
+  // the capture stream, the side streams of the parallel branches and their fork/join events,
+  // created on the first capture and kept until the object is destroyed (after the last
+  // executable graph captured from them)
+  hipStream_t cs_ = nullptr;
+  std::vector<hipStream_t> side_;
+  std::vector<hipEvent_t> ev_;
 };
 bool use_graphs();
 void set_use_graphs(bool on);

@@ -155,49 +155,55 @@ hipError_t launch_generation_phase(const GenSchedule& g, JobDev* table, const in
 }
 
 // ------------------------------------------------------------------ captured generations
-hipError_t GenGraph::capture(const GenSchedule& g, JobDev* table, const int2* d_blocks, const RecDev& R) {
-  reset();
-  hipStream_t cs = nullptr;
-  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-  if (e != hipSuccess) return e;
-  // side streams for the classes' parallel branches
-  std::vector<hipStream_t> side;
-  const size_t width = std::min(g.classes.size(), kGraphBranches);
-  for (size_t k = 0; k + 1 < width && e == hipSuccess; ++k) {
+hipError_t GenGraph::make_streams() {
+  if (cs_) return hipSuccess;
+  hipError_t e = hipStreamCreateWithFlags(&cs_, hipStreamNonBlocking);
+  for (size_t k = 0; k + 1 < kGraphBranches && e == hipSuccess; ++k) {
     hipStream_t x = nullptr;
     e = hipStreamCreateWithFlags(&x, hipStreamNonBlocking);
-    if (e == hipSuccess) side.push_back(x);
+    if (e == hipSuccess) side_.push_back(x);
   }
-  std::vector<hipEvent_t> ev(1 + side.size(), nullptr);
-  for (hipEvent_t& x : ev)
+  ev_.assign(kGraphBranches, nullptr);
+  for (hipEvent_t& x : ev_)
     if (e == hipSuccess) e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-  if (e == hipSuccess) {
-    // fork: every side stream waits for the start of the capture; class i runs on stream
-    // i mod width (0 = the capture stream); then every side stream joins back
-    hipError_t el = hipEventRecord(ev[0], cs);
-    for (size_t k = 0; k < side.size() && el == hipSuccess; ++k) el = hipStreamWaitEvent(side[k], ev[0], 0);
-    for (size_t i = 0; i < g.classes.size() && el == hipSuccess; ++i) {
-      const ClassChain& c = g.classes[i];
-      hipStream_t st = (i % width == 0) ? cs : side[i % width - 1];
-      for (int r = 0; r < c.reps && el == hipSuccess; ++r) el = launch_chain(c, table, d_blocks, R, st, nullptr);
-    }
-    for (size_t k = 0; k < side.size() && el == hipSuccess; ++k) el = hipEventRecord(ev[1 + k], side[k]);
-    for (size_t k = 0; k < side.size() && el == hipSuccess; ++k) el = hipStreamWaitEvent(cs, ev[1 + k], 0);
-    hipGraph_t graph = nullptr;
-    e = hipStreamEndCapture(cs, &graph);
-    if (e == hipSuccess) e = el;
-    if (e == hipSuccess) e = hipGraphInstantiate(&exec_, graph, nullptr, nullptr, 0);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (e != hipSuccess && exec_) {
-      (void)hipGraphExecDestroy(exec_);
-      exec_ = nullptr;
-    }
-  }
-  for (hipEvent_t x : ev)
+  return e;
+}
+
+GenGraph::~GenGraph() {
+  reset();
+  for (hipEvent_t x : ev_)
     if (x) (void)hipEventDestroy(x);
-  for (hipStream_t x : side) (void)hipStreamDestroy(x);
-  (void)hipStreamDestroy(cs);
+  for (hipStream_t x : side_) (void)hipStreamDestroy(x);
+  if (cs_) (void)hipStreamDestroy(cs_);
+}
+
+hipError_t GenGraph::capture(const GenSchedule& g, JobDev* table, const int2* d_blocks, const RecDev& R) {
+  reset();
+  hipError_t e = make_streams();
+  if (e != hipSuccess) return e;
+  // class i runs on stream i mod width (0 = the capture stream)
+  const size_t width = std::max<size_t>(1, std::min(g.classes.size(), kGraphBranches));
+  e = hipStreamBeginCapture(cs_, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  // fork: every side stream in use waits for the start of the capture; then every one joins back
+  hipError_t el = hipEventRecord(ev_[0], cs_);
+  for (size_t k = 0; k + 1 < width && el == hipSuccess; ++k) el = hipStreamWaitEvent(side_[k], ev_[0], 0);
+  for (size_t i = 0; i < g.classes.size() && el == hipSuccess; ++i) {
+    const ClassChain& c = g.classes[i];
+    hipStream_t st = (i % width == 0) ? cs_ : side_[i % width - 1];
+    for (int r = 0; r < c.reps && el == hipSuccess; ++r) el = launch_chain(c, table, d_blocks, R, st, nullptr);
+  }
+  for (size_t k = 0; k + 1 < width && el == hipSuccess; ++k) el = hipEventRecord(ev_[1 + k], side_[k]);
+  for (size_t k = 0; k + 1 < width && el == hipSuccess; ++k) el = hipStreamWaitEvent(cs_, ev_[1 + k], 0);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cs_, &graph);
+  if (e == hipSuccess) e = el;
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec_, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (e != hipSuccess && exec_) {
+    (void)hipGraphExecDestroy(exec_);
+    exec_ = nullptr;
+  }
   return e;
 }
 
