@@ -562,6 +562,10 @@ md_status md_server_destroy(md_server* s) {
     std::lock_guard<std::mutex> lk(s->mu);
     s->cv_done.notify_all();
   }
+  // the device work is drained; drop the executable graph before the buffers and the stream it
+  // was launched on
+  (void)hipStreamSynchronize(s->stream);
+  s->graph.reset();
   if (s->d_blocks) (void)hipFree(s->d_blocks);
   (void)hipFree(s->d_table);
   (void)hipHostFree(s->h_table);
