@@ -126,7 +126,7 @@ def single_ligand_path(md, drec, dligs, params, sample):
 
 # ------------------------------------------------------------------ CPU baseline (oracle)
 def _oracle_worker(args):
-    seed, budget_s = args
+    seed, budget_s, grad = args
     for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
         os.environ[var] = "1"      # one thread per process: `cores` counts what is used
     import numpy as np
@@ -141,12 +141,15 @@ def _oracle_worker(args):
     n = 0
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < budget_s:
-        S.energy_and_gradient(grid, ol, genes[n % len(genes)], want_margin=False)
+        if grad:
+            S.energy_and_gradient(grid, ol, genes[n % len(genes)], want_margin=False)
+        else:
+            S.energy(grid, ol, genes[n % len(genes)])
         n += 1
     return n, time.perf_counter() - t0
 
 
-def cpu_baseline(budget_s=10.0):
+def cpu_baseline(budget_s=10.0, grad=True):
     import multiprocessing as mp
     try:
         cores = len(os.sched_getaffinity(0))
@@ -156,7 +159,7 @@ def cpu_baseline(budget_s=10.0):
     ctx = mp.get_context("spawn")
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
-        res = pool.map(_oracle_worker, [(1000 + i, budget_s) for i in range(cores)])
+        res = pool.map(_oracle_worker, [(1000 + i, budget_s, grad) for i in range(cores)])
     wall = time.perf_counter() - t0
     n = sum(r[0] for r in res)
     per_proc = max(r[1] for r in res)
@@ -169,7 +172,7 @@ def cpu_baseline(budget_s=10.0):
     except OSError:
         pass
     return {"value": n / per_proc, "unit": "evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 oracle energy+gradient of random poses of the {WORKLOAD} ligand on its "
+            "sample": f"FP64 oracle {'energy+gradient' if grad else 'energy'} of random poses of the {WORKLOAD} ligand on its "
                       f"64^3 grid, one process per core, {budget_s:.0f} s each ({n} evals, "
                       f"{wall:.1f} s wall incl. start-up); CPU: {cpu}"}
 
@@ -187,11 +190,11 @@ def main():
                     help="after the timed region, one plain device copy of this size (a known-size "
                          "dispatch for calibrating byte counters under a profiler)")
     ap.add_argument("--workload", default=WORKLOAD,
-                    choices=[WORKLOAD, "batched_fp32", "serving_fp16", "paper_inputs"],
+                    choices=[WORKLOAD, "batched_fp32", "serving_fp16", "paper_inputs", "eval_sweep"],
                     help="plain_fp32_production (default): one ligand, 20 runs; batched_fp32: 256 "
                          "ligands in one batch; serving_fp16: Poisson arrivals into the server; "
                          "paper_inputs: the paper's three input sizes at 10 and 100 runs, docked "
-                         "with each block size")
+                         "with each block size; eval_sweep: md_eval of 2^16..2^20 independent poses")
     ap.add_argument("--generations", type=int, default=50,
                     help="batched_fp32: generations per timed batch (the full budget takes ~878)")
     ap.add_argument("--rates", default="50,100,200,350,500",
@@ -214,9 +217,11 @@ def main():
         return bench_serving(args)
     if args.workload == "paper_inputs":
         return bench_paper_inputs(args)
+    if args.workload == "eval_sweep":
+        return bench_eval_sweep(args)
 
     # the oracle baseline runs first, in spawned processes, before this process touches the GPU
-    base = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)
+    base = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds, grad=args.ls != "solis_wets")
 
     import numpy as np
     import torch
@@ -327,6 +332,59 @@ def _common(md):
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     md.lib()
+
+
+def bench_eval_sweep(args):
+    """The evaluation alone (md_eval: energy and gradient of independent poses, no search) of the
+    production ligand on its 64^3 FP32 maps, for 2^16 .. 2^20 random poses in the box; each size
+    timed with HIP events over --steps launches after --warmup.  value = evaluations/s at 2^20."""
+    import numpy as np
+    import torch
+
+    import paper_2203_02096_amd as md
+    from workload import configs, synth
+    _common(md)
+    rec = configs.receptor(WORKLOAD)
+    lig = configs.ligand(WORKLOAD)
+    drec = md.Receptor(rec.maps, rec.origin, rec.spacing, "fp32")
+    dlig = md.Ligand.from_synth(lig)
+    info = md.md_ligand_info(dlig)
+    tune = None if args.no_autotune else md.md_ligand_autotune(drec, dlig, n_starts=0)
+    flops = flop_model(info["n_atoms"], info["n_torsions"], info["n_pairs"], info["sum_moving"])
+    stream = torch.cuda.current_stream()
+    rows = []
+    for lg in range(16, 21):
+        n = 1 << lg
+        genes = torch.from_numpy(synth.random_genes(lig, rec, n, seed=lg, margin=2.0)).cuda()
+        e = torch.empty(n, device="cuda")
+        d = torch.empty(n, lig.n_genes, device="cuda")
+        for _ in range(max(1, args.warmup)):
+            md.md_eval(drec, dlig, genes, e, d, stream=stream)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(args.steps):
+            md.md_eval(drec, dlig, genes, e, d, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / args.steps
+        rows.append({"poses": n, "ms_per_launch": ms, "evals_per_s": n / (ms * 1e-3),
+                     "tflops": flops * n / (ms * 1e-3) / 1e12})
+        print(f"[eval_sweep] {n} poses: {ms:.3f} ms, {n / (ms * 1e-3):.3e} evals/s", file=sys.stderr, flush=True)
+    top = rows[-1]
+    out = {"metric": "energy+gradient evals/s (md_eval, independent poses)", "value": top["evals_per_s"],
+           "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": top["ms_per_launch"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "eval_sweep", "ligand": WORKLOAD, "n_atoms": info["n_atoms"],
+                      "n_torsions": info["n_torsions"], "n_pairs": info["n_pairs"]},
+           "launch_plan": md.md_ligand_get_plan(dlig), "autotuned": tune is not None,
+           "roofline": {"bound": "alu", "achieved": top["tflops"], "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                        "frac": top["tflops"] / PEAK_FP32_VALU_TFLOPS, "traffic": None, "kernel": "k_eval",
+                        "frac_of_nonpacked_fp32": top["tflops"] / (PEAK_FP32_VALU_TFLOPS / 2),
+                        "hbm_algorithmic_GBs": bytes_model(info["n_atoms"]) * top["evals_per_s"] / 1e9,
+                        "hbm_frac": bytes_model(info["n_atoms"]) * top["evals_per_s"] / 1e9 / PEAK_HBM_GBS},
+           "sweep": rows}
+    print(json.dumps(out), flush=True)
 
 
 def bench_paper_inputs(args):
