@@ -291,3 +291,33 @@ def test_dock_batch_rejects_bad_job(md):
     bad = md.dock_params(**configs.search_params("plain_fp32_small", pop_size=1))
     with pytest.raises(md.MdockError, match="job 1"):
         md.md_dock_batch(drec, [(lig, good), (lig, bad)])
+
+
+def test_batched_workload_full_shape_sampled(md):
+    """The batched workload at its full shape (256 ligands of 10-100 atoms against the 64^3 maps,
+    10 runs x 150 each, 6 % local search x 300) for 3 generations through md_dock_batch, as the
+    batched bench launches it: every job's evaluation count follows the closed form, and for 16
+    jobs spread over the batch every run's reported best energy is the oracle's energy of the
+    reported pose."""
+    from oracle import scoring as S
+    name = "batched_fp32"
+    rec, drec = _receptor(md, 64, 102)
+    ligs = configs.batched_ligands(name)
+    dligs = [md.Ligand.from_synth(l) for l in ligs]
+    P = md.dock_params(**configs.search_params(name, seed=11, max_generations=3))
+    res = md.md_dock_batch(drec, [(d, P) for d in dligs], want_xyz=False)
+    per_gen = (150 - 1) + 9 * 300
+    for r in res:
+        assert np.all(r["evals"] == 150 + 3 * per_gen)
+        assert np.all(np.diff(r["best_energy"]) >= 0)
+    grid = oracle_grid(rec)
+    checked = 0
+    for k in np.linspace(0, len(ligs) - 1, 16).astype(int):
+        ol = oracle_ligand(ligs[k])
+        for run in range(P.n_runs):
+            ref = S.energy_and_gradient(grid, ol, res[k]["best_genes"][run].astype(np.float64))
+            if ref.margin_energy >= 5e-5:
+                assert abs(ref.energy - res[k]["best_energy"][run]) <= 1e-4 * max(abs(ref.energy), ref.scale_energy)
+                checked += 1
+    _say(f"[batched full shape] {checked} sampled run bests re-scored by the oracle")
+    assert checked >= 0.9 * 16 * P.n_runs
