@@ -109,3 +109,45 @@ def test_server_cancel_and_errors(md, receptor):
     with pytest.raises(md.MdockError, match="budget"):
         small.submit(lig, _params(md, 3, n_runs=50, pop_size=1000))
     small.close()
+
+
+def test_serving_workload_full_shape_sampled(md):
+    """Requests of the serving workload at full shape (96^3 maps stored in FP16, log-normal
+    ligand sizes, 10 runs x 150, 250k evaluations per run, 6 % local search x 300), 24 of them
+    submitted together: closed-form counts, every sampled run best is the oracle's energy (on the
+    same FP16-rounded maps) of the reported pose, and two requests equal their docks alone."""
+    from oracle import scoring as S
+    from parity_util import oracle_ligand
+    name = "serving_fp16"
+    rec = configs.receptor(name)
+    drec = md.Receptor(rec.maps, rec.origin, rec.spacing, "fp16")
+    sizes = configs.serving_sizes(24, seed=77)
+    ligs = [synth.make_ligand(n, t, 7700 + k, configs.type_params()) for k, (n, t) in enumerate(sizes)]
+    dligs = [md.Ligand.from_synth(l) for l in ligs]
+    params = [md.dock_params(**configs.search_params(name, seed=500 + k)) for k in range(len(ligs))]
+    gens = md.md_dock_planned_generations(params[0])
+    srv = md.Server(drec, hbm_budget_bytes=1 << 30, max_slots=64)
+    try:
+        tickets = [srv.submit(d, p) for d, p in zip(dligs, params)]
+        res = [srv.wait(t, timeout_s=300, want_xyz=False) for t in tickets]
+    finally:
+        srv.close()
+    for r in res:
+        assert np.all(r["evals"] == 150 + gens * ((150 - 1) + 9 * 300))
+        assert np.all(r["generations"] == gens)
+    rounded = S.make_grid(np.asarray(rec.maps, np.float32).astype(np.float16).astype(np.float64),
+                          rec.origin, rec.spacing)
+    checked = 0
+    for k in range(0, len(ligs), 3):
+        ol = oracle_ligand(ligs[k])
+        for run in range(0, 10, 3):
+            ref = S.energy_and_gradient(rounded, ol, res[k]["best_genes"][run].astype(np.float64))
+            if ref.margin_energy >= 5e-5:
+                assert abs(ref.energy - res[k]["best_energy"][run]) <= 1e-4 * max(abs(ref.energy), ref.scale_energy)
+                checked += 1
+    for k in (0, 17):
+        alone = md.md_dock(drec, dligs[k], params[k], want_xyz=False)
+        for key in ("best_energy", "best_genes", "evals"):
+            assert np.array_equal(alone[key], res[k][key]), (k, key)
+    _say(f"[serving full shape] {gens} generations per request, {checked} sampled run bests re-scored")
+    assert checked >= 0.9 * 8 * 4
