@@ -202,13 +202,22 @@ md_status md_receptor_create(const md_grid_desc* d, const float* maps, md_map_pr
     for (long long i = 0; i < count; ++i)
       if (std::fabs(maps[i]) > 65504.f) return fail(MD_ERANGE, "md_receptor_create: map value outside FP16 range");
 
+  // device layout: the type maps as given, then the electrostatic and desolvation maps
+  // interleaved per node ([nz][ny][nx][2]): an atom reads both at the same eight corners, so a
+  // corner pair along x is one 16-byte (FP32) or 8-byte load for the two maps
+  std::vector<float> dev((size_t)count);
+  std::copy(maps, maps + (size_t)kTypes * nodes, dev.begin());
+  for (long long i = 0; i < nodes; ++i) {
+    dev[(size_t)kTypes * nodes + 2 * i] = maps[(size_t)kTypes * nodes + i];
+    dev[(size_t)kTypes * nodes + 2 * i + 1] = maps[(size_t)(kTypes + 1) * nodes + i];
+  }
   const size_t elem = stored == MD_MAP_FP32 ? 4 : 2;
   std::vector<uint16_t> half;
-  const void* src = maps;
+  const void* src = dev.data();
   if (stored != MD_MAP_FP32) {
     half.resize(count);
     for (long long i = 0; i < count; ++i)
-      half[i] = stored == MD_MAP_FP16 ? f32_to_f16_rne(maps[i]) : f32_to_bf16_rne(maps[i]);
+      half[i] = stored == MD_MAP_FP16 ? f32_to_f16_rne(dev[i]) : f32_to_bf16_rne(dev[i]);
     src = half.data();
   }
   md_receptor* r = new (std::nothrow) md_receptor();

@@ -85,7 +85,8 @@ struct RecDev {
   float ox, oy, oz;
   float h, inv_h;
   long long map_stride;       // nx*ny*nz
-  const void* maps;           // [9][nz][ny][nx]
+  const void* maps;           // [7][nz][ny][nx] type maps, then [nz][ny][nx][2] (electrostatic,
+                              // desolvation) interleaved per node
 };
 
 // GA parameters as the kernels see them.

@@ -4,7 +4,10 @@
 // Mapping: one 64-lane wavefront owns one pose (genotype).  Lanes hold atoms (atom l and,
 // for ligands above 64 atoms, l + 64), then stride over the intramolecular pair list; the
 // per-pose energy and the genotype gradient are wavefront reductions.  Waves of a block are
-// independent (no block barriers), so a block can hold poses of different work.
+// independent (no block barriers), so a block can hold poses of different work.  A plan may
+// instead let the 2 or 4 waves of a block share one local-search pose (eval_pose_shared):
+// they split the posing, the pair rows and the torsion gradients and meet in LDS at block
+// barriers, for searches too few to fill the device.
 //
 // Paper passages: the energy kernel's phases -- per-atom positions, rotations in a fixed
 // order, per-atom energy sum (Section "Approach 1", listing of decomposed target
@@ -276,14 +279,14 @@ __device__ __forceinline__ void grid_fetch(const RecDev& R, float x, float y, fl
     const long long nx = R.nx, nxy = (long long)R.nx * R.ny;
     const long long base = (long long)iz * nxy + (long long)iy * nx + ix;
     const long long mt = (long long)type * R.map_stride + base;
-    const long long me = (long long)kTypes * R.map_stride + base;
-    const long long md = (long long)(kTypes + 1) * R.map_stride + base;
+    const long long me = (long long)kTypes * R.map_stride + 2 * base;   // interleaved with md
+    const long long md = me + 1;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const long long off = ((k >> 2) & 1) * nxy + ((k >> 1) & 1) * nx + (k & 1);
       g.mt[k] = map_at<PREC>(R.maps, mt + off);
-      g.me[k] = map_at<PREC>(R.maps, me + off);
-      g.md[k] = map_at<PREC>(R.maps, md + off);
+      g.me[k] = map_at<PREC>(R.maps, me + 2 * off);
+      g.md[k] = map_at<PREC>(R.maps, md + 2 * off);
     }
   }
 }
