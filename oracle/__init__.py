@@ -2,8 +2,8 @@
 
 Plain, slow, readable NumPy code that states what the GPU path must compute:
 genotype -> pose, grid (intermolecular) energy, intramolecular pair energy, the
-analytic genotype gradient, ADADELTA local search and the Lamarckian genetic
-algorithm.  Only the test suite, the smoke check and the benchmark's CPU baseline
+analytic genotype gradient, the ADADELTA and Solis-Wets local searches and the
+Lamarckian genetic algorithm.  Only the test suite, the smoke check and the benchmark's CPU baseline
 may import it.  The product library never calls it and shares no code with it.
 
 Where the paper (Background, "Design and Structure of MiniMDock") only names a
@@ -14,6 +14,8 @@ AutoDock4); each such reading is listed with its constant values in `constants`.
 Pins: every function here is checked by `tests/test_oracle_*.py` against closed
 forms, library routines (scipy interpolation and rotations, torch's Adadelta),
 invariances, finite differences or brute force.  The LGA operator choices beyond
-its invariants are "parity unpinned" (see `lga`).
+its invariants are "parity unpinned" (see `lga`), and so are the Solis-Wets step
+parameters (the paper gives none; `solis_wets` is pinned on hand-worked trajectories,
+its update rules, its budget and closed-form minima).
 """
-from . import constants, rng, ligand, pose, scoring, adadelta, lga  # noqa: F401
+from . import constants, rng, ligand, pose, scoring, adadelta, solis_wets, lga  # noqa: F401

@@ -1,4 +1,4 @@
-"""Solis-Wets local search on the genotype (oracle).
+"""Solis-Wets local search on the genotype (oracle; test infrastructure only).
 
 The paper names Solis and Wets' random search ("Minimization by random search techniques",
 Mathematics of Operations Research 6(1), 1981) as the miniapp's local optimiser (Background,
