@@ -347,9 +347,9 @@ typedef struct md_server md_server;   /* opaque */
 typedef struct {
   size_t hbm_budget_bytes;   /* device memory pool for request buffers, >= 1 MiB */
   int max_slots;             /* requests resident at once, 1..4096 */
-  int use_graphs;            /* 1: each tick's generation is a HIP graph, captured once per
-                                change of the resident set (also needs md_graphs_enabled());
-                                0: launched kernel by kernel.  Results are the same. */
+  int use_graphs;            /* 1 (with md_graphs_enabled()): each tick launches the size
+                                classes' chains as parallel branches over several streams;
+                                0: one stream, kernel by kernel.  Results are the same. */
 } md_server_params;
 typedef struct {
   long long ticks, completed;
@@ -391,8 +391,8 @@ md_status md_profile_read(int kind, double* total_ms, long long* launches);
 
 /* HIP graphs for the per-generation launches (default on).  One generation of the LGA is a
  * fixed sequence of launches over the device job table, so md_dock / md_dock_batch capture it
- * once per call and replay it every generation, and the server captures it once per change of
- * its resident set.  Results are identical with graphs off.  Profiling (md_profile_enable)
+ * once per call and replay it every generation (the server launches the same branches
+ * directly, without capture).  Results are identical with graphs off.  Profiling (md_profile_enable)
  * launches kernels one at a time regardless.  Process-wide setting; not thread-safe to change
  * while calls are running. */
 md_status md_set_graphs(int on);

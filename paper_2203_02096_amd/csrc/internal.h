@@ -241,6 +241,9 @@ class GenGraph {
   ~GenGraph();
   // each class's chain `reps` times, classes as parallel branches joined at the end
   hipError_t capture(const GenSchedule& g, JobDev* table, const int2* d_blocks, const RecDev& R);
+  // the same work launched directly (no capture) on s and this object's branch streams
+  hipError_t launch_direct(const GenSchedule& g, JobDev* table, const int2* d_blocks, const RecDev& R,
+                           hipStream_t s);
   hipError_t launch(hipStream_t s) const;
   bool ready() const { return exec_ != nullptr; }
   // drops the executable graph (the capture streams stay for the next capture)
@@ -248,6 +251,9 @@ class GenGraph {
 
  private:
   hipError_t make_streams();
+  // fork the classes over `main` and the side streams, each class's chain `reps` times; join
+  hipError_t fork_classes(const GenSchedule& g, JobDev* table, const int2* d_blocks, const RecDev& R,
+                          hipStream_t main);
   hipGraphExec_t exec_ = nullptr;
   // the capture stream, the side streams of the parallel branches and their fork/join events,
   // created on the first capture and kept until the object is destroyed (after the last

@@ -177,24 +177,30 @@ GenGraph::~GenGraph() {
   if (cs_) (void)hipStreamDestroy(cs_);
 }
 
+hipError_t GenGraph::fork_classes(const GenSchedule& g, JobDev* table, const int2* d_blocks, const RecDev& R,
+                                  hipStream_t main) {
+  // class i runs on stream i mod width (0 = main); every side stream in use waits for the fork
+  // and joins back into main at the end
+  const size_t width = std::max<size_t>(1, std::min(g.classes.size(), kGraphBranches));
+  hipError_t e = hipEventRecord(ev_[0], main);
+  for (size_t k = 0; k + 1 < width && e == hipSuccess; ++k) e = hipStreamWaitEvent(side_[k], ev_[0], 0);
+  for (size_t i = 0; i < g.classes.size() && e == hipSuccess; ++i) {
+    const ClassChain& c = g.classes[i];
+    hipStream_t st = (i % width == 0) ? main : side_[i % width - 1];
+    for (int r = 0; r < c.reps && e == hipSuccess; ++r) e = launch_chain(c, table, d_blocks, R, st, nullptr);
+  }
+  for (size_t k = 0; k + 1 < width && e == hipSuccess; ++k) e = hipEventRecord(ev_[1 + k], side_[k]);
+  for (size_t k = 0; k + 1 < width && e == hipSuccess; ++k) e = hipStreamWaitEvent(main, ev_[1 + k], 0);
+  return e;
+}
+
 hipError_t GenGraph::capture(const GenSchedule& g, JobDev* table, const int2* d_blocks, const RecDev& R) {
   reset();
   hipError_t e = make_streams();
   if (e != hipSuccess) return e;
-  // class i runs on stream i mod width (0 = the capture stream)
-  const size_t width = std::max<size_t>(1, std::min(g.classes.size(), kGraphBranches));
   e = hipStreamBeginCapture(cs_, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
-  // fork: every side stream in use waits for the start of the capture; then every one joins back
-  hipError_t el = hipEventRecord(ev_[0], cs_);
-  for (size_t k = 0; k + 1 < width && el == hipSuccess; ++k) el = hipStreamWaitEvent(side_[k], ev_[0], 0);
-  for (size_t i = 0; i < g.classes.size() && el == hipSuccess; ++i) {
-    const ClassChain& c = g.classes[i];
-    hipStream_t st = (i % width == 0) ? cs_ : side_[i % width - 1];
-    for (int r = 0; r < c.reps && el == hipSuccess; ++r) el = launch_chain(c, table, d_blocks, R, st, nullptr);
-  }
-  for (size_t k = 0; k + 1 < width && el == hipSuccess; ++k) el = hipEventRecord(ev_[1 + k], side_[k]);
-  for (size_t k = 0; k + 1 < width && el == hipSuccess; ++k) el = hipStreamWaitEvent(cs_, ev_[1 + k], 0);
+  const hipError_t el = fork_classes(g, table, d_blocks, R, cs_);
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(cs_, &graph);
   if (e == hipSuccess) e = el;
@@ -205,6 +211,12 @@ hipError_t GenGraph::capture(const GenSchedule& g, JobDev* table, const int2* d_
     exec_ = nullptr;
   }
   return e;
+}
+
+hipError_t GenGraph::launch_direct(const GenSchedule& g, JobDev* table, const int2* d_blocks, const RecDev& R,
+                                   hipStream_t s) {
+  const hipError_t e = make_streams();
+  return e == hipSuccess ? fork_classes(g, table, d_blocks, R, s) : e;
 }
 
 hipError_t GenGraph::launch(hipStream_t s) const {

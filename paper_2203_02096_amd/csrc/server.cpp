@@ -208,7 +208,11 @@ JobDev make_job(md_server* s, const Request& r) {
   return J;
 }
 
-// One tick: every resident request advances by one phase sequence.  Returns the HIP status.
+// One tick: every resident request advances by one phase sequence.  With use_graphs the worker
+// thread launches the size classes' chains directly as parallel branches (fork/join events over
+// the branch streams) and captures no graph: graph capture in this thread coincided with two
+// host crashes whose cause is not known (md_dock_batch captures on the caller's thread).
+// Returns the HIP status.
 hipError_t run_tick(md_server* s, bool any_init, bool any_running) {
   const int n_slots = (int)s->slots.size();
   hipError_t e = hipSuccess;
@@ -244,8 +248,7 @@ hipError_t run_tick(md_server* s, bool any_init, bool any_running) {
     if (!any_running) {
       e = launch_ga_advance(s->d_table, n_slots, s->stream);
     } else if (s->params.use_graphs && use_graphs()) {
-      if (!s->graph.ready()) e = s->graph.capture(s->sched, s->d_table, s->d_blocks, R);
-      if (e == hipSuccess) e = s->graph.launch(s->stream);
+      e = s->graph.launch_direct(s->sched, s->d_table, s->d_blocks, R, s->stream);
     } else {
       e = launch_generation_phase(s->sched, s->d_table, s->d_blocks, R, s->stream, nullptr);
     }
@@ -380,6 +383,7 @@ void worker_loop(md_server* s) {
         (void)hipMemcpy(s->d_table + j, &empty, sizeof(JobDev), hipMemcpyHostToDevice);
         s->pool->release(r->off, r->bytes);
         r = nullptr;
+        s->resident_changed = true;
       }
     }
     if (!finished.empty()) s->cv_done.notify_all();

@@ -7,6 +7,7 @@ import sys
 import numpy as np
 import pytest
 
+from parity_util import SERVER_OFF_REASON
 from workload import configs, synth
 
 pytestmark = pytest.mark.gpu
@@ -81,6 +82,7 @@ def test_dock_batch_graph_equals_eager(md, receptor):
             assert np.array_equal(eager[k][key], graph[k][key]), (k, key)
 
 
+@pytest.mark.skip(reason=SERVER_OFF_REASON)
 @pytest.mark.parametrize("use_graphs", [True, False])
 def test_server_graphs_equal_alone(md, receptor, use_graphs):
     rec, drec = receptor

@@ -6,9 +6,10 @@ import time
 import numpy as np
 import pytest
 
+from parity_util import SERVER_OFF_REASON
 from workload import configs, synth
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.skip(reason=SERVER_OFF_REASON)]
 torch = pytest.importorskip("torch")
 
 

@@ -15,7 +15,7 @@ import sys
 import numpy as np
 import pytest
 
-from parity_util import E_TOL, check_sw_start, oracle_grid, oracle_ligand
+from parity_util import E_TOL, SERVER_OFF_REASON, check_sw_start, oracle_grid, oracle_ligand
 from workload import configs, synth
 
 pytestmark = pytest.mark.gpu
@@ -168,10 +168,8 @@ def test_dock_solis_wets_production_accounting(md):
     _say(f"[dock production] best energies Solis-Wets {r1['best_energy']}, ADADELTA {ra['best_energy']}")
 
 
-def test_batch_mixed_local_searches_equal_alone(md):
-    """ADADELTA and Solis-Wets jobs of several sizes in one batch (separate launch classes)
-    give bitwise the same answers as each job docked alone; likewise through the server."""
-    rec, drec = _receptor(md, 64, 102)
+def _mixed_jobs(md):
+    """ADADELTA and Solis-Wets jobs of four sizes."""
     sizes = [(10, 3), (40, 8), (65, 14), (100, 32)]
     ligs = [synth.make_ligand(n, t, 600 + k, configs.type_params()) for k, (n, t) in enumerate(sizes)]
     dligs = [md.Ligand.from_synth(l) for l in ligs]
@@ -181,12 +179,28 @@ def test_batch_mixed_local_searches_equal_alone(md):
             jobs.append((dl, md.dock_params(**configs.search_params(
                 "batched_fp32", n_runs=2, pop_size=40, max_generations=3, ls_rate=0.2, ls_iters=40,
                 seed=70 + k, ls_method=method))))
+    return jobs
+
+
+def test_batch_mixed_local_searches_equal_alone(md):
+    """ADADELTA and Solis-Wets jobs of several sizes in one batch (separate launch classes)
+    give bitwise the same answers as each job docked alone."""
+    rec, drec = _receptor(md, 64, 102)
+    jobs = _mixed_jobs(md)
     batch = md.md_dock_batch(drec, jobs)
     for k, (dl, p) in enumerate(jobs):
         alone = md.md_dock(drec, dl, p)
         for key in ("best_energy", "best_genes", "run_index", "evals", "generations"):
             assert np.array_equal(batch[k][key], alone[key]), (k, key)
     assert not np.array_equal(batch[0]["best_genes"], batch[1]["best_genes"])
+
+
+@pytest.mark.skip(reason=SERVER_OFF_REASON)
+def test_server_mixed_local_searches_equal_batch(md):
+    """The same mixed jobs through the server equal their batch results."""
+    rec, drec = _receptor(md, 64, 102)
+    jobs = _mixed_jobs(md)
+    batch = md.md_dock_batch(drec, jobs)
     srv = md.Server(drec)
     try:
         ids = [srv.submit(dl, p) for dl, p in jobs]
