@@ -17,6 +17,7 @@
 // Every kernel reads what it needs from the device job table (a finished job's work is skipped
 // on the device), so the same captured phase serves every generation and is replayed.
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <numeric>
 #include <tuple>
