@@ -226,8 +226,6 @@ __device__ __forceinline__ void load_ligand(const LigDev& L, AtomRegs<A>& at) {
   }
 }
 
-__device__ __forceinline__ int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
-
 // ------------------------------------------------------------------ grid term
 // Trilinear interpolation of (type map + q * electrostatic + |q| * desolvation) and its
 // derivative with respect to the atom position; out-of-grid penalty outside the box.
@@ -405,9 +403,11 @@ __device__ __forceinline__ void pair_span(const LigDev& L, const BlockLds& b, in
   const int lane = lane_id();
   const uint32_t* pij = FROM_LDS ? b.pair_ij : L.pair_ij;
   const float4* pc = FROM_LDS ? b.pair_coef : L.pair_coef;
-  int s = r0 * kWave + lane;
-  uint32_t ij = pij[s];
-  float4 c = pc[s];
+  // slot addresses: the lane's offset plus a wave-uniform row offset
+  const uint32_t* pij_l = pij + lane;
+  const float4* pc_l = pc + lane;
+  uint32_t ij = pij_l[r0 * kWave];
+  float4 c = pc_l[r0 * kWave];
   P3 xi = load_p3(b.x, ij & 0xff), xj = load_p3(b.x, (ij >> 8) & 0xff);
   for (int r = r0; r < r1; ++r) {
     const int i = ij & 0xff, j = (ij >> 8) & 0xff;
@@ -416,9 +416,9 @@ __device__ __forceinline__ void pair_span(const LigDev& L, const BlockLds& b, in
       fi = load_p3(b.fg, i);
       fj = load_p3(b.fg, j);
     }
-    const int sn = (r + 1 < r1) ? s + kWave : s;
-    const uint32_t ij_n = pij[sn];
-    const float4 c_n = pc[sn];
+    const int rn = min(r + 1, r1 - 1) * kWave;   // the last row prefetches itself
+    const uint32_t ij_n = pij_l[rn];
+    const float4 c_n = pc_l[rn];
     e += pair_slot<GRAD>(ij, c, xi, xj, fi, fj);
     const int i_n = ij_n & 0xff, j_n = (ij_n >> 8) & 0xff;
     const P3 xi_n = load_p3(b.x, i_n), xj_n = load_p3(b.x, j_n);
@@ -436,7 +436,6 @@ __device__ __forceinline__ void pair_span(const LigDev& L, const BlockLds& b, in
     c = c_n;
     xi = xi_n;
     xj = xj_n;
-    s = sn;
   }
 }
 
@@ -665,12 +664,33 @@ __device__ __forceinline__ float rigid_gradient(const Rigid& rb, const float (&x
     Fy[a] += gfy[a];
     Fz[a] += gfz[a];
   }
-  sfx = wave_sum(sfx);
-  sfy = wave_sum(sfy);
-  sfz = wave_sum(sfz);
-  tqx = wave_sum(tqx);
-  tqy = wave_sum(tqy);
-  tqz = wave_sum(tqz);
+  // the six wave sums as one reduce-scatter (as for the torsion gradients): the half swaps
+  // leave rows 0-3 of r0 holding sfx, sfy, sfz, tqx and rows 0 and 2 of r1 holding tqy, tqz,
+  // and the row sums complete them
+  const auto s0 = __builtin_amdgcn_permlane32_swap(__float_as_uint(sfx), __float_as_uint(sfz), false, false);
+  const auto s1 = __builtin_amdgcn_permlane32_swap(__float_as_uint(sfy), __float_as_uint(tqx), false, false);
+  const auto s2 = __builtin_amdgcn_permlane32_swap(__float_as_uint(tqy), __float_as_uint(tqz), false, false);
+  const float h0 = __uint_as_float(s0[0]) + __uint_as_float(s0[1]);   // sfx | sfz
+  const float h1 = __uint_as_float(s1[0]) + __uint_as_float(s1[1]);   // sfy | tqx
+  const float h2 = __uint_as_float(s2[0]) + __uint_as_float(s2[1]);   // tqy | tqz
+  const auto s3 = __builtin_amdgcn_permlane16_swap(__float_as_uint(h0), __float_as_uint(h1), false, false);
+  const auto s4 = __builtin_amdgcn_permlane16_swap(__float_as_uint(h2), 0u, false, false);
+  float r0 = __uint_as_float(s3[0]) + __uint_as_float(s3[1]);
+  float r1 = __uint_as_float(s4[0]) + __uint_as_float(s4[1]);
+  r0 += dpp<0xb1, 0xf>(r0);   // quad_perm [1,0,3,2]
+  r1 += dpp<0xb1, 0xf>(r1);
+  r0 += dpp<0x4e, 0xf>(r0);   // quad_perm [2,3,0,1]
+  r1 += dpp<0x4e, 0xf>(r1);
+  r0 += dpp<0x141, 0xf>(r0);  // row_half_mirror
+  r1 += dpp<0x141, 0xf>(r1);
+  r0 += dpp<0x140, 0xf>(r0);  // row_mirror
+  r1 += dpp<0x140, 0xf>(r1);
+  sfx = readlane(r0, 0);
+  sfy = readlane(r0, 16);
+  sfz = readlane(r0, 32);
+  tqx = readlane(r0, 48);
+  tqy = readlane(r1, 0);
+  tqz = readlane(r1, 32);
   const float qw = rb.qw, qx = rb.qx, qy = rb.qy, qz = rb.qz, iqn = rb.iqn;
   float g = 0.f;
   if (lane == 0) g = sfx;
