@@ -167,6 +167,16 @@ hipError_t GenGraph::make_streams() {
   ev_.assign(kGraphBranches, nullptr);
   for (hipEvent_t& x : ev_)
     if (e == hipSuccess) e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    // all or nothing: a later call starts over instead of finding a partial set
+    for (hipEvent_t x : ev_)
+      if (x) (void)hipEventDestroy(x);
+    for (hipStream_t x : side_) (void)hipStreamDestroy(x);
+    if (cs_) (void)hipStreamDestroy(cs_);
+    ev_.clear();
+    side_.clear();
+    cs_ = nullptr;
+  }
   return e;
 }
 
