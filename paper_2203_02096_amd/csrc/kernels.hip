@@ -541,8 +541,7 @@ __device__ __forceinline__ Rigid rigid_of(float xg) {
   r.ty = readlane(xg, 1);
   r.tz = readlane(xg, 2);
   float qw = readlane(xg, 3), qx = readlane(xg, 4), qy = readlane(xg, 5), qz = readlane(xg, 6);
-  const float qn = __builtin_sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
-  r.iqn = 1.f / qn;
+  r.iqn = __builtin_amdgcn_rsqf(qw * qw + qx * qx + qy * qy + qz * qz);   // 1 / |q|
   qw *= r.iqn;
   qx *= r.iqn;
   qy *= r.iqn;
@@ -1015,8 +1014,8 @@ __global__ __launch_bounds__(kBlock) void k_pose(LigDev L, int n, const float* _
 __device__ __forceinline__ float project_gene(float nx, int G) {
   const int lane = lane_id();
   const float q0 = readlane(nx, 3), q1 = readlane(nx, 4), q2 = readlane(nx, 5), q3 = readlane(nx, 6);
-  const float qn = __builtin_sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
-  if (lane >= 3 && lane < 7) nx = nx / qn;
+  const float iqn = __builtin_amdgcn_rsqf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+  if (lane >= 3 && lane < 7) nx = nx * iqn;
   if (lane >= 7 && lane < G) nx = wrap_angle(nx);
   return nx;
 }
@@ -1028,7 +1027,9 @@ __device__ __forceinline__ float adadelta_update(float x, float g, float& eg2, f
   float nx = x;
   if (lane < G) {
     eg2 = rho * eg2 + (1.f - rho) * g * g;
-    const float dx = -__builtin_sqrtf(edx2 + eps) / __builtin_sqrtf(eg2 + eps) * g;
+    // the hardware square root and reciprocal square root (about 1 ulp; both arguments are at
+    // least eps, far from denormals)
+    const float dx = -(__builtin_amdgcn_sqrtf(edx2 + eps) * __builtin_amdgcn_rsqf(eg2 + eps)) * g;
     edx2 = rho * edx2 + (1.f - rho) * dx * dx;
     nx = x + dx;
   }
