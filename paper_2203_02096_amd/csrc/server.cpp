@@ -124,8 +124,8 @@ struct md_server {
   int2* d_blocks = nullptr;
   size_t blocks_cap = 0;
   std::vector<std::shared_ptr<Request>> slots;   // resident request per slot (or null)
-  // launch schedule of the resident set; rebuilt (and the captured generation dropped) when
-  // the set changes
+  // launch schedule of the resident set, rebuilt when the set changes; `graph` provides the
+  // branch streams and fork/join events of the direct launch
   bool resident_changed = true;
   GenSchedule sched;
   GenGraph graph;

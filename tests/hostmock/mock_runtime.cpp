@@ -13,6 +13,7 @@
 // request's result does not depend on what else runs.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
