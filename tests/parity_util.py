@@ -115,6 +115,6 @@ def check_sw_start(grid, ol, start, g_out, e_out, tr_gpu, n_evals, seed, k):
 
 # The serving worker thread crashed the host process (SIGSEGV in that thread, no GPU fault) twice
 # while it captured generation graphs; the cause is not known.  Capture in the worker is switched
-# off, and the tests that run the server stay off the GPU until a cause is shown.
-SERVER_OFF_REASON = ("md_server's worker thread crashed the host process twice (SIGSEGV in that "
-                     "thread) with graph capture in the worker; cause not known, server tests held back")
+# off, and the test that was running at the second crash stays off the GPU until a cause is shown.
+SERVER_OFF_REASON = ("md_server's worker thread crashed the host process (SIGSEGV in that thread) while "
+                     "this test ran, with graph capture in the worker; cause not known, held back")

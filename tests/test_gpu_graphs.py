@@ -1,13 +1,12 @@
-"""HIP-graph generations: md_dock / md_dock_batch capture one LGA generation and replay it, and
-the server captures its tick once per change of the resident set.  Every result must equal the
-kernel-by-kernel launch order bitwise, after any number of replays, with eager device work and
-synchronisations between calls."""
+"""HIP-graph generations: md_dock / md_dock_batch capture one LGA generation and replay it.  Every
+result must equal the kernel-by-kernel launch order bitwise, after any number of replays, with
+eager device work and synchronisations between calls.  (The server's branch launch against
+kernel-by-kernel ticks is in test_gpu_zz_server.py.)"""
 import sys
 
 import numpy as np
 import pytest
 
-from parity_util import SERVER_OFF_REASON
 from workload import configs, synth
 
 pytestmark = pytest.mark.gpu
@@ -80,23 +79,3 @@ def test_dock_batch_graph_equals_eager(md, receptor):
     for k in range(len(ligs)):
         for key in KEYS:
             assert np.array_equal(eager[k][key], graph[k][key]), (k, key)
-
-
-@pytest.mark.skip(reason=SERVER_OFF_REASON)
-@pytest.mark.parametrize("use_graphs", [True, False])
-def test_server_graphs_equal_alone(md, receptor, use_graphs):
-    rec, drec = receptor
-    sizes = [(20, 3), (66, 14), (35, 6), (90, 20)]
-    ligs = [md.Ligand.from_synth(synth.make_ligand(n, t, 930 + k, configs.type_params()))
-            for k, (n, t) in enumerate(sizes)]
-    Ps = [md.dock_params(**configs.search_params("serving_fp16", n_runs=2, pop_size=30, max_generations=3 + k,
-                                                 ls_rate=0.2, ls_iters=15, seed=60 + k)) for k in range(len(ligs))]
-    _say(f"[graphs] server use_graphs={use_graphs}, 4 requests")
-    srv = md.Server(drec, hbm_budget_bytes=64 << 20, max_slots=2, use_graphs=use_graphs)
-    tickets = [srv.submit(l, p) for l, p in zip(ligs, Ps)]
-    results = [srv.wait(t, timeout_s=120) for t in tickets]
-    srv.close()
-    for k, (l, p) in enumerate(zip(ligs, Ps)):
-        alone = _dock(md, drec, l, p, False)
-        for key in KEYS:
-            assert np.array_equal(results[k][key], alone[key]), (k, key)

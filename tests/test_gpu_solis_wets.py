@@ -15,7 +15,7 @@ import sys
 import numpy as np
 import pytest
 
-from parity_util import E_TOL, SERVER_OFF_REASON, check_sw_start, oracle_grid, oracle_ligand
+from parity_util import E_TOL, check_sw_start, oracle_grid, oracle_ligand
 from workload import configs, synth
 
 pytestmark = pytest.mark.gpu
@@ -193,19 +193,3 @@ def test_batch_mixed_local_searches_equal_alone(md):
         for key in ("best_energy", "best_genes", "run_index", "evals", "generations"):
             assert np.array_equal(batch[k][key], alone[key]), (k, key)
     assert not np.array_equal(batch[0]["best_genes"], batch[1]["best_genes"])
-
-
-@pytest.mark.skip(reason=SERVER_OFF_REASON)
-def test_server_mixed_local_searches_equal_batch(md):
-    """The same mixed jobs through the server equal their batch results."""
-    rec, drec = _receptor(md, 64, 102)
-    jobs = _mixed_jobs(md)
-    batch = md.md_dock_batch(drec, jobs)
-    srv = md.Server(drec)
-    try:
-        ids = [srv.submit(dl, p) for dl, p in jobs]
-        for k, rid in enumerate(ids):
-            r = srv.wait(rid, timeout_s=120, want_xyz=False)
-            assert np.array_equal(r["best_energy"], batch[k]["best_energy"]), k
-    finally:
-        srv.close()

@@ -1,5 +1,11 @@
 """Continuous-batching server: requests that arrive while others run are admitted as slots and
-memory free up, and each result is the same as docking the request alone."""
+memory free up, and each result is the same as docking the request alone -- with the tick's
+class branches launched directly and kernel by kernel, and with mixed local optimisers.
+
+Every test here runs the server's worker thread, which crashed the host process twice while it
+captured generation graphs (capture in the worker is now switched off; the cause is not known).
+The file is collected last so that a failure here cannot hide the other GPU tests, and the test
+that was running at the second crash stays skipped."""
 import sys
 import time
 
@@ -9,7 +15,7 @@ import pytest
 from parity_util import SERVER_OFF_REASON
 from workload import configs, synth
 
-pytestmark = [pytest.mark.gpu, pytest.mark.skip(reason=SERVER_OFF_REASON)]
+pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
@@ -42,6 +48,7 @@ def _params(md, k, **over):
     return md.dock_params(**configs.search_params("serving_fp16", **kw))
 
 
+@pytest.mark.skip(reason=SERVER_OFF_REASON)
 def test_server_results_equal_alone(md, receptor):
     rec, drec = receptor
     ligs = [md.Ligand.from_synth(synth.make_ligand(n, t, 700 + k, configs.type_params()))
@@ -152,3 +159,62 @@ def test_serving_workload_full_shape_sampled(md):
             assert np.array_equal(alone[key], res[k][key]), (k, key)
     _say(f"[serving full shape] {gens} generations per request, {checked} sampled run bests re-scored")
     assert checked >= 0.9 * 8 * 4
+
+
+KEYS = ("best_energy", "best_genes", "best_xyz", "run_index", "evals", "generations")
+
+
+def _dock(md, drec, lig, P, graphs):
+    md.md_set_graphs(graphs)
+    try:
+        return md.md_dock(drec, lig, P)
+    finally:
+        md.md_set_graphs(True)
+
+
+@pytest.mark.parametrize("use_graphs", [True, False])
+def test_server_graphs_equal_alone(md, receptor, use_graphs):
+    rec, drec = receptor
+    sizes = [(20, 3), (66, 14), (35, 6), (90, 20)]
+    ligs = [md.Ligand.from_synth(synth.make_ligand(n, t, 930 + k, configs.type_params()))
+            for k, (n, t) in enumerate(sizes)]
+    Ps = [md.dock_params(**configs.search_params("serving_fp16", n_runs=2, pop_size=30, max_generations=3 + k,
+                                                 ls_rate=0.2, ls_iters=15, seed=60 + k)) for k in range(len(ligs))]
+    _say(f"[graphs] server use_graphs={use_graphs}, 4 requests")
+    srv = md.Server(drec, hbm_budget_bytes=64 << 20, max_slots=2, use_graphs=use_graphs)
+    tickets = [srv.submit(l, p) for l, p in zip(ligs, Ps)]
+    results = [srv.wait(t, timeout_s=120) for t in tickets]
+    srv.close()
+    for k, (l, p) in enumerate(zip(ligs, Ps)):
+        alone = _dock(md, drec, l, p, False)
+        for key in KEYS:
+            assert np.array_equal(results[k][key], alone[key]), (k, key)
+
+
+def _mixed_jobs(md):
+    """ADADELTA and Solis-Wets jobs of four sizes."""
+    sizes = [(10, 3), (40, 8), (65, 14), (100, 32)]
+    ligs = [synth.make_ligand(n, t, 600 + k, configs.type_params()) for k, (n, t) in enumerate(sizes)]
+    dligs = [md.Ligand.from_synth(l) for l in ligs]
+    jobs = []
+    for k, dl in enumerate(dligs):
+        for method in ("adadelta", "solis_wets"):
+            jobs.append((dl, md.dock_params(**configs.search_params(
+                "batched_fp32", n_runs=2, pop_size=40, max_generations=3, ls_rate=0.2, ls_iters=40,
+                seed=70 + k, ls_method=method))))
+    return jobs
+
+
+def test_server_mixed_local_searches_equal_batch(md, receptor):
+    """The same mixed jobs through the server equal their batch results."""
+    rec, drec = receptor
+    jobs = _mixed_jobs(md)
+    batch = md.md_dock_batch(drec, jobs)
+    srv = md.Server(drec)
+    try:
+        ids = [srv.submit(dl, p) for dl, p in jobs]
+        for k, rid in enumerate(ids):
+            r = srv.wait(rid, timeout_s=120, want_xyz=False)
+            assert np.array_equal(r["best_energy"], batch[k]["best_energy"]), k
+    finally:
+        srv.close()
