@@ -267,8 +267,8 @@ __device__ __forceinline__ void grid_fetch(const RecDev& R, float x, float y, fl
   g.ez = z - fminf(fmaxf(z, R.oz), hz);
   g.fx = g.fy = g.fz = 0.f;
   g.q = q;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) g.mt[k] = g.me[k] = g.md[k] = 0.f;
+  // the corner values are read only where the atom is inside (grid_finish), so lanes outside
+  // leave them unset
   if (g.inside) {
     const int ix = (int)gx, iy = (int)gy, iz = (int)gz;
     g.fx = gx - (float)ix;
