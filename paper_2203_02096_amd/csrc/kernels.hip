@@ -1099,7 +1099,10 @@ constexpr int kSwMaxEvals = 1 << 24;   // keeps the draw indices below 2^31
 __device__ __forceinline__ float box_muller(uint32_t k1, uint32_t k2) {
   const float u1 = (float)(k1 + 1u) * (1.0f / 16777216.0f);   // (0, 1], exact
   const float u2 = (float)k2 * (1.0f / 16777216.0f);          // [0, 1), exact
-  return __builtin_sqrtf(-2.f * logf(u1)) * cospif(2.f * u2);
+  // hardware log2, square root and cosine (the cosine takes revolutions, so cos(2 pi u2) is
+  // v_cos(u2)); u1 >= 2^-24 keeps every argument in the normal range
+  const float ln_u1 = __builtin_amdgcn_logf(u1) * 0.69314718055994531f;
+  return __builtin_amdgcn_sqrtf(-2.f * ln_u1) * __builtin_amdgcn_cosf(u2);
 }
 
 // One wave's search from genes_in[row_in]; the final genotype goes to genes_out[row_out] and
