@@ -163,7 +163,7 @@ typedef struct {
  * {4, 8} x LDS budget {32, 48, 64, 96, 128, 160} KiB, waves per pose {2, 4} x LDS budget {64,
  * 160} KiB, then lane-group sizes N/2 and N/4 for the best -- and applies the fastest to `lig`.  n_starts is the number of local searches one launch
  * will run (md_dock: n_runs x ceil(ls_rate x pop_size)); the candidates are timed on that many
- * random starts inside the box (a few ADADELTA steps each, best of three launches), since the
+ * random starts inside the box (steps for about 1 ms per launch, best of five launches), since the
  * best plan depends on how well the launch fills the device.  n_starts = 0 (or >= 8192) tunes
  * for launches that fill the device many times over (batches, servers): that plan is also
  * recorded for the ligand's size class (atoms per lane and pair count within a quarter octave),
@@ -304,8 +304,9 @@ md_status md_dock_batch(const md_receptor* rec, int n_jobs, const md_dock_job* j
  * and GA phase, as parallel branches of the captured generation), so the plan that is fastest
  * for a ligand alone on the whole device need not be fastest in the mix.  This times whole-batch
  * plan policies on the batch itself -- md_dock_batch of these ligands and parameters, run to
- * generations/3 and to `generations` generations, the per-generation time being the difference
- * over the extra generations (which leaves out per-call costs) -- and applies the fastest policy
+ * generations/3 and to `generations` generations (the shorter of two runs at each length, after
+ * a warm-up), the per-generation time being the difference over the extra generations (which
+ * leaves out per-call costs) -- and applies the fastest policy
  * to every ligand: MD_POLICY_DEFAULT (every ligand on the default plan),
  * MD_POLICY_TUNED_ALONE (md_ligand_autotune for full-device launches, per size class),
  * MD_POLICY_LDS_ALL (LDS budget 160 KiB: all pair rows staged), MD_POLICY_WIDE_BLOCKS (8 waves

@@ -124,10 +124,10 @@ struct Bench {
   int n, iters;
   float *genes_in, *genes_out, *energy;
   hipEvent_t a, b;
-  // microseconds per evaluation (best of three launches after one warm-up), or < 0 on error
+  // microseconds per evaluation (best of five launches after one warm-up), or < 0 on error
   double time(const LigDev& L, hipError_t* err) {
     double best = 1e300;
-    for (int rep = 0; rep < 4; ++rep) {
+    for (int rep = 0; rep < 6; ++rep) {
       hipError_t e = hipEventRecord(a, s);
       if (e == hipSuccess)
         e = launch_local_search(L, *R, n, genes_in, genes_out, energy, iters, 0.8f, 0.01f, nullptr, s);
@@ -248,10 +248,10 @@ md_status md_ligand_autotune(const md_receptor* rec, md_ligand* lig, int n_start
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const RecDev& R = rec->dev;
   const LigHost base = lig->host;
-  // the launch size to tune for; enough steps for ~0.5 ms per launch
+  // the launch size to tune for; enough steps for ~1 ms per launch
   const int n = fill ? kFillStarts : n_starts;
   const double slots = (double)base.n_rows * kWave + 64.0;
-  const int iters = (int)std::max(2.0, std::min(300.0, std::round(4e7 / (n * slots))));
+  const int iters = (int)std::max(2.0, std::min(300.0, std::round(8e7 / (n * slots))));
   const std::vector<float> g = tuning_genes(R, base.n_genes, n);
   Bench bench{&R, s, n, iters, nullptr, nullptr, nullptr, nullptr, nullptr};
   const size_t gb = g.size() * sizeof(float);
@@ -412,11 +412,16 @@ md_status md_batch_autotune(const md_receptor* rec, int n, md_ligand* const* lig
     *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return st;
   };
+  // the shorter of two runs at each length, after a warm-up (first use of the plans)
   auto time_batch = [&](double* ms) -> md_status {
-    double t1 = 0.0, t2 = 0.0;
-    md_status st = run(g1, &t1);                  // warm-up (first use of the plans)
-    if (st == MD_OK) st = run(g1, &t1);
-    if (st == MD_OK) st = run(g2, &t2);
+    double t1 = 1e300, t2 = 1e300, t = 0.0;
+    md_status st = run(g1, &t);
+    for (int rep = 0; rep < 2 && st == MD_OK; ++rep) {
+      st = run(g1, &t);
+      t1 = std::min(t1, t);
+      if (st == MD_OK) st = run(g2, &t);
+      t2 = std::min(t2, t);
+    }
     *ms = std::max(t2 - t1, 1e-6) / (g2 - g1);
     return st;
   };
