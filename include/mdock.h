@@ -113,6 +113,7 @@ typedef struct {
 /* Validates, preprocesses and uploads (synchronously, current device).
  * Errors: MD_EINVAL, MD_ERANGE, MD_ENOMEM, MD_EDEVICE. */
 md_status md_ligand_create(const md_ligand_desc* desc, md_ligand** out);
+/* MD_EBUSY (nothing freed) while a server request holds the ligand (see md_server_*). */
 md_status md_ligand_destroy(md_ligand* lig);
 int md_ligand_num_genes(const md_ligand* lig);     /* 7 + n_torsions, or -1 for NULL */
 int md_ligand_num_atoms(const md_ligand* lig);
@@ -148,7 +149,8 @@ typedef struct {
 } md_plan;
 md_status md_ligand_get_plan(const md_ligand* lig, md_plan* out);
 /* Re-plans the ligand (host work + one upload; waits for the device to be idle).  The ligand
- * must not be in use by another call.  Errors: MD_EINVAL, MD_ERANGE, MD_EDEVICE. */
+ * must not be in use by another call.  Errors: MD_EINVAL, MD_ERANGE, MD_EBUSY (a server request
+ * holds the ligand), MD_EDEVICE. */
 md_status md_ligand_set_plan(md_ligand* lig, const md_plan* plan);
 
 enum { MD_TUNE_FORCE = 1 };   /* time candidates even if the size class is already tuned */
@@ -167,10 +169,12 @@ typedef struct {
  * best plan depends on how well the launch fills the device.  n_starts = 0 (or >= 8192) tunes
  * for launches that fill the device many times over (batches, servers): that plan is also
  * recorded for the ligand's size class (atoms per lane and pair count within a quarter octave),
- * which md_ligand_create then uses for later ligands of that class, and which a later call for
- * such a class applies without timing (unless MD_TUNE_FORCE).  Runs on `hip_stream`,
- * synchronously.  The ligand must not be in use by another call.  info may be NULL.
- * Errors: MD_EINVAL, MD_ERANGE (n_starts > 2^20), MD_EDEVICE. */
+ * and a later call for a ligand of such a class applies it without timing (unless
+ * MD_TUNE_FORCE).  md_ligand_create never consults the record: a new ligand always starts with
+ * the default plan, so its results do not depend on what was tuned earlier in the process.  Runs
+ * on `hip_stream`, synchronously.  The ligand must not be in use by another call.  info may be
+ * NULL.  Errors: MD_EINVAL, MD_ERANGE (n_starts > 2^20), MD_EBUSY (a server request holds the
+ * ligand), MD_EDEVICE. */
 md_status md_ligand_autotune(const md_receptor* rec, md_ligand* lig, int n_starts, int flags,
                              void* hip_stream, md_tune_info* info);
 /* Host only (no device needed): the pair schedule that `plan` gives the ligand `d`, for tests and
@@ -219,6 +223,18 @@ md_status md_local_search(const md_receptor* rec, const md_ligand* lig, int n,
                           const float* genes_in_dev, float* genes_out_dev,
                           float* energy_out_dev, int n_iters, float rho, float eps,
                           float* trace_dev, void* hip_stream);
+
+/* md_local_search that also records every step's iterate and gradient, for checking each step
+ * of the search on its own (the evaluation at the iterate and the update that leaves it).
+ * trace_genes_dev: NULL or [n][n_iters][n_genes], the genotype x_s evaluated at step s;
+ * trace_grad_dev: NULL or [n][n_iters][n_genes], the gradient at x_s that the update used.
+ * x_{s+1} is trace_genes_dev[s + 1]; the accumulators start at zero as in md_local_search.
+ * Same results, arguments and errors as md_local_search otherwise. */
+md_status md_local_search_traced(const md_receptor* rec, const md_ligand* lig, int n,
+                                 const float* genes_in_dev, float* genes_out_dev,
+                                 float* energy_out_dev, int n_iters, float rho, float eps,
+                                 float* trace_dev, float* trace_genes_dev, float* trace_grad_dev,
+                                 void* hip_stream);
 
 /* Solis-Wets random search (Solis and Wets, Math. Oper. Res. 6(1), 1981; the local optimiser
  * the paper names in Background, "Design and Structure of MiniMDock") from each start
@@ -341,9 +357,12 @@ int md_dock_planned_generations(const md_dock_params* params);
  * expensive class takes for one; without, one generation per tick -- and retires finished
  * requests at once, freeing their slot and memory for the next admission.  A
  * request's result equals md_dock of the same ligand and parameters.
- * The receptor and every submitted ligand must stay alive until the server is destroyed (or
- * the request is released).  Calls are thread-safe.  md_server_destroy drops queued requests,
- * lets resident ones finish, and must not race with md_server_wait on another thread. */
+ * A queued or resident request holds its ligand: until the request has left the device
+ * (finished, canceled and out of its slot, or failed), md_ligand_destroy, md_ligand_set_plan
+ * and the autotuners refuse that ligand with MD_EBUSY.  Finished requests keep their results
+ * and no longer touch the ligand.  The receptor must stay alive until the server is destroyed.
+ * Calls are thread-safe.  md_server_destroy drops queued requests, lets resident ones finish,
+ * and must not race with md_server_wait on another thread. */
 typedef struct md_server md_server;   /* opaque */
 typedef struct {
   size_t hbm_budget_bytes;   /* device memory pool for request buffers, >= 1 MiB */
@@ -368,11 +387,15 @@ md_status md_server_submit(md_server* srv, const md_ligand* lig, const md_dock_p
 md_status md_server_poll(md_server* srv, unsigned long long ticket, md_dock_result* out, int* done);
 /* Blocks until the request finishes (timeout_s < 0: no limit; MD_EBUSY on timeout). */
 md_status md_server_wait(md_server* srv, unsigned long long ticket, md_dock_result* out, double timeout_s);
+/* A queued request is canceled at once; a resident one leaves its slot after the current tick
+ * and is reported canceled (poll, wait: MD_ECANCELED) only then.  A request that finishes in
+ * that tick is reported finished.  Canceling a finished request changes nothing. */
 md_status md_server_cancel(md_server* srv, unsigned long long ticket);
 /* Host monotonic times (s) of submission, admission to a slot and completion. */
 md_status md_server_request_times(md_server* srv, unsigned long long ticket, double* submit_s,
                                   double* start_s, double* end_s);
-/* Forgets a finished request (frees its host-side result); MD_EBUSY while it runs. */
+/* Forgets a finished, canceled or failed request (frees its host-side result); MD_EBUSY while
+ * it is queued or on the device (a canceled resident request until it has left its slot). */
 md_status md_server_release(md_server* srv, unsigned long long ticket);
 md_status md_server_get_stats(md_server* srv, md_server_stats* out);
 md_status md_server_destroy(md_server* srv);

@@ -267,8 +267,9 @@ md_status md_ligand_create(const md_ligand_desc* d, md_ligand** out) {
     delete l;
     return fail(range ? MD_ERANGE : MD_EINVAL, "md_ligand_create: " + err);
   }
-  PlanParams tuned;
-  if (tuned_plan_for(l->host, &tuned)) plan_ligand(l->host, tuned);
+  // the default plan, whatever was tuned earlier in the process: a tuned plan changes the order
+  // of floating-point sums, so applying it is the caller's choice (md_ligand_autotune reads the
+  // tune table), never a side effect of creation
   hipError_t e = hipGetDevice(&l->device);
   if (e == hipSuccess) e = enable_large_lds();
   if (e == hipSuccess) e = upload_ligand(l->host, &l->d_buf, &l->dev);
@@ -282,6 +283,7 @@ md_status md_ligand_create(const md_ligand_desc* d, md_ligand** out) {
 
 md_status md_ligand_destroy(md_ligand* l) {
   if (!l) return MD_OK;
+  if (l->holds.load() > 0) return fail(MD_EBUSY, "md_ligand_destroy: a server request still uses the ligand");
   if (l->d_buf) (void)hipFree(l->d_buf);
   delete l;
   return MD_OK;
@@ -352,20 +354,37 @@ md_status md_pose(const md_ligand* lig, int n_poses, const float* genes, float* 
   return MD_OK;
 }
 
+namespace {
+md_status local_search_common(const char* who, const md_receptor* rec, const md_ligand* lig, int n,
+                              const float* genes_in, float* genes_out, float* energy_out, int n_iters, float rho,
+                              float eps, float* trace, float* trace_x, float* trace_g, void* hip_stream) {
+  const std::string w(who);
+  if (!rec || !lig) return fail(MD_EINVAL, w + ": null handle");
+  if (n < 0) return fail(MD_EINVAL, w + ": n < 0");
+  if (n_iters < 1) return fail(MD_EINVAL, w + ": n_iters must be >= 1");
+  if (!(rho >= 0.f && rho < 1.f) || !(eps > 0.f) || !std::isfinite(eps))
+    return fail(MD_EINVAL, w + ": rho must be in [0,1) and eps > 0");
+  if (n == 0) return MD_OK;
+  if (!genes_in || !genes_out || !energy_out) return fail(MD_EINVAL, w + ": null buffer");
+  MD_HIP(launch_local_search(lig->dev, rec->dev, n, genes_in, genes_out, energy_out, n_iters, rho, eps, trace,
+                             trace_x, trace_g, static_cast<hipStream_t>(hip_stream)),
+         (w + " launch").c_str());
+  return MD_OK;
+}
+}  // namespace
+
 md_status md_local_search(const md_receptor* rec, const md_ligand* lig, int n, const float* genes_in,
                           float* genes_out, float* energy_out, int n_iters, float rho, float eps,
                           float* trace, void* hip_stream) {
-  if (!rec || !lig) return fail(MD_EINVAL, "md_local_search: null handle");
-  if (n < 0) return fail(MD_EINVAL, "md_local_search: n < 0");
-  if (n_iters < 1) return fail(MD_EINVAL, "md_local_search: n_iters must be >= 1");
-  if (!(rho >= 0.f && rho < 1.f) || !(eps > 0.f) || !std::isfinite(eps))
-    return fail(MD_EINVAL, "md_local_search: rho must be in [0,1) and eps > 0");
-  if (n == 0) return MD_OK;
-  if (!genes_in || !genes_out || !energy_out) return fail(MD_EINVAL, "md_local_search: null buffer");
-  MD_HIP(launch_local_search(lig->dev, rec->dev, n, genes_in, genes_out, energy_out, n_iters, rho, eps,
-                             trace, static_cast<hipStream_t>(hip_stream)),
-         "md_local_search launch");
-  return MD_OK;
+  return local_search_common("md_local_search", rec, lig, n, genes_in, genes_out, energy_out, n_iters, rho, eps,
+                             trace, nullptr, nullptr, hip_stream);
+}
+
+md_status md_local_search_traced(const md_receptor* rec, const md_ligand* lig, int n, const float* genes_in,
+                                 float* genes_out, float* energy_out, int n_iters, float rho, float eps,
+                                 float* trace, float* trace_genes, float* trace_grad, void* hip_stream) {
+  return local_search_common("md_local_search_traced", rec, lig, n, genes_in, genes_out, energy_out, n_iters, rho,
+                             eps, trace, trace_genes, trace_grad, hip_stream);
 }
 
 md_status md_local_search_sw(const md_receptor* rec, const md_ligand* lig, int n, const float* genes_in,
@@ -533,6 +552,7 @@ md_status md_dock_batch(const md_receptor* rec, int n_jobs, const md_dock_job* j
     J.best_row = reinterpret_cast<int*>(w + o.br);
     J.best_energy = reinterpret_cast<float*>(w + o.be);
     J.best_genes = reinterpret_cast<float*>(w + o.bg);
+    J.best_xyz = jobs[j].result->best_xyz ? reinterpret_cast<float*>(w + o.bx) : nullptr;
     J.gen = 0;
     J.cur = 0;
     J.planned = md_dock_planned_generations(&p);
@@ -566,10 +586,7 @@ md_status md_dock_batch(const md_receptor* rec, int n_jobs, const md_dock_job* j
     // the graph's launches read the workspace: finish them before the graph is destroyed
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   }
-  for (int j = 0; j < n_jobs && e == hipSuccess; ++j)
-    if (jobs[j].result->best_xyz)
-      e = launch_pose(table[j].L, jobs[j].params.n_runs, table[j].best_genes,
-                      reinterpret_cast<float*>(w + offs[j].bx), s);
+  // the epilogue that finished each job wrote its best genes, energies and poses
   std::vector<char> host(results_bytes);
   if (e == hipSuccess) e = hipMemcpyAsync(host.data(), w + o_results, results_bytes, hipMemcpyDeviceToHost, s);
   hipError_t ef = hipFreeAsync(w, s);

@@ -130,7 +130,7 @@ struct Bench {
     for (int rep = 0; rep < 6; ++rep) {
       hipError_t e = hipEventRecord(a, s);
       if (e == hipSuccess)
-        e = launch_local_search(L, *R, n, genes_in, genes_out, energy, iters, 0.8f, 0.01f, nullptr, s);
+        e = launch_local_search(L, *R, n, genes_in, genes_out, energy, iters, 0.8f, 0.01f, nullptr, nullptr, nullptr, s);
       if (e == hipSuccess) e = hipEventRecord(b, s);
       if (e == hipSuccess) e = hipEventSynchronize(b);
       float ms = 0.f;
@@ -147,15 +147,6 @@ struct Bench {
 
 }  // namespace
 
-namespace mdock {
-bool tuned_plan_for(const LigHost& h, PlanParams* out) {
-  std::lock_guard<std::mutex> lk(g_table_mu);
-  auto it = g_table.find(size_class(h));
-  if (it == g_table.end()) return false;
-  *out = it->second.plan;
-  return true;
-}
-}  // namespace mdock
 
 extern "C" {
 
@@ -167,6 +158,7 @@ md_status md_ligand_get_plan(const md_ligand* lig, md_plan* out) {
 
 md_status md_ligand_set_plan(md_ligand* lig, const md_plan* plan) {
   if (!lig || !plan) return api_fail(MD_EINVAL, "md_ligand_set_plan: null argument");
+  if (lig->holds.load() > 0) return api_fail(MD_EBUSY, "md_ligand_set_plan: a server request still uses the ligand");
   if (!valid_plan(*plan))
     return api_fail(MD_ERANGE, "md_ligand_set_plan: lds_budget in [0, 163840], group_div in [2, 8], "
                                "waves_per_block in {1, 2, 4, 8}, waves_per_pose in {1, 2, 4}");
@@ -217,6 +209,7 @@ int md_tune_table_size(void) {
 md_status md_ligand_autotune(const md_receptor* rec, md_ligand* lig, int n_starts, int flags,
                              void* hip_stream, md_tune_info* info) {
   if (!rec || !lig) return api_fail(MD_EINVAL, "md_ligand_autotune: null handle");
+  if (lig->holds.load() > 0) return api_fail(MD_EBUSY, "md_ligand_autotune: a server request still uses the ligand");
   if (flags & ~MD_TUNE_FORCE) return api_fail(MD_EINVAL, "md_ligand_autotune: unknown flags");
   if (n_starts < 0 || n_starts > (1 << 20)) return api_fail(MD_ERANGE, "md_ligand_autotune: n_starts in [0, 2^20]");
   md_tune_info out{};
@@ -373,8 +366,11 @@ md_status md_batch_autotune(const md_receptor* rec, int n, md_ligand* const* lig
                             md_batch_tune_info* info) {
   if (!rec || n < 1 || !ligands || !params) return api_fail(MD_EINVAL, "md_batch_autotune: null argument");
   if (generations < 2 || generations > 1000) return api_fail(MD_ERANGE, "md_batch_autotune: generations in [2, 1000]");
-  for (int k = 0; k < n; ++k)
+  for (int k = 0; k < n; ++k) {
     if (!ligands[k]) return api_fail(MD_EINVAL, "md_batch_autotune: null ligand");
+    if (ligands[k]->holds.load() > 0)
+      return api_fail(MD_EBUSY, "md_batch_autotune: a server request still uses ligand " + std::to_string(k));
+  }
   // scratch results and shortened searches: each policy is timed at g1 and at g2 generations and
   // charged (t2 - t1) / (g2 - g1) per generation, which leaves out the per-call costs
   // (workspace, schedule, graph capture, initial population)

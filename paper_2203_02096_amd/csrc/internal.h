@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <functional>
 #include <string>
@@ -116,6 +117,7 @@ struct JobDev {
   int* best_row;              // [runs] outputs once done
   float* best_energy;         // [runs]
   float* best_genes;          // [runs][G]
+  float* best_xyz;            // [runs][n_atoms][3] posed atoms of best_genes, or NULL
   int gen;                    // next generation (1-based)
   int cur;                    // index of the current population buffer
   int planned;                // generations to run
@@ -182,9 +184,11 @@ void plan_ligand(LigHost& h, const PlanParams& pp);
 hipError_t launch_eval(const LigDev& L, const RecDev& R, int n, const float* genes, float* energy,
                        float* grad, hipStream_t s);
 hipError_t launch_pose(const LigDev& L, int n, const float* genes, float* xyz, hipStream_t s);
+// trace: NULL or [n][iters] energies; trace_x, trace_g: NULL or [n][iters][n_genes] iterates
+// and gradients of every step
 hipError_t launch_local_search(const LigDev& L, const RecDev& R, int n, const float* genes_in,
                                float* genes_out, float* energy_out, int iters, float rho, float eps,
-                               float* trace, hipStream_t s);
+                               float* trace, float* trace_x, float* trace_g, hipStream_t s);
 hipError_t launch_solis_wets(const LigDev& L, const RecDev& R, int n, const float* genes_in, float* genes_out,
                              float* energy_out, int n_evals, unsigned long long seed, float* trace, hipStream_t s);
 // GA phases over a job table.  blocks: [n_blocks] (job, first wave of the block within the
@@ -200,6 +204,8 @@ hipError_t launch_ga_local_search(JobDev* jobs, const int2* blocks, int n_blocks
 // Lets every evaluation kernel take up to kMaxLdsPerBlock of dynamic LDS (once per device).
 hipError_t enable_large_lds();
 hipError_t launch_ga_advance(JobDev* jobs, int n_jobs, hipStream_t s);
+// an empty one-wave kernel: the single sink of a captured phase
+hipError_t launch_join(hipStream_t s);
 // the epilogue for the jobs list[k].x, k < n
 hipError_t launch_ga_advance_list(JobDev* jobs, const int2* list, int n, hipStream_t s);
 
@@ -253,7 +259,7 @@ class GenGraph {
   hipError_t make_streams();
   // fork the classes over `main` and the side streams, each class's chain `reps` times; join
   hipError_t fork_classes(const GenSchedule& g, JobDev* table, const int2* d_blocks, const RecDev& R,
-                          hipStream_t main);
+                          hipStream_t main, bool sink);
   hipGraphExec_t exec_ = nullptr;
   // the capture stream, the side streams of the parallel branches and their fork/join events,
   // created on the first capture and kept until the object is destroyed (after the last
@@ -279,11 +285,12 @@ struct md_ligand {
   void* d_buf = nullptr;
   mdock::LigHost host;
   int device = 0;
+  // server requests that may still read the ligand's device buffer (queued or resident); while
+  // any does, the ligand is neither destroyed nor re-planned
+  mutable std::atomic<int> holds{0};
 };
 
 namespace mdock {
 // Uploads a prepared ligand (api.cpp): one device allocation, *L gets views into it.
 hipError_t upload_ligand(const LigHost& h, void** d_buf, LigDev* L);
-// Autotuner table (autotune.cpp): the tuned plan of this ligand's size class, if any.
-bool tuned_plan_for(const LigHost& h, PlanParams* out);
 }  // namespace mdock

@@ -954,17 +954,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_eval(LigDev L, RecDev R, int n, c
   if (lane == 0 && ps.w == 0) energy[pose] = E;
 }
 
+// Posed coordinates of this lane's atom slots for the genotype held one gene per lane (xg):
+// torsions from the deepest to the root-most about their reference-frame axes (Rodrigues), then
+// the unit quaternion's rotation and the translation.  Every lane of the wave must take part.
 template <int A>
-__global__ __launch_bounds__(kBlock) void k_pose(LigDev L, int n, const float* __restrict__ genes,
-                                                 float* __restrict__ xyz) {
-  const int pose = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-  if (pose >= n) return;
-  AtomRegs<A> at;
-  load_ligand<A>(L, at);
+__device__ __forceinline__ void pose_atoms(const AtomRegs<A>& at, int T, float xg, float (&x)[A], float (&y)[A],
+                                           float (&z)[A]) {
   const int lane = lane_id();
-  const int G = L.n_genes;
-  const int T = L.n_tors;
-  const float xg = lane < G ? genes[(long long)pose * G + lane] : 0.f;
   float qw = readlane(xg, 3), qx = readlane(xg, 4), qy = readlane(xg, 5), qz = readlane(xg, 6);
   const float iqn = 1.f / __builtin_sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
   qw *= iqn; qx *= iqn; qy *= iqn; qz *= iqn;
@@ -1001,12 +997,39 @@ __global__ __launch_bounds__(kBlock) void k_pose(LigDev L, int n, const float* _
   const float r20 = 2.f * (qx * qz - qw * qy), r21 = 2.f * (qy * qz + qw * qx), r22 = 1.f - 2.f * (qx * qx + qy * qy);
 #pragma unroll
   for (int a = 0; a < A; ++a) {
-    if (!at.valid[a]) continue;
-    const long long o = ((long long)pose * L.n_atoms + lane + kWave * a) * 3;
-    xyz[o + 0] = r00 * px[a] + r01 * py[a] + r02 * pz[a] + tx;
-    xyz[o + 1] = r10 * px[a] + r11 * py[a] + r12 * pz[a] + ty;
-    xyz[o + 2] = r20 * px[a] + r21 * py[a] + r22 * pz[a] + tz;
+    x[a] = r00 * px[a] + r01 * py[a] + r02 * pz[a] + tx;
+    y[a] = r10 * px[a] + r11 * py[a] + r12 * pz[a] + ty;
+    z[a] = r20 * px[a] + r21 * py[a] + r22 * pz[a] + tz;
   }
+}
+
+// Writes the posed atoms of one genotype to xyz[n_atoms][3].
+template <int A>
+__device__ __forceinline__ void store_pose(const LigDev& L, const AtomRegs<A>& at, float xg, float* __restrict__ xyz) {
+  float x[A], y[A], z[A];
+  pose_atoms<A>(at, L.n_tors, xg, x, y, z);
+#pragma unroll
+  for (int a = 0; a < A; ++a) {
+    if (!at.valid[a]) continue;
+    const long long o = (long long)(lane_id() + kWave * a) * 3;
+    xyz[o + 0] = x[a];
+    xyz[o + 1] = y[a];
+    xyz[o + 2] = z[a];
+  }
+}
+
+// Two atom slots per lane for every ligand size: the same code as the generation epilogue's
+// best poses, so both give bitwise the same coordinates for the same genes.
+__global__ __launch_bounds__(kBlock) void k_pose(LigDev L, int n, const float* __restrict__ genes,
+                                                 float* __restrict__ xyz) {
+  const int pose = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  if (pose >= n) return;
+  AtomRegs<2> at;
+  load_ligand<2>(L, at);
+  const int lane = lane_id();
+  const int G = L.n_genes;
+  const float xg = lane < G ? genes[(long long)pose * G + lane] : 0.f;
+  store_pose<2>(L, at, xg, xyz + (long long)pose * L.n_atoms * 3);
 }
 
 // A moved genotype back on its domain: the quaternion (lanes 3..6) renormalised, the torsions
@@ -1037,12 +1060,13 @@ __device__ __forceinline__ float adadelta_update(float x, float g, float& eg2, f
 }
 
 // ADADELTA from genes_in[row_in] for `iters` steps; the best genotype goes to genes_out[row_out]
-// and its energy is returned (wave-uniform).  trace: NULL or [iters] energies of every step.
+// and its energy is returned (wave-uniform).  trace: NULL or [iters] energies of every step;
+// trace_x / trace_g: NULL or [iters][G] iterates and gradients of every step.
 template <int A, int PREC, int W>
 __device__ float local_search_wave(const LigDev& L, const RecDev& R, const BlockLds& b, const AtomRegs<A>& at,
                                    const float* genes_in, long long row_in, float* genes_out,
                                    long long row_out, int iters, float rho, float eps, float* trace,
-                                   PoseShare& ps) {
+                                   PoseShare& ps, float* trace_x = nullptr, float* trace_g = nullptr) {
   const int lane = lane_id();
   const int G = L.n_genes;
   float x = lane < G ? genes_in[row_in * G + lane] : 0.f;
@@ -1053,6 +1077,8 @@ __device__ float local_search_wave(const LigDev& L, const RecDev& R, const Block
     float g = 0.f;
     const float E = eval_pose<A, PREC, true, W>(L, R, b, at, x, g, ps);
     if (trace && lane == 0 && ps.w == 0) trace[it] = E;
+    if (trace_x && lane < G && ps.w == 0) trace_x[(long long)it * G + lane] = x;
+    if (trace_g && lane < G && ps.w == 0) trace_g[(long long)it * G + lane] = g;
     if (E < best_e) {
       best_e = E;
       best_x = x;
@@ -1069,15 +1095,18 @@ __global__ __launch_bounds__(kMaxBlock) MDOCK_SEARCH_OCCUPANCY void k_local_sear
                                                          const float* genes_in, float* genes_out,
                                                          float* __restrict__ energy_out,
                                                          int iters, float rho, float eps,
-                                                         float* __restrict__ trace) {
+                                                         float* __restrict__ trace, float* __restrict__ trace_x,
+                                                         float* __restrict__ trace_g) {
   const BlockLds b = stage_block<A>(L);
   PoseShare ps;
   const int job = block_pose<W>(ps);
   if (job >= n) return;
   AtomRegs<A> at;
   load_ligand<A>(L, at);
+  const long long tg = (long long)job * iters * L.n_genes;
   const float E = local_search_wave<A, PREC, W>(L, R, b, at, genes_in, job, genes_out, job, iters, rho, eps,
-                                                trace ? trace + (long long)job * iters : nullptr, ps);
+                                                trace ? trace + (long long)job * iters : nullptr, ps,
+                                                trace_x ? trace_x + tg : nullptr, trace_g ? trace_g + tg : nullptr);
   if (lane_id() == 0 && ps.w == 0) energy_out[job] = E;
 }
 
@@ -1492,14 +1521,22 @@ __global__ __launch_bounds__(kBlock) void k_ga_advance(JobDev* __restrict__ jobs
   if (done) {
     const float* genes = J.genes[cur];
     const float* energy = J.energy[cur];
+    const int G = P.n_genes;
+    // the best pose's coordinates come from the genes this wave has just picked, in the same
+    // pass, so a returned pose always belongs to the returned genotype
+    float* bx = J.best_xyz;
+    AtomRegs<2> at;
+    if (bx) load_ligand<2>(J.L, at);
     for (int run = 0; run < P.n_runs; ++run) {
       const long long base = (long long)run * P.pop_size;
       const int bi = wave_argmin(energy + base, P.pop_size);
-      if (lane < P.n_genes) J.best_genes[run * P.n_genes + lane] = genes[(base + bi) * P.n_genes + lane];
+      const float xg = lane < G ? genes[(base + bi) * G + lane] : 0.f;
+      if (lane < G) J.best_genes[run * G + lane] = xg;
       if (lane == 0) {
         J.best_row[run] = (int)(base + bi);
         J.best_energy[run] = energy[base + bi];
       }
+      if (bx) store_pose<2>(J.L, at, xg, bx + (long long)run * J.L.n_atoms * 3);
     }
   }
   if (lane == 0) {
@@ -1508,6 +1545,11 @@ __global__ __launch_bounds__(kBlock) void k_ga_advance(JobDev* __restrict__ jobs
     J.state = done ? kJobDone : kJobRunning;
   }
 }
+
+// The last node of a captured phase: it follows the join of every size-class branch, so the
+// executable graph has this single sink and work queued after the graph's launch on a stream
+// is ordered after every branch.
+__global__ void k_join() {}
 
 inline unsigned blocks_for(long long waves, int wpb = kWavesPerBlock) {
   return (unsigned)((waves + wpb - 1) / wpb);
@@ -1589,21 +1631,18 @@ hipError_t launch_eval(const LigDev& L, const RecDev& R, int n, const float* gen
 
 hipError_t launch_pose(const LigDev& L, int n, const float* genes, float* xyz, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  if (L.n_atoms > kWave)
-    hipLaunchKernelGGL((k_pose<2>), dim3(blocks_for(n)), dim3(kBlock), 0, s, L, n, genes, xyz);
-  else
-    hipLaunchKernelGGL((k_pose<1>), dim3(blocks_for(n)), dim3(kBlock), 0, s, L, n, genes, xyz);
+  hipLaunchKernelGGL(k_pose, dim3(blocks_for(n)), dim3(kBlock), 0, s, L, n, genes, xyz);
   return hipGetLastError();
 }
 
 hipError_t launch_local_search(const LigDev& L, const RecDev& R, int n, const float* genes_in,
                                float* genes_out, float* energy_out, int iters, float rho, float eps,
-                               float* trace, hipStream_t s) {
+                               float* trace, float* trace_x, float* trace_g, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int A = L.n_atoms > kWave ? 2 : 1;
   MDOCK_DISPATCH_W(k_local_search, A, R.precision, L.wpp, dim3(blocks_for(n, poses_per_block(L))),
                    dim3(kWave * L.wpb), (size_t)L.lds_bytes, s, L, R, n, genes_in, genes_out, energy_out, iters,
-                   rho, eps, trace);
+                   rho, eps, trace, trace_x, trace_g);
   return hipGetLastError();
 }
 
@@ -1648,6 +1687,11 @@ hipError_t launch_ga_local_search(JobDev* jobs, const int2* blocks, int n_blocks
   else
     MDOCK_DISPATCH_W(k_ga_local_search, A, R.precision, wpp, dim3(n_blocks), dim3(kWave * wpb), (size_t)lds, s,
                      jobs, blocks, R);
+  return hipGetLastError();
+}
+
+hipError_t launch_join(hipStream_t s) {
+  hipLaunchKernelGGL(k_join, dim3(1), dim3(kWave), 0, s);
   return hipGetLastError();
 }
 

@@ -189,9 +189,12 @@ GenGraph::~GenGraph() {
 }
 
 hipError_t GenGraph::fork_classes(const GenSchedule& g, JobDev* table, const int2* d_blocks, const RecDev& R,
-                                  hipStream_t main) {
+                                  hipStream_t main, bool sink) {
   // class i runs on stream i mod width (0 = main); every side stream in use waits for the fork
-  // and joins back into main at the end
+  // and joins back into main at the end.  With `sink` (capture) an empty kernel on main after
+  // the join becomes the graph's only sink: without it each branch's last node is a sink of
+  // its own, and nothing but the runtime's handling of several sinks would order work queued
+  // after the graph's launch behind the side branches.
   const size_t width = std::max<size_t>(1, std::min(g.classes.size(), kGraphBranches));
   hipError_t e = hipEventRecord(ev_[0], main);
   for (size_t k = 0; k + 1 < width && e == hipSuccess; ++k) e = hipStreamWaitEvent(side_[k], ev_[0], 0);
@@ -202,6 +205,7 @@ hipError_t GenGraph::fork_classes(const GenSchedule& g, JobDev* table, const int
   }
   for (size_t k = 0; k + 1 < width && e == hipSuccess; ++k) e = hipEventRecord(ev_[1 + k], side_[k]);
   for (size_t k = 0; k + 1 < width && e == hipSuccess; ++k) e = hipStreamWaitEvent(main, ev_[1 + k], 0);
+  if (e == hipSuccess && sink) e = launch_join(main);
   return e;
 }
 
@@ -211,7 +215,7 @@ hipError_t GenGraph::capture(const GenSchedule& g, JobDev* table, const int2* d_
   if (e != hipSuccess) return e;
   e = hipStreamBeginCapture(cs_, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return e;
-  const hipError_t el = fork_classes(g, table, d_blocks, R, cs_);
+  const hipError_t el = fork_classes(g, table, d_blocks, R, cs_, true);
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(cs_, &graph);
   if (e == hipSuccess) e = el;
@@ -227,7 +231,7 @@ hipError_t GenGraph::capture(const GenSchedule& g, JobDev* table, const int2* d_
 hipError_t GenGraph::launch_direct(const GenSchedule& g, JobDev* table, const int2* d_blocks, const RecDev& R,
                                    hipStream_t s) {
   const hipError_t e = make_streams();
-  return e == hipSuccess ? fork_classes(g, table, d_blocks, R, s) : e;
+  return e == hipSuccess ? fork_classes(g, table, d_blocks, R, s, false) : e;
 }
 
 hipError_t GenGraph::launch(hipStream_t s) const {

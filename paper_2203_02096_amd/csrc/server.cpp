@@ -94,9 +94,14 @@ enum ReqState { kQueued, kResident, kFinished, kCanceled, kFailed };
 
 struct Request {
   unsigned long long ticket = 0;
+  // the ligand, read only while the request holds it (queued or resident: see drop_hold); the
+  // result shape is kept apart so finished requests never touch the ligand again
   const md_ligand* lig = nullptr;
+  bool held = false;
+  int n_genes = 0, n_atoms = 0;
   md_dock_params params{};
   ReqState state = kQueued;
+  bool cancel_requested = false;   // resident: leaves its slot after the current tick
   int slot = -1;
   size_t off = 0, bytes = 0;
   // offsets inside the request's pool block
@@ -144,6 +149,15 @@ struct md_server {
 };
 
 namespace {
+
+// The request no longer reads its ligand (it left the queue or its slot): release the hold
+// taken at submit.  Caller holds the server lock.
+void drop_hold(Request& r) {
+  if (r.held) {
+    r.lig->holds.fetch_sub(1);
+    r.held = false;
+  }
+}
 
 void layout(Request& r) {
   const LigDev& L = r.lig->dev;
@@ -201,6 +215,7 @@ JobDev make_job(md_server* s, const Request& r) {
   J.best_row = reinterpret_cast<int*>(w + r.o_br);
   J.best_energy = reinterpret_cast<float*>(w + r.o_be);
   J.best_genes = reinterpret_cast<float*>(w + r.o_bg);
+  J.best_xyz = reinterpret_cast<float*>(w + r.o_bx);
   J.gen = 0;
   J.cur = 0;
   J.planned = r.planned;
@@ -264,10 +279,10 @@ hipError_t collect(md_server* s, Request& r) {
   const LigDev& L = r.lig->dev;
   const int runs = r.params.n_runs, G = L.n_genes, N = L.n_atoms;
   char* w = s->pool_base + r.off;
-  hipError_t e = launch_pose(L, runs, reinterpret_cast<float*>(w + r.o_bg), reinterpret_cast<float*>(w + r.o_bx), s->stream);
+  // the generation epilogue that finished the request wrote its best genes, energies and poses
   std::vector<float> be(runs), bg((size_t)runs * G), bx((size_t)runs * N * 3);
   std::vector<long long> er(runs);
-  if (e == hipSuccess) e = hipMemcpyAsync(be.data(), w + r.o_be, runs * 4, hipMemcpyDeviceToHost, s->stream);
+  hipError_t e = hipMemcpyAsync(be.data(), w + r.o_be, runs * 4, hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(bg.data(), w + r.o_bg, bg.size() * 4, hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(bx.data(), w + r.o_bx, bx.size() * 4, hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(er.data(), w + r.o_er, runs * 8, hipMemcpyDeviceToHost, s->stream);
@@ -352,10 +367,12 @@ void worker_loop(md_server* s) {
         if (r) {
           r->state = kFailed;
           r->error = s->fatal;
+          drop_hold(*r);
         }
       for (auto& r : s->queue) {
         r->state = kFailed;
         r->error = s->fatal;
+        drop_hold(*r);
       }
       s->queue.clear();
       std::fill(s->slots.begin(), s->slots.end(), nullptr);
@@ -364,34 +381,39 @@ void worker_loop(md_server* s) {
     }
     for (auto& r : finished) {
       r->t_end = t1;
-      if (r->state == kResident) {
-        r->state = kFinished;
-        ++s->completed;
-      }
+      r->state = kFinished;   // a cancel that came during the last tick is too late
+      ++s->completed;
+      drop_hold(*r);
       s->pool->release(r->off, r->bytes);
       s->slots[r->slot] = nullptr;
       s->resident_changed = true;
       s->h_table[r->slot].state = kJobEmpty;
     }
-    // requests canceled while resident: drop them from their slots (device entry marked empty)
+    // requests canceled while resident: drop them from their slots (device entry marked empty;
+    // the stream is idle after the tick) and only then report them canceled
+    bool dropped = false;
     for (int j = 0; j < (int)s->slots.size(); ++j) {
       auto& r = s->slots[j];
-      if (r && r->state == kCanceled) {
+      if (r && r->cancel_requested) {
         JobDev empty{};
         empty.state = kJobEmpty;
         s->h_table[j] = empty;
         (void)hipMemcpy(s->d_table + j, &empty, sizeof(JobDev), hipMemcpyHostToDevice);
         s->pool->release(r->off, r->bytes);
+        r->state = kCanceled;
+        r->t_end = t1;
+        drop_hold(*r);
         r = nullptr;
         s->resident_changed = true;
+        dropped = true;
       }
     }
-    if (!finished.empty()) s->cv_done.notify_all();
+    if (!finished.empty() || dropped) s->cv_done.notify_all();
   }
 }
 
 md_status fill_result(const Request& r, md_dock_result* out) {
-  const int runs = r.params.n_runs, G = r.lig->dev.n_genes, N = r.lig->dev.n_atoms;
+  const int runs = r.params.n_runs, G = r.n_genes, N = r.n_atoms;
   if (out->n_runs < runs || out->n_genes < G || !out->best_energy || !out->best_genes)
     return server_fail(MD_EINVAL, "md_server: result buffers too small or null");
   if (out->best_xyz && out->n_atoms < N) return server_fail(MD_EINVAL, "md_server: best_xyz capacity too small");
@@ -453,6 +475,8 @@ md_status md_server_submit(md_server* s, const md_ligand* lig, const md_dock_par
   if (!err.empty()) return server_fail(MD_EINVAL, "md_server_submit: " + err);
   auto r = std::make_shared<Request>();
   r->lig = lig;
+  r->n_genes = lig->dev.n_genes;
+  r->n_atoms = lig->dev.n_atoms;
   r->params = *p;
   r->planned = md_dock_planned_generations(p);
   layout(*r);
@@ -462,6 +486,8 @@ md_status md_server_submit(md_server* s, const md_ligand* lig, const md_dock_par
   if (!s->fatal.empty()) return server_fail(MD_EDEVICE, s->fatal);
   r->ticket = s->next_ticket++;
   r->t_submit = now_s();
+  lig->holds.fetch_add(1);
+  r->held = true;
   s->requests[r->ticket] = r;
   s->queue.push_back(r);
   *ticket = r->ticket;
@@ -508,8 +534,10 @@ md_status md_server_cancel(md_server* s, unsigned long long ticket) {
   if (r->state == kQueued) {
     s->queue.erase(std::remove(s->queue.begin(), s->queue.end(), r), s->queue.end());
     r->state = kCanceled;
+    drop_hold(*r);
   } else if (r->state == kResident) {
-    r->state = kCanceled;   // the worker frees the slot after the current tick
+    r->cancel_requested = true;   // the worker frees the slot after the current tick
+    s->cv_work.notify_one();
   }
   s->cv_done.notify_all();
   return MD_OK;
@@ -533,7 +561,8 @@ md_status md_server_release(md_server* s, unsigned long long ticket) {
   auto it = s->requests.find(ticket);
   if (it == s->requests.end()) return server_fail(MD_ENOTFOUND, "md_server_release: unknown ticket");
   const ReqState st = it->second->state;
-  if (st == kQueued || st == kResident) return server_fail(MD_EBUSY, "md_server_release: request still running");
+  if (st == kQueued || st == kResident || it->second->held)
+    return server_fail(MD_EBUSY, "md_server_release: request still queued or on the device");
   s->requests.erase(it);
   return MD_OK;
 }
@@ -557,7 +586,10 @@ md_status md_server_destroy(md_server* s) {
   {
     std::lock_guard<std::mutex> lk(s->mu);
     s->stop = true;
-    for (auto& r : s->queue) r->state = kCanceled;   // queued work is dropped, resident work drains
+    for (auto& r : s->queue) {   // queued work is dropped, resident work drains
+      r->state = kCanceled;
+      drop_hold(*r);
+    }
     s->queue.clear();
     s->cv_work.notify_all();
   }

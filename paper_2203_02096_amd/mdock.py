@@ -104,6 +104,9 @@ SIGNATURES = {
                                   C.c_int, C.c_float, C.c_float, C.c_void_p, C.c_void_p]),
     "md_local_search_sw": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_int, C.c_ulonglong, C.c_void_p, C.c_void_p]),
+    "md_local_search_traced": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_int, C.c_float, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p]),
     "md_dock": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(DockParams), C.POINTER(DockResult), C.c_void_p]),
     "md_dock_batch": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(DockJob), C.c_void_p]),
     "md_dock_planned_generations": (C.c_int, [C.POINTER(DockParams)]),
@@ -282,6 +285,23 @@ def md_local_search(rec: Receptor, lig: Ligand, genes_in, genes_out, energy_out,
                                  _dev_ptr(energy_out, "energy_out", (n,), torch.float32),
                                  int(n_iters), float(rho), float(eps), tp, _stream_ptr(stream)),
            "md_local_search")
+
+
+def md_local_search_traced(rec: Receptor, lig: Ligand, genes_in, genes_out, energy_out, n_iters=300,
+                           rho=0.8, eps=1e-2, trace=None, trace_genes=None, trace_grad=None, stream=None):
+    """md_local_search that also records each step's iterate and gradient ([n][n_iters][n_genes])."""
+    import torch
+    n = genes_in.shape[0]
+    G = lig.n_genes
+    tp = _dev_ptr(trace, "trace", (n, n_iters), torch.float32) if trace is not None else None
+    tx = _dev_ptr(trace_genes, "trace_genes", (n, n_iters, G), torch.float32) if trace_genes is not None else None
+    tg = _dev_ptr(trace_grad, "trace_grad", (n, n_iters, G), torch.float32) if trace_grad is not None else None
+    _check(lib().md_local_search_traced(rec.handle, lig.handle, n,
+                                        _dev_ptr(genes_in, "genes_in", (n, G), torch.float32),
+                                        _dev_ptr(genes_out, "genes_out", (n, G), torch.float32),
+                                        _dev_ptr(energy_out, "energy_out", (n,), torch.float32),
+                                        int(n_iters), float(rho), float(eps), tp, tx, tg, _stream_ptr(stream)),
+           "md_local_search_traced")
 
 
 def md_local_search_sw(rec: Receptor, lig: Ligand, genes_in, genes_out, energy_out, n_evals=300,

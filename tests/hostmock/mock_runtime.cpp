@@ -226,7 +226,8 @@ hipError_t launch_pose(const LigDev& L, int n, const float* genes, float* xyz, h
 }
 
 hipError_t launch_local_search(const LigDev& L, const RecDev&, int n, const float* genes_in, float* genes_out,
-                               float* energy_out, int iters, float, float, float* trace, hipStream_t s) {
+                               float* energy_out, int iters, float, float, float* trace, float*, float*,
+                               hipStream_t s) {
   if (n < 0 || iters < 1) return hipErrorInvalidValue;
   const int G = L.n_genes;
   run_or_record(s, [=] {
@@ -242,7 +243,7 @@ hipError_t launch_local_search(const LigDev& L, const RecDev&, int n, const floa
 
 hipError_t launch_solis_wets(const LigDev& L, const RecDev& R, int n, const float* genes_in, float* genes_out,
                              float* energy_out, int n_evals, unsigned long long, float* trace, hipStream_t s) {
-  return launch_local_search(L, R, n, genes_in, genes_out, energy_out, n_evals, 0.f, 0.f, trace, s);
+  return launch_local_search(L, R, n, genes_in, genes_out, energy_out, n_evals, 0.f, 0.f, trace, nullptr, nullptr, s);
 }
 
 hipError_t launch_ga_init(JobDev* jobs, const int2* blocks, int n_blocks, int, int wpb, int, const RecDev&,
@@ -343,6 +344,12 @@ void advance_one(JobDev& J) {
       for (long long i = base; i < base + J.P.pop_size; ++i)
         if (J.energy[cur][i] < J.energy[cur][bi]) bi = i;
       for (int g = 0; g < G; ++g) J.best_genes[run * G + g] = J.genes[cur][bi * G + g];
+      if (J.best_xyz) {
+        const int N = J.L.n_atoms;
+        for (int a = 0; a < N; ++a)
+          for (int c = 0; c < 3; ++c)
+            J.best_xyz[((size_t)run * N + a) * 3 + c] = J.best_genes[run * G + (a + c) % G] + (float)a;
+      }
       J.best_row[run] = (int)bi;
       J.best_energy[run] = J.energy[cur][bi];
     }
@@ -353,6 +360,11 @@ void advance_one(JobDev& J) {
 }
 
 }  // namespace
+
+hipError_t launch_join(hipStream_t s) {
+  run_or_record(s, [] {});
+  return hipSuccess;
+}
 
 hipError_t launch_ga_advance(JobDev* jobs, int n_jobs, hipStream_t s) {
   if (!jobs || n_jobs < 0) return hipErrorInvalidValue;

@@ -267,6 +267,40 @@ int main(int argc, char** argv) {
       CHECK(md_server_destroy(srv) == MD_OK, "destroy with work pending");
     }
   }
+  // a queued or resident request holds its ligand: the ligand can be neither destroyed nor
+  // re-planned and the request not released until it has left the device; a canceled resident
+  // request is reported canceled only once its slot is free, and then everything goes
+  {
+    md_server_params sp{};
+    sp.hbm_budget_bytes = 1u << 20;
+    sp.max_slots = 1;
+    sp.use_graphs = 1;
+    md_server* srv = nullptr;
+    CHECK(md_server_create(g_rec, &sp, &srv) == MD_OK, "create");
+    Lig own = make_ligand(30);
+    std::mt19937 rng(11);
+    md_dock_params p = params_for(rng, false);
+    p.max_generations = 1 << 20;
+    unsigned long long t1 = 0, t2 = 0;
+    CHECK(md_server_submit(srv, own.h, &p, &t1) == MD_OK, "submit long");
+    CHECK(md_server_submit(srv, own.h, &p, &t2) == MD_OK, "submit queued");
+    CHECK(md_ligand_destroy(own.h) == MD_EBUSY, "destroy of a held ligand refused");
+    md_plan plan{65536, 3, 4, 0, 0, 0, 1};
+    CHECK(md_ligand_set_plan(own.h, &plan) == MD_EBUSY, "re-plan of a held ligand refused");
+    CHECK(md_server_release(srv, t1) == MD_EBUSY, "release of a running request refused");
+    md_server_stats st{};
+    for (int k = 0; k < 100000 && st.resident == 0; ++k) {   // wait until t1 is on the device
+      CHECK(md_server_get_stats(srv, &st) == MD_OK, "stats");
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+    CHECK(md_server_cancel(srv, t2) == MD_OK && md_server_release(srv, t2) == MD_OK, "queued cancel frees at once");
+    CHECK(md_server_cancel(srv, t1) == MD_OK, "cancel resident");
+    CHECK(md_server_wait(srv, t1, nullptr, 30.0) == MD_ECANCELED, "wait sees the cancel");
+    CHECK(md_server_get_stats(srv, &st) == MD_OK && st.resident == 0 && st.pool_used_bytes == 0, "slot freed");
+    CHECK(md_server_release(srv, t1) == MD_OK, "release after the slot is free");
+    CHECK(md_ligand_destroy(own.h) == MD_OK, "destroy once no request holds the ligand");
+    md_server_destroy(srv);
+  }
   // a request larger than the pool is refused at submit
   {
     md_server_params sp{};

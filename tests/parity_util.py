@@ -118,3 +118,72 @@ def check_sw_start(grid, ol, start, g_out, e_out, tr_gpu, n_evals, seed, k):
 # off, and the test that was running at the second crash stays off the GPU until a cause is shown.
 SERVER_OFF_REASON = ("md_server's worker thread crashed the host process (SIGSEGV in that thread) while "
                      "this test ran, with graph capture in the worker; cause not known, held back")
+
+
+def assert_xyz_is_pose(md, dlig, res):
+    """A dock result's best_xyz must be the library's own pose (md_pose) of its best_genes, bit
+    for bit: both come from one posing routine, and a mismatch means the coordinates were taken
+    from other genes than the ones returned."""
+    import torch
+    genes = torch.from_numpy(np.ascontiguousarray(res["best_genes"], np.float32)).cuda()
+    xyz = torch.empty(genes.shape[0], dlig.n_atoms, 3, device="cuda")
+    md.md_pose(dlig, genes, xyz)
+    torch.cuda.synchronize()
+    want = xyz.cpu().numpy()
+    bad = np.argwhere(np.any(res["best_xyz"] != want, axis=(1, 2))).ravel()
+    assert bad.size == 0, ("best_xyz is not the pose of best_genes in runs", bad.tolist())
+
+
+# Clean poses.  Random genotypes (workload.synth.random_genes) mostly put atoms outside the grid
+# or fold torsions into clashes, and a clash or out-of-grid term can be 1e2-1e5 times the sum of
+# all in-grid atom terms, so the tolerance above (relative to the sum of |terms|) would then not
+# see an error of the whole grid term.  A clean pose has (a) every atom at least one grid spacing
+# inside every face of the box, (b) torsion angles within CLEAN_TWIST of the reference
+# conformation (which the ligand generator builds with every non-bonded distance >= 2 A) and
+# (c) an energy tolerance at most CLEAN_POWER times the sum of |in-grid atom terms|, so that an
+# error of that size in the grid term fails the comparison.  (A floor on pair distances such as
+# 0.8 R_ij cannot be met: the 1-4 pairs of these ligands sit at 0.53-0.62 R_ij already in the
+# reference conformation.)
+CLEAN_TWIST = 0.3
+CLEAN_POWER = 1e-2
+
+
+def clean_genes(lig, rec, n, seed, olig=None, grid=None, max_tries=None):
+    """n clean genotypes [n][7+T] float32 for ligand `lig` (workload.synth.Ligand) in receptor
+    `rec`; orientation uniform, translation uniform over the placements that keep the ligand's
+    box inside the grid, torsions uniform within CLEAN_TWIST.  Returns (genes, tries)."""
+    from oracle import pose as OP
+    olig = olig or oracle_ligand(lig)
+    grid = grid or oracle_grid(rec)
+    rng = np.random.default_rng([seed, 0xC1EA])
+    lo = np.asarray(rec.origin, np.float64)
+    hi = lo + (np.asarray(rec.shape_xyz, np.float64) - 1) * rec.spacing
+    T = lig.n_torsions
+    out, tries = [], 0
+    max_tries = max_tries or 50 * n
+    while len(out) < n:
+        tries += 1
+        assert tries <= max_tries, f"clean poses: {len(out)} of {n} after {tries} draws"
+        q = rng.normal(size=4)
+        q /= np.linalg.norm(q)
+        g = np.concatenate([[0.0, 0.0, 0.0], q, rng.uniform(-CLEAN_TWIST, CLEAN_TWIST, T)])
+        x = OP.pose(olig, g)
+        tlo = lo + rec.spacing - x.min(axis=0)
+        thi = hi - rec.spacing - x.max(axis=0)
+        if np.any(tlo >= thi):
+            continue
+        g[0:3] = rng.uniform(tlo, thi)
+        g = g.astype(np.float32).astype(np.float64)   # the GPU gets these float32 genes
+        r = S.energy_and_gradient(grid, olig, g)
+        e_atoms, _, _ = S.grid_energies(grid, r.x, olig.types, olig.charges)
+        if E_TOL * max(abs(r.energy), r.scale_energy) > CLEAN_POWER * float(np.sum(np.abs(e_atoms))):
+            continue
+        out.append(g)
+    return np.asarray(out, np.float32).reshape(n, lig.n_genes), tries
+
+
+def tolerance_over_grid_terms(grid, olig, r):
+    """The energy tolerance of an oracle result r over the sum of |in-grid atom terms| of its
+    pose: how large a grid-term error, relative to the grid term, the comparison would miss."""
+    e_atoms, _, _ = S.grid_energies(grid, r.x, olig.types, olig.charges)
+    return E_TOL * max(abs(r.energy), r.scale_energy) / max(float(np.sum(np.abs(e_atoms))), 1e-300)

@@ -6,7 +6,8 @@ import sys
 import numpy as np
 import pytest
 
-from parity_util import compare, oracle_eval_many, oracle_grid, oracle_ligand
+from parity_util import (assert_xyz_is_pose, clean_genes, compare, oracle_eval_many, oracle_grid, oracle_ligand,
+                         tolerance_over_grid_terms)
 from workload import configs, synth
 
 pytestmark = pytest.mark.gpu
@@ -48,32 +49,65 @@ EVAL_CASES = [
     ("edge_64a_12t", 64, 102, 64, 12, 305, 41),
     ("edge_65a_12t", 64, 102, 65, 12, 306, 41),
     ("rigid_30a_0t", 40, 101, 30, 0, 307, 101),
+    ("rigid_100a_0t", 64, 102, 100, 0, 311, 41),
+    ("rigid_128a_0t", 64, 102, 128, 0, 312, 29),
     ("tiny_1a", 40, 101, 1, 0, 308, 67),
     ("tiny_2a", 40, 101, 2, 0, 309, 67),
     ("tiny_4a_1t", 40, 101, 4, 1, 310, 67),
 ]
 
 
-@pytest.mark.parametrize("case", EVAL_CASES, ids=[c[0] for c in EVAL_CASES])
-def test_eval_parity(md, case):
-    name, gn, ms, na, nt, ls, npose = case
-    _say(f"[eval parity] {name}: grid {gn}^3 atoms {na} torsions {nt} poses {npose}")
-    rec, drec = _receptor(md, gn, ms)
-    lig = synth.make_ligand(na, nt, ls, configs.type_params())
-    dlig = md.Ligand.from_synth(lig)
-    genes = synth.random_genes(lig, rec, npose, seed=ls, margin=2.0)
+def _eval_both(md, drec, dlig, genes):
+    """md_eval with and without the gradient; the energies must agree bitwise."""
+    n = genes.shape[0]
     g_dev = torch.from_numpy(genes).cuda()
-    e_dev = torch.empty(npose, device="cuda")
-    d_dev = torch.empty(npose, lig.n_genes, device="cuda")
+    e_dev = torch.empty(n, device="cuda")
+    d_dev = torch.empty(n, genes.shape[1], device="cuda")
     md.md_eval(drec, dlig, g_dev, e_dev, d_dev)
-    e_only = torch.empty(npose, device="cuda")
+    e_only = torch.empty(n, device="cuda")
     md.md_eval(drec, dlig, g_dev, e_only, None)
     torch.cuda.synchronize()
     E, D, E2 = e_dev.cpu().numpy(), d_dev.cpu().numpy(), e_only.cpu().numpy()
     assert np.array_equal(E, E2), "energy-only and energy+gradient paths must agree bitwise"
+    return E, D
+
+
+@pytest.mark.parametrize("case", EVAL_CASES, ids=[c[0] for c in EVAL_CASES])
+def test_eval_parity(md, case):
+    """Clean poses (every atom inside the grid, torsions near the clash-free reference, the
+    tolerance at most 1 % of the in-grid atom terms): every energy and gradient within the
+    tolerance rule, so an error of the grid term as a whole cannot pass."""
+    name, gn, ms, na, nt, ls, npose = case
+    _say(f"[eval parity clean] {name}: grid {gn}^3 atoms {na} torsions {nt} poses {npose}")
+    rec, drec = _receptor(md, gn, ms)
+    lig = synth.make_ligand(na, nt, ls, configs.type_params())
+    dlig = md.Ligand.from_synth(lig)
+    grid, ol = oracle_grid(rec), oracle_ligand(lig)
+    genes, tries = clean_genes(lig, rec, npose, seed=ls, olig=ol, grid=grid)
+    E, D = _eval_both(md, drec, dlig, genes)
+    ref = oracle_eval_many(grid, ol, genes)
+    stats = compare(ref, E, D)
+    power = [tolerance_over_grid_terms(grid, ol, r) for r in ref]
+    _say(f"[eval parity clean] {name}: {stats}; {npose} clean of {tries} draws; "
+         f"tolerance / sum|grid terms| median {np.median(power):.2e} max {np.max(power):.2e}")
+    assert stats["checked_energy"] >= 0.9 * npose and stats["checked"] >= 0.75 * npose
+
+
+@pytest.mark.parametrize("case", EVAL_CASES, ids=[c[0] for c in EVAL_CASES])
+def test_eval_parity_wild(md, case):
+    """Edge cases: random poses anywhere in the box shrunk by 2 A -- atoms outside the grid (the
+    out-of-grid penalty and its restoring gradient) and folded torsions (clashing pairs at the
+    0.5 A clamp).  Same tolerance rule; here the clash and penalty terms dominate the scale."""
+    name, gn, ms, na, nt, ls, npose = case
+    _say(f"[eval parity wild] {name}: grid {gn}^3 atoms {na} torsions {nt} poses {npose}")
+    rec, drec = _receptor(md, gn, ms)
+    lig = synth.make_ligand(na, nt, ls, configs.type_params())
+    dlig = md.Ligand.from_synth(lig)
+    genes = synth.random_genes(lig, rec, npose, seed=ls, margin=2.0)
+    E, D = _eval_both(md, drec, dlig, genes)
     ref = oracle_eval_many(oracle_grid(rec), oracle_ligand(lig), genes)
     stats = compare(ref, E, D)
-    _say(f"[eval parity] {name}: {stats}")
+    _say(f"[eval parity wild] {name}: {stats}")
     assert stats["checked_energy"] >= 0.9 * npose and stats["checked"] >= 0.75 * npose
 
 
@@ -254,7 +288,9 @@ def test_dock_batch_equals_alone(md):
                                                      seed=50 + k)) for k in range(len(ligs))]
     batch = md.md_dock_batch(drec, list(zip(dligs, params)))
     for k in range(len(ligs)):
+        assert_xyz_is_pose(md, dligs[k], batch[k])
         alone = md.md_dock(drec, dligs[k], params[k])
+        assert_xyz_is_pose(md, dligs[k], alone)
         _say(f"[batch] ligand {BATCH_SIZES[k]}: best {batch[k]['best_energy'][0]:.5g} alone {alone['best_energy'][0]:.5g}")
         for key in ("best_energy", "best_genes", "best_xyz", "run_index", "evals", "generations"):
             assert np.array_equal(batch[k][key], alone[key]), (k, key)

@@ -110,12 +110,16 @@ def test_autotune_and_table(md, receptor):
     assert md.md_tune_table_size() == 1
     plan = md.md_ligand_get_plan(dlig)
     assert plan == info["plan"]
-    # same class: the tuned plan is applied at creation and by a second autotune, untimed
+    # same class: creation keeps the default plan whatever the table holds; a second autotune
+    # applies the table's plan untimed
     twin = md.Ligand.from_synth(synth.make_ligand(40, 8, 1402, configs.type_params()))
-    assert md.md_ligand_get_plan(twin)["waves_per_block"] == plan["waves_per_block"]
-    assert md.md_ligand_get_plan(twin)["lds_budget"] == plan["lds_budget"]
+    fresh = md.Ligand.from_synth(synth.make_ligand(40, 8, 1402, configs.type_params()))
+    assert md.md_ligand_get_plan(twin) == md.md_ligand_get_plan(fresh)
+    assert md.md_ligand_get_plan(twin)["waves_per_block"] == 4 and md.md_ligand_get_plan(twin)["lds_budget"] == 65536
     again = md.md_ligand_autotune(drec, twin)
     assert again["from_table"]
+    assert md.md_ligand_get_plan(twin)["waves_per_block"] == plan["waves_per_block"]
+    assert md.md_ligand_get_plan(twin)["lds_budget"] == plan["lds_budget"]
     # parity after tuning
     genes = synth.random_genes(lig, rec, 65, seed=9, margin=2.0)
     e = torch.empty(65, device="cuda")
@@ -155,4 +159,25 @@ def test_batch_autotune(md, receptor):
             assert np.array_equal(batch[k][key], alone[key]), (k, key)
         r = S.energy_and_gradient(grid, oracle_ligand(ligs[k]), batch[k]["best_genes"][0].astype(np.float64))
         assert abs(float(batch[k]["best_energy"][0]) - r.energy) <= 1e-4 * max(abs(r.energy), r.scale_energy)
+    md.md_tune_table_clear()
+
+
+def test_creation_independent_of_tuning_history(md, receptor):
+    """Two creations of one ligand, one before and one after a tuning call that records a plan
+    for its size class, get the same plan and dock to bitwise the same result."""
+    rec, drec = receptor
+    md.md_tune_table_clear()
+    lig = synth.make_ligand(52, 9, 1403, configs.type_params())
+    P = md.dock_params(**configs.search_params("serving_fp16", n_runs=2, pop_size=30, max_generations=2,
+                                               ls_rate=0.2, ls_iters=15, seed=8))
+    before = md.Ligand.from_synth(lig)
+    res_before = md.md_dock(drec, before, P)
+    md.md_ligand_autotune(drec, md.Ligand.from_synth(synth.make_ligand(52, 9, 1404, configs.type_params())),
+                          force=True)
+    assert md.md_tune_table_size() == 1
+    after = md.Ligand.from_synth(lig)
+    assert md.md_ligand_get_plan(after) == md.md_ligand_get_plan(before)
+    res_after = md.md_dock(drec, after, P)
+    for k in ("best_energy", "best_genes", "best_xyz", "evals"):
+        assert np.array_equal(res_before[k], res_after[k]), k
     md.md_tune_table_clear()

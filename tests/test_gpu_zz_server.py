@@ -12,7 +12,7 @@ import time
 import numpy as np
 import pytest
 
-from parity_util import SERVER_OFF_REASON
+from parity_util import SERVER_OFF_REASON, assert_xyz_is_pose
 from workload import configs, synth
 
 pytestmark = pytest.mark.gpu
@@ -186,6 +186,7 @@ def test_server_graphs_equal_alone(md, receptor, use_graphs):
     results = [srv.wait(t, timeout_s=120) for t in tickets]
     srv.close()
     for k, (l, p) in enumerate(zip(ligs, Ps)):
+        assert_xyz_is_pose(md, l, results[k])
         alone = _dock(md, drec, l, p, False)
         for key in KEYS:
             assert np.array_equal(results[k][key], alone[key]), (k, key)
