@@ -13,9 +13,11 @@ AutoDock4); each such reading is listed with its constant values in `constants`.
 
 Pins: every function here is checked by `tests/test_oracle_*.py` against closed
 forms, library routines (scipy interpolation and rotations, torch's Adadelta),
-invariances, finite differences or brute force.  The LGA operator choices beyond
-its invariants are "parity unpinned" (see `lga`), and so are the Solis-Wets step
-parameters (the paper gives none; `solis_wets` is pinned on hand-worked trajectories,
-its update rules, its budget and closed-form minima).
+invariances, finite differences or brute force; the LGA on 1-3-atom ligands against
+exact lower bounds and a brute-force lattice minimum, its initial-population sampler
+by distribution tests.  The GA operator choices beyond those and its invariants are
+"parity unpinned" (see `lga`), and so are the Solis-Wets step parameters (the paper
+gives none; `solis_wets` is pinned on hand-worked trajectories, its update rules, its
+budget and closed-form minima).
 """
 from . import constants, rng, ligand, pose, scoring, adadelta, solis_wets, lga  # noqa: F401

@@ -10,7 +10,8 @@ individual and summed per run (Section "Removing architecture-specific code",
 the sum_evals listings), which drives termination.
 
 Operator choices (readings; the paper names the operators only -- parity
-unpinned beyond the invariants the tests check):
+unpinned beyond the invariants, the small-ligand lattice minima and the sampler's
+distribution that the tests check):
   * initial individual: translation uniform in the grid box, orientation a uniform
     random unit quaternion (Shoemake's method from three uniforms), torsions
     uniform in (-pi, pi];
