@@ -4,9 +4,12 @@
 // receptor, which makes scheduling and load balance part of the problem (introduction, the
 // high-throughput workflow figure and the paragraph on heterogeneously sized ligands).  Here
 // requests arrive while others run: a worker thread admits queued requests into free slots as
-// long as their device buffers fit in a fixed HBM pool, runs one generation of every resident
-// request per tick through the same job-table kernels as md_dock_batch, and retires finished
-// requests at once, so their slots and memory are reused on the next tick.
+// long as their device buffers fit in a fixed HBM pool, advances every resident request per tick
+// through the same job-table kernels as md_dock_batch, and retires finished requests as soon as
+// their tick is done, so their slots and memory are reused.  Ticks are pipelined two deep: the
+// next tick is queued on the device before the host reads the previous tick's job table and
+// copies out its finished results (on a stream of its own), so the device does not wait for the
+// host between ticks.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -101,7 +104,8 @@ struct Request {
   int n_genes = 0, n_atoms = 0;
   md_dock_params params{};
   ReqState state = kQueued;
-  bool cancel_requested = false;   // resident: leaves its slot after the current tick
+  bool cancel_requested = false;   // resident: leaves its slot once its entry is cleared
+  long long cancel_tick = -1;      // the tick queued after its entry was cleared
   int slot = -1;
   size_t off = 0, bytes = 0;
   // offsets inside the request's pool block
@@ -125,7 +129,12 @@ struct md_server {
   char* pool_base = nullptr;
   std::unique_ptr<Pool> pool;
   JobDev* d_table = nullptr;     // [max_slots]
-  JobDev* h_table = nullptr;     // pinned mirror
+  JobDev* h_table = nullptr;     // pinned: the host's copy of every entry
+  JobDev* h_up[2] = {nullptr, nullptr};     // pinned: entries uploaded before tick t, for t even / odd
+                                            //     (reused only after that tick is done)
+  JobDev* h_tick[2] = {nullptr, nullptr};   // pinned: the table after tick t, for t even / odd
+  hipEvent_t tick_done[2] = {nullptr, nullptr};
+  hipStream_t copy_stream = nullptr;        // result copies, beside the next tick
   int2* d_blocks = nullptr;
   size_t blocks_cap = 0;
   std::vector<std::shared_ptr<Request>> slots;   // resident request per slot (or null)
@@ -223,27 +232,24 @@ JobDev make_job(md_server* s, const Request& r) {
   return J;
 }
 
-// One tick: every resident request advances by one phase sequence.  With use_graphs the worker
-// thread launches the size classes' chains directly as parallel branches (fork/join events over
-// the branch streams) and captures no graph: graph capture in this thread coincided with two
-// host crashes whose cause is not known (md_dock_batch captures on the caller's thread).
-// Returns the HIP status.
-hipError_t run_tick(md_server* s, bool any_init, bool any_running) {
+// Queues one tick: every resident request advances by one phase sequence.  With use_graphs the
+// size classes' chains are launched directly as parallel branches (fork/join events over the
+// branch streams), several generations for the cheap classes; the worker captures no graph (graph
+// capture in this thread coincided with two host crashes whose cause is not known; md_dock_batch
+// captures on the caller's thread).  The tick ends with a copy of the job table into
+// h_tick[t & 1] and the event tick_done[t & 1].  Returns the HIP status.
+// jobs: the resident set when it changed since the last tick (taken under the server's lock), or
+// null to keep the schedule.
+hipError_t queue_tick(md_server* s, long long t, const std::vector<SchedJob>* jobs, bool any_init, bool any_running) {
   const int n_slots = (int)s->slots.size();
   hipError_t e = hipSuccess;
-  if (s->resident_changed) {
-    std::vector<SchedJob> jobs;
-    for (int j = 0; j < n_slots; ++j) {
-      const auto& r = s->slots[j];
-      if (!r) continue;
-      const md_dock_params& p = r->params;
-      jobs.push_back(SchedJob{j, &r->lig->dev, p.n_runs, p.pop_size, n_local_search_of(&p), p.ls_iters,
-                              p.ls_method});
-    }
-    build_schedule(jobs, s->sched, (s->params.use_graphs && use_graphs()) ? kTickMaxGenerations : 0, 1);
-    s->graph.reset();
+  if (jobs) {
+    build_schedule(*jobs, s->sched, (s->params.use_graphs && use_graphs()) ? kTickMaxGenerations : 0, 1);
     const size_t nb = s->sched.blocks.size();
     if (nb > s->blocks_cap) {
+      // the tick in flight reads the block table: let it finish before the buffer goes
+      e = hipStreamSynchronize(s->stream);
+      if (e != hipSuccess) return e;
       if (s->d_blocks) (void)hipFree(s->d_blocks);
       s->blocks_cap = std::max<size_t>(nb, 2 * s->blocks_cap);
       e = hipMalloc(&s->d_blocks, s->blocks_cap * sizeof(int2));
@@ -253,9 +259,9 @@ hipError_t run_tick(md_server* s, bool any_init, bool any_running) {
         return e;
       }
     }
+    // stream-ordered after the tick in flight, which still reads the old table
     if (nb) e = hipMemcpyAsync(s->d_blocks, s->sched.blocks.data(), nb * sizeof(int2), hipMemcpyHostToDevice, s->stream);
     if (e != hipSuccess) return e;
-    s->resident_changed = false;
   }
   const RecDev& R = s->rec->dev;
   if (any_init) e = launch_init_phase(s->sched, s->d_table, s->d_blocks, R, s->stream, nullptr);
@@ -269,24 +275,27 @@ hipError_t run_tick(md_server* s, bool any_init, bool any_running) {
     }
   }
   if (e == hipSuccess)
-    e = hipMemcpyAsync(s->h_table, s->d_table, sizeof(JobDev) * n_slots, hipMemcpyDeviceToHost, s->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    e = hipMemcpyAsync(s->h_tick[t & 1], s->d_table, sizeof(JobDev) * n_slots, hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipEventRecord(s->tick_done[t & 1], s->stream);
   return e;
 }
 
-// Copy a finished request's results to the host (called by the worker, stream idle).
-hipError_t collect(md_server* s, Request& r) {
+// Copy a finished request's results to the host on the copy stream, after the tick that finished
+// it (the tick queued behind it skips the request).  Called by the worker without the lock.
+hipError_t collect(md_server* s, Request& r, hipEvent_t finished_tick) {
   const LigDev& L = r.lig->dev;
   const int runs = r.params.n_runs, G = L.n_genes, N = L.n_atoms;
   char* w = s->pool_base + r.off;
   // the generation epilogue that finished the request wrote its best genes, energies and poses
   std::vector<float> be(runs), bg((size_t)runs * G), bx((size_t)runs * N * 3);
   std::vector<long long> er(runs);
-  hipError_t e = hipMemcpyAsync(be.data(), w + r.o_be, runs * 4, hipMemcpyDeviceToHost, s->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(bg.data(), w + r.o_bg, bg.size() * 4, hipMemcpyDeviceToHost, s->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(bx.data(), w + r.o_bx, bx.size() * 4, hipMemcpyDeviceToHost, s->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(er.data(), w + r.o_er, runs * 8, hipMemcpyDeviceToHost, s->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  hipStream_t cs = s->copy_stream;
+  hipError_t e = hipStreamWaitEvent(cs, finished_tick, 0);
+  if (e == hipSuccess) e = hipMemcpyAsync(be.data(), w + r.o_be, runs * 4, hipMemcpyDeviceToHost, cs);
+  if (e == hipSuccess) e = hipMemcpyAsync(bg.data(), w + r.o_bg, bg.size() * 4, hipMemcpyDeviceToHost, cs);
+  if (e == hipSuccess) e = hipMemcpyAsync(bx.data(), w + r.o_bx, bx.size() * 4, hipMemcpyDeviceToHost, cs);
+  if (e == hipSuccess) e = hipMemcpyAsync(er.data(), w + r.o_er, runs * 8, hipMemcpyDeviceToHost, cs);
+  if (e == hipSuccess) e = hipStreamSynchronize(cs);
   if (e != hipSuccess) return e;
   std::vector<int> order(runs);
   std::iota(order.begin(), order.end(), 0);
@@ -307,13 +316,24 @@ hipError_t collect(md_server* s, Request& r) {
   return hipSuccess;
 }
 
+// The worker: each pass (1) admits queued requests and clears the entries of canceled ones,
+// (2) queues tick t for the resident requests, (3) waits for tick t - 1, retires the requests it
+// finished (results copied out beside tick t) and frees the slots of requests canceled before it.
+// Tick t - 1's table is read only for the requests that occupied their slots when it was queued.
 void worker_loop(md_server* s) {
   (void)hipSetDevice(s->device);
+  const int n_slots = (int)s->slots.size();
+  // occupants of every slot when tick t & 1 was queued
+  std::vector<std::shared_ptr<Request>> occ[2] = {std::vector<std::shared_ptr<Request>>(n_slots),
+                                                  std::vector<std::shared_ptr<Request>>(n_slots)};
+  long long t = 0;                 // next tick
+  bool prev_inflight = false;      // tick t - 1 queued and not yet processed
   std::unique_lock<std::mutex> lk(s->mu);
   while (true) {
     // admit queued requests into free slots while their buffers fit in the pool
-    std::vector<int> admitted;
-    for (int j = 0; j < (int)s->slots.size() && !s->queue.empty(); ++j) {
+    std::vector<int> uploads;
+    bool any_init = false;
+    for (int j = 0; j < n_slots && !s->queue.empty(); ++j) {
       if (s->slots[j]) continue;
       auto r = s->queue.front();
       size_t off;
@@ -326,41 +346,85 @@ void worker_loop(md_server* s) {
       s->slots[j] = r;
       s->resident_changed = true;
       s->h_table[j] = make_job(s, *r);
-      admitted.push_back(j);
+      uploads.push_back(j);
+      any_init = true;
     }
-    bool any = false, any_init = !admitted.empty(), any_running = false;
-    for (auto& r : s->slots)
-      if (r) {
-        any = true;
-        if (s->h_table[r->slot].state == kJobRunning) any_running = true;
+    // requests canceled while resident: their entries are cleared before the next tick, their
+    // slots and memory are freed once the tick in flight (the last one that may run them) is done
+    for (int j = 0; j < n_slots; ++j) {
+      auto& r = s->slots[j];
+      if (r && r->cancel_requested && r->cancel_tick < 0) {
+        JobDev empty{};
+        empty.state = kJobEmpty;
+        s->h_table[j] = empty;
+        uploads.push_back(j);
+        r->cancel_tick = t;
+        s->resident_changed = true;
       }
-    if (!any) {
+    }
+    bool any = false, any_running = false;
+    for (int j = 0; j < n_slots; ++j) {
+      const auto& r = s->slots[j];
+      if (r && !r->cancel_requested) {
+        any = true;
+        if (std::find(uploads.begin(), uploads.end(), j) == uploads.end()) any_running = true;
+      }
+    }
+    const bool cancels = std::any_of(s->slots.begin(), s->slots.end(),
+                                     [](const std::shared_ptr<Request>& r) { return r && r->cancel_requested; });
+    if (!any && !prev_inflight && !cancels) {
       if (s->stop) break;
       s->cv_work.wait(lk);
       continue;
     }
-    // upload new slots' job entries, run one tick without holding the lock
-    std::vector<std::pair<int, JobDev>> uploads;
-    for (int j : admitted) uploads.push_back({j, s->h_table[j]});
+    const bool queue_now = any || cancels;
+    std::vector<SchedJob> jobs;
+    bool rebuild = false;
+    if (queue_now) {
+      for (int j = 0; j < n_slots; ++j) occ[t & 1][j] = (s->slots[j] && !s->slots[j]->cancel_requested) ? s->slots[j] : nullptr;
+      if (s->resident_changed) {
+        for (int j = 0; j < n_slots; ++j) {
+          const auto& r = occ[t & 1][j];
+          if (!r) continue;
+          const md_dock_params& p = r->params;
+          jobs.push_back(SchedJob{j, &r->lig->dev, p.n_runs, p.pop_size, n_local_search_of(&p), p.ls_iters,
+                                  p.ls_method});
+        }
+        rebuild = true;
+        s->resident_changed = false;
+      }
+    }
     lk.unlock();
     const double t0 = now_s();
     hipError_t e = hipSuccess;
-    for (auto& u : uploads)
+    // (2) upload new and cleared entries, queue tick t.  The copies read their pinned source when
+    // they run, so each tick parity has its own staging entries, rewritten only after that
+    // parity's previous tick (and the uploads queued before it) is done.
+    for (int j : uploads) {
+      s->h_up[t & 1][j] = s->h_table[j];
       if (e == hipSuccess)
-        e = hipMemcpyAsync(s->d_table + u.first, &u.second, sizeof(JobDev), hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    if (e == hipSuccess) e = run_tick(s, any_init, any_running);
+        e = hipMemcpyAsync(s->d_table + j, s->h_up[t & 1] + j, sizeof(JobDev), hipMemcpyHostToDevice, s->stream);
+    }
+    const bool queued = queue_now && e == hipSuccess;
+    if (queued) e = queue_tick(s, t, rebuild ? &jobs : nullptr, any_init, any_running);
+    // (3) tick t - 1: wait, find the requests it finished, copy their results beside tick t
     std::vector<std::shared_ptr<Request>> finished;
-    if (e == hipSuccess) {
-      for (auto& r : s->slots)
-        if (r && s->h_table[r->slot].state == kJobDone) finished.push_back(r);
+    if (e == hipSuccess && prev_inflight) {
+      const int pb = (int)((t - 1) & 1);
+      e = hipEventSynchronize(s->tick_done[pb]);
+      // (a request finished by tick t - 2 is still in tick t - 1's occupants, already retired;
+      // only this thread changes the state of a request that reached a slot)
+      if (e == hipSuccess)
+        for (int j = 0; j < n_slots; ++j)
+          if (occ[pb][j] && occ[pb][j]->state == kResident && s->h_tick[pb][j].state == kJobDone)
+            finished.push_back(occ[pb][j]);
       for (auto& r : finished)
-        if (e == hipSuccess) e = collect(s, *r);
+        if (e == hipSuccess) e = collect(s, *r, s->tick_done[pb]);
     }
     const double t1 = now_s();
     lk.lock();
     s->busy_s += t1 - t0;
-    ++s->ticks;
+    if (queued) ++s->ticks;
     if (e != hipSuccess) {
       s->fatal = std::string("device error in the serving loop: ") + hipGetErrorString(e);
       for (auto& r : s->slots)
@@ -381,7 +445,7 @@ void worker_loop(md_server* s) {
     }
     for (auto& r : finished) {
       r->t_end = t1;
-      r->state = kFinished;   // a cancel that came during the last tick is too late
+      r->state = kFinished;   // a cancel that came after its last tick was queued is too late
       ++s->completed;
       drop_hold(*r);
       s->pool->release(r->off, r->bytes);
@@ -389,27 +453,27 @@ void worker_loop(md_server* s) {
       s->resident_changed = true;
       s->h_table[r->slot].state = kJobEmpty;
     }
-    // requests canceled while resident: drop them from their slots (device entry marked empty;
-    // the stream is idle after the tick) and only then report them canceled
+    // canceled requests whose entry was cleared before tick t - 1: no tick runs them any more
     bool dropped = false;
-    for (int j = 0; j < (int)s->slots.size(); ++j) {
-      auto& r = s->slots[j];
-      if (r && r->cancel_requested) {
-        JobDev empty{};
-        empty.state = kJobEmpty;
-        s->h_table[j] = empty;
-        (void)hipMemcpy(s->d_table + j, &empty, sizeof(JobDev), hipMemcpyHostToDevice);
-        s->pool->release(r->off, r->bytes);
-        r->state = kCanceled;
-        r->t_end = t1;
-        drop_hold(*r);
-        r = nullptr;
-        s->resident_changed = true;
-        dropped = true;
+    if (prev_inflight)
+      for (int j = 0; j < n_slots; ++j) {
+        auto& r = s->slots[j];
+        if (r && r->cancel_requested && r->cancel_tick >= 0 && r->cancel_tick <= t - 1) {
+          s->pool->release(r->off, r->bytes);
+          r->state = kCanceled;
+          r->t_end = t1;
+          drop_hold(*r);
+          r = nullptr;
+          s->resident_changed = true;
+          dropped = true;
+        }
       }
-    }
+    if (prev_inflight) occ[(t - 1) & 1].assign(n_slots, nullptr);
+    prev_inflight = queued;
+    if (queued) ++t;
     if (!finished.empty() || dropped) s->cv_done.notify_all();
   }
+  // a fatal error leaves the stream to md_server_destroy, which synchronises it
 }
 
 md_status fill_result(const Request& r, md_dock_result* out) {
@@ -447,10 +511,22 @@ md_status md_server_create(const md_receptor* rec, const md_server_params* p, md
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s->pool_base), p->hbm_budget_bytes);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s->d_table), sizeof(JobDev) * p->max_slots);
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&s->h_table), sizeof(JobDev) * p->max_slots);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k)
+    e = hipHostMalloc(reinterpret_cast<void**>(&s->h_tick[k]), sizeof(JobDev) * p->max_slots);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k)
+    e = hipHostMalloc(reinterpret_cast<void**>(&s->h_up[k]), sizeof(JobDev) * p->max_slots);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&s->tick_done[k], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     if (s->pool_base) (void)hipFree(s->pool_base);
     if (s->d_table) (void)hipFree(s->d_table);
     if (s->h_table) (void)hipHostFree(s->h_table);
+    for (int k = 0; k < 2; ++k) {
+      if (s->h_tick[k]) (void)hipHostFree(s->h_tick[k]);
+      if (s->h_up[k]) (void)hipHostFree(s->h_up[k]);
+      if (s->tick_done[k]) (void)hipEventDestroy(s->tick_done[k]);
+    }
+    if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
     return e == hipErrorOutOfMemory ? server_fail(MD_ENOMEM, "md_server_create: out of device memory")
@@ -536,7 +612,7 @@ md_status md_server_cancel(md_server* s, unsigned long long ticket) {
     r->state = kCanceled;
     drop_hold(*r);
   } else if (r->state == kResident) {
-    r->cancel_requested = true;   // the worker frees the slot after the current tick
+    r->cancel_requested = true;   // the worker clears its entry, then frees the slot
     s->cv_work.notify_one();
   }
   s->cv_done.notify_all();
@@ -601,11 +677,18 @@ md_status md_server_destroy(md_server* s) {
   // the device work is drained; drop the executable graph before the buffers and the stream it
   // was launched on
   (void)hipStreamSynchronize(s->stream);
+  (void)hipStreamSynchronize(s->copy_stream);
   s->graph.reset();
   if (s->d_blocks) (void)hipFree(s->d_blocks);
   (void)hipFree(s->d_table);
   (void)hipHostFree(s->h_table);
+  for (int k = 0; k < 2; ++k) {
+    (void)hipHostFree(s->h_tick[k]);
+    (void)hipHostFree(s->h_up[k]);
+    (void)hipEventDestroy(s->tick_done[k]);
+  }
   (void)hipFree(s->pool_base);
+  (void)hipStreamDestroy(s->copy_stream);
   (void)hipStreamDestroy(s->stream);
   delete s;
   return MD_OK;

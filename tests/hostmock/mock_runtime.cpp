@@ -3,22 +3,40 @@
 // the serving worker thread, its locks and buffer lifetimes, the batch schedule and the graph
 // capture bookkeeping -- under ThreadSanitizer and AddressSanitizer on a machine without a GPU.
 //
-// Streams execute work in the calling thread at once (every call is therefore ordered with the
-// calls before it on any stream); a stream in capture mode, or one that joined a capture through
-// an event recorded in it, records the work into the capture instead, and a launched graph runs
-// the recorded work.  "Device" memory is host memory.  The GA launchers emulate the job-table
-// state machine of the real kernels (initial population, generations, local-search picks, the
-// epilogue that counts evaluations, swaps populations, advances the generation and finishes the
-// job) with values that depend only on a job's own seed, run, individual and generation, so a
-// request's result does not depend on what else runs.
+// Streams are asynchronous, as on the device: each stream has a thread of its own that runs the
+// stream's work in order, after a short random delay per operation, while the caller goes on.  A
+// copy between device memory and pinned host memory (hipHostMalloc) reads its source and writes
+// its destination when it runs; as with the runtime's staged copies, a copy from pageable host
+// memory takes its source when it is queued, and a copy into pageable host memory returns once
+// it has run.  A launch runs its emulated
+// kernel then, an event completes when the work recorded before it on its stream has run, and a
+// stream that waits for an event holds its later work until then.  So a host write into a
+// buffer that queued work still reads, a read of results before their stream was synchronised,
+// or a missing wait between streams shows up as a data race (ThreadSanitizer), a use after free
+// (AddressSanitizer) or a wrong result.  The null stream runs work at once in the caller.  A
+// stream in capture mode, or one that joined a capture through an event recorded in it, records
+// the work into the capture instead, and a launched graph runs the recorded work as one
+// operation of the stream it is launched on.  "Device" memory is host memory.  The GA launchers
+// emulate the job-table state machine of the real kernels (initial population, generations,
+// local-search picks, the epilogue that counts evaluations, swaps populations, advances the
+// generation and finishes the job) with values that depend only on a job's own seed, run,
+// individual and generation, so a request's result does not depend on what else runs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <functional>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <random>
+#include <set>
 #include <thread>
 #include <vector>
 
@@ -28,12 +46,23 @@ struct Capture {
   std::vector<std::function<void()>> ops;
   std::vector<MockStream*> streams;
 };
+
 struct MockStream {
   Capture* cap = nullptr;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<std::function<void()>> q;
+  long long queued = 0, done = 0;   // operations queued and run so far
+  bool quit = false;
+  std::thread th;
 };
+
 struct MockEvent {
   Capture* cap = nullptr;
+  MockStream* s = nullptr;          // recorded on s after `target` operations (null: complete)
+  long long target = 0;
 };
+
 struct MockGraph {
   std::vector<std::function<void()>> ops;
 };
@@ -43,11 +72,76 @@ struct MockGraphExec {
 
 namespace {
 
+std::mutex g_streams_mu;
+std::set<MockStream*> g_streams;
+
+// pinned host allocations: start -> size
+std::mutex g_pinned_mu;
+std::map<const char*, size_t> g_pinned;
+
+bool is_pinned(const void* p) {
+  const char* c = static_cast<const char*>(p);
+  std::lock_guard<std::mutex> lk(g_pinned_mu);
+  auto it = g_pinned.upper_bound(c);
+  if (it == g_pinned.begin()) return false;
+  --it;
+  return c < it->first + it->second;
+}
+
+void stream_main(MockStream* s) {
+  std::mt19937 rng((unsigned)reinterpret_cast<uintptr_t>(s));
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (true) {
+    s->cv.wait(lk, [&] { return s->quit || !s->q.empty(); });
+    if (s->q.empty()) return;
+    std::function<void()> f = std::move(s->q.front());
+    s->q.pop_front();
+    lk.unlock();
+    // the device's share of the operation: lets the host and the other streams run meanwhile
+    std::this_thread::sleep_for(std::chrono::microseconds(rng() % 40));
+    f();
+    lk.lock();
+    ++s->done;
+    s->cv.notify_all();
+  }
+}
+
+// Waits until stream s has run its first `target` operations.
+void wait_for(MockStream* s, long long target) {
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv.wait(lk, [&] { return s->done >= target; });
+}
+
+long long enqueue(MockStream* s, std::function<void()> f) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->q.push_back(std::move(f));
+  s->cv.notify_all();
+  return ++s->queued;
+}
+
+void sync_stream(MockStream* s) {
+  long long target;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    target = s->queued;
+  }
+  wait_for(s, target);
+}
+
+// (holds the registry's lock, so no stream is destroyed meanwhile; stream threads never take it)
+void sync_all() {
+  std::lock_guard<std::mutex> lk(g_streams_mu);
+  for (MockStream* s : g_streams) sync_stream(s);
+}
+
+// Work for stream s: recorded into its capture, run at once (null stream) or queued.
 void run_or_record(hipStream_t s, std::function<void()> f) {
   if (s && s->cap)
     s->cap->ops.push_back(std::move(f));
-  else
+  else if (!s)
     f();
+  else
+    enqueue(s, std::move(f));
 }
 
 bool capturing(hipStream_t s) { return s && s->cap; }
@@ -60,7 +154,10 @@ hipError_t hipGetDevice(int* dev) {
   return hipSuccess;
 }
 hipError_t hipSetDevice(int dev) { return dev == 0 ? hipSuccess : hipErrorInvalidValue; }
-hipError_t hipDeviceSynchronize() { return hipSuccess; }
+hipError_t hipDeviceSynchronize() {
+  sync_all();
+  return hipSuccess;
+}
 const char* hipGetErrorString(hipError_t e) { return e == hipSuccess ? "no error" : "emulated runtime error"; }
 
 hipError_t hipMalloc(void** p, size_t bytes) {
@@ -70,7 +167,9 @@ hipError_t hipMalloc(void** p, size_t bytes) {
   std::memset(*p, 0xA5, bytes);   // device memory starts with no defined contents
   return hipSuccess;
 }
+// like the runtime's, waits for the device's queued work first
 hipError_t hipFree(void* p) {
+  sync_all();
   std::free(p);
   return hipSuccess;
 }
@@ -80,36 +179,76 @@ hipError_t hipMallocAsync(void** p, size_t bytes, hipStream_t s) {
 }
 hipError_t hipFreeAsync(void* p, hipStream_t s) {
   if (capturing(s)) return hipErrorStreamCaptureUnsupported;
+  run_or_record(s, [p] { std::free(p); });
+  return hipSuccess;
+}
+hipError_t hipHostMalloc(void** p, size_t bytes, unsigned) {
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e == hipSuccess) {
+    std::lock_guard<std::mutex> lk(g_pinned_mu);
+    g_pinned[static_cast<const char*>(*p)] = std::max<size_t>(bytes, 1);
+  }
+  return e;
+}
+hipError_t hipHostFree(void* p) {
+  {
+    std::lock_guard<std::mutex> lk(g_pinned_mu);
+    g_pinned.erase(static_cast<const char*>(p));
+  }
   return hipFree(p);
 }
-hipError_t hipHostMalloc(void** p, size_t bytes, unsigned) { return hipMalloc(p, bytes); }
-hipError_t hipHostFree(void* p) { return hipFree(p); }
 hipError_t hipMemcpy(void* dst, const void* src, size_t bytes, hipMemcpyKind) {
   if (bytes && (!dst || !src)) return hipErrorInvalidValue;
+  sync_all();
   if (bytes) std::memmove(dst, src, bytes);
   return hipSuccess;
 }
-hipError_t hipMemcpyAsync(void* dst, const void* src, size_t bytes, hipMemcpyKind, hipStream_t s) {
+hipError_t hipMemcpyAsync(void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t s) {
   if (bytes && (!dst || !src)) return hipErrorInvalidValue;
   if (capturing(s)) return hipErrorStreamCaptureUnsupported;   // the library records no copies
-  if (bytes) std::memmove(dst, src, bytes);
+  if (!bytes) return hipSuccess;
+  if (kind == hipMemcpyHostToDevice && !is_pinned(src)) {
+    // staged: the pageable source is taken now
+    auto staged = std::make_shared<std::vector<char>>(static_cast<const char*>(src),
+                                                      static_cast<const char*>(src) + bytes);
+    run_or_record(s, [dst, staged] { std::memmove(dst, staged->data(), staged->size()); });
+    return hipSuccess;
+  }
+  run_or_record(s, [dst, src, bytes] { std::memmove(dst, src, bytes); });
+  if (kind == hipMemcpyDeviceToHost && !is_pinned(dst) && s) sync_stream(s);   // pageable destination
   return hipSuccess;
 }
 
 hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned) {
   if (!s) return hipErrorInvalidValue;
-  *s = new MockStream();
+  MockStream* x = new MockStream();
+  x->th = std::thread(stream_main, x);
+  {
+    std::lock_guard<std::mutex> lk(g_streams_mu);
+    g_streams.insert(x);
+  }
+  *s = x;
   return hipSuccess;
 }
 hipError_t hipStreamDestroy(hipStream_t s) {
   if (!s || s->cap) return hipErrorInvalidValue;
+  {
+    std::lock_guard<std::mutex> lk(g_streams_mu);
+    g_streams.erase(s);
+  }
+  sync_stream(s);   // the runtime lets queued work finish
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->quit = true;
+    s->cv.notify_all();
+  }
+  s->th.join();
   delete s;
   return hipSuccess;
 }
 hipError_t hipStreamSynchronize(hipStream_t s) {
   if (capturing(s)) return hipErrorStreamCaptureUnsupported;
-  // the device's share of a tick: lets the other threads run meanwhile
-  std::this_thread::sleep_for(std::chrono::microseconds(20));
+  if (s) sync_stream(s);
   return hipSuccess;
 }
 hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned) {
@@ -118,6 +257,13 @@ hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned) {
     if (s->cap) return hipErrorInvalidValue;
     s->cap = e->cap;
     e->cap->streams.push_back(s);
+    return hipSuccess;
+  }
+  if (s->cap) return hipSuccess;   // inside one capture the recorded order is kept
+  if (e->s && e->s != s) {
+    MockStream* src = e->s;
+    const long long target = e->target;
+    enqueue(s, [src, target] { wait_for(src, target); });
   }
   return hipSuccess;
 }
@@ -149,11 +295,24 @@ hipError_t hipEventDestroy(hipEvent_t e) {
 hipError_t hipEventRecord(hipEvent_t e, hipStream_t s) {
   if (!e) return hipErrorInvalidValue;
   e->cap = s ? s->cap : nullptr;
+  e->s = nullptr;
+  e->target = 0;
+  if (s && !s->cap) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    e->s = s;
+    e->target = s->queued;
+  }
   return hipSuccess;
 }
-hipError_t hipEventSynchronize(hipEvent_t e) { return e ? hipSuccess : hipErrorInvalidValue; }
+hipError_t hipEventSynchronize(hipEvent_t e) {
+  if (!e) return hipErrorInvalidValue;
+  if (e->s) wait_for(e->s, e->target);
+  return hipSuccess;
+}
 hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b) {
   if (!ms || !a || !b) return hipErrorInvalidValue;
+  if (a->s) wait_for(a->s, a->target);
+  if (b->s) wait_for(b->s, b->target);
   *ms = 0.25f;
   return hipSuccess;
 }
@@ -168,12 +327,16 @@ hipError_t hipGraphDestroy(hipGraph_t graph) {
   return hipSuccess;
 }
 hipError_t hipGraphExecDestroy(hipGraphExec_t exec) {
+  sync_all();   // a launched graph may still be running
   delete exec;
   return hipSuccess;
 }
 hipError_t hipGraphLaunch(hipGraphExec_t exec, hipStream_t s) {
   if (!exec) return hipErrorInvalidValue;
-  for (const auto& f : exec->ops) run_or_record(s, f);
+  const MockGraphExec* x = exec;
+  run_or_record(s, [x] {
+    for (const auto& f : x->ops) f();
+  });
   return hipSuccess;
 }
 
