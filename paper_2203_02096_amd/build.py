@@ -19,10 +19,24 @@ SOURCES = ["api.cpp", "autotune.cpp", "ligand_prep.cpp", "schedule.cpp", "server
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
-    # packed FP32 instructions stay off: plain scalar FP32 code only
+    # packed FP32 instructions stay off: plain scalar FP32 code only.  The feature reaches the
+    # host compile too (the driver cannot pass -Xclang options to one side only), where it is
+    # ignored with a note that run() leaves out.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]
+HOST_FEATURE_NOTE = "'-packed-fp32-ops' is not a recognized feature for this target (ignoring feature)"
+
+
+def run(cmd):
+    """Runs one compiler command; its output is printed without the host pass's note about the
+    device-only feature."""
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    lines = [l for l in r.stdout.splitlines() if l.strip() != HOST_FEATURE_NOTE]
+    if lines:
+        print("\n".join(lines), flush=True)
+    if r.returncode != 0:
+        raise subprocess.CalledProcessError(r.returncode, cmd)
 
 
 def hipcc() -> str:
@@ -43,13 +57,13 @@ def build(verbose: bool = False) -> str:
             cmd[1:1] = ["-x", "hip"]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        run(cmd)
         objs.append(obj)
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    run(cmd)
     os.replace(tmp, LIB)
     return LIB
 

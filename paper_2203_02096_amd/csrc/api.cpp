@@ -105,7 +105,7 @@ namespace mdock {
 
 // One device allocation per ligand holding every constant the kernels read; *L gets views into it.
 hipError_t upload_ligand(const LigHost& h, void** d_buf, LigDev* L) {
-  const size_t N = h.n_atoms, T = h.n_tors, S = h.pair_ij.size();   // S: scheduled slots
+  const size_t N = h.n_atoms, T = h.n_tors, S = h.pair_ij.size() + kWave;   // S: scheduled slots + a pad row
   size_t off = 0;
   const size_t o_p0q = off; off = align16(off + N * sizeof(float4));
   const size_t o_type = off; off = align16(off + N * sizeof(int));
@@ -127,8 +127,16 @@ hipError_t upload_ligand(const LigHost& h, void** d_buf, LigDev* L) {
   put(o_ab, h.tor_ab.data(), T * sizeof(int2));
   put(o_gene, h.tor_gene.data(), T * sizeof(int));
   put(o_gtor, h.gene_tor.data(), T * sizeof(int));
-  put(o_ij, h.pair_ij.data(), S * sizeof(uint32_t));
-  put(o_coef, h.pair_coef.data(), S * sizeof(float4));
+  // device slots: byte offsets of the two atoms' entries; then a padding row of empty slots
+  std::vector<uint32_t> ij(S, (uint32_t)(4 * N) | ((uint32_t)(4 * N) << 16));
+  for (size_t k = 0; k < h.pair_ij.size(); ++k)
+    ij[k] = 4u * (h.pair_ij[k] & 0xffu) | ((4u * ((h.pair_ij[k] >> 8) & 0xffu)) << 16);
+  put(o_ij, ij.data(), S * sizeof(uint32_t));
+  // the second coefficient of an H-bond pair is stored negated (its 12-10 marker)
+  std::vector<float4> coef(h.pair_coef);
+  for (size_t k = 0; k < coef.size(); ++k)
+    if ((h.pair_ij[k] >> 16) & 1u) coef[k].y = -coef[k].y;
+  put(o_coef, coef.data(), coef.size() * sizeof(float4));
   void* d = nullptr;
   hipError_t e = hipMalloc(&d, buf.size());
   if (e == hipSuccess) e = hipMemcpy(d, buf.data(), buf.size(), hipMemcpyHostToDevice);
@@ -153,6 +161,7 @@ hipError_t upload_ligand(const LigHost& h, void** d_buf, LigDev* L) {
   l.pair_ij = reinterpret_cast<const uint32_t*>(b + o_ij);
   l.pair_coef = reinterpret_cast<const float4*>(b + o_coef);
   l.n_rows = h.n_rows;
+  l.mix_rows = h.mix_rows;
   l.pl_rows = h.pl_rows;
   l.group_lanes = h.group_lanes;
   l.n_copies = h.n_copies;
@@ -194,7 +203,9 @@ md_status md_receptor_create(const md_grid_desc* d, const float* maps, md_map_pr
   if (stored != MD_MAP_FP32 && stored != MD_MAP_FP16 && stored != MD_MAP_BF16)
     return fail(MD_EINVAL, "md_receptor_create: bad storage precision");
   const long long nodes = (long long)d->nx * d->ny * d->nz;
-  if (nodes > (1ll << 31) / kMaps) return fail(MD_ERANGE, "md_receptor_create: grid too large");
+  const long long elem_bytes = stored == MD_MAP_FP32 ? 4 : 2;
+  if (nodes > ((1ll << 31) - 1) / (kMaps * elem_bytes))
+    return fail(MD_ERANGE, "md_receptor_create: grid too large (the stored maps must stay below 2 GiB)");
   const long long count = nodes * kMaps;
   for (long long i = 0; i < count; ++i)
     if (!std::isfinite(maps[i])) return fail(MD_EINVAL, "md_receptor_create: non-finite map value");
@@ -244,6 +255,13 @@ md_status md_receptor_create(const md_grid_desc* d, const float* maps, md_map_pr
   R.inv_h = 1.0f / d->spacing;
   R.map_stride = nodes;
   R.maps = r->d_maps;
+  R.map_bytes = (unsigned)(count * elem);
+  R.gx_max = (float)(d->nx - 1);
+  R.gy_max = (float)(d->ny - 1);
+  R.gz_max = (float)(d->nz - 1);
+  R.hx = R.ox + R.gx_max * R.h;
+  R.hy = R.oy + R.gy_max * R.h;
+  R.hz = R.oz + R.gz_max * R.h;
   *out = r;
   return MD_OK;
 }

@@ -68,11 +68,14 @@ struct LigDev {
   const int2* tor_ab;         // [T] atoms (a, b)
   const int* tor_gene;        // [T] gene index (7 + caller's torsion index)
   const int* gene_tor;        // [T] internal torsion of gene 7 + j
-  const uint32_t* pair_ij;    // [n_rows*64] i | j << 8 | hbond << 16 (| kPairPad)
-  const float4* pair_coef;    // [n_rows*64] weighted C12, weighted C6 or C10, W_el*332*qi*qj,
+  const uint32_t* pair_ij;    // [(n_rows + 1)*64] byte offsets 4 i | 4 j << 16 of the slot's
+                              //     atoms in a coordinate or force array; row n_rows is padding
+  const float4* pair_coef;    // [(n_rows + 1)*64] weighted C12, weighted C6 or C10, W_el*332*qi*qj,
                               //     W_ds*(S_i V_j + S_j V_i); zero in empty slots
   int n_rows;                 // rows of 64 pair slots
-  int pl_rows;                // rows staged in LDS (a prefix)
+  int mix_rows;               // rows [0, mix_rows) may hold H-bond pairs (the sign of a slot's
+                              //     second coefficient marks one), rows [mix_rows, n_rows) hold none
+  int pl_rows;                // rows read from LDS (a prefix; one more row is staged behind them)
   int group_lanes;            // lanes per conflict-free group
   int n_copies;               // force-array copies (groups in use)
   int wpb;                    // waves per block of the evaluation kernels
@@ -88,6 +91,10 @@ struct RecDev {
   long long map_stride;       // nx*ny*nz
   const void* maps;           // [7][nz][ny][nx] type maps, then [nz][ny][nx][2] (electrostatic,
                               // desolvation) interleaved per node
+  unsigned map_bytes;         // bytes of the map allocation (< 2^31: the kernels address it with
+                              //     32-bit buffer offsets)
+  float gx_max, gy_max, gz_max;   // n - 1 per axis: inside iff 0 <= g < n - 1 (grid units)
+  float hx, hy, hz;           // upper corner of the box, origin + (n - 1) h
 };
 
 // GA parameters as the kernels see them.
@@ -146,7 +153,7 @@ struct LigHost {
   std::vector<float4> raw_coef;
   std::vector<uint32_t> pair_ij;   // scheduled rows, padded (see LigDev)
   std::vector<float4> pair_coef;
-  int n_pairs = 0, n_rows = 0, pl_rows = 0, group_lanes = 64, n_copies = 1, wpb = kWavesPerBlock;
+  int n_pairs = 0, n_rows = 0, mix_rows = 0, pl_rows = 0, group_lanes = 64, n_copies = 1, wpb = kWavesPerBlock;
   int wpp = 1;
   int lds_bytes = 0;
   PlanParams plan;
@@ -154,21 +161,29 @@ struct LigHost {
 
 // LDS layout helpers shared by the host plan and the kernels.
 __host__ __device__ inline size_t lds_align16(size_t v) { return (v + 15) & ~size_t(15); }
-// per wave: posed coordinates [64*A + 1] and the force-array copies [n_copies][n_atoms + 1],
-// float4 each (the last entry of each is the spare one that empty slots name), then the torsion
-// table [3*n_tors] float4 (per-pose rotations, later posed axes and pivots)
+// Coordinates and forces are kept as three float arrays (x, y, z) of pitch 64A + 1 (A atoms per
+// lane; the last entry is the spare one that empty pair slots name): the pair loop's gathers
+// then read 4-byte words at a 4-byte stride, which spreads random atoms over the LDS banks.
+__host__ __device__ inline int lds_pitch(int A) { return kWave * A + 1; }
+__host__ __device__ inline size_t lds_coord_bytes(int A) { return lds_align16((size_t)12 * lds_pitch(A)); }
+// per wave: posed coordinates [3][64A + 1] and the force-array copies [n_copies][3][64A + 1],
+// float each (16-byte aligned blocks), then the torsion table [3*roundup4(n_tors)] float4
+// (per-pose rotations, later posed axes and pivots; padded so the torsion gradients can read
+// whole batches of four)
 __host__ __device__ inline size_t lds_wave_bytes(int n_atoms, int n_copies, int A, int n_tors) {
-  return (size_t)16 * (kWave * A + 1) + (size_t)16 * n_copies * (n_atoms + 1) + (size_t)48 * n_tors;
+  (void)n_atoms;
+  return lds_coord_bytes(A) * (size_t)(1 + n_copies) + (size_t)48 * ((n_tors + 3) & ~3);
 }
-__host__ __device__ inline size_t lds_pairs_bytes(int rows) { return (size_t)rows * kWave * (16 + 4); }
-// waves sharing a pose (W > 1): the pose's coordinates [64A + 1] (float4), its torsion gradients
-// by gene lane [64] (float), then two alternating sets (even and odd evaluations) of the per-wave
-// intramolecular force partials [W][n_atoms + 1], the grid forces [n_atoms + 1] (float4 each)
-// and the per-wave energy partials [W] (one float4 slot each)
+// rows read from LDS, plus the row behind them that the pair loop's prefetch reads
+__host__ __device__ inline int lds_staged_rows(int rows) { return rows > 0 ? rows + 1 : 0; }
+__host__ __device__ inline size_t lds_pairs_bytes(int rows) { return (size_t)lds_staged_rows(rows) * kWave * (16 + 4); }
+// waves sharing a pose (W > 1): the pose's coordinates [3][64A + 1] (float), its torsion
+// gradients by gene lane [64] (float), then two alternating sets (even and odd evaluations) of
+// the per-wave intramolecular force partials [W][n_atoms + 1], the grid forces [n_atoms + 1]
+// (float4 each) and the per-wave energy partials [W] (one float4 slot each)
 __host__ __device__ inline size_t lds_pose_share_bytes(int n_atoms, int W) {
   const int A = n_atoms > kWave ? 2 : 1;
-  return W > 1 ? (size_t)16 * (kWave * A + 1) + (size_t)4 * kWave +
-                     (size_t)2 * 16 * ((size_t)(W + 1) * (n_atoms + 1) + W)
+  return W > 1 ? lds_coord_bytes(A) + (size_t)4 * kWave + (size_t)2 * 16 * ((size_t)(W + 1) * (n_atoms + 1) + W)
                : 0;
 }
 

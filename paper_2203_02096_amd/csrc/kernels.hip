@@ -121,14 +121,29 @@ __device__ __forceinline__ float wrap_angle(float th) {
 // group of the pair schedule; then, when the block's waves share one pose, the share sets
 // (partial forces and energies, see eval_pose).
 struct BlockLds {
-  const float4* pair_coef;   // [pl_rows*64]
-  const uint32_t* pair_ij;   // [pl_rows*64]
-  float4* x;                 // this wave: [64*A + 1] posed x, y, z
-  float4* f;                 // this wave: [n_copies][n_atoms + 1] intramolecular forces
-  float4* fg;                // this lane's group copy
-  float4* tor;               // this wave: [3*n_tors] torsion table (see eval_pose)
-  float4* share;             // waves sharing a pose: two sets of [W + 1][n_atoms + 1] + [W]
+  const float4* pair_coef;   // [(pl_rows + 1)*64]
+  const uint32_t* pair_ij;   // [(pl_rows + 1)*64]
+  float* x;                  // this wave: posed x, y, z as [3][64A + 1]
+  float* f;                  // this wave: [n_copies] blocks of intramolecular forces [3][64A + 1]
+  float* fg;                 // this lane's group copy
+  float4* tor;               // this wave: [3*roundup4(n_tors)] torsion table (see eval_pose)
+  float4* share;             // waves sharing a pose: the pose's coordinates, then two sets of
+                             // [W + 1][n_atoms + 1] + [W] (see eval_pose_shared)
 };
+
+// x, y, z of entry i of a coordinate or force array of pitch 64A + 1
+template <int A>
+__device__ __forceinline__ float3 load3(const float* a, int i) {
+  constexpr int P = kWave * A + 1;
+  return make_float3(a[i], a[P + i], a[2 * P + i]);
+}
+template <int A>
+__device__ __forceinline__ void store3(float* a, int i, float x, float y, float z) {
+  constexpr int P = kWave * A + 1;
+  a[i] = x;
+  a[P + i] = y;
+  a[2 * P + i] = z;
+}
 
 // Which of the waves sharing a pose this one is, and which share set its next evaluation uses
 // (sets alternate, so one barrier per evaluation suffices: a wave can rewrite a set only after
@@ -146,7 +161,7 @@ template <int A>
 __device__ __forceinline__ BlockLds stage_block(const LigDev& L) {
   BlockLds b;
   unsigned char* cur = g_lds;
-  const int ns = L.pl_rows * kWave;
+  const int ns = lds_staged_rows(L.pl_rows) * kWave;
   float4* pc = reinterpret_cast<float4*>(cur);
   uint32_t* pij = reinterpret_cast<uint32_t*>(cur + (size_t)ns * 16);
   cur += lds_pairs_bytes(L.pl_rows);
@@ -161,18 +176,19 @@ __device__ __forceinline__ BlockLds stage_block(const LigDev& L) {
   cur += (size_t)w * wave_bytes;
   b.pair_coef = pc;
   b.pair_ij = pij;
-  b.x = reinterpret_cast<float4*>(cur);
-  cur += (size_t)16 * (kWave * A + 1);
-  b.f = reinterpret_cast<float4*>(cur);
-  cur += (size_t)16 * L.n_copies * (L.n_atoms + 1);
+  const size_t cb = lds_coord_bytes(A);
+  b.x = reinterpret_cast<float*>(cur);
+  cur += cb;
+  b.f = reinterpret_cast<float*>(cur);
+  cur += cb * L.n_copies;
   b.tor = reinterpret_cast<float4*>(cur);
-  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (lane == 0) b.x[kWave * A] = z;
-  if (L.wpp > 1 && threadIdx.x == 0) b.share[kWave * A] = z;   // spare entry of the shared pose
-  const int nf = L.n_copies * (L.n_atoms + 1);
-  for (int k = lane; k < nf; k += kWave) b.f[k] = z;
+  if (lane == 0) store3<A>(b.x, kWave * A, 0.f, 0.f, 0.f);
+  if (L.wpp > 1 && threadIdx.x == 0)   // spare entry of the shared pose's coordinates
+    store3<A>(reinterpret_cast<float*>(b.share), kWave * A, 0.f, 0.f, 0.f);
+  const int nf = (int)(L.n_copies * cb / 4);
+  for (int k = lane; k < nf; k += kWave) b.f[k] = 0.f;
   const int g = min(lane / L.group_lanes, max(L.n_copies - 1, 0));
-  b.fg = b.f + g * (L.n_atoms + 1);
+  b.fg = b.f + g * (cb / 4);
   __syncthreads();
   return b;
 }
@@ -183,7 +199,7 @@ __device__ __forceinline__ BlockLds stage_block(const LigDev& L) {
 template <int A>
 struct AtomRegs {
   float px[A], py[A], pz[A], q[A];
-  int type[A];
+  uint32_t tofs[A];          // element offset of the atom's type map
   uint32_t mask[A];
   bool valid[A];
   int gene_of_tor;
@@ -193,7 +209,7 @@ struct AtomRegs {
 };
 
 template <int A>
-__device__ __forceinline__ void load_ligand(const LigDev& L, AtomRegs<A>& at) {
+__device__ __forceinline__ void load_ligand(const LigDev& L, AtomRegs<A>& at, long long map_stride = 0) {
   const int lane = lane_id();
 #pragma unroll
   for (int a = 0; a < A; ++a) {
@@ -204,7 +220,7 @@ __device__ __forceinline__ void load_ligand(const LigDev& L, AtomRegs<A>& at) {
     at.py[a] = p.y;
     at.pz[a] = p.z;
     at.q[a] = p.w;
-    at.type[a] = at.valid[a] ? L.atom_type[i] : 0;
+    at.tofs[a] = at.valid[a] ? (uint32_t)L.atom_type[i] * (uint32_t)map_stride : 0u;
     at.mask[a] = at.valid[a] ? L.atom_mask[i] : 0u;
   }
   at.gene_of_tor = 0;
@@ -230,15 +246,21 @@ __device__ __forceinline__ void load_ligand(const LigDev& L, AtomRegs<A>& at) {
 // Trilinear interpolation of (type map + q * electrostatic + |q| * desolvation) and its
 // derivative with respect to the atom position; out-of-grid penalty outside the box.
 // Split in two so the corner loads are in flight while the pair term runs.
+// The map allocation as a raw buffer resource: 32-bit byte offsets per lane, the wave-uniform
+// parts of an address in the scalar offset, and reads past the allocation return zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t map_rsrc(const RecDev& R) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(R.maps), 0, (int)R.map_bytes, 0x00020000);
+}
+
+// Two stored map values (FP16 or BF16 halves of a dword, low half first) as floats.
 template <int PREC>
-__device__ __forceinline__ float map_at(const void* maps, long long idx) {
-  if constexpr (PREC == 0) {
-    return static_cast<const float*>(maps)[idx];
-  } else if constexpr (PREC == 1) {
-    return __half2float(static_cast<const __half*>(maps)[idx]);
+__device__ __forceinline__ void unpack2(uint32_t v, float& lo, float& hi) {
+  if constexpr (PREC == 1) {
+    lo = __half2float(__ushort_as_half((unsigned short)(v & 0xffffu)));
+    hi = __half2float(__ushort_as_half((unsigned short)(v >> 16)));
   } else {
-    uint32_t b = (uint32_t)(static_cast<const uint16_t*>(maps)[idx]) << 16;
-    return __uint_as_float(b);
+    lo = __uint_as_float(v << 16);
+    hi = __uint_as_float(v & 0xffff0000u);
   }
 }
 
@@ -251,40 +273,62 @@ struct GridFetch {
   bool inside;
 };
 
+// tofs: the element offset of the atom's type map.  The corner pairs along x are single loads:
+// 8 (FP32) or 4 (FP16/BF16) bytes of the type map, 16 or 8 bytes of the interleaved electrostatic
+// and desolvation maps; the +y corners take a per-lane offset, the +z corners and the interleaved
+// maps' base the scalar offset.
 template <int PREC>
-__device__ __forceinline__ void grid_fetch(const RecDev& R, float x, float y, float z, int type, float q,
-                                           bool valid, GridFetch& g) {
+__device__ __forceinline__ void grid_fetch(const RecDev& R, __amdgpu_buffer_rsrc_t rs, float x, float y, float z,
+                                           uint32_t tofs, float q, bool valid, GridFetch& g) {
+  constexpr uint32_t ES = PREC == 0 ? 4 : 2;   // bytes per stored value
   const float gx = (x - R.ox) * R.inv_h;
   const float gy = (y - R.oy) * R.inv_h;
   const float gz = (z - R.oz) * R.inv_h;
-  g.inside = valid && gx >= 0.f && gy >= 0.f && gz >= 0.f && gx < (float)(R.nx - 1) &&
-             gy < (float)(R.ny - 1) && gz < (float)(R.nz - 1);
-  const float hx = R.ox + (float)(R.nx - 1) * R.h;
-  const float hy = R.oy + (float)(R.ny - 1) * R.h;
-  const float hz = R.oz + (float)(R.nz - 1) * R.h;
-  g.ex = x - fminf(fmaxf(x, R.ox), hx);
-  g.ey = y - fminf(fmaxf(y, R.oy), hy);
-  g.ez = z - fminf(fmaxf(z, R.oz), hz);
+  g.inside = valid && gx >= 0.f && gy >= 0.f && gz >= 0.f && gx < R.gx_max && gy < R.gy_max && gz < R.gz_max;
+  g.ex = x - fminf(fmaxf(x, R.ox), R.hx);
+  g.ey = y - fminf(fmaxf(y, R.oy), R.hy);
+  g.ez = z - fminf(fmaxf(z, R.oz), R.hz);
   g.fx = g.fy = g.fz = 0.f;
   g.q = q;
   // the corner values are read only where the atom is inside (grid_finish), so lanes outside
   // leave them unset
   if (g.inside) {
-    const int ix = (int)gx, iy = (int)gy, iz = (int)gz;
-    g.fx = gx - (float)ix;
-    g.fy = gy - (float)iy;
-    g.fz = gz - (float)iz;
-    const long long nx = R.nx, nxy = (long long)R.nx * R.ny;
-    const long long base = (long long)iz * nxy + (long long)iy * nx + ix;
-    const long long mt = (long long)type * R.map_stride + base;
-    const long long me = (long long)kTypes * R.map_stride + 2 * base;   // interleaved with md
-    const long long md = me + 1;
+    const uint32_t ix = (uint32_t)gx, iy = (uint32_t)gy, iz = (uint32_t)gz;
+    g.fx = __builtin_amdgcn_fractf(gx);   // gx - floor(gx), exact
+    g.fy = __builtin_amdgcn_fractf(gy);
+    g.fz = __builtin_amdgcn_fractf(gz);
+    const uint32_t nx = (uint32_t)R.nx, nxy = (uint32_t)R.nx * (uint32_t)R.ny;
+    const uint32_t base = (iz * (uint32_t)R.ny + iy) * nx + ix;
+    const uint32_t ot = (base + tofs) * ES, ot1 = ot + nx * ES;        // type map, rows y and y+1
+    const uint32_t oe = base * (2 * ES), oe1 = oe + nx * (2 * ES);     // interleaved maps
+    const uint32_t sz = nxy * ES;                                       // +z, type map
+    const uint32_t se = (uint32_t)kTypes * (uint32_t)R.map_stride * ES;   // interleaved maps' base
+    const uint32_t sez = se + 2 * sz;
+    if constexpr (PREC == 0) {
+      const uint32_t o[4] = {ot, ot1, ot, ot1}, so[4] = {0u, 0u, sz, sz};
+      const uint32_t oq[4] = {oe, oe1, oe, oe1}, sq[4] = {se, se, sez, sez};
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const long long off = ((k >> 2) & 1) * nxy + ((k >> 1) & 1) * nx + (k & 1);
-      g.mt[k] = map_at<PREC>(R.maps, mt + off);
-      g.me[k] = map_at<PREC>(R.maps, me + 2 * off);
-      g.md[k] = map_at<PREC>(R.maps, md + 2 * off);
+      for (int c = 0; c < 4; ++c) {
+        const auto t = __builtin_amdgcn_raw_buffer_load_b64(rs, o[c], so[c], 0);
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, oq[c], sq[c], 0);
+        g.mt[2 * c] = __uint_as_float(t[0]);
+        g.mt[2 * c + 1] = __uint_as_float(t[1]);
+        g.me[2 * c] = __uint_as_float(v[0]);
+        g.md[2 * c] = __uint_as_float(v[1]);
+        g.me[2 * c + 1] = __uint_as_float(v[2]);
+        g.md[2 * c + 1] = __uint_as_float(v[3]);
+      }
+    } else {
+      const uint32_t o[4] = {ot, ot1, ot, ot1}, so[4] = {0u, 0u, sz, sz};
+      const uint32_t oq[4] = {oe, oe1, oe, oe1}, sq[4] = {se, se, sez, sez};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const uint32_t t = __builtin_amdgcn_raw_buffer_load_b32(rs, o[c], so[c], 0);
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, oq[c], sq[c], 0);
+        unpack2<PREC>(t, g.mt[2 * c], g.mt[2 * c + 1]);
+        unpack2<PREC>(v[0], g.me[2 * c], g.md[2 * c]);
+        unpack2<PREC>(v[1], g.me[2 * c + 1], g.md[2 * c + 1]);
+      }
     }
   }
 }
@@ -305,19 +349,18 @@ __device__ __forceinline__ float grid_finish(const RecDev& R, const GridFetch& g
   const float aq = fabsf(g.q);
 #pragma unroll
   for (int k = 0; k < 8; ++k) c[k] = g.mt[k] + g.q * g.me[k] + aq * g.md[k];
+  // lerps a + f (b - a): the differences they form along x, y and z are the gradient's parts
   const float fx = g.fx, fy = g.fy, fz = g.fz;
-  const float ux = 1.f - fx, uy = 1.f - fy, uz = 1.f - fz;
-  const float x00 = ux * c[0] + fx * c[1];
-  const float x10 = ux * c[2] + fx * c[3];
-  const float x01 = ux * c[4] + fx * c[5];
-  const float x11 = ux * c[6] + fx * c[7];
-  const float y0 = uy * x00 + fy * x10;
-  const float y1 = uy * x01 + fy * x11;
-  const float v = uz * y0 + fz * y1;
   const float d00 = c[1] - c[0], d10 = c[3] - c[2], d01 = c[5] - c[4], d11 = c[7] - c[6];
-  dx = (uz * (uy * d00 + fy * d10) + fz * (uy * d01 + fy * d11)) * R.inv_h;
-  dy = (uz * (x10 - x00) + fz * (x11 - x01)) * R.inv_h;
-  dz = (y1 - y0) * R.inv_h;
+  const float x00 = c[0] + fx * d00, x10 = c[2] + fx * d10, x01 = c[4] + fx * d01, x11 = c[6] + fx * d11;
+  const float e0 = x10 - x00, e1 = x11 - x01;
+  const float y0 = x00 + fy * e0, y1 = x01 + fy * e1;
+  const float ez = y1 - y0;
+  const float v = y0 + fz * ez;
+  const float gx0 = d00 + fy * (d10 - d00), gx1 = d01 + fy * (d11 - d01);
+  dx = (gx0 + fz * (gx1 - gx0)) * R.inv_h;
+  dy = (e0 + fz * (e1 - e0)) * R.inv_h;
+  dz = ez * R.inv_h;
   return v;
 }
 
@@ -328,7 +371,9 @@ __device__ __forceinline__ float grid_finish(const RecDev& R, const GridFetch& g
 // by exp2, and one reciprocal that serves both 1/eps and d eps/dr / eps:
 //   eps = A + B/den = D/den with D = A den + B, so 1/eps = den^2 q and
 //   (d eps/dr)/eps = B k lambda B e q, where q = 1/(den D).
-__device__ __forceinline__ float pair_term(float r2, bool hb, float4 c, float& f_over_r) {
+// HB: 0 every pair 12-6, 2 per pair (12-10 where c.y < 0); |c.y| is the coefficient either way.
+template <int HB>
+__device__ __forceinline__ float pair_term(float r2, float4 c, float& f_over_r) {
   // No automatic contraction here: every fused multiply-add is written out, so the energy-only
   // and the gradient instantiations compute the energy with the same operations.
 #pragma clang fp contract(off)
@@ -339,14 +384,14 @@ __device__ __forceinline__ float pair_term(float r2, bool hb, float4 c, float& f
   const float ir2 = ir * ir;
   const float ir6 = ir2 * ir2 * ir2;
   const float ir12 = ir6 * ir6;
+  const bool hb = HB == 2 && c.y < 0.f;
+  const float cy = fabsf(c.y);
   const float irn = hb ? ir6 * ir2 * ir2 : ir6;
   const float nn = hb ? 10.f : 6.f;
   const float a12 = c.x * ir12;
-  const float elj = __builtin_fmaf(-c.y, irn, a12);
-  const float dlj = __builtin_fmaf(nn * c.y, irn, -12.f * a12) * ir;
+  const float elj = __builtin_fmaf(-cy, irn, a12);
   const float gs = __builtin_amdgcn_exp2f(rt2 * (-1.4426950408889634f / (2.f * kDesolvSigma * kDesolvSigma)));
   const float eds = c.w * gs;
-  const float dds = (rt * (-1.f / (kDesolvSigma * kDesolvSigma))) * eds;
   // electrostatics with the distance-dependent dielectric, inside the 20.48 A cutoff
   const float ex = __builtin_amdgcn_exp2f(rt * (-kDielLambda * kDielB * 1.4426950408889634f));
   const float den = __builtin_fmaf(kDielK, ex, 1.f);
@@ -354,37 +399,57 @@ __device__ __forceinline__ float pair_term(float r2, bool hb, float4 c, float& f
   const float q = __builtin_amdgcn_rcpf(den * D);
   const float ieps = (den * den) * q;
   const float eel = (c.z * ir) * ieps;
-  const float del = __builtin_fmaf(ex * (kDielB * kDielK * kDielLambda * kDielB), q, ir) * -eel;
   const bool in1 = r2 < kCutoff * kCutoff, in2 = r2 < kCutoffEl * kCutoffEl;
   const float e = (in1 ? elj + eds : 0.f) + (in2 ? eel : 0.f);
-  const float dedr = (in1 ? dlj + dds : 0.f) + (in2 ? del : 0.f);
-  f_over_r = (r2 < kRmin * kRmin) ? 0.f : dedr * ir;
+  // (dE/dr) / r of each term: the 12-6 / 12-10 part, the Gaussian's -E / sigma^2, and the
+  // electrostatic -E_el (1/r + eps'/eps) / r; zero below R_MIN
+  const float flj = __builtin_fmaf(nn * cy, irn, -12.f * a12) * ir2;
+  const float fds = eds * (-1.f / (kDesolvSigma * kDesolvSigma));
+  const float fel = (__builtin_fmaf(ex * (kDielB * kDielK * kDielLambda * kDielB), q, ir) * -eel) * ir;
+  const bool lo = r2 >= kRmin * kRmin;
+  f_over_r = (in1 && lo ? flj + fds : 0.f) + (in2 && lo ? fel : 0.f);
   return e;
 }
 
 // The pair rows.  Within a lane group no atom occurs twice in a row and a wave's LDS operations
 // complete in order, so each lane adds its pair's force, (dE/dr / r)(x_i - x_j) on i and its
-// negative on j, into its group's force copy with a plain read-modify-write.  Software
-// pipelined one row deep: a row's force entries and the next row's records are requested before
-// the row's arithmetic, the next row's coordinates before its force writes (the coordinates are
-// not written here, and the force reads follow the previous row's writes in program order).
+// negative on j, into its group's force copy with a plain read-modify-write.  A slot holds the
+// byte offsets 4 i | 4 j << 16 of its atoms' entries, so each address is one add.  The H-bond
+// pairs sit in the first rows, so the rows after them skip the per-slot choice of the 12-10
+// form.  Software pipelined one row deep: a row's force entries and the next row's
+// records are requested before the row's arithmetic, the next row's coordinates before its force
+// writes (the coordinates are not written here, and the force reads follow the previous row's
+// writes in program order); the loop is unrolled by two, and the pair arrays hold one row past
+// every span (the next class's first row or a padding row), so the prefetch needs no clamp.
 // A two-row-deep pipeline measured slower: its extra registers cost a wave per SIMD.  Each lane
 // adds its slots' energies in row order, so the energy-only and gradient paths agree bitwise.
 struct P3 {
   float x, y, z;
 };
 
-__device__ __forceinline__ P3 load_p3(const float4* a, int k) {
-  const float4* p = a + k;
-  return P3{p->x, p->y, p->z};
+// x, y, z at byte offset `off` of a coordinate or force array of pitch 64A + 1
+template <int A>
+__device__ __forceinline__ P3 load_p3b(const char* base, uint32_t off) {
+  constexpr int P = kWave * A + 1;
+  const float* p = reinterpret_cast<const float*>(base + off);
+  return P3{p[0], p[P], p[2 * P]};
 }
 
-template <bool GRAD>
-__device__ __forceinline__ float pair_slot(uint32_t ij, float4 c, P3 xi, P3 xj, P3& fi, P3& fj) {
+template <int A>
+__device__ __forceinline__ void store_p3b(char* base, uint32_t off, P3 v) {
+  constexpr int P = kWave * A + 1;
+  float* p = reinterpret_cast<float*>(base + off);
+  p[0] = v.x;
+  p[P] = v.y;
+  p[2 * P] = v.z;
+}
+
+template <bool GRAD, int HB>
+__device__ __forceinline__ float pair_slot(float4 c, P3 xi, P3 xj, P3& fi, P3& fj) {
   const float dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
   const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
   float fr;
-  const float e = pair_term(r2, (ij >> 16) & 1u, c, fr);
+  const float e = pair_term<HB>(r2, c, fr);
   if (GRAD) {
     const float fx = fr * dx, fy = fr * dy, fz = fr * dz;
     fi.x += fx;
@@ -397,54 +462,61 @@ __device__ __forceinline__ float pair_slot(uint32_t ij, float4 c, P3 xi, P3 xj, 
   return e;
 }
 
-template <bool GRAD, bool FROM_LDS>
-__device__ __forceinline__ void pair_span(const LigDev& L, const BlockLds& b, int r0, int r1, float& e) {
-  if (r0 >= r1) return;
-  const int lane = lane_id();
-  const uint32_t* pij = FROM_LDS ? b.pair_ij : L.pair_ij;
-  const float4* pc = FROM_LDS ? b.pair_coef : L.pair_coef;
-  // slot addresses: the lane's offset plus a wave-uniform row offset
-  const uint32_t* pij_l = pij + lane;
-  const float4* pc_l = pc + lane;
-  uint32_t ij = pij_l[r0 * kWave];
-  float4 c = pc_l[r0 * kWave];
-  P3 xi = load_p3(b.x, ij & 0xff), xj = load_p3(b.x, (ij >> 8) & 0xff);
-  for (int r = r0; r < r1; ++r) {
-    const int i = ij & 0xff, j = (ij >> 8) & 0xff;
-    P3 fi, fj;
-    if (GRAD) {
-      fi = load_p3(b.fg, i);
-      fj = load_p3(b.fg, j);
-    }
-    const int rn = min(r + 1, r1 - 1) * kWave;   // the last row prefetches itself
-    const uint32_t ij_n = pij_l[rn];
-    const float4 c_n = pc_l[rn];
-    e += pair_slot<GRAD>(ij, c, xi, xj, fi, fj);
-    const int i_n = ij_n & 0xff, j_n = (ij_n >> 8) & 0xff;
-    const P3 xi_n = load_p3(b.x, i_n), xj_n = load_p3(b.x, j_n);
-    if (GRAD) {
-      float4* pi = b.fg + i;
-      float4* pj = b.fg + j;
-      pi->x = fi.x;
-      pi->y = fi.y;
-      pi->z = fi.z;
-      pj->x = fj.x;
-      pj->y = fj.y;
-      pj->z = fj.z;
-    }
-    ij = ij_n;
-    c = c_n;
-    xi = xi_n;
-    xj = xj_n;
+// One row: this row's slot (ij, c) with its coordinates (xi, xj) already loaded; requests the
+// next row's slot from (nij, nc) and its coordinates.
+template <int A, bool GRAD, int HB>
+__device__ __forceinline__ void pair_row(const char* xs, char* fs, uint32_t ij, float4 c, P3 xi, P3 xj,
+                                         const uint32_t* nij, const float4* nc, uint32_t& ij_n, float4& c_n,
+                                         P3& xi_n, P3& xj_n, float& e) {
+  const uint32_t oi = ij & 0xffffu, oj = ij >> 16;
+  P3 fi, fj;
+  if (GRAD) {
+    fi = load_p3b<A>(fs, oi);
+    fj = load_p3b<A>(fs, oj);
+  }
+  ij_n = *nij;
+  c_n = *nc;
+  e += pair_slot<GRAD, HB>(c, xi, xj, fi, fj);
+  xi_n = load_p3b<A>(xs, ij_n & 0xffffu);
+  xj_n = load_p3b<A>(xs, ij_n >> 16);
+  if (GRAD) {
+    store_p3b<A>(fs, oi, fi);
+    store_p3b<A>(fs, oj, fj);
   }
 }
 
-// Pair rows [r0, r1): the staged prefix from LDS, the rest from global memory.
-template <bool GRAD>
+template <int A, bool GRAD, bool FROM_LDS, int HB>
+__device__ __forceinline__ void pair_span(const LigDev& L, const BlockLds& b, int r0, int r1, float& e) {
+  if (r0 >= r1) return;
+  const int lane = lane_id();
+  const uint32_t* pij = (FROM_LDS ? b.pair_ij : L.pair_ij) + lane + (size_t)r0 * kWave;
+  const float4* pc = (FROM_LDS ? b.pair_coef : L.pair_coef) + lane + (size_t)r0 * kWave;
+  const char* xs = reinterpret_cast<const char*>(b.x);
+  char* fs = reinterpret_cast<char*>(b.fg);
+  uint32_t ij0 = pij[0], ij1;
+  float4 c0 = pc[0], c1;
+  P3 xi0 = load_p3b<A>(xs, ij0 & 0xffffu), xj0 = load_p3b<A>(xs, ij0 >> 16), xi1, xj1;
+  int r = r0;
+  for (; r + 2 <= r1; r += 2) {
+    pair_row<A, GRAD, HB>(xs, fs, ij0, c0, xi0, xj0, pij + kWave, pc + kWave, ij1, c1, xi1, xj1, e);
+    pair_row<A, GRAD, HB>(xs, fs, ij1, c1, xi1, xj1, pij + 2 * kWave, pc + 2 * kWave, ij0, c0, xi0, xj0, e);
+    pij += 2 * kWave;
+    pc += 2 * kWave;
+  }
+  if (r < r1) pair_row<A, GRAD, HB>(xs, fs, ij0, c0, xi0, xj0, pij + kWave, pc + kWave, ij1, c1, xi1, xj1, e);
+}
+
+// Pair rows [r0, r1): the staged prefix from LDS, the rest from global memory; the rows that may
+// hold H-bond pairs [0, mix_rows) first, then the others.  In row order, so every caller adds
+// alike.
+template <int A, bool GRAD>
 __device__ __forceinline__ float pair_rows(const LigDev& L, const BlockLds& b, int r0, int r1) {
   float e = 0.f;
-  pair_span<GRAD, true>(L, b, r0, min(r1, L.pl_rows), e);
-  pair_span<GRAD, false>(L, b, max(r0, L.pl_rows), r1, e);
+  const int h = L.mix_rows, s = L.pl_rows;
+  pair_span<A, GRAD, true, 2>(L, b, r0, min(min(r1, h), s), e);
+  pair_span<A, GRAD, false, 2>(L, b, max(r0, s), min(r1, h), e);
+  pair_span<A, GRAD, true, 0>(L, b, max(r0, h), min(r1, s), e);
+  pair_span<A, GRAD, false, 0>(L, b, max(max(r0, h), s), r1, e);
   return e;
 }
 
@@ -470,60 +542,6 @@ __device__ __forceinline__ void share_rows(int n_rows, int w, int& r0, int& r1) 
     }
     start += take;
   }
-}
-
-// Torsion gradients: for torsion k (posed axis u_k and pivot p_k, held in lane k) the sum over
-// the atoms it moves of u_k . ((x - p_k) x F).  Torsions go in batches of four: each lane forms
-// its atoms' terms for the batch's torsions kb..kb+3, then a reduce-scatter with gfx950's
-// register-half swaps (no lane addresses, no LDS) leaves the 16 lanes of row r holding parts of
-// torsion kb + r's sum -- v_permlane32_swap pairs torsions (kb, kb+2) and (kb+1, kb+3) across the
-// wave halves, v_permlane16_swap pairs the results across rows -- and the row's DPP sum (the
-// first four steps of wave_sum) completes it.  Gene lane L (torsion tk) reads its torsion's row.
-template <int A>
-__device__ __forceinline__ float torsion_gradients(const AtomRegs<A>& at, int T, float3 tu, float3 tp,
-                                                   const float* x, const float* y, const float* z,
-                                                   const float* Fx, const float* Fy, const float* Fz,
-                                                   int kb0 = 0, int kb_step = 4) {
-  const int tk = at.tor_of_gene;
-  float g = 0.f;
-  for (int kb = kb0; kb < T; kb += kb_step) {
-    float c[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int k = kb + j;
-      c[j] = 0.f;
-      if (k < T) {
-        const float ux = readlane(tu.x, k), uy = readlane(tu.y, k), uz = readlane(tu.z, k);
-        const float px = readlane(tp.x, k), py = readlane(tp.y, k), pz = readlane(tp.z, k);
-#pragma unroll
-        for (int a = 0; a < A; ++a) {
-          if ((at.mask[a] >> k) & 1u) {
-            const float rx = x[a] - px, ry = y[a] - py, rz = z[a] - pz;
-            const float cx = ry * Fz[a] - rz * Fy[a];
-            const float cy = rz * Fx[a] - rx * Fz[a];
-            const float cz = rx * Fy[a] - ry * Fx[a];
-            c[j] += ux * cx + uy * cy + uz * cz;
-          }
-        }
-      }
-    }
-    // lanes 0-31 end with torsion kb (h0) / kb+1 (h1) summed over both halves, lanes 32-63
-    // with kb+2 / kb+3
-    const auto s0 = __builtin_amdgcn_permlane32_swap(__float_as_uint(c[0]), __float_as_uint(c[2]), false, false);
-    const auto s1 = __builtin_amdgcn_permlane32_swap(__float_as_uint(c[1]), __float_as_uint(c[3]), false, false);
-    const float h0 = __uint_as_float(s0[0]) + __uint_as_float(s0[1]);
-    const float h1 = __uint_as_float(s1[0]) + __uint_as_float(s1[1]);
-    // rows 0, 1, 2, 3 end with torsions kb, kb+1, kb+2, kb+3
-    const auto s2 = __builtin_amdgcn_permlane16_swap(__float_as_uint(h0), __float_as_uint(h1), false, false);
-    float v = __uint_as_float(s2[0]) + __uint_as_float(s2[1]);
-    v += dpp<0xb1, 0xf>(v);    // quad_perm [1,0,3,2]
-    v += dpp<0x4e, 0xf>(v);    // quad_perm [2,3,0,1]
-    v += dpp<0x141, 0xf>(v);   // row_half_mirror
-    v += dpp<0x140, 0xf>(v);   // row_mirror
-    const float mine = __shfl(v, ((tk - kb) & 3) * 16, kWave);
-    if (tk >= kb && tk < kb + 4) g = mine;
-  }
-  return g;
 }
 
 // ------------------------------------------------------------------ one pose
@@ -562,6 +580,71 @@ __device__ __forceinline__ Rigid rigid_of(float xg) {
   return r;
 }
 
+// Torsion gradients: for torsion k (posed axis u_k, posed pivot p_k) the sum over the atoms it
+// moves of u_k . ((x - p_k) x F).  With r = x - t and s_k = p_k - t (t the pose's translation,
+// so both stay short) that term is u_k . (r x F) - F . (u_k x s_k): each lane forms r x F of its
+// atoms once, and per torsion only two dot products remain, with u_k and m_k = u_k x s_k read
+// from the wave's torsion table (torsion_axes).  Torsions go in batches of four: each lane forms
+// its atoms' terms for the batch's torsions kb..kb+3, then a reduce-scatter with gfx950's
+// register-half swaps (no lane addresses, no LDS) leaves the 16 lanes of row r holding parts of
+// torsion kb + r's sum -- v_permlane32_swap pairs torsions (kb, kb+2) and (kb+1, kb+3) across the
+// wave halves, v_permlane16_swap pairs the results across rows -- and the row's DPP sum (the
+// first four steps of wave_sum) completes it.  Gene lane L (torsion tk) reads its torsion's row.
+template <int A>
+__device__ __forceinline__ float torsion_gradients(const LigDev& L, const AtomRegs<A>& at, int T, const float4* tor,
+                                                   const Rigid& rb, const float* x, const float* y, const float* z,
+                                                   const float* Fx, const float* Fy, const float* Fz,
+                                                   int kb0 = 0, int kb_step = 4) {
+  const int tk = at.tor_of_gene;
+  float tqx[A], tqy[A], tqz[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) {
+    const float rx = x[a] - rb.tx, ry = y[a] - rb.ty, rz = z[a] - rb.tz;
+    tqx[a] = ry * Fz[a] - rz * Fy[a];
+    tqy[a] = rz * Fx[a] - rx * Fz[a];
+    tqz[a] = rx * Fy[a] - ry * Fx[a];
+  }
+  float g = 0.f;
+  for (int kb = kb0; kb < T; kb += kb_step) {
+    // the batch's four table entries first (the table is padded to a multiple of four torsions),
+    // so one wait covers them
+    float4 u[4], m[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      u[j] = tor[2 * (kb + j)];
+      m[j] = tor[2 * (kb + j) + 1];
+    }
+    float c[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = kb + j;
+      c[j] = 0.f;
+#pragma unroll
+      for (int a = 0; a < A; ++a) {
+        const float t = (u[j].x * tqx[a] + u[j].y * tqy[a] + u[j].z * tqz[a]) -
+                        (m[j].x * Fx[a] + m[j].y * Fy[a] + m[j].z * Fz[a]);
+        if (k < T && ((at.mask[a] >> k) & 1u)) c[j] += t;
+      }
+    }
+    // lanes 0-31 end with torsion kb (h0) / kb+1 (h1) summed over both halves, lanes 32-63
+    // with kb+2 / kb+3
+    const auto s0 = __builtin_amdgcn_permlane32_swap(__float_as_uint(c[0]), __float_as_uint(c[2]), false, false);
+    const auto s1 = __builtin_amdgcn_permlane32_swap(__float_as_uint(c[1]), __float_as_uint(c[3]), false, false);
+    const float h0 = __uint_as_float(s0[0]) + __uint_as_float(s0[1]);
+    const float h1 = __uint_as_float(s1[0]) + __uint_as_float(s1[1]);
+    // rows 0, 1, 2, 3 end with torsions kb, kb+1, kb+2, kb+3
+    const auto s2 = __builtin_amdgcn_permlane16_swap(__float_as_uint(h0), __float_as_uint(h1), false, false);
+    float v = __uint_as_float(s2[0]) + __uint_as_float(s2[1]);
+    v += dpp<0xb1, 0xf>(v);    // quad_perm [1,0,3,2]
+    v += dpp<0x4e, 0xf>(v);    // quad_perm [2,3,0,1]
+    v += dpp<0x141, 0xf>(v);   // row_half_mirror
+    v += dpp<0x140, 0xf>(v);   // row_mirror
+    const float mine = __shfl(v, ((tk - kb) & 3) * 16, kWave);
+    if (tk >= kb && tk < kb + 4) g = mine;
+  }
+  return g;
+}
+
 // Lane k < T writes torsion k's rotation about its reference-frame axis through its reference
 // pivot as x -> M x + t (Rodrigues: M = c I + s [u]x + (1 - c) u u^T, t = p - M p) into the wave's
 // torsion table, from which the atom loop reads it with broadcast loads.
@@ -590,8 +673,8 @@ __device__ __forceinline__ void build_torsion_table(const AtomRegs<A>& at, float
 // Posed coordinates of this lane's atom slots a with use[a]: torsions from the deepest to the
 // root-most (each applied by the lanes whose atom it moves), then orientation and translation.
 template <int A>
-__device__ __forceinline__ void pose_slots(const AtomRegs<A>& at, const float4* tor, const Rigid& rb, int T,
-                                           const bool (&use)[A], float (&x)[A], float (&y)[A], float (&z)[A]) {
+__device__ __forceinline__ void pose_slots(const LigDev& L, const AtomRegs<A>& at, const float4* tor, const Rigid& rb,
+                                           int T, const bool (&use)[A], float (&x)[A], float (&y)[A], float (&z)[A]) {
   float px[A], py[A], pz[A];
 #pragma unroll
   for (int a = 0; a < A; ++a) {
@@ -599,8 +682,12 @@ __device__ __forceinline__ void pose_slots(const AtomRegs<A>& at, const float4* 
     py[a] = at.py[a];
     pz[a] = at.pz[a];
   }
+  // torsion k's transform is applied while torsion k - 1's is being read
+  float4 m0 = T > 0 ? tor[3 * (T - 1) + 0] : float4{}, m1 = T > 0 ? tor[3 * (T - 1) + 1] : float4{},
+         m2 = T > 0 ? tor[3 * (T - 1) + 2] : float4{};
   for (int k = T - 1; k >= 0; --k) {
-    const float4 m0 = tor[3 * k + 0], m1 = tor[3 * k + 1], m2 = tor[3 * k + 2];
+    const int kn = max(k - 1, 0);
+    const float4 n0 = tor[3 * kn + 0], n1 = tor[3 * kn + 1], n2 = tor[3 * kn + 2];
 #pragma unroll
     for (int a = 0; a < A; ++a) {
       if (use[a] && ((at.mask[a] >> k) & 1u)) {
@@ -610,6 +697,9 @@ __device__ __forceinline__ void pose_slots(const AtomRegs<A>& at, const float4* 
         pz[a] = m2.x * ox + m2.y * oy + m2.z * oz + m2.w;
       }
     }
+    m0 = n0;
+    m1 = n1;
+    m2 = n2;
   }
 #pragma unroll
   for (int a = 0; a < A; ++a) {
@@ -624,17 +714,19 @@ template <int A>
 __device__ __forceinline__ void sum_force_copies(const LigDev& L, const BlockLds& b, const AtomRegs<A>& at,
                                                  float (&Fx)[A], float (&Fy)[A], float (&Fz)[A]) {
   const int lane = lane_id();
-  const int N = L.n_atoms, K = L.n_copies;
+  const int K = L.n_copies;
+  const int cs = (int)(lds_coord_bytes(A) / 4);   // floats per copy
 #pragma unroll
   for (int a = 0; a < A; ++a) {
     if (at.valid[a]) {
       const int i = lane + kWave * a;
       for (int g = 0; g < K; ++g) {
-        const float4 v = b.f[g * (N + 1) + i];
+        float* c = b.f + g * cs;
+        const float3 v = load3<A>(c, i);
         Fx[a] += v.x;
         Fy[a] += v.y;
         Fz[a] += v.z;
-        b.f[g * (N + 1) + i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        store3<A>(c, i, 0.f, 0.f, 0.f);
       }
     }
   }
@@ -703,18 +795,23 @@ __device__ __forceinline__ float rigid_gradient(const Rigid& rb, const float (&x
   return g;
 }
 
-// Lane k < T: the posed axis and pivot of torsion k, from the posed coordinates xs.
+// Lane k < T: torsion k's posed axis u_k (from the posed coordinates xs of its two atoms) and
+// u_k x (p_k - t), p_k its posed pivot and t the pose's translation, into the wave's torsion
+// table as tor[2k] and tor[2k + 1] (the posing has finished reading the table's rotations).
 template <int A>
-__device__ __forceinline__ void torsion_axes(const AtomRegs<A>& at, const float4* xs, int T, float3& tu, float3& tp) {
-  tu = make_float3(0.f, 0.f, 0.f);
-  tp = make_float3(0.f, 0.f, 0.f);
-  if (lane_id() < T) {
-    const float4 xa = xs[at.ta], xb = xs[at.tb];
+__device__ __forceinline__ void torsion_axes(const AtomRegs<A>& at, const float* xs, int T, const Rigid& rb,
+                                             float4* tor) {
+  const int lane = lane_id();
+  if (lane < T) {
+    const float3 xa = load3<A>(xs, at.ta), xb = load3<A>(xs, at.tb);
     const float ux = xb.x - xa.x, uy = xb.y - xa.y, uz = xb.z - xa.z;
     const float il = __builtin_amdgcn_rsqf(ux * ux + uy * uy + uz * uz);
-    tu = make_float3(ux * il, uy * il, uz * il);
-    tp = make_float3(xa.x, xa.y, xa.z);
+    const float nx = ux * il, ny = uy * il, nz = uz * il;
+    const float sx = xa.x - rb.tx, sy = xa.y - rb.ty, sz = xa.z - rb.tz;
+    tor[2 * lane] = make_float4(nx, ny, nz, 0.f);
+    tor[2 * lane + 1] = make_float4(ny * sz - nz * sy, nz * sx - nx * sz, nx * sy - ny * sx, 0.f);
   }
+  wave_sync();
 }
 
 // Energy (returned, identical in every lane) and, with GRAD, the gradient component of
@@ -731,18 +828,19 @@ __device__ float eval_pose_one(const LigDev& L, const RecDev& R, const BlockLds&
 #pragma unroll
   for (int a = 0; a < A; ++a) all[a] = true;
   float x[A], y[A], z[A];
-  pose_slots<A>(at, b.tor, rb, T, all, x, y, z);
+  pose_slots<A>(L, at, b.tor, rb, T, all, x, y, z);
 #pragma unroll
-  for (int a = 0; a < A; ++a) b.x[lane + kWave * a] = make_float4(x[a], y[a], z[a], 0.f);
+  for (int a = 0; a < A; ++a) store3<A>(b.x, lane + kWave * a, x[a], y[a], z[a]);
 
   // grid term: issue the corner loads now, finish after the pair term
   GridFetch gf[A];
+  const __amdgpu_buffer_rsrc_t rs = map_rsrc(R);
 #pragma unroll
-  for (int a = 0; a < A; ++a) grid_fetch<PREC>(R, x[a], y[a], z[a], at.type[a], at.q[a], at.valid[a], gf[a]);
+  for (int a = 0; a < A; ++a) grid_fetch<PREC>(R, rs, x[a], y[a], z[a], at.tofs[a], at.q[a], at.valid[a], gf[a]);
   wave_sync();
 
   // intramolecular pairs; with GRAD each atom then sums (and clears) its force copies
-  float e_lane = pair_rows<GRAD>(L, b, 0, L.n_rows);
+  float e_lane = pair_rows<A, GRAD>(L, b, 0, L.n_rows);
   float Fx[A], Fy[A], Fz[A];
 #pragma unroll
   for (int a = 0; a < A; ++a) Fx[a] = Fy[a] = Fz[a] = 0.f;
@@ -761,9 +859,8 @@ __device__ float eval_pose_one(const LigDev& L, const RecDev& R, const BlockLds&
   // torsions: every lane forms, for every torsion k, axis . (arm x force) of its atoms that k
   // moves, and reduce-scatters across the wave sum four torsions at a time
   if (T > 0) {
-    float3 tu, tp;
-    torsion_axes<A>(at, b.x, T, tu, tp);
-    const float gk = torsion_gradients<A>(at, T, tu, tp, x, y, z, Fx, Fy, Fz);
+    torsion_axes<A>(at, b.x, T, rb, b.tor);
+    const float gk = torsion_gradients<A>(L, at, T, b.tor, rb, x, y, z, Fx, Fy, Fz);
     if (lane >= 7 && lane < L.n_genes) g = gk;
   }
   g_out = g;
@@ -786,9 +883,10 @@ __device__ float eval_pose_shared(const LigDev& L, const RecDev& R, const BlockL
   const int lane = lane_id();
   const int T = L.n_tors;
   const int N = L.n_atoms;
-  float4* X = b.share;                                          // [64A + 1] posed coordinates
-  float* GG = reinterpret_cast<float*>(X + kWave * A + 1);      // [64] torsion gradients by gene lane
-  float4* sets = X + kWave * A + 1 + kWave / 4;                 // two share sets
+  float* X = reinterpret_cast<float*>(b.share);                 // [3][64A + 1] posed coordinates
+  unsigned char* sb = reinterpret_cast<unsigned char*>(b.share) + lds_coord_bytes(A);
+  float* GG = reinterpret_cast<float*>(sb);                     // [64] torsion gradients by gene lane
+  float4* sets = reinterpret_cast<float4*>(sb + 4 * kWave);     // two share sets
   const Rigid rb = rigid_of(xg);
 
   // pose of this wave's slot (waves >= A have none) and its grid loads
@@ -799,22 +897,23 @@ __device__ float eval_pose_shared(const LigDev& L, const RecDev& R, const BlockL
     gv[a] = at.valid[a] && mine[a];
   }
   GridFetch gf[A];
+  const __amdgpu_buffer_rsrc_t rs = map_rsrc(R);
   if (ps.w < A) {
     build_torsion_table<A>(at, b.tor, xg, T);
     float x[A], y[A], z[A];
-    pose_slots<A>(at, b.tor, rb, T, mine, x, y, z);
+    pose_slots<A>(L, at, b.tor, rb, T, mine, x, y, z);
 #pragma unroll
     for (int a = 0; a < A; ++a) {
       if (mine[a]) {
-        X[lane + kWave * a] = make_float4(x[a], y[a], z[a], 0.f);
-        grid_fetch<PREC>(R, x[a], y[a], z[a], at.type[a], at.q[a], gv[a], gf[a]);
+        store3<A>(X, lane + kWave * a, x[a], y[a], z[a]);
+        grid_fetch<PREC>(R, rs, x[a], y[a], z[a], at.tofs[a], at.q[a], gv[a], gf[a]);
       } else {
-        grid_fetch<PREC>(R, 0.f, 0.f, 0.f, at.type[a], at.q[a], false, gf[a]);
+        grid_fetch<PREC>(R, rs, 0.f, 0.f, 0.f, at.tofs[a], at.q[a], false, gf[a]);
       }
     }
   } else {
 #pragma unroll
-    for (int a = 0; a < A; ++a) grid_fetch<PREC>(R, 0.f, 0.f, 0.f, at.type[a], at.q[a], false, gf[a]);
+    for (int a = 0; a < A; ++a) grid_fetch<PREC>(R, rs, 0.f, 0.f, 0.f, at.tofs[a], at.q[a], false, gf[a]);
   }
   __syncthreads();
 
@@ -822,7 +921,7 @@ __device__ float eval_pose_shared(const LigDev& L, const RecDev& R, const BlockL
   float x[A], y[A], z[A];
 #pragma unroll
   for (int a = 0; a < A; ++a) {
-    const float4 v = X[lane + kWave * a];
+    const float3 v = load3<A>(X, lane + kWave * a);
     x[a] = v.x;
     y[a] = v.y;
     z[a] = v.z;
@@ -831,7 +930,7 @@ __device__ float eval_pose_shared(const LigDev& L, const RecDev& R, const BlockL
   bs.x = X;
   int r0, r1;
   share_rows<A, W>(L.n_rows, ps.w, r0, r1);
-  float e_lane = pair_rows<GRAD>(L, bs, r0, r1);
+  float e_lane = pair_rows<A, GRAD>(L, bs, r0, r1);
   float Fx[A], Fy[A], Fz[A];
 #pragma unroll
   for (int a = 0; a < A; ++a) Fx[a] = Fy[a] = Fz[a] = 0.f;
@@ -894,9 +993,8 @@ __device__ float eval_pose_shared(const LigDev& L, const RecDev& R, const BlockL
   float g = rigid_gradient<A>(rb, x, y, z, gfx, gfy, gfz, Fx, Fy, Fz);
   // this wave's torsion batches, published by gene lane, then every wave reads all
   if (T > 0) {
-    float3 tu, tp;
-    torsion_axes<A>(at, X, T, tu, tp);
-    const float gk = torsion_gradients<A>(at, T, tu, tp, x, y, z, Fx, Fy, Fz, 4 * ps.w, 4 * W);
+    torsion_axes<A>(at, X, T, rb, b.tor);
+    const float gk = torsion_gradients<A>(L, at, T, b.tor, rb, x, y, z, Fx, Fy, Fz, 4 * ps.w, 4 * W);
     const bool gene_t = lane >= 7 && lane < L.n_genes;
     if (gene_t && ((at.tor_of_gene >> 2) % W) == ps.w) GG[lane] = gk;
     __syncthreads();
@@ -939,7 +1037,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_eval(LigDev L, RecDev R, int n, c
   const int pose = block_pose<W>(ps);
   if (pose >= n) return;
   AtomRegs<A> at;
-  load_ligand<A>(L, at);
+  load_ligand<A>(L, at, R.map_stride);
   const int lane = lane_id();
   const int G = L.n_genes;
   const float xg = lane < G ? genes[(long long)pose * G + lane] : 0.f;
@@ -1102,7 +1200,7 @@ __global__ __launch_bounds__(kMaxBlock) MDOCK_SEARCH_OCCUPANCY void k_local_sear
   const int job = block_pose<W>(ps);
   if (job >= n) return;
   AtomRegs<A> at;
-  load_ligand<A>(L, at);
+  load_ligand<A>(L, at, R.map_stride);
   const long long tg = (long long)job * iters * L.n_genes;
   const float E = local_search_wave<A, PREC, W>(L, R, b, at, genes_in, job, genes_out, job, iters, rho, eps,
                                                 trace ? trace + (long long)job * iters : nullptr, ps,
@@ -1210,7 +1308,7 @@ __global__ __launch_bounds__(kMaxBlock) MDOCK_SEARCH_OCCUPANCY void k_solis_wets
   const int job = block_pose<W>(ps);
   if (job >= n) return;
   AtomRegs<A> at;
-  load_ligand<A>(L, at);
+  load_ligand<A>(L, at, R.map_stride);
   const uint64_t key = draw_prefix(seed, 0u, 0u, (uint32_t)job, kPLsSw);
   const float E = solis_wets_wave<A, PREC, W>(L, R, b, at, genes_in, job, genes_out, job, n_evals, key,
                                               trace ? trace + (long long)job * n_evals : nullptr, ps);
@@ -1350,7 +1448,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_ga_init(JobDev* __restrict__ jobs
   const int w = bt.y + threadIdx.x / kWave;
   if (w >= P.n_runs * P.pop_size) return;
   AtomRegs<A> at;
-  load_ligand<A>(L, at);
+  load_ligand<A>(L, at, R.map_stride);
   const int lane = lane_id();
   const int G = L.n_genes;
   const int run = w / P.pop_size, indiv = w % P.pop_size;
@@ -1396,7 +1494,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_ga_generation(JobDev* __restrict_
     return;
   }
   AtomRegs<A> at;
-  load_ligand<A>(L, at);
+  load_ligand<A>(L, at, R.map_stride);
   const float x = offspring_gene(P, genes_in, E, rbase, G, L.n_tors, run, gen, slot);
   float g;
   PoseShare ps{0, 0};
@@ -1450,7 +1548,7 @@ __global__ __launch_bounds__(kMaxBlock) MDOCK_SEARCH_OCCUPANCY void k_ga_local_s
   const int w = bt.y + (int)(threadIdx.x / kWave) / W;
   if (w >= P.n_runs * P.n_ls) return;
   AtomRegs<A> at;
-  load_ligand<A>(L, at);
+  load_ligand<A>(L, at, R.map_stride);
   const long long row = J.ls_rows[w];
   float* pop = J.genes[cur ^ 1];
   const float E = local_search_wave<A, PREC, W>(L, R, b, at, pop, row, pop, row, P.ls_iters, P.rho, P.eps,
@@ -1477,7 +1575,7 @@ __global__ __launch_bounds__(kMaxBlock) MDOCK_SEARCH_OCCUPANCY void k_ga_solis_w
   const int w = bt.y + (int)(threadIdx.x / kWave) / W;
   if (w >= P.n_runs * P.n_ls) return;
   AtomRegs<A> at;
-  load_ligand<A>(L, at);
+  load_ligand<A>(L, at, R.map_stride);
   const int row = J.ls_rows[w];
   const uint64_t key = draw_prefix(P.seed, (uint32_t)(row / P.pop_size), (uint32_t)gen,
                                    (uint32_t)(row % P.pop_size), kPLsSw);

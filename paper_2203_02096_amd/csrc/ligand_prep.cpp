@@ -191,8 +191,12 @@ std::string prepare_ligand(int n, const float* xyz, const int* type, const float
 // Pair schedule: rows of 64 slots, lanes split into groups of about N/div lanes in which no atom
 // occurs twice per row (so the kernel's per-group force updates never collide).  Greedy row by
 // row: the remaining pairs whose atoms have the most pairs left go first, each into the first
-// group where both of its atoms are still free.  Empty slots name the spare atom N.  Then the
-// LDS plan: per-wave buffers first, then as many pair rows as fit the block budget.
+// group where both of its atoms are still free.  The H-bond pairs go into the first rows (their
+// free slots then take other pairs), so the rows after them need no per-slot choice between the
+// 12-6 and 12-10 forms; when that layout takes more rows than one sequence of all pairs, the
+// latter is used and every row up to the last H-bond pair is mixed (mix_rows).  Empty slots name
+// the spare atom N.  Then the LDS plan: per-wave buffers first, then as many pair rows as fit the
+// block budget (plus the one row behind them that the pair loop prefetches).
 void plan_ligand(LigHost& out, const PlanParams& pp) {
   const int n = out.n_atoms;
   const int P = (int)out.raw_ij.size();
@@ -206,32 +210,40 @@ void plan_ligand(LigHost& out, const PlanParams& pp) {
     ++left[v & 0xff];
     ++left[(v >> 8) & 0xff];
   }
-  std::vector<int> rem(P);
-  std::iota(rem.begin(), rem.end(), 0);
-  std::vector<uint32_t> ij;
-  std::vector<float4> coef;
-  int groups_used = 0;
-  while (!rem.empty()) {
+  // One row under construction: its slots, the atoms each lane group already holds, and how far
+  // each group is filled.
+  struct Row {
+    std::vector<int> slot;
+    std::vector<uint64_t> used;
+    std::vector<int> fill;
+  };
+  auto new_row = [&]() {
+    Row r;
+    r.slot.assign(kWave, -1);
+    r.used.assign(2 * K, 0);
+    r.fill.resize(K);
+    for (int g = 0; g < K; ++g) r.fill[g] = g * m;
+    return r;
+  };
+  // places what fits of `rem` into the row (the pairs whose atoms have the most pairs left first,
+  // each into the first group where both atoms are still free) and keeps the rest in `rem`
+  auto fill_row = [&](Row& row, std::vector<int>& rem, std::vector<int>& left, int& groups_used) {
     std::stable_sort(rem.begin(), rem.end(), [&](int x, int y) {
       const uint32_t a = out.raw_ij[x], b = out.raw_ij[y];
       return left[a & 0xff] + left[(a >> 8) & 0xff] > left[b & 0xff] + left[(b >> 8) & 0xff];
     });
-    std::vector<int> slot(kWave, -1);
-    std::vector<uint64_t> used(2 * K, 0);
-    std::vector<int> fill(K);
-    for (int g = 0; g < K; ++g) fill[g] = g * m;
     std::vector<int> next;
     for (int p : rem) {
       const int i = out.raw_ij[p] & 0xff, j = (out.raw_ij[p] >> 8) & 0xff;
       bool placed = false;
       for (int g = 0; g < K && !placed; ++g) {
         const int end = std::min(kWave, (g + 1) * m);
-        const bool bi = (used[2 * g + (i >> 6)] >> (i & 63)) & 1u;
-        const bool bj = (used[2 * g + (j >> 6)] >> (j & 63)) & 1u;
-        if (fill[g] < end && !bi && !bj) {
-          slot[fill[g]++] = p;
-          used[2 * g + (i >> 6)] |= 1ull << (i & 63);
-          used[2 * g + (j >> 6)] |= 1ull << (j & 63);
+        const bool bi = (row.used[2 * g + (i >> 6)] >> (i & 63)) & 1u;
+        const bool bj = (row.used[2 * g + (j >> 6)] >> (j & 63)) & 1u;
+        if (row.fill[g] < end && !bi && !bj) {
+          row.slot[row.fill[g]++] = p;
+          row.used[2 * g + (i >> 6)] |= 1ull << (i & 63);
+          row.used[2 * g + (j >> 6)] |= 1ull << (j & 63);
           --left[i];
           --left[j];
           groups_used = std::max(groups_used, g + 1);
@@ -240,13 +252,56 @@ void plan_ligand(LigHost& out, const PlanParams& pp) {
       }
       if (!placed) next.push_back(p);
     }
-    const uint32_t pad = kPairPad | (uint32_t)n | ((uint32_t)n << 8);
-    for (int l = 0; l < kWave; ++l) {
-      ij.push_back(slot[l] < 0 ? pad : out.raw_ij[slot[l]]);
-      coef.push_back(slot[l] < 0 ? make_float4(0.f, 0.f, 0.f, 0.f) : out.raw_coef[slot[l]]);
-    }
     rem.swap(next);
+  };
+  std::vector<int> all(P), plain, hbond;
+  std::iota(all.begin(), all.end(), 0);
+  for (int p = 0; p < P; ++p) ((out.raw_ij[p] >> 16) & 1u ? hbond : plain).push_back(p);
+  // (a) every pair in one sequence of rows
+  std::vector<Row> rows_a;
+  int groups_a = 0;
+  {
+    std::vector<int> l = left;
+    while (!all.empty()) {
+      rows_a.push_back(new_row());
+      fill_row(rows_a.back(), all, l, groups_a);
+    }
   }
+  // (b) the H-bond pairs' rows first, their free slots filled with other pairs, then rows of
+  // other pairs only
+  std::vector<Row> rows_b;
+  int groups_b = 0;
+  {
+    std::vector<int> l = left;
+    while (!hbond.empty()) {
+      rows_b.push_back(new_row());
+      fill_row(rows_b.back(), hbond, l, groups_b);
+    }
+    for (Row& r : rows_b) fill_row(r, plain, l, groups_b);
+    while (!plain.empty()) {
+      rows_b.push_back(new_row());
+      fill_row(rows_b.back(), plain, l, groups_b);
+    }
+  }
+  // (b) spares the kernel the per-slot H-bond select on the rows after the H-bond rows; it is
+  // used unless it takes more rows (H-bond pairs concentrate on the few donor and acceptor atoms,
+  // which limits how many fit a conflict-free row)
+  const bool use_b = rows_b.size() <= rows_a.size();
+  const std::vector<Row>& rows = use_b ? rows_b : rows_a;
+  int mix = 0;
+  for (size_t r = 0; r < rows.size(); ++r)
+    for (int s2 : rows[r].slot)
+      if (s2 >= 0 && ((out.raw_ij[s2] >> 16) & 1u)) mix = (int)r + 1;
+  out.mix_rows = mix;
+  const int groups_used = use_b ? groups_b : groups_a;
+  std::vector<uint32_t> ij;
+  std::vector<float4> coef;
+  const uint32_t pad = kPairPad | (uint32_t)n | ((uint32_t)n << 8);
+  for (const Row& r : rows)
+    for (int l = 0; l < kWave; ++l) {
+      ij.push_back(r.slot[l] < 0 ? pad : out.raw_ij[r.slot[l]]);
+      coef.push_back(r.slot[l] < 0 ? make_float4(0.f, 0.f, 0.f, 0.f) : out.raw_coef[r.slot[l]]);
+    }
   out.n_pairs = P;
   out.n_rows = (int)(ij.size() / kWave);
   out.pair_ij.swap(ij);
