@@ -105,3 +105,52 @@ def test_shared_pose_layout(n, t, wpp):
     coords = -(-12 * (64 * A + 1) // 16) * 16
     assert shared["lds_bytes"] - alone["lds_bytes"] == coords + 4 * 64 + 2 * 16 * ((wpp + 1) * (n + 1) + wpp)
 
+
+
+_PREVIEW_SCRIPT = """
+import hashlib, sys
+sys.path.insert(0, sys.argv[1])
+import paper_2203_02096_amd as md
+from workload import configs, synth
+for n, t in ((20, 4), (65, 12), (128, 32)):
+    info, slots, m = md.md_schedule_preview(synth.make_ligand(n, t, 9000 + n, configs.type_params()))
+    print(n, sorted(info.items()), m, hashlib.sha256(slots.tobytes()).hexdigest())
+"""
+
+
+def _preview_digest(lig, **plan):
+    info, slots, m = md.md_schedule_preview(lig, **plan)
+    return sorted(info.items()), m, slots.tobytes()
+
+
+@pytest.mark.parametrize("n,t", [(20, 4), (65, 12), (128, 32)])
+def test_two_creations_give_the_same_schedule(n, t):
+    """The schedule is a function of the ligand alone: two creations from separate copies of the
+    same arrays, and one after planning other ligands in between, give the same plan and the
+    same slots byte for byte."""
+    tp = configs.type_params()
+    first = _preview_digest(synth.make_ligand(n, t, 9000 + n, tp))
+    for k in range(3):
+        md.md_schedule_preview(synth.make_ligand(10 + 17 * k, 2 + k, 31 + k, tp), group_div=2 + k)
+    again = synth.make_ligand(n, t, 9000 + n, tp)
+    copy = synth.Ligand(again.xyz.copy(), again.types.copy(), again.charges.copy(), again.bonds.copy(),
+                        again.torsions.copy(), again.root, again.type_params.copy())
+    assert _preview_digest(copy) == first
+
+
+def test_schedule_same_in_a_fresh_process():
+    """Nothing in the planner depends on addresses or on process state: a second process plans
+    the same ligands to the same slots."""
+    import hashlib
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    outs = [subprocess.run([sys.executable, "-c", _PREVIEW_SCRIPT, root], capture_output=True, text=True,
+                           timeout=120, check=True).stdout for _ in range(2)]
+    assert outs[0] == outs[1] and len(outs[0].splitlines()) == 3
+    here = []
+    for n, t in ((20, 4), (65, 12), (128, 32)):
+        info, m, raw = _preview_digest(synth.make_ligand(n, t, 9000 + n, configs.type_params()))
+        here.append(f"{n} {info} {m} {hashlib.sha256(raw).hexdigest()}")
+    assert outs[0].splitlines() == here
