@@ -146,6 +146,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2203_02096_amd.build`")
+        # torch brings its own copy of the HIP runtime, and the device buffers and streams passed
+        # to the library are torch's: torch is loaded first so that the library binds to that
+        # copy.  Loaded the other way round, the process holds two HIP runtimes and the second
+        # one to open the GPU finds no device.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)

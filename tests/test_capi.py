@@ -34,6 +34,21 @@ def test_every_declared_symbol_exported(md):
     assert set(names) == set(md.mdock.SIGNATURES)
 
 
+def test_one_hip_runtime_in_the_process(md):
+    """Loading the library, even before anything imported torch, leaves one HIP runtime in the
+    process: torch's, the one whose device buffers and streams the binding passes in.  (With two,
+    the second to open the GPU reports that there is no device.)"""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, sys.argv[1]); import paper_2203_02096_amd as m; m.lib(); "
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code, ROOT], capture_output=True, text=True, timeout=180,
+                         check=True).stdout.strip()
+    import ast
+    paths = ast.literal_eval(out)
+    assert len(paths) == 1, paths
+
+
 def test_version(md):
     assert b"gfx950" in md.lib().md_version()
 
