@@ -129,7 +129,8 @@ md_status md_ligand_info(const md_ligand* lig, int* n_atoms, int* n_torsions, in
  * A ligand's launch plan: the evaluation kernels run `waves_per_block` poses per block; each
  * block takes at most `lds_budget` bytes of LDS, which stages the first `staged_rows` of the
  * ligand's `total_rows` rows of 64 intramolecular pair slots (the rest are read from global
- * memory); the lanes of a pair row form conflict-free groups of about n_atoms / group_div lanes.
+ * memory); the lanes of a pair row form conflict-free groups of about n_atoms / group_div lanes
+ * (more where the waves' per-group force copies would not fit 160 KiB of LDS).
  * waves_per_pose > 1 (2 or 4) lets that many waves evaluate one pose together in the local
  * searches (md_local_search, md_local_search_sw, md_eval and the docking searches): each takes a
  * share of the pair rows, and their partial forces and energies meet in LDS once per evaluation

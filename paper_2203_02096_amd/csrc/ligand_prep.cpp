@@ -202,7 +202,17 @@ void plan_ligand(LigHost& out, const PlanParams& pp) {
   const int P = (int)out.raw_ij.size();
   const int A = n > kWave ? 2 : 1;
   const int div = std::max(2, std::min(8, pp.group_div));
-  const int want = std::max(1, std::min(kWave, n / div));
+  const int wpp = (pp.wpp == 2 || pp.wpp == 4) ? pp.wpp : 1;
+  const int wpb = wpp > 1 ? wpp : std::max(1, std::min(kMaxWavesPerBlock, pp.wpb));
+  // groups of about n / group_div lanes, larger where the block's waves could not hold one force
+  // copy per group in LDS
+  int want = std::max(1, std::min(kWave, n / div));
+  auto fits = [&](int w) {
+    const int k = (kWave + w - 1) / w;
+    return (size_t)wpb * lds_wave_bytes(n, k, A, out.n_tors) + lds_pose_share_bytes(n, wpp) <=
+           (size_t)kMaxLdsPerBlock;
+  };
+  while (want < kWave && !fits(want)) ++want;
   const int K = (kWave + want - 1) / want;
   const int m = (kWave + K - 1) / K;
   std::vector<int> left(n, 0);
@@ -309,8 +319,8 @@ void plan_ligand(LigHost& out, const PlanParams& pp) {
   out.group_lanes = m;
   out.n_copies = groups_used;
   out.plan = pp;
-  out.wpp = (pp.wpp == 2 || pp.wpp == 4) ? pp.wpp : 1;
-  out.wpb = out.wpp > 1 ? out.wpp : std::max(1, std::min(kMaxWavesPerBlock, pp.wpb));
+  out.wpp = wpp;
+  out.wpb = wpb;
   const size_t budget = (size_t)std::max(0, std::min(pp.lds_budget, kMaxLdsPerBlock));
   const size_t waves = (size_t)out.wpb * lds_wave_bytes(n, out.n_copies, A, out.n_tors) +
                        lds_pose_share_bytes(n, out.wpp);

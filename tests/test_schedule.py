@@ -15,7 +15,8 @@ md = pytest.importorskip("paper_2203_02096_amd")
 CASES = [(4, 1), (6, 2), (10, 3), (20, 4), (33, 7), (40, 8), (64, 12), (65, 12), (90, 20), (128, 32)]
 PLANS = [dict(), dict(group_div=2), dict(group_div=4), dict(group_div=8, waves_per_block=1),
          dict(lds_budget=0), dict(lds_budget=160 * 1024, waves_per_block=8), dict(lds_budget=20000),
-         dict(waves_per_block=4, waves_per_pose=4), dict(lds_budget=160 * 1024, waves_per_block=8, waves_per_pose=2)]
+         dict(waves_per_block=4, waves_per_pose=4), dict(lds_budget=160 * 1024, waves_per_block=8, waves_per_pose=2),
+         dict(group_div=8, waves_per_block=8)]
 
 
 def _lib_available():
@@ -68,6 +69,7 @@ def test_schedule_invariants(n, t, plan):
     # LDS: staged rows within the budget, and as many as fit; the pair loop's prefetch reads one
     # row behind the staged ones, which is staged too
     budget = PLANS[plan].get("lds_budget", 65536)
+    assert info["lds_bytes"] <= 160 * 1024
     assert 0 <= info["staged_rows"] <= rows
     per_row = 64 * 20
     staged = info["staged_rows"] + (1 if info["staged_rows"] > 0 else 0)
