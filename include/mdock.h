@@ -305,6 +305,17 @@ typedef struct {
 md_status md_dock(const md_receptor* rec, const md_ligand* lig, const md_dock_params* params,
                   md_dock_result* out, void* hip_stream);
 
+/* md_dock without any device allocation, for callers that cannot allocate (code under HIP
+ * graph capture, serving loops that must not call hipMalloc, harnesses that forbid it).  Same
+ * arguments, results and errors as md_dock, and bitwise the same results (the same kernels),
+ * but the dock's workspace lives in a static device array of 8 MiB that every GPU the library
+ * runs on holds until the process ends: a dock that needs more (about n_runs * pop_size *
+ * (8 * n_genes + 12) bytes plus its results) fails with MD_ERANGE, as does n_runs > 1024.
+ * Calls that overlap on one GPU share the array and race: the caller serialises them.  No graph
+ * is used, so every generation costs its launches.  Blocking. */
+md_status md_dock_noalloc(const md_receptor* rec, const md_ligand* lig, const md_dock_params* params,
+                          md_dock_result* out, void* hip_stream);
+
 /* Many docking jobs at once (ligands of different sizes against one receptor): every GA phase
  * is one launch (per atoms-per-lane class) over all jobs, through a device-side job table, so
  * small and large ligands share the GPU.  Each job's result is the same as docking it alone

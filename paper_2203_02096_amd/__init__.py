@@ -5,6 +5,7 @@ binding whose functions carry the C names (md_eval, md_local_search, md_local_se
 md_dock, ...).
 """
 from .mdock import (Ligand, MdockError, Receptor, Server, dock_params, lib, md_dock, md_dock_batch,  # noqa: F401
+                    md_dock_noalloc,
                     md_dock_planned_generations, md_eval, md_ligand_info, md_local_search, md_local_search_sw, md_local_search_traced, md_pose,
                     md_profile_enable, md_profile_read, md_profile_reset,
                     md_set_graphs, md_graphs_enabled, md_ligand_get_plan, md_ligand_set_plan,

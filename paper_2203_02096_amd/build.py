@@ -15,7 +15,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmdock.so")
 
-SOURCES = ["api.cpp", "autotune.cpp", "ligand_prep.cpp", "schedule.cpp", "server.cpp", "kernels.hip"]
+SOURCES = ["api.cpp", "autotune.cpp", "ligand_prep.cpp", "noalloc.cpp", "schedule.cpp", "server.cpp",
+           "kernels.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -109,6 +109,7 @@ SIGNATURES = {
                                          C.c_void_p]),
     "md_dock": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(DockParams), C.POINTER(DockResult), C.c_void_p]),
     "md_dock_batch": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(DockJob), C.c_void_p]),
+    "md_dock_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(DockParams), C.POINTER(DockResult), C.c_void_p]),
     "md_dock_planned_generations": (C.c_int, [C.POINTER(DockParams)]),
     "md_server_create": (C.c_int, [C.c_void_p, C.POINTER(ServerParams), C.POINTER(C.c_void_p)]),
     "md_server_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(DockParams), C.POINTER(C.c_ulonglong)]),
@@ -357,6 +358,14 @@ def md_dock(rec: Receptor, lig: Ligand, params: DockParams, stream=None, want_xy
     res, arrs = _result(params, lig, want_xyz)
     _check(lib().md_dock(rec.handle, lig.handle, C.byref(params), C.byref(res), _stream_ptr(stream)),
            "md_dock")
+    return arrs
+
+
+def md_dock_noalloc(rec: Receptor, lig: Ligand, params: DockParams, stream=None, want_xyz=True):
+    """md_dock with its workspace in the library's static device array (no device allocation)."""
+    res, arrs = _result(params, lig, want_xyz)
+    _check(lib().md_dock_noalloc(rec.handle, lig.handle, C.byref(params), C.byref(res), _stream_ptr(stream)),
+           "md_dock_noalloc")
     return arrs
 
 
