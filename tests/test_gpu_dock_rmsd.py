@@ -11,7 +11,7 @@ of the method, and the tolerance is settled on the oracle's own rounding spread:
   * every reported best energy is the oracle's energy of the reported pose (1e-4 rule), and the
     evaluation and generation counts are exact;
   * best-pose RMSD (library vs oracle): the median may be at most twice the median RMSD of the
-    perturbed oracle docks, and a one-sided Mann-Whitney test may not find the library's RMSDs
+    perturbed oracle docks (0.90 A, so 1.8 A), and a one-sided Mann-Whitney test may not find the library's RMSDs
     larger than the perturbed ones (p >= 0.01);
   * best energies: the mean of (library - oracle) may not exceed three standard errors of the
     perturbed docks' (perturbed - oracle) spread, in either direction -- the library neither
@@ -35,6 +35,7 @@ E_TOL = 1e-4
 MEDIAN_FACTOR = 2.0
 P_MIN = 0.01
 SE_FACTOR = 3.0
+RMSD_MEDIAN_TOL = 1.8      # Angstrom: twice the perturbed oracle docks' median (0.90 A), rounded up
 
 
 def _say(*a):
@@ -81,6 +82,6 @@ def test_small_dock_best_pose_within_rounding_spread():
     _say(f"[best pose] median RMSD lib {med_gpu:.3f} A, perturbed oracle {med_pert:.3f} A, "
          f"Mann-Whitney p {pval:.3f}; mean dE lib {np.mean(d_gpu):+.3f}, perturbed {np.mean(d_pert):+.3f}, "
          f"bound +-{bound:.3f} kcal/mol")
-    assert med_gpu <= MEDIAN_FACTOR * med_pert
+    assert med_gpu <= MEDIAN_FACTOR * med_pert and med_gpu <= RMSD_MEDIAN_TOL
     assert pval >= P_MIN
     assert abs(float(np.mean(d_gpu))) <= bound
