@@ -48,7 +48,7 @@ extern "C" {
 
 typedef enum {
   MD_OK = 0,
-  MD_EINVAL = -1,     /* malformed argument (null pointer, bad tree, bad index, NaN ...) */
+  MD_EINVAL = -1,     /* malformed argument (null pointer, bad bond graph, bad index, NaN ...) */
   MD_ERANGE = -2,     /* size outside the supported limits */
   MD_ENOMEM = -3,     /* device or host allocation failed */
   MD_EDEVICE = -4,    /* a HIP call failed (no device, launch failure ...) */
@@ -85,9 +85,9 @@ md_status md_receptor_create(const md_grid_desc* desc, const float* maps,
 md_status md_receptor_destroy(md_receptor* rec);
 
 /* ------------------------------------------------------------------ ligand
- * Point atoms joined by a bond tree; the listed bonds are rotatable (degrees of freedom
- * together with translation and orientation; Background, "Design and Structure of
- * MiniMDock").  The library moves the reference coordinates so their centroid is the
+ * Point atoms joined by a connected bond graph (rings allowed inside rigid fragments); the
+ * listed bonds are rotatable (degrees of freedom together with translation and orientation;
+ * Background, "Design and Structure of MiniMDock") and lie in no ring.  The library moves the reference coordinates so their centroid is the
  * origin, orients each torsion from the root side, finds each torsion's moving set, and
  * builds the intramolecular pair list: pairs at least three bonds apart whose path
  * crosses a rotatable bond.
@@ -100,12 +100,13 @@ typedef struct {
   const float* xyz;          /* host [n_atoms][3], Angstrom */
   const int* type;           /* host [n_atoms], in [0, n_types) */
   const float* charge;       /* host [n_atoms], e */
-  int n_bonds;               /* must be n_atoms - 1 */
-  const int* bonds;          /* host [n_bonds][2]; must form a tree */
+  int n_bonds;               /* n_atoms - 1 (a tree) .. 4 n_atoms */
+  const int* bonds;          /* host [n_bonds][2]; connected, no bond twice */
   int n_torsions;
   const int* torsions;       /* host [n_torsions] indices into bonds; each bond must have
-                                further atoms on both ends (no terminal bond), no repeats */
-  int root_atom;             /* anchor of the tree, usually 0 */
+                                further atoms on both ends (no terminal bond), lie in no
+                                ring, no repeats */
+  int root_atom;             /* anchor of the torsion tree, usually 0 */
   int n_types;               /* must be 7 */
   const float* type_params;  /* host [n_types][7] */
 } md_ligand_desc;
@@ -433,6 +434,59 @@ md_status md_profile_read(int kind, double* total_ms, long long* launches);
  * while calls are running. */
 md_status md_set_graphs(int on);
 int md_graphs_enabled(void);
+
+/* ------------------------------------------------------------------ file front end
+ * Readers of the docking program's input files.  The paper docks real small, medium and large
+ * ligands against real receptor maps inside a screening workflow (Background, "Design and
+ * Structure of MiniMDock"; introduction, workflow figure); these readers turn AutoGrid map files,
+ * PDBQT ligands and the atom_par lines of an AutoDock parameter file into the arrays that
+ * md_receptor_create and md_ligand_create take.  Host only, no device work.  Errors name the
+ * offending line. */
+
+/* One AutoGrid map file held in memory (text, `length` bytes): header records (SPACING s,
+ * NELEMENTS nx ny nz -- even interval counts --, CENTER cx cy cz; GRID_PARAMETER_FILE,
+ * GRID_DATA_FILE and MACROMOLECULE are accepted and ignored), then one value per line, x
+ * fastest, then y, then z.  desc gets nodes per axis (n + 1), the spacing, the minimum corner
+ * (CENTER - SPACING * n / 2) and n_types = 7; values [nz][ny][nx] go to `values` (capacity
+ * floats; NULL: count only); *n_values (may be NULL) gets the count.  A receptor is nine such
+ * maps of one grid, stacked in md_receptor_create's order.  Errors: MD_EINVAL (malformed header
+ * or value, value count not (nx+1)(ny+1)(nz+1)), MD_ERANGE (capacity too small). */
+md_status md_autogrid_map_parse(const char* text, long long length, md_grid_desc* desc, float* values,
+                                long long capacity, long long* n_values);
+
+/* A parsed PDBQT ligand: capacities in, counts and arrays out (caller-owned arrays). */
+typedef struct {
+  int max_atoms, max_bonds, max_torsions;   /* capacities of the arrays below */
+  int n_atoms, n_bonds, n_torsions;         /* set on return (also on MD_ERANGE) */
+  int root_atom;                            /* the first atom of the ROOT block: 0 */
+  float* xyz;                               /* [max_atoms][3] Angstrom */
+  float* charge;                            /* [max_atoms] partial charges, e */
+  int* type;                                /* [max_atoms] index into type_names */
+  int* bonds;                               /* [max_bonds][2] atom indices */
+  int* torsions;                            /* [max_torsions] indices into bonds */
+  int* serial;                              /* [max_atoms] the file's serial numbers, or NULL */
+} md_pdbqt_ligand;
+
+/* A PDBQT ligand held in memory: ATOM / HETATM records (serial number in columns 7-11,
+ * coordinates in columns 31-54, the partial charge and the AutoDock atom type as the record's
+ * last two fields), one ROOT block and nested BRANCH a b / ENDBRANCH blocks (a, b serial
+ * numbers: a on the root side).  Atoms keep the file's order.  Each atom type is looked up in
+ * type_names[n_types] (the receptor's type maps, e.g. {"A","C","HD","N","NA","OA","SA"}).
+ * Bonds: atom pairs closer than 1.2 times the sum of their elements' single-bond covalent radii,
+ * plus every BRANCH bond; torsions: the BRANCH bonds, in file order.  Rings are allowed inside
+ * rigid fragments (md_ligand_create rejects a rotatable bond in a ring).  Errors: MD_EINVAL
+ * (malformed or unknown record, atom type without a map or covalent radius, unmatched BRANCH,
+ * no ROOT), MD_ERANGE (capacities too small; the counts are set). */
+md_status md_pdbqt_parse(const char* text, long long length, int n_types, const char* const* type_names,
+                         md_pdbqt_ligand* out);
+
+/* The atom_par records of an AutoDock parameter file held in memory ("atom_par type Rii epsii
+ * vol solpar Rij_hb epsij_hb hbond ..."), as md_ligand_desc type_params rows [n_types][7] for
+ * the types named in type_names: R_eq = Rii, eps = epsii, volume, solvation parameter, H-bond
+ * role (hbond code 0: none, 1-2: donor, 3-5: acceptor), R_hb, eps_hb.  Records of other types
+ * are skipped.  Errors: MD_EINVAL (malformed record, a named type without a record). */
+md_status md_atom_par_parse(const char* text, long long length, int n_types, const char* const* type_names,
+                            float* type_params);
 
 const char* md_last_error(void);
 const char* md_version(void);

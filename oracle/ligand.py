@@ -1,5 +1,5 @@
-"""Ligand preprocessing for the oracle: bond tree, rotatable bonds, moving sets,
-and the intramolecular pair list.
+"""Ligand preprocessing for the oracle: bond graph (rings allowed inside rigid fragments),
+rotatable bonds, moving sets, and the intramolecular pair list.
 
 The paper describes the ligand as point atoms whose degrees of freedom are the
 rigid-body translation (and orientation) plus the rotatable bonds (Background,
@@ -10,8 +10,9 @@ energy sum (Section "Approach 1", listing of decomposed target functions).
 Readings taken here (the paper gives none of them):
   * reference coordinates are moved so that their centroid is the origin, which is
     the centre of the orientation and the point the translation genes place;
-  * atom `root` (default 0) anchors the tree; torsion k turns the atoms on the far
-    side of its bond (a_k, b_k), a_k being the end nearer the root;
+  * atom `root` (default 0) anchors the torsion tree; torsion k turns the atoms on the far
+    side of its bond (a_k, b_k), a_k being the end nearer the root; a rotatable bond lies in
+    no ring (cutting it splits the molecule), so its far side is well defined;
   * intramolecular pairs are the atom pairs at least three bonds apart (1-4 and
     beyond) whose connecting path crosses at least one rotatable bond; pairs inside
     one rigid fragment keep a constant distance and are left out.
@@ -74,8 +75,10 @@ def prepare(xyz, types, charges, bonds, torsions, type_params, root=0) -> Oracle
     tp = np.asarray(type_params, dtype=np.float64).reshape(-1, 7)
     if n < 1:
         raise LigandError("a ligand needs at least one atom")
-    if bonds.shape[0] != n - 1:
-        raise LigandError("bonds must form a tree (n_atoms - 1 bonds)")
+    if bonds.shape[0] < n - 1:
+        raise LigandError("a connected bond graph needs at least n_atoms - 1 bonds")
+    if len({frozenset((int(a), int(b))) for a, b in bonds}) != bonds.shape[0]:
+        raise LigandError("bond listed twice")
     if np.any(bonds < 0) or np.any(bonds >= n) or np.any(bonds[:, 0] == bonds[:, 1]):
         raise LigandError("bond atom index out of range")
     if np.any(types < 0) or np.any(types >= tp.shape[0]):
@@ -91,7 +94,7 @@ def prepare(xyz, types, charges, bonds, torsions, type_params, root=0) -> Oracle
         raise LigandError("bonds do not connect every atom")
 
     T = torsions.shape[0]
-    if len(set(torsions.tolist())) != T or np.any(torsions < 0) or np.any(torsions >= n - 1):
+    if len(set(torsions.tolist())) != T or np.any(torsions < 0) or np.any(torsions >= bonds.shape[0]):
         raise LigandError("torsion bond index invalid or repeated")
     tors_a = np.zeros(T, dtype=np.int64)
     tors_b = np.zeros(T, dtype=np.int64)
@@ -103,18 +106,22 @@ def prepare(xyz, types, charges, bonds, torsions, type_params, root=0) -> Oracle
         if len(neighbours[a]) < 2 or len(neighbours[b]) < 2:
             raise LigandError("a terminal bond cannot be a torsion")
         tors_a[k], tors_b[k] = a, b
-        # far side of the bond: everything reachable from b without crossing (a, b)
+        # far side of the bond: everything reachable from b without crossing (a, b); in a ring
+        # the other way round reaches a, and the bond has no far side
         seen = {int(b)}
         dq = deque([int(b)])
         while dq:
             x = dq.popleft()
             for y in neighbours[x]:
-                if y != a and y not in seen:
+                if (x, y) != (b, a) and y not in seen:
                     seen.add(y)
                     dq.append(y)
+        if int(a) in seen:
+            raise LigandError("a rotatable bond cannot lie in a ring")
         moving[k, list(seen)] = True
 
-    # pair list: graph distance >= 3 and a rotatable bond on the path
+    # pair list: graph distance >= 3 and a rotatable bond on the path (every path between two
+    # atoms crosses the same rotatable bonds, since none lies in a ring)
     rot_bonds = {frozenset((int(tors_a[k]), int(tors_b[k]))) for k in range(T)}
     pairs = []
     for i in range(n):

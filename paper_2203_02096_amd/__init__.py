@@ -10,4 +10,5 @@ from .mdock import (Ligand, MdockError, Receptor, Server, dock_params, lib, md_d
                     md_profile_enable, md_profile_read, md_profile_reset,
                     md_set_graphs, md_graphs_enabled, md_ligand_get_plan, md_ligand_set_plan,
                     md_ligand_autotune, md_tune_table_clear, md_tune_table_size, md_schedule_preview,
-                    md_batch_autotune)
+                    md_batch_autotune, md_autogrid_map_parse, md_pdbqt_parse, md_atom_par_parse,
+                    receptor_from_autogrid, ligand_from_pdbqt)

@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmdock.so")
 
-SOURCES = ["api.cpp", "autotune.cpp", "ligand_prep.cpp", "noalloc.cpp", "schedule.cpp", "server.cpp",
+SOURCES = ["api.cpp", "autotune.cpp", "formats.cpp", "ligand_prep.cpp", "noalloc.cpp", "schedule.cpp", "server.cpp",
            "kernels.hip"]
 
 HIPCC_FLAGS = [

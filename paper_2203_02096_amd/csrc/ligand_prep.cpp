@@ -23,7 +23,7 @@ bool finite3(const float* p) {
   return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]);
 }
 
-// graph distances from `src` over the tree adjacency
+// graph distances from `src` over the bond graph
 std::vector<int> bfs(const std::vector<std::vector<int>>& adj, int src, std::vector<int>* parent) {
   std::vector<int> d(adj.size(), -1);
   if (parent) parent->assign(adj.size(), -1);
@@ -61,7 +61,7 @@ std::string prepare_ligand(int n, const float* xyz, const int* type, const float
   }
   if (n_types != kTypes) return "n_types must be 7";
   if (!xyz || !type || !charge || !tp) return "null ligand array";
-  if (n_bonds != n - 1) return "bonds must form a tree: n_bonds must equal n_atoms - 1";
+  if (n_bonds < n - 1 || n_bonds > 4 * n) return "n_bonds must be in [n_atoms - 1, 4 n_atoms] (a connected bond graph)";
   if (n_bonds > 0 && !bonds) return "null bond array";
   if (n_torsions > 0 && !torsions) return "null torsion array";
   if (root < 0 || root >= n) return "root atom out of range";
@@ -80,6 +80,7 @@ std::string prepare_ligand(int n, const float* xyz, const int* type, const float
   for (int b = 0; b < n_bonds; ++b) {
     int a0 = bonds[2 * b], a1 = bonds[2 * b + 1];
     if (a0 < 0 || a0 >= n || a1 < 0 || a1 >= n || a0 == a1) return "bond atom index out of range";
+    if (std::find(adj[a0].begin(), adj[a0].end(), a1) != adj[a0].end()) return "bond listed twice";
     adj[a0].push_back(a1);
     adj[a1].push_back(a0);
   }
@@ -101,12 +102,20 @@ std::string prepare_ligand(int n, const float* xyz, const int* type, const float
     if (depth[a] > depth[b]) std::swap(a, b);
     if (adj[a].size() < 2 || adj[b].size() < 2) return "a terminal bond cannot be a torsion";
     Tor t{a, b, 7 + k, depth[a], std::vector<char>(n, 0)};
-    // far side of the bond: atoms whose path to the root passes through b
-    for (int i = 0; i < n; ++i) {
-      int x = i;
-      while (x != root && x != b) x = parent[x];
-      t.moving[i] = (x == b) ? 1 : 0;
+    // far side of the bond: everything reachable from b without crossing (a, b); a bond in a
+    // ring has no far side (a is reached too)
+    std::vector<int> stack{b};
+    t.moving[b] = 1;
+    while (!stack.empty()) {
+      const int x = stack.back();
+      stack.pop_back();
+      for (int y : adj[x])
+        if (!t.moving[y] && !(x == b && y == a)) {
+          t.moving[y] = 1;
+          stack.push_back(y);
+        }
     }
+    if (t.moving[a]) return "a rotatable bond cannot lie in a ring";
     tors.push_back(std::move(t));
   }
   std::stable_sort(tors.begin(), tors.end(),

@@ -38,6 +38,13 @@ class LigandDesc(C.Structure):
                 ("n_types", C.c_int), ("type_params", C.POINTER(C.c_float))]
 
 
+class PdbqtLigand(C.Structure):
+    _fields_ = [("max_atoms", C.c_int), ("max_bonds", C.c_int), ("max_torsions", C.c_int),
+                ("n_atoms", C.c_int), ("n_bonds", C.c_int), ("n_torsions", C.c_int), ("root_atom", C.c_int),
+                ("xyz", C.POINTER(C.c_float)), ("charge", C.POINTER(C.c_float)), ("type", C.POINTER(C.c_int)),
+                ("bonds", C.POINTER(C.c_int)), ("torsions", C.POINTER(C.c_int)), ("serial", C.POINTER(C.c_int))]
+
+
 class DockParams(C.Structure):
     _fields_ = [("n_runs", C.c_int), ("pop_size", C.c_int), ("max_evals_per_run", C.c_longlong),
                 ("max_generations", C.c_int), ("ls_rate", C.c_float), ("ls_iters", C.c_int),
@@ -90,6 +97,10 @@ class DockJob(C.Structure):
 
 # name -> (restype, argtypes); the complete exported surface of include/mdock.h
 SIGNATURES = {
+    "md_autogrid_map_parse": (C.c_int, [C.c_char_p, C.c_longlong, C.c_void_p, C.c_void_p, C.c_longlong,
+                                        C.POINTER(C.c_longlong)]),
+    "md_pdbqt_parse": (C.c_int, [C.c_char_p, C.c_longlong, C.c_int, C.POINTER(C.c_char_p), C.c_void_p]),
+    "md_atom_par_parse": (C.c_int, [C.c_char_p, C.c_longlong, C.c_int, C.POINTER(C.c_char_p), C.c_void_p]),
     "md_receptor_create": (C.c_int, [C.POINTER(GridDesc), C.POINTER(C.c_float), C.c_int, C.c_void_p,
                                      C.POINTER(C.c_void_p)]),
     "md_receptor_destroy": (C.c_int, [C.c_void_p]),
@@ -261,6 +272,72 @@ class Ligand:
             self.close()
         except Exception:
             pass
+
+
+def _text(t):
+    return t.encode() if isinstance(t, str) else bytes(t)
+
+
+def _names(type_names):
+    arr = (C.c_char_p * len(type_names))(*[n.encode() for n in type_names])
+    return arr
+
+
+def md_autogrid_map_parse(text):
+    """One AutoGrid map file's text -> (desc dict, values float32 [nz][ny][nx])."""
+    b = _text(text)
+    d = GridDesc()
+    n = C.c_longlong()
+    _check(lib().md_autogrid_map_parse(b, len(b), C.byref(d), None, 0, C.byref(n)), "md_autogrid_map_parse")
+    vals = np.zeros(n.value, np.float32)
+    _check(lib().md_autogrid_map_parse(b, len(b), C.byref(d), _fptr(vals), vals.size, C.byref(n)),
+           "md_autogrid_map_parse")
+    desc = dict(shape=(d.nx, d.ny, d.nz), spacing=d.spacing, origin=tuple(d.origin))
+    return desc, vals.reshape(d.nz, d.ny, d.nx)
+
+
+def md_pdbqt_parse(text, type_names, max_atoms=256, max_bonds=1024, max_torsions=64):
+    """A PDBQT ligand's text -> dict of xyz, charges, types (indices into type_names), bonds,
+    torsions (indices into bonds), root, serial."""
+    b = _text(text)
+    names = _names(type_names)
+    out = dict(xyz=np.zeros((max_atoms, 3), np.float32), charges=np.zeros(max_atoms, np.float32),
+               types=np.zeros(max_atoms, np.int32), bonds=np.zeros((max_bonds, 2), np.int32),
+               torsions=np.zeros(max_torsions, np.int32), serial=np.zeros(max_atoms, np.int32))
+    r = PdbqtLigand(max_atoms, max_bonds, max_torsions, 0, 0, 0, 0, _fptr(out["xyz"]), _fptr(out["charges"]),
+                    _iptr(out["types"]), _iptr(out["bonds"]), _iptr(out["torsions"]), _iptr(out["serial"]))
+    _check(lib().md_pdbqt_parse(b, len(b), len(type_names), names, C.byref(r)), "md_pdbqt_parse")
+    n, nb, nt = r.n_atoms, r.n_bonds, r.n_torsions
+    return dict(xyz=out["xyz"][:n].copy(), charges=out["charges"][:n].copy(), types=out["types"][:n].copy(),
+                bonds=out["bonds"][:nb].copy(), torsions=out["torsions"][:nt].copy(), root=r.root_atom,
+                serial=out["serial"][:n].copy())
+
+
+def md_atom_par_parse(text, type_names):
+    """atom_par records -> type_params float32 [len(type_names)][7]."""
+    b = _text(text)
+    tp = np.zeros((len(type_names), 7), np.float32)
+    _check(lib().md_atom_par_parse(b, len(b), len(type_names), _names(type_names), _fptr(tp)),
+           "md_atom_par_parse")
+    return tp
+
+
+def receptor_from_autogrid(map_texts, precision="fp32", stream=None):
+    """Nine AutoGrid map texts of one grid (the seven type maps in type order, then the
+    electrostatic and the desolvation map) -> Receptor."""
+    if len(map_texts) != 9:
+        raise ValueError("a receptor is 7 type maps, the electrostatic map and the desolvation map")
+    descs, vals = zip(*[md_autogrid_map_parse(t) for t in map_texts])
+    if any(d != descs[0] for d in descs):
+        raise ValueError("the maps do not share one grid")
+    return Receptor(np.stack(vals), descs[0]["origin"], descs[0]["spacing"], precision, stream)
+
+
+def ligand_from_pdbqt(text, type_names, type_params):
+    """A PDBQT ligand whose atom types index the receptor's seven type maps (type_names), with
+    the type parameters of those types -> Ligand."""
+    p = md_pdbqt_parse(text, type_names)
+    return Ligand(p["xyz"], p["types"], p["charges"], p["bonds"], p["torsions"], type_params, p["root"])
 
 
 def md_eval(rec: Receptor, lig: Ligand, genes, energy, grad=None, stream=None):

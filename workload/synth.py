@@ -56,7 +56,7 @@ class Ligand:
     xyz: np.ndarray             # float32 [n_atoms][3] reference conformation
     types: np.ndarray           # int32 [n_atoms]
     charges: np.ndarray         # float32 [n_atoms]
-    bonds: np.ndarray           # int32 [n_atoms-1][2], a tree
+    bonds: np.ndarray           # int32 [n_bonds][2], connected (the generated ligands are trees)
     torsions: np.ndarray        # int32 [n_torsions], indices into bonds
     root: int = 0
     type_params: np.ndarray = field(default=None)   # float32 [N_TYPES][7]
