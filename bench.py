@@ -49,7 +49,8 @@ PEAK_HBM_GBS = 8000.0
 
 PROFILES = {"adadelta": os.path.join(ROOT, "profiles", "k_local_search_plain_fp32_production.txt"),
             "solis_wets": os.path.join(ROOT, "profiles", "k_ga_solis_wets_plain_fp32_production.txt"),
-            "batched": os.path.join(ROOT, "profiles", "k_ga_local_search_batched_fp32.txt")}
+            "batched": os.path.join(ROOT, "profiles", "k_ga_local_search_batched_fp32.txt"),
+            "serving": os.path.join(ROOT, "profiles", "k_ga_local_search_serving_fp16.txt")}
 KERNEL_SRC = os.path.join(ROOT, "paper_2203_02096_amd", "csrc", "kernels.hip")
 
 
@@ -68,7 +69,9 @@ def measured_profile(ls="adadelta"):
     vals = dict(l.split(": ", 1) for l in text.splitlines() if ": " in l and not l.startswith(" "))
     if vals.get("kernel_source_sha256", "").strip() != sha:
         return none
-    out = {"traffic": float(vals.get("traffic_bytes_per_launch", vals.get("traffic_bytes_per_generation", "nan"))),
+    traffic = next((vals[k] for k in ("traffic_bytes_per_launch", "traffic_bytes_per_generation",
+                                      "traffic_bytes_per_request") if k in vals), "nan")
+    out = {"traffic": float(traffic),
            "valu_issue_utilisation": float(vals["valu_issue_utilisation"]),
            "valu_instructions_per_eval": float(vals["valu_instructions_per_eval"])}
     for k in ("l2_read_bytes_per_launch", "l2_hit_rate"):
@@ -234,7 +237,7 @@ def main():
     ap.add_argument("--full-budget", action="store_true",
                     help="batched_fp32: each step docks every ligand to its full budget")
     ap.add_argument("--no-baselines", action="store_true",
-                    help="batched_fp32: leave out the single-ligand baselines (for profiler runs)")
+                    help="batched_fp32, serving_fp16: leave out the single-ligand baselines (for profiler runs)")
     ap.add_argument("--rates", default="25,50,75,100,150",
                     help="serving_fp16: arrival rates (ligands/s)")
     ap.add_argument("--requests", type=int, default=2000, help="serving_fp16: requests per rate")
@@ -725,6 +728,16 @@ def bench_serving(args):
     n_ls = max(0, min(P.pop_size, math.ceil(sp["ls_rate"] * P.pop_size - 1e-4)))
     gens = md.md_dock_planned_generations(P)
     evals_per_req = P.n_runs * (P.pop_size + gens * ((P.pop_size - P.elitism) + n_ls * P.ls_iters))
+    # a known-size plain copy before the served requests: calibrates byte counters under a
+    # profiler and marks where the requests' dispatches begin (the plan tuning's end before it)
+    if args.copy_mib > 0:
+        import torch
+        src = torch.ones(args.copy_mib * (1 << 20) // 4, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     results = []
     for rate in [float(r) for r in args.rates.split(",")]:
         srv = md.Server(drec, hbm_budget_bytes=8 << 30, max_slots=256)
@@ -771,8 +784,15 @@ def bench_serving(args):
     best = max(results, key=lambda r: r["ligands_per_s"] or 0.0)
     ls_per_req = P.n_runs * gens * n_ls * P.ls_iters
     roof = mix_roofline(md, ligs, [ls_per_req] * len(ligs), best["span_s"], 2)
-    single_eps, single_lps, idx = single_ligand_path(
-        md, drec, ligs, [md.dock_params(**{**sp, "seed": args.seed * 1000 + k}) for k in range(len(ligs))], 16)
+    prof = measured_profile("serving")
+    roof.update({"traffic": prof["traffic"], "traffic_unit": "HBM bytes per request of local-search launches",
+                 "valu_issue_utilisation": prof["valu_issue_utilisation"],
+                 "valu_instructions_per_eval": prof["valu_instructions_per_eval"], "l2_hit_rate": prof["l2_hit_rate"]})
+    single_eps = single_lps = None
+    idx = []
+    if not args.no_baselines:
+        single_eps, single_lps, idx = single_ligand_path(
+            md, drec, ligs, [md.dock_params(**{**sp, "seed": args.seed * 1000 + k}) for k in range(len(ligs))], 16)
     out = {"metric": "ligands docked/s (serving)", "value": capacity, "unit": "ligands/s",
            "n_gpus": 1, "steps": len(results), "warmup": 0, "ms_per_step": None, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -784,7 +804,8 @@ def bench_serving(args):
                                           f"span from the first arrival to the last completion"},
            "ls_evals_per_s": len(ligs) * ls_per_req / best["span_s"],
            "single_ligand_path": {"ligands_per_s": single_lps, "evals_per_s": single_eps,
-                                  "speedup_of_serving": best["ligands_per_s"] / single_lps, "ligands": len(idx),
+                                  "speedup_of_serving": best["ligands_per_s"] / single_lps if single_lps else None,
+                                  "ligands": len(idx),
                                   "what": "md_dock of 16 of the requests one after another, same parameters "
                                           "and plans, same GPU"},
            "capacity_ligands_per_s": capacity,
