@@ -403,11 +403,12 @@ __device__ __forceinline__ float pair_term(float r2, float4 c, float& f_over_r) 
   const float e = (in1 ? elj + eds : 0.f) + (in2 ? eel : 0.f);
   // (dE/dr) / r of each term: the 12-6 / 12-10 part, the Gaussian's -E / sigma^2, and the
   // electrostatic -E_el (1/r + eps'/eps) / r; zero below R_MIN
-  const float flj = __builtin_fmaf(nn * cy, irn, -12.f * a12) * ir2;
-  const float fds = eds * (-1.f / (kDesolvSigma * kDesolvSigma));
+  // 12-6: (6 b - 12 a) / r^2 with b = a - elj is -6 (a + elj) / r^2
+  const float flj = HB == 0 ? (a12 + elj) * (-6.f * ir2) : __builtin_fmaf(nn * cy, irn, -12.f * a12) * ir2;
+  const float flds = __builtin_fmaf(eds, -1.f / (kDesolvSigma * kDesolvSigma), flj);
   const float fel = (__builtin_fmaf(ex * (kDielB * kDielK * kDielLambda * kDielB), q, ir) * -eel) * ir;
   const bool lo = r2 >= kRmin * kRmin;
-  f_over_r = (in1 && lo ? flj + fds : 0.f) + (in2 && lo ? fel : 0.f);
+  f_over_r = (in1 && lo ? flds : 0.f) + (in2 && lo ? fel : 0.f);
   return e;
 }
 
@@ -492,7 +493,12 @@ __device__ __forceinline__ void pair_span(const LigDev& L, const BlockLds& b, in
   const uint32_t* pij = (FROM_LDS ? b.pair_ij : L.pair_ij) + lane + (size_t)r0 * kWave;
   const float4* pc = (FROM_LDS ? b.pair_coef : L.pair_coef) + lane + (size_t)r0 * kWave;
   const char* xs = reinterpret_cast<const char*>(b.x);
-  char* fs = reinterpret_cast<char*>(b.fg);
+  // the force copy's byte offset from the coordinates, kept opaque so that no constant part of it
+  // is folded into the LDS instructions' offset fields (whose 8-bit dword range the y and z
+  // entries would then exceed, costing an address add per atom and row)
+  uint32_t fofs = static_cast<uint32_t>(reinterpret_cast<const char*>(b.fg) - xs);
+  asm("" : "+v"(fofs));
+  char* fs = const_cast<char*>(xs) + fofs;
   uint32_t ij0 = pij[0], ij1;
   float4 c0 = pc[0], c1;
   P3 xi0 = load_p3b<A>(xs, ij0 & 0xffffu), xj0 = load_p3b<A>(xs, ij0 >> 16), xi1, xj1;
@@ -614,16 +620,17 @@ __device__ __forceinline__ float torsion_gradients(const LigDev& L, const AtomRe
       u[j] = tor[2 * (kb + j)];
       m[j] = tor[2 * (kb + j) + 1];
     }
+    // an atom's mask has no bit at or beyond T (k stays below 32: T <= 32, padded to 4)
     float c[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int k = kb + j;
-      c[j] = 0.f;
 #pragma unroll
       for (int a = 0; a < A; ++a) {
-        const float t = (u[j].x * tqx[a] + u[j].y * tqy[a] + u[j].z * tqz[a]) -
-                        (m[j].x * Fx[a] + m[j].y * Fy[a] + m[j].z * Fz[a]);
-        if (k < T && ((at.mask[a] >> k) & 1u)) c[j] += t;
+        const float ut = u[j].x * tqx[a] + u[j].y * tqy[a] + u[j].z * tqz[a];
+        const float t = __builtin_fmaf(-m[j].z, Fz[a], __builtin_fmaf(-m[j].y, Fy[a], __builtin_fmaf(-m[j].x, Fx[a], ut)));
+        const float v = __builtin_amdgcn_ubfe(at.mask[a], k, 1) ? t : 0.f;
+        c[j] = a == 0 ? v : c[j] + v;
       }
     }
     // lanes 0-31 end with torsion kb (h0) / kb+1 (h1) summed over both halves, lanes 32-63
@@ -690,11 +697,12 @@ __device__ __forceinline__ void pose_slots(const LigDev& L, const AtomRegs<A>& a
     const float4 n0 = tor[3 * kn + 0], n1 = tor[3 * kn + 1], n2 = tor[3 * kn + 2];
 #pragma unroll
     for (int a = 0; a < A; ++a) {
-      if (use[a] && ((at.mask[a] >> k) & 1u)) {
+      if (use[a] && __builtin_amdgcn_ubfe(at.mask[a], k, 1)) {
+        // three fused multiply-adds per coordinate, the offset innermost
         const float ox = px[a], oy = py[a], oz = pz[a];
-        px[a] = m0.x * ox + m0.y * oy + m0.z * oz + m0.w;
-        py[a] = m1.x * ox + m1.y * oy + m1.z * oz + m1.w;
-        pz[a] = m2.x * ox + m2.y * oy + m2.z * oz + m2.w;
+        px[a] = __builtin_fmaf(m0.x, ox, __builtin_fmaf(m0.y, oy, __builtin_fmaf(m0.z, oz, m0.w)));
+        py[a] = __builtin_fmaf(m1.x, ox, __builtin_fmaf(m1.y, oy, __builtin_fmaf(m1.z, oz, m1.w)));
+        pz[a] = __builtin_fmaf(m2.x, ox, __builtin_fmaf(m2.y, oy, __builtin_fmaf(m2.z, oz, m2.w)));
       }
     }
     m0 = n0;
@@ -703,9 +711,9 @@ __device__ __forceinline__ void pose_slots(const LigDev& L, const AtomRegs<A>& a
   }
 #pragma unroll
   for (int a = 0; a < A; ++a) {
-    x[a] = rb.r00 * px[a] + rb.r01 * py[a] + rb.r02 * pz[a] + rb.tx;
-    y[a] = rb.r10 * px[a] + rb.r11 * py[a] + rb.r12 * pz[a] + rb.ty;
-    z[a] = rb.r20 * px[a] + rb.r21 * py[a] + rb.r22 * pz[a] + rb.tz;
+    x[a] = __builtin_fmaf(rb.r00, px[a], __builtin_fmaf(rb.r01, py[a], __builtin_fmaf(rb.r02, pz[a], rb.tx)));
+    y[a] = __builtin_fmaf(rb.r10, px[a], __builtin_fmaf(rb.r11, py[a], __builtin_fmaf(rb.r12, pz[a], rb.ty)));
+    z[a] = __builtin_fmaf(rb.r20, px[a], __builtin_fmaf(rb.r21, py[a], __builtin_fmaf(rb.r22, pz[a], rb.tz)));
   }
 }
 
