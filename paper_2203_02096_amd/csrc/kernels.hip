@@ -64,6 +64,21 @@ __device__ __forceinline__ float wave_sum(float v) {
   return readlane(v, 63);
 }
 
+// Wavefront sum by the tree the gradient path's reduce-scatter gives the energy (rigid_gradient
+// with WITH_E): each lane adds its partner 32 lanes away, then the partner row, then the row is
+// summed by DPP; so the energy-only and the gradient evaluations agree bitwise.
+__device__ __forceinline__ float wave_sum_rs(float v) {
+  const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  const float h = __uint_as_float(s[0]) + __uint_as_float(s[1]);
+  const auto t = __builtin_amdgcn_permlane16_swap(__float_as_uint(h), __float_as_uint(h), false, false);
+  float r = __uint_as_float(t[0]) + __uint_as_float(t[1]);
+  r += dpp<0xb1, 0xf>(r);    // quad_perm [1,0,3,2]
+  r += dpp<0x4e, 0xf>(r);    // quad_perm [2,3,0,1]
+  r += dpp<0x141, 0xf>(r);   // row_half_mirror
+  r += dpp<0x140, 0xf>(r);   // row_mirror
+  return readlane(r, 16);
+}
+
 // ------------------------------------------------------------------ counter-based RNG
 // SplitMix64 (Steele, Lea, Flood 2014) folded over the draw's coordinates.
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
@@ -127,6 +142,7 @@ struct BlockLds {
   float* f;                  // this wave: [n_copies] blocks of intramolecular forces [3][64A + 1]
   float* fg;                 // this lane's group copy
   float4* tor;               // this wave: [3*roundup4(n_tors)] torsion table (see eval_pose)
+  float* rg;                 // this wave: [8] rigid-body gene gradients (see rigid_gradient)
   float4* share;             // waves sharing a pose: the pose's coordinates, then two sets of
                              // [W + 1][n_atoms + 1] + [W] (see eval_pose_shared)
 };
@@ -182,6 +198,7 @@ __device__ __forceinline__ BlockLds stage_block(const LigDev& L) {
   b.f = reinterpret_cast<float*>(cur);
   cur += cb * L.n_copies;
   b.tor = reinterpret_cast<float4*>(cur);
+  b.rg = reinterpret_cast<float*>(cur + (size_t)48 * ((L.n_tors + 3) & ~3));
   if (lane == 0) store3<A>(b.x, kWave * A, 0.f, 0.f, 0.f);
   if (L.wpp > 1 && threadIdx.x == 0)   // spare entry of the shared pose's coordinates
     store3<A>(reinterpret_cast<float*>(b.share), kWave * A, 0.f, 0.f, 0.f);
@@ -670,9 +687,9 @@ __device__ __forceinline__ void build_torsion_table(const AtomRegs<A>& at, float
     const float m10 = oc * uy * ux + sn * uz, m11 = oc * uy * uy + c, m12 = oc * uy * uz - sn * ux;
     const float m20 = oc * uz * ux - sn * uy, m21 = oc * uz * uy + sn * ux, m22 = oc * uz * uz + c;
     const float vx = at.tpx, vy = at.tpy, vz = at.tpz;
-    tor[3 * lane + 0] = make_float4(m00, m01, m02, vx - (m00 * vx + m01 * vy + m02 * vz));
-    tor[3 * lane + 1] = make_float4(m10, m11, m12, vy - (m10 * vx + m11 * vy + m12 * vz));
-    tor[3 * lane + 2] = make_float4(m20, m21, m22, vz - (m20 * vx + m21 * vy + m22 * vz));
+    tor[3 * lane + 0] = make_float4(m00, m01, m02, __builtin_fmaf(-m00, vx, __builtin_fmaf(-m01, vy, __builtin_fmaf(-m02, vz, vx))));
+    tor[3 * lane + 1] = make_float4(m10, m11, m12, __builtin_fmaf(-m10, vx, __builtin_fmaf(-m11, vy, __builtin_fmaf(-m12, vz, vy))));
+    tor[3 * lane + 2] = make_float4(m20, m21, m22, __builtin_fmaf(-m20, vx, __builtin_fmaf(-m21, vy, __builtin_fmaf(-m22, vz, vz))));
   }
   wave_sync();
 }
@@ -747,7 +764,7 @@ template <int A>
 __device__ __forceinline__ float rigid_gradient(const Rigid& rb, const float (&x)[A], const float (&y)[A],
                                                 const float (&z)[A], const float (&gfx)[A], const float (&gfy)[A],
                                                 const float (&gfz)[A], float (&Fx)[A], float (&Fy)[A],
-                                                float (&Fz)[A]) {
+                                                float (&Fz)[A], float* rg, float e_lane = 0.f, float* E = nullptr) {
   const int lane = lane_id();
   float sfx = 0.f, sfy = 0.f, sfz = 0.f, tqx = 0.f, tqy = 0.f, tqz = 0.f;
 #pragma unroll
@@ -772,8 +789,14 @@ __device__ __forceinline__ float rigid_gradient(const Rigid& rb, const float (&x
   const float h0 = __uint_as_float(s0[0]) + __uint_as_float(s0[1]);   // sfx | sfz
   const float h1 = __uint_as_float(s1[0]) + __uint_as_float(s1[1]);   // sfy | tqx
   const float h2 = __uint_as_float(s2[0]) + __uint_as_float(s2[1]);   // tqy | tqz
+  // with E, the energy rides in the free rows 1 and 3 of r1 (the same tree as wave_sum_rs)
+  uint32_t h3 = 0u;
+  if (E) {
+    const auto s5 = __builtin_amdgcn_permlane32_swap(__float_as_uint(e_lane), __float_as_uint(e_lane), false, false);
+    h3 = __float_as_uint(__uint_as_float(s5[0]) + __uint_as_float(s5[1]));
+  }
   const auto s3 = __builtin_amdgcn_permlane16_swap(__float_as_uint(h0), __float_as_uint(h1), false, false);
-  const auto s4 = __builtin_amdgcn_permlane16_swap(__float_as_uint(h2), 0u, false, false);
+  const auto s4 = __builtin_amdgcn_permlane16_swap(__float_as_uint(h2), h3, false, false);
   float r0 = __uint_as_float(s3[0]) + __uint_as_float(s3[1]);
   float r1 = __uint_as_float(s4[0]) + __uint_as_float(s4[1]);
   r0 += dpp<0xb1, 0xf>(r0);   // quad_perm [1,0,3,2]
@@ -790,17 +813,20 @@ __device__ __forceinline__ float rigid_gradient(const Rigid& rb, const float (&x
   tqx = readlane(r0, 48);
   tqy = readlane(r1, 0);
   tqz = readlane(r1, 32);
+  if (E) *E = readlane(r1, 16);
   const float qw = rb.qw, qx = rb.qx, qy = rb.qy, qz = rb.qz, iqn = rb.iqn;
-  float g = 0.f;
-  if (lane == 0) g = sfx;
-  if (lane == 1) g = sfy;
-  if (lane == 2) g = sfz;
   // dE/dq for q/|q| = (w, v): (-2 tau.v, 2 (w tau - v x tau)) / |q|
-  if (lane == 3) g = -2.f * (tqx * qx + tqy * qy + tqz * qz) * iqn;
-  if (lane == 4) g = 2.f * (qw * tqx - (qy * tqz - qz * tqy)) * iqn;
-  if (lane == 5) g = 2.f * (qw * tqy - (qz * tqx - qx * tqz)) * iqn;
-  if (lane == 6) g = 2.f * (qw * tqz - (qx * tqy - qy * tqx)) * iqn;
-  return g;
+  const float g3 = -2.f * (tqx * qx + tqy * qy + tqz * qz) * iqn;
+  const float g4 = 2.f * (qw * tqx - (qy * tqz - qz * tqy)) * iqn;
+  const float g5 = 2.f * (qw * tqy - (qz * tqx - qx * tqz)) * iqn;
+  const float g6 = 2.f * (qw * tqz - (qx * tqy - qy * tqx)) * iqn;
+  // the seven wave-uniform values go to the gene lanes through LDS (lane 0 writes, lane l < 7
+  // reads entry l; a wave's LDS operations complete in order), instead of one select per gene
+  if (lane == 0) {
+    reinterpret_cast<float4*>(rg)[0] = make_float4(sfx, sfy, sfz, g3);
+    reinterpret_cast<float4*>(rg)[1] = make_float4(g4, g5, g6, 0.f);
+  }
+  return rg[min(lane, 7)];
 }
 
 // Lane k < T: torsion k's posed axis u_k (from the posed coordinates xs of its two atoms) and
@@ -859,11 +885,12 @@ __device__ float eval_pose_one(const LigDev& L, const RecDev& R, const BlockLds&
   float gfx[A], gfy[A], gfz[A];
 #pragma unroll
   for (int a = 0; a < A; ++a) e_lane += grid_finish(R, gf[a], at.valid[a], gfx[a], gfy[a], gfz[a]);
-  const float E = wave_sum(e_lane);
-  if (!GRAD) return E;
+  if (!GRAD) return wave_sum_rs(e_lane);
   wave_sync();
 
-  float g = rigid_gradient<A>(rb, x, y, z, gfx, gfy, gfz, Fx, Fy, Fz);
+  // the energy's wave sum rides in the rigid-body reduce-scatter
+  float E;
+  float g = rigid_gradient<A>(rb, x, y, z, gfx, gfy, gfz, Fx, Fy, Fz, b.rg, e_lane, &E);
   // torsions: every lane forms, for every torsion k, axis . (arm x force) of its atoms that k
   // moves, and reduce-scatters across the wave sum four torsions at a time
   if (T > 0) {
@@ -998,7 +1025,7 @@ __device__ float eval_pose_shared(const LigDev& L, const RecDev& R, const BlockL
   }
   if (!GRAD) return E;
 
-  float g = rigid_gradient<A>(rb, x, y, z, gfx, gfy, gfz, Fx, Fy, Fz);
+  float g = rigid_gradient<A>(rb, x, y, z, gfx, gfy, gfz, Fx, Fy, Fz, b.rg);
   // this wave's torsion batches, published by gene lane, then every wave reads all
   if (T > 0) {
     torsion_axes<A>(at, X, T, rb, b.tor);
