@@ -169,11 +169,10 @@ __host__ __device__ inline size_t lds_coord_bytes(int A) { return lds_align16((s
 // per wave: posed coordinates [3][64A + 1] and the force-array copies [n_copies][3][64A + 1],
 // float each (16-byte aligned blocks), then the torsion table [3*roundup4(n_tors)] float4
 // (per-pose rotations, later posed axes and pivots; padded so the torsion gradients can read
-// whole batches of four), then the rigid-body gene gradients [8] float (handed from the lanes
-// that reduced them to the gene lanes)
+// whole batches of four)
 __host__ __device__ inline size_t lds_wave_bytes(int n_atoms, int n_copies, int A, int n_tors) {
   (void)n_atoms;
-  return lds_coord_bytes(A) * (size_t)(1 + n_copies) + (size_t)48 * ((n_tors + 3) & ~3) + 32;
+  return lds_coord_bytes(A) * (size_t)(1 + n_copies) + (size_t)48 * ((n_tors + 3) & ~3);
 }
 // rows read from LDS, plus the row behind them that the pair loop's prefetch reads
 __host__ __device__ inline int lds_staged_rows(int rows) { return rows > 0 ? rows + 1 : 0; }

@@ -142,7 +142,6 @@ struct BlockLds {
   float* f;                  // this wave: [n_copies] blocks of intramolecular forces [3][64A + 1]
   float* fg;                 // this lane's group copy
   float4* tor;               // this wave: [3*roundup4(n_tors)] torsion table (see eval_pose)
-  float* rg;                 // this wave: [8] rigid-body gene gradients (see rigid_gradient)
   float4* share;             // waves sharing a pose: the pose's coordinates, then two sets of
                              // [W + 1][n_atoms + 1] + [W] (see eval_pose_shared)
 };
@@ -198,7 +197,6 @@ __device__ __forceinline__ BlockLds stage_block(const LigDev& L) {
   b.f = reinterpret_cast<float*>(cur);
   cur += cb * L.n_copies;
   b.tor = reinterpret_cast<float4*>(cur);
-  b.rg = reinterpret_cast<float*>(cur + (size_t)48 * ((L.n_tors + 3) & ~3));
   if (lane == 0) store3<A>(b.x, kWave * A, 0.f, 0.f, 0.f);
   if (L.wpp > 1 && threadIdx.x == 0)   // spare entry of the shared pose's coordinates
     store3<A>(reinterpret_cast<float*>(b.share), kWave * A, 0.f, 0.f, 0.f);
@@ -687,9 +685,15 @@ __device__ __forceinline__ void build_torsion_table(const AtomRegs<A>& at, float
     const float m10 = oc * uy * ux + sn * uz, m11 = oc * uy * uy + c, m12 = oc * uy * uz - sn * ux;
     const float m20 = oc * uz * ux - sn * uy, m21 = oc * uz * uy + sn * ux, m22 = oc * uz * uz + c;
     const float vx = at.tpx, vy = at.tpy, vz = at.tpz;
-    tor[3 * lane + 0] = make_float4(m00, m01, m02, __builtin_fmaf(-m00, vx, __builtin_fmaf(-m01, vy, __builtin_fmaf(-m02, vz, vx))));
-    tor[3 * lane + 1] = make_float4(m10, m11, m12, __builtin_fmaf(-m10, vx, __builtin_fmaf(-m11, vy, __builtin_fmaf(-m12, vz, vy))));
-    tor[3 * lane + 2] = make_float4(m20, m21, m22, __builtin_fmaf(-m20, vx, __builtin_fmaf(-m21, vy, __builtin_fmaf(-m22, vz, vz))));
+    if constexpr (A == 1) {
+      tor[3 * lane + 0] = make_float4(m00, m01, m02, __builtin_fmaf(-m00, vx, __builtin_fmaf(-m01, vy, __builtin_fmaf(-m02, vz, vx))));
+      tor[3 * lane + 1] = make_float4(m10, m11, m12, __builtin_fmaf(-m10, vx, __builtin_fmaf(-m11, vy, __builtin_fmaf(-m12, vz, vy))));
+      tor[3 * lane + 2] = make_float4(m20, m21, m22, __builtin_fmaf(-m20, vx, __builtin_fmaf(-m21, vy, __builtin_fmaf(-m22, vz, vz))));
+    } else {
+      tor[3 * lane + 0] = make_float4(m00, m01, m02, vx - (m00 * vx + m01 * vy + m02 * vz));
+      tor[3 * lane + 1] = make_float4(m10, m11, m12, vy - (m10 * vx + m11 * vy + m12 * vz));
+      tor[3 * lane + 2] = make_float4(m20, m21, m22, vz - (m20 * vx + m21 * vy + m22 * vz));
+    }
   }
   wave_sync();
 }
@@ -706,11 +710,14 @@ __device__ __forceinline__ void pose_slots(const LigDev& L, const AtomRegs<A>& a
     py[a] = at.py[a];
     pz[a] = at.pz[a];
   }
-  // torsion k's transform is applied while torsion k - 1's is being read
+  // torsion k's transform is applied while torsion k - 1's is being read; for k = 0 that read
+  // is of the 48 bytes before the table (the end of this wave's last force copy, inside its LDS),
+  // whose values go unused, so the addresses form one stride and need no clamp
   float4 m0 = T > 0 ? tor[3 * (T - 1) + 0] : float4{}, m1 = T > 0 ? tor[3 * (T - 1) + 1] : float4{},
          m2 = T > 0 ? tor[3 * (T - 1) + 2] : float4{};
   for (int k = T - 1; k >= 0; --k) {
-    const int kn = max(k - 1, 0);
+    // (two atoms per lane keep the clamped form, which their register allocation prefers)
+    const int kn = A == 1 ? k - 1 : max(k - 1, 0);
     const float4 n0 = tor[3 * kn + 0], n1 = tor[3 * kn + 1], n2 = tor[3 * kn + 2];
 #pragma unroll
     for (int a = 0; a < A; ++a) {
@@ -764,7 +771,7 @@ template <int A>
 __device__ __forceinline__ float rigid_gradient(const Rigid& rb, const float (&x)[A], const float (&y)[A],
                                                 const float (&z)[A], const float (&gfx)[A], const float (&gfy)[A],
                                                 const float (&gfz)[A], float (&Fx)[A], float (&Fy)[A],
-                                                float (&Fz)[A], float* rg, float e_lane = 0.f, float* E = nullptr) {
+                                                float (&Fz)[A], float e_lane = 0.f, float* E = nullptr) {
   const int lane = lane_id();
   float sfx = 0.f, sfy = 0.f, sfz = 0.f, tqx = 0.f, tqy = 0.f, tqz = 0.f;
 #pragma unroll
@@ -815,18 +822,16 @@ __device__ __forceinline__ float rigid_gradient(const Rigid& rb, const float (&x
   tqz = readlane(r1, 32);
   if (E) *E = readlane(r1, 16);
   const float qw = rb.qw, qx = rb.qx, qy = rb.qy, qz = rb.qz, iqn = rb.iqn;
+  float g = 0.f;
+  if (lane == 0) g = sfx;
+  if (lane == 1) g = sfy;
+  if (lane == 2) g = sfz;
   // dE/dq for q/|q| = (w, v): (-2 tau.v, 2 (w tau - v x tau)) / |q|
-  const float g3 = -2.f * (tqx * qx + tqy * qy + tqz * qz) * iqn;
-  const float g4 = 2.f * (qw * tqx - (qy * tqz - qz * tqy)) * iqn;
-  const float g5 = 2.f * (qw * tqy - (qz * tqx - qx * tqz)) * iqn;
-  const float g6 = 2.f * (qw * tqz - (qx * tqy - qy * tqx)) * iqn;
-  // the seven wave-uniform values go to the gene lanes through LDS (lane 0 writes, lane l < 7
-  // reads entry l; a wave's LDS operations complete in order), instead of one select per gene
-  if (lane == 0) {
-    reinterpret_cast<float4*>(rg)[0] = make_float4(sfx, sfy, sfz, g3);
-    reinterpret_cast<float4*>(rg)[1] = make_float4(g4, g5, g6, 0.f);
-  }
-  return rg[min(lane, 7)];
+  if (lane == 3) g = -2.f * (tqx * qx + tqy * qy + tqz * qz) * iqn;
+  if (lane == 4) g = 2.f * (qw * tqx - (qy * tqz - qz * tqy)) * iqn;
+  if (lane == 5) g = 2.f * (qw * tqy - (qz * tqx - qx * tqz)) * iqn;
+  if (lane == 6) g = 2.f * (qw * tqz - (qx * tqy - qy * tqx)) * iqn;
+  return g;
 }
 
 // Lane k < T: torsion k's posed axis u_k (from the posed coordinates xs of its two atoms) and
@@ -885,12 +890,15 @@ __device__ float eval_pose_one(const LigDev& L, const RecDev& R, const BlockLds&
   float gfx[A], gfy[A], gfz[A];
 #pragma unroll
   for (int a = 0; a < A; ++a) e_lane += grid_finish(R, gf[a], at.valid[a], gfx[a], gfy[a], gfz[a]);
-  if (!GRAD) return wave_sum_rs(e_lane);
-  wave_sync();
-
-  // the energy's wave sum rides in the rigid-body reduce-scatter
+  // one atom per lane: the energy's wave sum rides in the rigid-body reduce-scatter (and the
+  // energy-only path sums by the same tree); two atoms per lane: its own sum, which needs fewer
+  // live registers at the reduction
+  if (!GRAD) return A == 1 ? wave_sum_rs(e_lane) : wave_sum(e_lane);
   float E;
-  float g = rigid_gradient<A>(rb, x, y, z, gfx, gfy, gfz, Fx, Fy, Fz, b.rg, e_lane, &E);
+  if constexpr (A != 1) E = wave_sum(e_lane);
+  wave_sync();
+  float g = A == 1 ? rigid_gradient<A>(rb, x, y, z, gfx, gfy, gfz, Fx, Fy, Fz, e_lane, &E)
+                   : rigid_gradient<A>(rb, x, y, z, gfx, gfy, gfz, Fx, Fy, Fz);
   // torsions: every lane forms, for every torsion k, axis . (arm x force) of its atoms that k
   // moves, and reduce-scatters across the wave sum four torsions at a time
   if (T > 0) {
@@ -1025,7 +1033,7 @@ __device__ float eval_pose_shared(const LigDev& L, const RecDev& R, const BlockL
   }
   if (!GRAD) return E;
 
-  float g = rigid_gradient<A>(rb, x, y, z, gfx, gfy, gfz, Fx, Fy, Fz, b.rg);
+  float g = rigid_gradient<A>(rb, x, y, z, gfx, gfy, gfz, Fx, Fy, Fz);
   // this wave's torsion batches, published by gene lane, then every wave reads all
   if (T > 0) {
     torsion_axes<A>(at, X, T, rb, b.tor);
