@@ -7,7 +7,9 @@
 // setting the pace of small ones:
 //  * size classes: jobs are grouped by atoms per lane, waves per block and how many blocks of
 //    their LDS plan fit on a compute unit; each class has its own chain of launches with the
-//    class's LDS size, so a small ligand never runs with a large ligand's LDS reservation;
+//    class's LDS size, so a small ligand never runs with a large ligand's LDS reservation --
+//    except that a class too small to fill the device joins a larger class whose reservation
+//    covers it, rather than run alone as a latency-bound tail;
 //  * longest first: inside a launch, the blocks of the most expensive jobs come first, so the
 //    long waves start early and the short ones fill the tail;
 //  * independent chains: a class's generation (selection/crossover/mutation + evaluation,
@@ -56,6 +58,44 @@ void build_schedule(const std::vector<SchedJob>& jobs, GenSchedule& out, int max
     const int A = j.L->n_atoms > kWave ? 2 : 1;
     cls[Key(A, j.L->wpb, -occupancy_class(j.L->lds_bytes) * j.L->wpb, j.ls_method, std::max(1, j.L->wpp))]
         .push_back(k);
+  }
+  // A class too small to fill the device on its own (fewer local-search waves than a quarter of
+  // the device's wave slots) runs as a tail of its own launches, one search's latency long,
+  // whichever its ligands' plans.  Such a class joins the largest class of the same atoms per
+  // lane, waves per block, local optimiser and waves per search whose LDS reservation already
+  // covers its plans (its blocks then take that reservation): its searches, longest first, then
+  // fill the larger launch's tail.  Plans, and so results, are unchanged.
+  {
+    constexpr long long kSmallClassWaves = 1024;
+    std::map<Key, long long> waves;
+    std::map<Key, int> lds;
+    for (const auto& kv : cls)
+      for (int k : kv.second) {
+        const SchedJob& j = jobs[k];
+        waves[kv.first] += (long long)j.n_runs * j.n_ls * std::max(1, j.L->wpp);
+        lds[kv.first] = std::max(lds[kv.first], j.L->lds_bytes);
+      }
+    std::vector<Key> order;
+    for (const auto& kv : cls) order.push_back(kv.first);
+    std::stable_sort(order.begin(), order.end(), [&](const Key& a, const Key& b) { return waves[a] < waves[b]; });
+    for (const Key& small : order) {
+      if (waves[small] >= kSmallClassWaves || !cls.count(small)) continue;
+      const Key* into = nullptr;
+      for (const auto& kv : cls) {
+        const Key& k = kv.first;
+        if (k == small || std::get<0>(k) != std::get<0>(small) || std::get<1>(k) != std::get<1>(small) ||
+            std::get<3>(k) != std::get<3>(small) || std::get<4>(k) != std::get<4>(small))
+          continue;
+        if (lds[k] < lds[small] || waves[k] < waves[small]) continue;
+        if (!into || waves[k] > waves[*into]) into = &kv.first;
+      }
+      if (!into) continue;
+      const Key target = *into;
+      std::vector<int>& dst = cls[target];
+      dst.insert(dst.end(), cls[small].begin(), cls[small].end());
+      waves[target] += waves[small];
+      cls.erase(small);
+    }
   }
   std::vector<double> cost(jobs.size());
   for (size_t k = 0; k < jobs.size(); ++k) {
