@@ -145,7 +145,8 @@ md_status md_ligand_info(const md_ligand* lig, int* n_atoms, int* n_torsions, in
 typedef struct {
   int lds_budget;       /* 0..163840 (gfx950: a block may take the whole 160 KiB LDS of a CU) */
   int group_div;        /* 2..8 */
-  int waves_per_block;  /* 1, 2, 4 or 8 */
+  int waves_per_block;  /* 1, 2, 4, 8, 12 or 16; ligands of more than 64 atoms take at most 12
+                           (larger values are reduced to 12) */
   int lds_bytes, staged_rows, total_rows;   /* outputs: the resulting layout */
   int waves_per_pose;   /* 1 (or 0), 2 or 4 */
 } md_plan;
@@ -164,8 +165,9 @@ typedef struct {
   int from_table;              /* 1: the class was tuned before; its plan was applied untimed */
 } md_tune_info;
 /* Autotuner: times the local-search kernel on `rec` for candidate plans -- waves per block
- * {4, 8} x LDS budget {32, 48, 64, 96, 128, 160} KiB, waves per pose {2, 4} x LDS budget {64,
- * 160} KiB, then lane-group sizes N/2 and N/4 for the best -- and applies the fastest to `lig`.  n_starts is the number of local searches one launch
+ * {4, 8} x LDS budget {32, 48, 64, 96, 128, 160} KiB, the widest blocks (16 waves, 12 for more
+ * than 64 atoms) x {96, 128, 160} KiB, waves per pose {2, 4} x LDS budget {64, 160} KiB, then
+ * lane-group sizes N/2 and N/4 for the best -- and applies the fastest to `lig`.  n_starts is the number of local searches one launch
  * will run (md_dock: n_runs x ceil(ls_rate x pop_size)); the candidates are timed on that many
  * random starts inside the box (steps for about 1 ms per launch, best of five launches), since the
  * best plan depends on how well the launch fills the device.  n_starts = 0 (or >= 8192) tunes
@@ -341,12 +343,14 @@ md_status md_dock_batch(const md_receptor* rec, int n_jobs, const md_dock_job* j
  * MD_POLICY_LDS_ALL (LDS budget 160 KiB: all pair rows staged), MD_POLICY_WIDE_BLOCKS (8 waves
  * per block), MD_POLICY_SMALL_GROUPS (lane groups of about N/2), MD_POLICY_SHARED_LARGE (ligands of
  * more than 64 atoms search with 4 waves per pose, the rest with the default plan: shorter
- * generations for the largest ligands, whose searches set the pace).  The ligands must not be in use
+ * generations for the largest ligands, whose searches set the pace), MD_POLICY_FULL_BLOCKS (the
+ * widest blocks -- 16 waves, 12 for more than 64 atoms -- with an LDS budget of 160 KiB: one block
+ * per compute unit at full occupancy, all pair rows staged once per block).  The ligands must not be in use
  * by another call.  Blocking.  info may be NULL.  Errors: MD_EINVAL, MD_ERANGE
  * (generations outside [2, 1000]), and md_dock_batch's. */
 enum {
   MD_POLICY_DEFAULT = 0, MD_POLICY_TUNED_ALONE = 1, MD_POLICY_LDS_ALL = 2, MD_POLICY_WIDE_BLOCKS = 3,
-  MD_POLICY_SMALL_GROUPS = 4, MD_POLICY_SHARED_LARGE = 5, MD_BATCH_POLICIES = 6
+  MD_POLICY_SMALL_GROUPS = 4, MD_POLICY_SHARED_LARGE = 5, MD_POLICY_FULL_BLOCKS = 6, MD_BATCH_POLICIES = 7
 };
 typedef struct {
   int policy;                     /* the policy applied */

@@ -580,9 +580,10 @@ md_status md_dock_batch(const md_receptor* rec, int n_jobs, const md_dock_job* j
   const int2* d_blocks = reinterpret_cast<const int2*>(w + o_blocks);
   const RecDev& R = rec->dev;
 
-  // Initial populations, then the generations: one launch at a time when profiling (each is
-  // timed), else one captured generation replayed max_planned times (jobs that finish early
-  // skip the rest on the device).
+  // Initial populations, then the generations: when profiling, phase by phase (each phase's
+  // class launches concurrent, the phase timed) or, without graphs, one launch at a time; else
+  // one captured generation replayed max_planned times (jobs that finish early skip the rest on
+  // the device).
   LaunchTimer timer(s);
   const LaunchHook hook = [&](int kind, const std::function<hipError_t()>& f) { return timer.run(kind, f); };
   hipError_t e = hipMemcpyAsync(d_table, table.data(), sizeof(JobDev) * n_jobs, hipMemcpyHostToDevice, s);
@@ -591,7 +592,15 @@ md_status md_dock_batch(const md_receptor* rec, int n_jobs, const md_dock_job* j
                        hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = launch_init_phase(sched, d_table, d_blocks, R, s, &hook);
   if (e == hipSuccess) e = timer.run(MD_K_SUM_EVALS, [&] { return launch_ga_advance(d_table, n_jobs, s); });
-  if (g_prof.on || !use_graphs() || max_planned < 2) {
+  if (g_prof.on && use_graphs() && max_planned >= 2) {
+    // timed: each phase's launches concurrent over the classes, as the captured generation runs
+    // them, and the phase bracketed by the timer
+    GenGraph branches;
+    for (int g = 1; g <= max_planned && e == hipSuccess; ++g)
+      e = branches.launch_phased(sched, d_table, d_blocks, R, s, &hook);
+    // the branch streams are destroyed with `branches`: finish their work first
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  } else if (g_prof.on || !use_graphs() || max_planned < 2) {
     for (int g = 1; g <= max_planned && e == hipSuccess; ++g)
       e = launch_generation_phase(sched, d_table, d_blocks, R, s, &hook);
   } else {

@@ -52,7 +52,7 @@ std::map<std::pair<int, int>, TuneEntry> g_table;
 bool valid_plan(const md_plan& p) {
   return p.lds_budget >= 0 && p.lds_budget <= kMaxLdsPerBlock && p.group_div >= 2 && p.group_div <= 8 &&
          (p.waves_per_block == 1 || p.waves_per_block == 2 || p.waves_per_block == 4 ||
-          p.waves_per_block == 8) &&
+          p.waves_per_block == 8 || p.waves_per_block == 12 || p.waves_per_block == 16) &&
          (p.waves_per_pose == 0 || p.waves_per_pose == 1 || p.waves_per_pose == 2 || p.waves_per_pose == 4);
 }
 
@@ -161,7 +161,7 @@ md_status md_ligand_set_plan(md_ligand* lig, const md_plan* plan) {
   if (lig->holds.load() > 0) return api_fail(MD_EBUSY, "md_ligand_set_plan: a server request still uses the ligand");
   if (!valid_plan(*plan))
     return api_fail(MD_ERANGE, "md_ligand_set_plan: lds_budget in [0, 163840], group_div in [2, 8], "
-                               "waves_per_block in {1, 2, 4, 8}, waves_per_pose in {1, 2, 4}");
+                               "waves_per_block in {1, 2, 4, 8, 12, 16}, waves_per_pose in {1, 2, 4}");
   LigHost probe = lig->host;
   plan_ligand(probe, to_params(*plan));
   if (probe.lds_bytes > kMaxLdsPerBlock)
@@ -176,7 +176,7 @@ md_status md_schedule_preview(const md_ligand_desc* d, md_plan* plan, unsigned* 
   if (!d || !plan) return api_fail(MD_EINVAL, "md_schedule_preview: null argument");
   if (!valid_plan(*plan))
     return api_fail(MD_ERANGE, "md_schedule_preview: lds_budget in [0, 163840], group_div in [2, 8], "
-                               "waves_per_block in {1, 2, 4, 8}, waves_per_pose in {1, 2, 4}");
+                               "waves_per_block in {1, 2, 4, 8, 12, 16}, waves_per_pose in {1, 2, 4}");
   LigHost h;
   bool range = false;
   const std::string err = prepare_ligand(d->n_atoms, d->xyz, d->type, d->charge, d->n_bonds, d->bonds,
@@ -301,8 +301,11 @@ md_status md_ligand_autotune(const md_receptor* rec, md_ligand* lig, int n_start
     }
   }
   const int budgets[] = {32 * 1024, 48 * 1024, 64 * 1024, 96 * 1024, 128 * 1024, kMaxLdsPerBlock};
-  for (int wpb : {4, 8})
+  const int wide = max_waves_per_block(base.n_atoms > kWave ? 2 : 1);
+  for (int wpb : {4, 8, wide})
     for (int budget : budgets) {
+      // the widest blocks (one per compute unit) only with the large budgets
+      if (wpb == wide && budget < 96 * 1024) continue;
       if (e != hipSuccess) break;
       PlanParams pp;
       pp.wpb = wpb;
@@ -427,6 +430,8 @@ md_status md_batch_autotune(const md_receptor* rec, int n, md_ligand* const* lig
     plans[MD_POLICY_LDS_ALL][k].lds_budget = kMaxLdsPerBlock;
     plans[MD_POLICY_WIDE_BLOCKS][k].wpb = 8;
     plans[MD_POLICY_SMALL_GROUPS][k].group_div = 2;
+    plans[MD_POLICY_FULL_BLOCKS][k].wpb = max_waves_per_block(ligands[k]->host.n_atoms > kWave ? 2 : 1);
+    plans[MD_POLICY_FULL_BLOCKS][k].lds_budget = kMaxLdsPerBlock;
     if (ligands[k]->host.n_atoms > kWave) {
       plans[MD_POLICY_SHARED_LARGE][k].wpp = 4;
       plans[MD_POLICY_SHARED_LARGE][k].wpb = 4;

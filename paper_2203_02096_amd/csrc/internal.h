@@ -19,8 +19,13 @@ constexpr int kTypes = 7;
 constexpr int kMaps = kTypes + 2;
 constexpr int kWavesPerBlock = 4;                  // blocks of the kernels without a ligand plan
 constexpr int kBlock = kWave * kWavesPerBlock;
-constexpr int kMaxWavesPerBlock = 8;               // evaluation kernels: the plan's waves per block
+// evaluation kernels: the plan's waves per block; one atom per lane takes at most 128 VGPRs
+// (four waves per SIMD, so a block of 16 waves fits a compute unit), two atoms per lane at most
+// 168 (three waves per SIMD: blocks of up to 12 waves)
+constexpr int kMaxWavesPerBlock = 16;
+constexpr int kMaxWavesPerBlock2 = 12;
 constexpr int kMaxBlock = kWave * kMaxWavesPerBlock;
+__host__ __device__ constexpr int max_waves_per_block(int A) { return A == 1 ? kMaxWavesPerBlock : kMaxWavesPerBlock2; }
 // Waves that share one pose in the local-search kernels (1, 2 or 4): the pair rows are split
 // between them and their partial forces and energies meet in LDS once per evaluation.  A block
 // whose waves share a pose holds exactly that one pose.
@@ -135,7 +140,7 @@ struct JobDev {
 struct PlanParams {
   int lds_budget = (int)kLdsBudget;   // dynamic LDS of one block, bytes (<= kMaxLdsPerBlock)
   int group_div = 3;                  // lanes per conflict-free group ~ n_atoms / group_div
-  int wpb = kWavesPerBlock;           // waves per block (1..kMaxWavesPerBlock)
+  int wpb = kWavesPerBlock;           // waves per block (1..max_waves_per_block(A))
   int wpp = 1;                        // waves per pose in the local searches (1, 2, 4; > 1 sets wpb)
 };
 
@@ -266,6 +271,12 @@ class GenGraph {
   hipError_t launch_direct(const GenSchedule& g, JobDev* table, const int2* d_blocks, const RecDev& R,
                            hipStream_t s);
   hipError_t launch(hipStream_t s) const;
+  // one generation of every class phase by phase (GA generation, local-search picks, local
+  // search, epilogue): each phase's class launches run concurrently over s and the branch
+  // streams, as in the captured generation, and `hook` brackets the whole phase on s (so a
+  // timing hook measures each phase as the classes share the device)
+  hipError_t launch_phased(const GenSchedule& g, JobDev* table, const int2* d_blocks, const RecDev& R,
+                           hipStream_t s, const LaunchHook* hook);
   bool ready() const { return exec_ != nullptr; }
   // drops the executable graph (the capture streams stay for the next capture)
   void reset();

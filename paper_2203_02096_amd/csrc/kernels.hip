@@ -1062,6 +1062,11 @@ __device__ __forceinline__ float eval_pose(const LigDev& L, const RecDev& R, con
 // One-wave searches keep the register budget of 4 waves per SIMD (one atom per lane) or 3 (two):
 // each search is a long dependent chain, and those waves are what hides its latency.
 #define MDOCK_SEARCH_OCCUPANCY __attribute__((amdgpu_waves_per_eu(W == 1 ? (A == 1 ? 4 : 3) : 1)))
+// Block-size bound of the evaluation kernels: the plan's widest block (16 waves of one atom per
+// lane, 12 of two), or 8 waves for the shared-pose instantiations (as before: it caps their
+// registers at two waves per SIMD).
+#define MDOCK_BLOCK_BOUND_W(A, W) __launch_bounds__((W) == 1 ? kWave * max_waves_per_block(A) : kWave * 8)
+#define MDOCK_BLOCK_BOUND(A) __launch_bounds__(kWave * max_waves_per_block(A))
 
 // One block = blockDim / (64 W) poses; W > 1: the block's waves share its one pose.
 template <int W>
@@ -1073,7 +1078,7 @@ __device__ __forceinline__ int block_pose(PoseShare& ps) {
 }
 
 template <int A, int PREC, int W>
-__global__ __launch_bounds__(kMaxBlock) void k_eval(LigDev L, RecDev R, int n, const float* __restrict__ genes,
+__global__ MDOCK_BLOCK_BOUND_W(A, W) void k_eval(LigDev L, RecDev R, int n, const float* __restrict__ genes,
                                                  float* __restrict__ energy, float* __restrict__ grad) {
   const BlockLds b = stage_block<A>(L);
   PoseShare ps;
@@ -1232,7 +1237,7 @@ __device__ float local_search_wave(const LigDev& L, const RecDev& R, const Block
 
 // Standalone local search: one pose (W waves) per start genotype.
 template <int A, int PREC, int W>
-__global__ __launch_bounds__(kMaxBlock) MDOCK_SEARCH_OCCUPANCY void k_local_search(LigDev L, RecDev R, int n,
+__global__ MDOCK_BLOCK_BOUND_W(A, W) MDOCK_SEARCH_OCCUPANCY void k_local_search(LigDev L, RecDev R, int n,
                                                          const float* genes_in, float* genes_out,
                                                          float* __restrict__ energy_out,
                                                          int iters, float rho, float eps,
@@ -1342,7 +1347,7 @@ __device__ float solis_wets_wave(const LigDev& L, const RecDev& R, const BlockLd
 // Standalone Solis-Wets: one wave per start genotype; start k draws from coordinates
 // (seed, 0, 0, k).
 template <int A, int PREC, int W>
-__global__ __launch_bounds__(kMaxBlock) MDOCK_SEARCH_OCCUPANCY void k_solis_wets(LigDev L, RecDev R, int n, const float* genes_in,
+__global__ MDOCK_BLOCK_BOUND_W(A, W) MDOCK_SEARCH_OCCUPANCY void k_solis_wets(LigDev L, RecDev R, int n, const float* genes_in,
                                                        float* genes_out, float* __restrict__ energy_out,
                                                        int n_evals, unsigned long long seed,
                                                        float* __restrict__ trace) {
@@ -1480,7 +1485,7 @@ __device__ float offspring_gene(const GaDev& P, const float* __restrict__ genes_
 // not in the phase's state leaves before staging anything (uniform per block).
 
 template <int A, int PREC>
-__global__ __launch_bounds__(kMaxBlock) void k_ga_init(JobDev* __restrict__ jobs, const int2* __restrict__ blocks,
+__global__ MDOCK_BLOCK_BOUND(A) void k_ga_init(JobDev* __restrict__ jobs, const int2* __restrict__ blocks,
                                                     RecDev R) {
   const int2 bt = blocks[blockIdx.x];
   JobDev& J = jobs[bt.x];
@@ -1508,7 +1513,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_ga_init(JobDev* __restrict__ jobs
 }
 
 template <int A, int PREC>
-__global__ __launch_bounds__(kMaxBlock) void k_ga_generation(JobDev* __restrict__ jobs,
+__global__ MDOCK_BLOCK_BOUND(A) void k_ga_generation(JobDev* __restrict__ jobs,
                                                           const int2* __restrict__ blocks, RecDev R) {
   const int2 bt = blocks[blockIdx.x];
   JobDev& J = jobs[bt.x];
@@ -1578,7 +1583,7 @@ __global__ __launch_bounds__(kBlock) void k_ga_ls_pick(JobDev* __restrict__ jobs
 // Local search on the picked individuals; a block holds blockDim / (64 W) searches from
 // (job, first search) of its block-table entry.
 template <int A, int PREC, int W>
-__global__ __launch_bounds__(kMaxBlock) MDOCK_SEARCH_OCCUPANCY void k_ga_local_search(JobDev* __restrict__ jobs,
+__global__ MDOCK_BLOCK_BOUND_W(A, W) MDOCK_SEARCH_OCCUPANCY void k_ga_local_search(JobDev* __restrict__ jobs,
                                                             const int2* __restrict__ blocks, RecDev R) {
   const int2 bt = blocks[blockIdx.x];
   JobDev& J = jobs[bt.x];
@@ -1605,7 +1610,7 @@ __global__ __launch_bounds__(kMaxBlock) MDOCK_SEARCH_OCCUPANCY void k_ga_local_s
 // Solis-Wets on the picked individuals (Lamarckian write-back); the search of individual i of
 // run r in generation g draws from coordinates (seed, r, g, i).
 template <int A, int PREC, int W>
-__global__ __launch_bounds__(kMaxBlock) MDOCK_SEARCH_OCCUPANCY void k_ga_solis_wets(JobDev* __restrict__ jobs,
+__global__ MDOCK_BLOCK_BOUND_W(A, W) MDOCK_SEARCH_OCCUPANCY void k_ga_solis_wets(JobDev* __restrict__ jobs,
                                                           const int2* __restrict__ blocks, RecDev R) {
   const int2 bt = blocks[blockIdx.x];
   JobDev& J = jobs[bt.x];

@@ -212,7 +212,7 @@ void plan_ligand(LigHost& out, const PlanParams& pp) {
   const int A = n > kWave ? 2 : 1;
   const int div = std::max(2, std::min(8, pp.group_div));
   const int wpp = (pp.wpp == 2 || pp.wpp == 4) ? pp.wpp : 1;
-  const int wpb = wpp > 1 ? wpp : std::max(1, std::min(kMaxWavesPerBlock, pp.wpb));
+  const int wpb = wpp > 1 ? wpp : std::max(1, std::min(max_waves_per_block(A), pp.wpb));
   // groups of about n / group_div lanes, larger where the block's waves could not hold one force
   // copy per group in LDS
   int want = std::max(1, std::min(kWave, n / div));

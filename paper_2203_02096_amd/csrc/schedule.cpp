@@ -165,22 +165,39 @@ hipError_t launch_init_phase(const GenSchedule& g, JobDev* table, const int2* d_
 
 namespace {
 
+// The launch of one phase (kind) of one class's generation on stream st (none where the class
+// has no such work).
+hipError_t launch_step(const ClassChain& c, int kind, JobDev* table, const int2* d_blocks, const RecDev& R,
+                       hipStream_t st) {
+  switch (kind) {
+    case MD_K_GENERATION:
+      return launch_ga_generation(table, d_blocks + c.pop_first, c.pop_count, c.A, c.wpb, c.lds, R, st);
+    case MD_K_LS_PICK:
+      return c.run_count > 0 ? launch_ga_ls_pick(table, d_blocks + c.run_first, c.run_count, st) : hipSuccess;
+    case MD_K_LOCAL_SEARCH:
+      return c.ls_count > 0 ? launch_ga_local_search(table, d_blocks + c.ls_first, c.ls_count, c.A, c.wpb, c.wpp,
+                                                     c.lds, c.ls_method, R, st)
+                            : hipSuccess;
+    default:
+      return launch_ga_advance_list(table, d_blocks + c.adv_first, c.adv_count, st);
+  }
+}
+
+constexpr int kChainKinds[4] = {MD_K_GENERATION, MD_K_LS_PICK, MD_K_LOCAL_SEARCH, MD_K_SUM_EVALS};
+
+bool has_step(const ClassChain& c, int kind) {
+  return !(kind == MD_K_LS_PICK && c.run_count == 0) && !(kind == MD_K_LOCAL_SEARCH && c.ls_count == 0);
+}
+
 // One generation of one class on stream st.
 hipError_t launch_chain(const ClassChain& c, JobDev* table, const int2* d_blocks, const RecDev& R, hipStream_t st,
                         const LaunchHook* hook) {
-  auto run = [&](int kind, const std::function<hipError_t()>& f) { return hook ? (*hook)(kind, f) : f(); };
-  hipError_t e = run(MD_K_GENERATION, [&] {
-    return launch_ga_generation(table, d_blocks + c.pop_first, c.pop_count, c.A, c.wpb, c.lds, R, st);
-  });
-  if (e == hipSuccess && c.run_count > 0)
-    e = run(MD_K_LS_PICK, [&] { return launch_ga_ls_pick(table, d_blocks + c.run_first, c.run_count, st); });
-  if (e == hipSuccess && c.ls_count > 0)
-    e = run(MD_K_LOCAL_SEARCH, [&] {
-      return launch_ga_local_search(table, d_blocks + c.ls_first, c.ls_count, c.A, c.wpb, c.wpp, c.lds, c.ls_method,
-                                    R, st);
-    });
-  if (e == hipSuccess)
-    e = run(MD_K_SUM_EVALS, [&] { return launch_ga_advance_list(table, d_blocks + c.adv_first, c.adv_count, st); });
+  hipError_t e = hipSuccess;
+  for (int kind : kChainKinds) {
+    if (e != hipSuccess || !has_step(c, kind)) continue;
+    auto f = [&] { return launch_step(c, kind, table, d_blocks, R, st); };
+    e = hook ? (*hook)(kind, f) : f();
+  }
   return e;
 }
 
@@ -272,6 +289,30 @@ hipError_t GenGraph::launch_direct(const GenSchedule& g, JobDev* table, const in
                                    hipStream_t s) {
   const hipError_t e = make_streams();
   return e == hipSuccess ? fork_classes(g, table, d_blocks, R, s, false) : e;
+}
+
+hipError_t GenGraph::launch_phased(const GenSchedule& g, JobDev* table, const int2* d_blocks, const RecDev& R,
+                                   hipStream_t s, const LaunchHook* hook) {
+  hipError_t e = make_streams();
+  const size_t width = std::max<size_t>(1, std::min(g.classes.size(), kGraphBranches));
+  for (int kind : kChainKinds) {
+    if (e != hipSuccess) break;
+    bool any = false;
+    for (const ClassChain& c : g.classes) any = any || has_step(c, kind);
+    if (!any) continue;
+    auto phase = [&]() -> hipError_t {
+      hipError_t ep = hipEventRecord(ev_[0], s);
+      for (size_t k = 0; k + 1 < width && ep == hipSuccess; ++k) ep = hipStreamWaitEvent(side_[k], ev_[0], 0);
+      for (size_t i = 0; i < g.classes.size() && ep == hipSuccess; ++i)
+        if (has_step(g.classes[i], kind))
+          ep = launch_step(g.classes[i], kind, table, d_blocks, R, (i % width == 0) ? s : side_[i % width - 1]);
+      for (size_t k = 0; k + 1 < width && ep == hipSuccess; ++k) ep = hipEventRecord(ev_[1 + k], side_[k]);
+      for (size_t k = 0; k + 1 < width && ep == hipSuccess; ++k) ep = hipStreamWaitEvent(s, ev_[1 + k], 0);
+      return ep;
+    };
+    e = hook ? (*hook)(kind, phase) : phase();
+  }
+  return e;
 }
 
 hipError_t GenGraph::launch(hipStream_t s) const {

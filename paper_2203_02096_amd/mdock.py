@@ -88,7 +88,7 @@ class BatchTuneInfo(C.Structure):
     _fields_ = [("policy", C.c_int), ("n_policies", C.c_int), ("ms_per_generation", C.c_double * 8)]
 
 
-BATCH_POLICIES = ["default", "tuned_alone", "lds_all", "wide_blocks", "small_groups", "shared_large"]
+BATCH_POLICIES = ["default", "tuned_alone", "lds_all", "wide_blocks", "small_groups", "shared_large", "full_blocks"]
 
 
 class DockJob(C.Structure):

@@ -43,6 +43,9 @@ PLANS = [dict(lds_budget=0, group_div=3, waves_per_block=4),
          dict(lds_budget=32 * 1024, group_div=2, waves_per_block=1),
          dict(lds_budget=96 * 1024, group_div=4, waves_per_block=2),
          dict(lds_budget=65536, group_div=8, waves_per_block=8),
+         # the widest blocks: 16 waves (12 for more than 64 atoms), one block per compute unit
+         dict(lds_budget=160 * 1024, group_div=3, waves_per_block=16),
+         dict(lds_budget=160 * 1024, group_div=2, waves_per_block=12),
          # waves sharing a pose (the block holds one pose)
          dict(lds_budget=65536, group_div=3, waves_per_block=2, waves_per_pose=2),
          dict(lds_budget=160 * 1024, group_div=3, waves_per_block=4, waves_per_pose=4),

@@ -16,7 +16,8 @@ CASES = [(4, 1), (6, 2), (10, 3), (20, 4), (33, 7), (40, 8), (64, 12), (65, 12),
 PLANS = [dict(), dict(group_div=2), dict(group_div=4), dict(group_div=8, waves_per_block=1),
          dict(lds_budget=0), dict(lds_budget=160 * 1024, waves_per_block=8), dict(lds_budget=20000),
          dict(waves_per_block=4, waves_per_pose=4), dict(lds_budget=160 * 1024, waves_per_block=8, waves_per_pose=2),
-         dict(group_div=8, waves_per_block=8)]
+         dict(group_div=8, waves_per_block=8), dict(lds_budget=160 * 1024, waves_per_block=16),
+         dict(lds_budget=160 * 1024, waves_per_block=12, group_div=2)]
 
 
 def _lib_available():
@@ -83,7 +84,8 @@ def test_schedule_invariants(n, t, plan):
 
 def test_schedule_preview_rejects_bad_plans():
     lig = synth.make_ligand(20, 4, 77, configs.type_params())
-    for bad in (dict(group_div=1), dict(group_div=9), dict(waves_per_block=3), dict(lds_budget=-1),
+    for bad in (dict(group_div=1), dict(group_div=9), dict(waves_per_block=3), dict(waves_per_block=32),
+                dict(waves_per_block=10), dict(lds_budget=-1),
                 dict(lds_budget=160 * 1024 + 1), dict(waves_per_pose=3), dict(waves_per_pose=8)):
         with pytest.raises(md.MdockError):
             md.md_schedule_preview(lig, **bad)
@@ -156,3 +158,13 @@ def test_schedule_same_in_a_fresh_process():
         info, m, raw = _preview_digest(synth.make_ligand(n, t, 9000 + n, configs.type_params()))
         here.append(f"{n} {info} {m} {hashlib.sha256(raw).hexdigest()}")
     assert outs[0].splitlines() == here
+
+
+@pytest.mark.parametrize("n,t", [(20, 4), (64, 12), (65, 12), (128, 32)])
+def test_widest_blocks(n, t):
+    """16 waves per block for one atom per lane; two atoms per lane (more than 64 atoms) take at
+    most 12 (three waves per SIMD), so a request for 16 is reduced to 12."""
+    lig = synth.make_ligand(n, t, 7000 + n, configs.type_params())
+    info, _, _ = md.md_schedule_preview(lig, lds_budget=160 * 1024, waves_per_block=16)
+    assert info["waves_per_block"] == (16 if n <= 64 else 12)
+    assert info["lds_bytes"] <= 160 * 1024
