@@ -228,11 +228,13 @@ def main():
                     help="after the timed region, one plain device copy of this size (a known-size "
                          "dispatch for calibrating byte counters under a profiler)")
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD,
-                    choices=[WORKLOAD, "batched_fp32", "serving_fp16", "paper_inputs", "eval_sweep"],
+                    choices=[WORKLOAD, "batched_fp32", "serving_fp16", "paper_inputs", "eval_sweep", "eval_phases"],
                     help="batched_fp32 (default): 256 ligands in one batch; plain_fp32_production: "
                          "one ligand, 20 runs; serving_fp16: Poisson arrivals into the server; "
                          "paper_inputs: the paper's three input sizes at 10 and 100 runs, docked "
-                         "with each block size; eval_sweep: md_eval of 2^16..2^20 independent poses")
+                         "with each block size; eval_sweep: md_eval of 2^16..2^20 independent poses; "
+                         "eval_phases: md_eval with and without gradient and torsions, then a search, for "
+                         "per-phase instruction counts under a profiler")
     ap.add_argument("--generations", type=int, default=50,
                     help="batched_fp32: generations per step (the full budget takes 878)")
     ap.add_argument("--full-budget", action="store_true",
@@ -261,6 +263,8 @@ def main():
         return bench_paper_inputs(args)
     if args.workload == "eval_sweep":
         return bench_eval_sweep(args)
+    if args.workload == "eval_phases":
+        return bench_eval_phases(args)
 
     # the oracle baseline runs first, in spawned processes, before this process touches the GPU
     base = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds, grad=args.ls != "solis_wets")
@@ -374,6 +378,66 @@ def _common(md):
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     md.lib()
+
+
+def bench_eval_phases(args):
+    """Per-phase instruction budget of one evaluation: md_eval of 2^16 random poses of the
+    production ligand with and without the gradient, and of the same atoms with no rotatable bond
+    (no torsions, hence no intramolecular pairs), then md_local_search (300 ADADELTA steps) from
+    the same starts; the default plan throughout.  Launched in that order, each `--warmup` +
+    `--steps` times, so a profiler's per-dispatch counters (SQ_INSTS_VALU, ...) divided by the
+    evaluations of each launch give the budget: the differences separate the gradient, the
+    torsions and pairs, and the search step's own work."""
+    import numpy as np
+    import torch
+
+    import paper_2203_02096_amd as md
+    from workload import configs, synth
+    _common(md)
+    rec = configs.receptor(WORKLOAD)
+    lig = configs.ligand(WORKLOAD)
+    rigid = synth.Ligand(lig.xyz, lig.types, lig.charges, lig.bonds, np.zeros(0, np.int32), lig.root,
+                         lig.type_params)
+    drec = md.Receptor(rec.maps, rec.origin, rec.spacing, "fp32")
+    n = 1 << 16
+    stream = torch.cuda.current_stream()
+    rows = []
+    for name, L, grad, search in (("torsions8_gradient", lig, True, False), ("torsions8_energy", lig, False, False),
+                                  ("rigid_gradient", rigid, True, False), ("rigid_energy", rigid, False, False),
+                                  ("torsions8_search300", lig, True, True)):
+        dlig = md.Ligand.from_synth(L)
+        info = md.md_ligand_info(dlig)
+        genes = torch.from_numpy(synth.random_genes(L, rec, n, seed=5, margin=2.0)).cuda()
+        e = torch.empty(n, device="cuda")
+        d = torch.empty(n, L.n_genes, device="cuda")
+        out_g = torch.empty_like(genes)
+        iters = 300 if search else 1
+
+        def launch():
+            if search:
+                md.md_local_search(drec, dlig, genes, out_g, e, iters, stream=stream)
+            else:
+                md.md_eval(drec, dlig, genes, e, d if grad else None, stream=stream)
+        for _ in range(args.warmup):
+            launch()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(args.steps):
+            launch()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / args.steps
+        rows.append({"variant": name, "evals_per_launch": n * iters, "ms_per_launch": ms,
+                     "ns_per_eval": ms * 1e6 / (n * iters), "n_atoms": info["n_atoms"],
+                     "n_torsions": info["n_torsions"], "n_pairs": info["n_pairs"],
+                     "launches": args.warmup + args.steps})
+        print(f"[eval_phases] {name}: {ms:.3f} ms per launch", file=sys.stderr, flush=True)
+    out = {"metric": "energy+gradient evals/s (md_eval, independent poses)", "value": n / (rows[0]["ms_per_launch"] * 1e-3),
+           "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": rows[0]["ms_per_launch"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "eval_phases", "ligand": WORKLOAD, "poses": n}, "variants": rows}
+    print(json.dumps(out), flush=True)
 
 
 def bench_eval_sweep(args):
