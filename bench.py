@@ -535,6 +535,8 @@ def bench_paper_inputs(args):
                     t0 = time.perf_counter()
                     md.md_dock(drec, dlig, P, stream=stream, want_xyz=False)
                     ts.append(time.perf_counter() - t0)
+                print(f"[paper_inputs] {size} nruns {nruns} plan {md.md_ligand_get_plan(dlig)}: "
+                      f"{float(np.median(ts)):.3f} s", file=sys.stderr, flush=True)
                 return float(np.median(ts))
 
             per_wpb, per_wpp = {}, {}
