@@ -79,3 +79,32 @@ def test_dock_batch_graph_equals_eager(md, receptor):
     for k in range(len(ligs)):
         for key in KEYS:
             assert np.array_equal(eager[k][key], graph[k][key]), (k, key)
+
+
+def test_profiled_batch_equals_graph(md, receptor):
+    """A profiled batch (each GA phase's size-class launches concurrent over the branch streams,
+    each phase timed) gives bitwise the results of the captured graph; small size classes join a
+    larger class's launches either way (the plans below give several LDS classes of few waves)."""
+    rec, drec = receptor
+    sizes = [(12, 2), (40, 8), (70, 16), (25, 4), (100, 20), (55, 10), (18, 3)]
+    ligs = [md.Ligand.from_synth(synth.make_ligand(n, t, 930 + k, configs.type_params()))
+            for k, (n, t) in enumerate(sizes)]
+    md.md_ligand_set_plan(ligs[0], lds_budget=160 * 1024, waves_per_block=4)
+    md.md_ligand_set_plan(ligs[3], lds_budget=32 * 1024, waves_per_block=4)
+    md.md_ligand_set_plan(ligs[6], lds_budget=160 * 1024, waves_per_block=16)
+    Ps = [md.dock_params(**configs.search_params("serving_fp16", n_runs=3, pop_size=30, max_generations=5,
+                                                 ls_rate=0.2, ls_iters=20, seed=60 + k)) for k in range(len(ligs))]
+    _say("[graphs] md_dock_batch of 7 ligands, graph then profiled")
+    md.md_set_graphs(True)
+    graph = md.md_dock_batch(drec, list(zip(ligs, Ps)))
+    md.md_profile_reset()
+    md.md_profile_enable(True)
+    try:
+        prof = md.md_dock_batch(drec, list(zip(ligs, Ps)))
+    finally:
+        md.md_profile_enable(False)
+    ms, n = md.md_profile_read("local_search")
+    assert n == 5 and ms > 0          # one timed local-search phase per generation
+    for k in range(len(ligs)):
+        for key in KEYS:
+            assert np.array_equal(graph[k][key], prof[k][key]), (k, key)
