@@ -622,6 +622,12 @@ def bench_batched(args):
     t_tune = time.perf_counter()
     tuned = None if args.no_autotune else md.md_batch_autotune(drec, jobs, generations=9)
     t_tune = time.perf_counter() - t_tune
+    plan_mix = {}
+    for dl in dligs:
+        pl = md.md_ligand_get_plan(dl)
+        key = (f"{'A2' if dl.n_atoms > 64 else 'A1'}_wpb{pl['waves_per_block']}_wpp{pl['waves_per_pose']}"
+               f"_lds{pl['lds_budget'] // 1024}k")
+        plan_mix[key] = plan_mix.get(key, 0) + 1
     n_ls = max(0, min(P.pop_size, math.ceil(sp["ls_rate"] * P.pop_size - 1e-4)))
     per_gen = (P.pop_size - P.elitism) + n_ls * P.ls_iters
     total_evals = len(jobs) * P.n_runs * (P.pop_size + gens * per_gen)
@@ -693,7 +699,7 @@ def bench_batched(args):
                                   f"full budget ({full_gens} generations)"),
            "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                           "what": "per step (the whole batch)"},
-           "autotune": {**(tuned or {"policy": "default (not tuned)"}), "seconds": t_tune},
+           "autotune": {**(tuned or {"policy": "default (not tuned)"}), "seconds": t_tune, "plan_mix": plan_mix},
            "roofline": {"bound": "alu", "achieved": tf, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                         "frac": tf / PEAK_FP32_VALU_TFLOPS, "traffic": prof["traffic"],
                         "traffic_unit": "HBM bytes per generation of local-search launches",
