@@ -77,9 +77,13 @@ typedef struct {
 
 /* maps: host float32, layout [n_types + 2][nz][ny][nx], finite values.
  * stored: storage precision on the device (FP16/BF16 round to nearest even; the
- * interpolation and everything after it stays FP32).  On the device the electrostatic and
- * desolvation values of a node sit side by side (every atom reads both at the same corners).
- * The copy is complete when the call returns.  Errors: MD_EINVAL (null/non-finite/bad sizes), MD_ENOMEM, MD_EDEVICE. */
+ * interpolation and everything after it stays FP32).  On the device every grid cell holds its
+ * eight corner values per map in one record (the electrostatic and desolvation values side by
+ * side, since every atom reads both at the same corners): 72 stored values per node, 288 bytes
+ * (FP32) or 144 (FP16/BF16), so that an atom's corners are three aligned runs of memory.
+ * The copy is complete when the call returns.  Errors: MD_EINVAL (null/non-finite/bad sizes),
+ * MD_ERANGE (FP16 overflow; cell records of 2 GiB or more: above about 7.4M nodes in FP32,
+ * 14.9M in FP16/BF16), MD_ENOMEM, MD_EDEVICE. */
 md_status md_receptor_create(const md_grid_desc* desc, const float* maps,
                              md_map_precision stored, void* hip_stream, md_receptor** out);
 md_status md_receptor_destroy(md_receptor* rec);

@@ -204,8 +204,8 @@ md_status md_receptor_create(const md_grid_desc* d, const float* maps, md_map_pr
     return fail(MD_EINVAL, "md_receptor_create: bad storage precision");
   const long long nodes = (long long)d->nx * d->ny * d->nz;
   const long long elem_bytes = stored == MD_MAP_FP32 ? 4 : 2;
-  if (nodes > ((1ll << 31) - 1) / (kMaps * elem_bytes))
-    return fail(MD_ERANGE, "md_receptor_create: grid too large (the stored maps must stay below 2 GiB)");
+  if (nodes > ((1ll << 31) - 1) / (kCellValues * elem_bytes))
+    return fail(MD_ERANGE, "md_receptor_create: grid too large (the stored cell records must stay below 2 GiB)");
   const long long count = nodes * kMaps;
   for (long long i = 0; i < count; ++i)
     if (!std::isfinite(maps[i])) return fail(MD_EINVAL, "md_receptor_create: non-finite map value");
@@ -213,30 +213,47 @@ md_status md_receptor_create(const md_grid_desc* d, const float* maps, md_map_pr
     for (long long i = 0; i < count; ++i)
       if (std::fabs(maps[i]) > 65504.f) return fail(MD_ERANGE, "md_receptor_create: map value outside FP16 range");
 
-  // device layout: the type maps as given, then the electrostatic and desolvation maps
-  // interleaved per node ([nz][ny][nx][2]): an atom reads both at the same eight corners, so a
-  // corner pair along x is one 16-byte (FP32) or 8-byte load for the two maps
-  std::vector<float> dev((size_t)count);
-  std::copy(maps, maps + (size_t)kTypes * nodes, dev.begin());
-  for (long long i = 0; i < nodes; ++i) {
-    dev[(size_t)kTypes * nodes + 2 * i] = maps[(size_t)kTypes * nodes + i];
-    dev[(size_t)kTypes * nodes + 2 * i + 1] = maps[(size_t)(kTypes + 1) * nodes + i];
-  }
+  // device layout: one record per cell, named by its lowest node (x fastest), holding the
+  // cell's eight corner values (corner bit 0 +x, bit 1 +y, bit 2 +z): the type maps' records
+  // [7][cells][8], then the electrostatic and desolvation maps' [cells][8][2] (every atom reads
+  // both at the same corners).  An atom's 24 corner values are then three aligned 32- or
+  // 64-byte runs, whatever its cell; corners past the last node (records of the last layer,
+  // which no inside atom reads) hold zero.
   const size_t elem = stored == MD_MAP_FP32 ? 4 : 2;
-  std::vector<uint16_t> half;
-  const void* src = dev.data();
-  if (stored != MD_MAP_FP32) {
-    half.resize(count);
-    for (long long i = 0; i < count; ++i)
-      half[i] = stored == MD_MAP_FP16 ? f32_to_f16_rne(dev[i]) : f32_to_bf16_rne(dev[i]);
-    src = half.data();
-  }
+  const long long dcount = nodes * kCellValues;
+  std::vector<float> f32;
+  std::vector<uint16_t> f16;
+  if (stored == MD_MAP_FP32)
+    f32.assign((size_t)dcount, 0.f);
+  else
+    f16.assign((size_t)dcount, 0);
+  auto put = [&](long long k, float v) {
+    if (stored == MD_MAP_FP32)
+      f32[(size_t)k] = v;
+    else
+      f16[(size_t)k] = stored == MD_MAP_FP16 ? f32_to_f16_rne(v) : f32_to_bf16_rne(v);
+  };
+  const long long ed = (long long)kTypes * nodes * 8;
+  for (long long z = 0; z < d->nz; ++z)
+    for (long long y = 0; y < d->ny; ++y)
+      for (long long x = 0; x < d->nx; ++x) {
+        const long long cell = (z * d->ny + y) * d->nx + x;
+        for (int c = 0; c < 8; ++c) {
+          const long long cx = x + (c & 1), cy = y + ((c >> 1) & 1), cz = z + (c >> 2);
+          if (cx >= d->nx || cy >= d->ny || cz >= d->nz) continue;
+          const long long node = (cz * d->ny + cy) * d->nx + cx;
+          for (int t = 0; t < kTypes; ++t) put(((long long)t * nodes + cell) * 8 + c, maps[t * nodes + node]);
+          put(ed + cell * 16 + 2 * c, maps[kTypes * nodes + node]);
+          put(ed + cell * 16 + 2 * c + 1, maps[(kTypes + 1) * nodes + node]);
+        }
+      }
+  const void* src = stored == MD_MAP_FP32 ? static_cast<const void*>(f32.data()) : static_cast<const void*>(f16.data());
   md_receptor* r = new (std::nothrow) md_receptor();
   if (!r) return fail(MD_ENOMEM, "md_receptor_create: out of host memory");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   hipError_t e = hipGetDevice(&r->device);
-  if (e == hipSuccess) e = hipMalloc(&r->d_maps, count * elem);
-  if (e == hipSuccess) e = hipMemcpyAsync(r->d_maps, src, count * elem, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMalloc(&r->d_maps, dcount * elem);
+  if (e == hipSuccess) e = hipMemcpyAsync(r->d_maps, src, dcount * elem, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     if (r->d_maps) (void)hipFree(r->d_maps);
@@ -255,7 +272,7 @@ md_status md_receptor_create(const md_grid_desc* d, const float* maps, md_map_pr
   R.inv_h = 1.0f / d->spacing;
   R.map_stride = nodes;
   R.maps = r->d_maps;
-  R.map_bytes = (unsigned)(count * elem);
+  R.map_bytes = (unsigned)(dcount * elem);
   R.gx_max = (float)(d->nx - 1);
   R.gy_max = (float)(d->ny - 1);
   R.gz_max = (float)(d->nz - 1);

@@ -17,6 +17,9 @@ constexpr int kMaxTorsions = 32;
 constexpr int kMaxGenes = 7 + kMaxTorsions;
 constexpr int kTypes = 7;
 constexpr int kMaps = kTypes + 2;
+// stored values per grid cell record: eight corners of each type map, eight corner pairs of the
+// electrostatic and desolvation maps
+constexpr int kCellValues = kTypes * 8 + 16;
 constexpr int kWavesPerBlock = 4;                  // blocks of the kernels without a ligand plan
 constexpr int kBlock = kWave * kWavesPerBlock;
 // evaluation kernels: the plan's waves per block; one atom per lane takes at most 128 VGPRs
@@ -93,9 +96,11 @@ struct RecDev {
   int precision;              // 0 fp32, 1 fp16, 2 bf16
   float ox, oy, oz;
   float h, inv_h;
-  long long map_stride;       // nx*ny*nz
-  const void* maps;           // [7][nz][ny][nx] type maps, then [nz][ny][nx][2] (electrostatic,
-                              // desolvation) interleaved per node
+  long long map_stride;       // cell records per type map: nx*ny*nz (a cell is named by its
+                              // lowest node, x fastest)
+  const void* maps;           // [7][cells][8] type-map corner records, then [cells][8][2]
+                              // (electrostatic, desolvation) corner pairs; corner bit 0 +x,
+                              // bit 1 +y, bit 2 +z
   unsigned map_bytes;         // bytes of the map allocation (< 2^31: the kernels address it with
                               //     32-bit buffer offsets)
   float gx_max, gy_max, gz_max;   // n - 1 per axis: inside iff 0 <= g < n - 1 (grid units)

@@ -214,7 +214,7 @@ __device__ __forceinline__ BlockLds stage_block(const LigDev& L) {
 template <int A>
 struct AtomRegs {
   float px[A], py[A], pz[A], q[A];
-  uint32_t tofs[A];          // element offset of the atom's type map
+  uint32_t tofs[A];          // record offset of the atom's type map (type * cells)
   uint32_t mask[A];
   bool valid[A];
   int gene_of_tor;
@@ -288,10 +288,10 @@ struct GridFetch {
   bool inside;
 };
 
-// tofs: the element offset of the atom's type map.  The corner pairs along x are single loads:
-// 8 (FP32) or 4 (FP16/BF16) bytes of the type map, 16 or 8 bytes of the interleaved electrostatic
-// and desolvation maps; the +y corners take a per-lane offset, the +z corners and the interleaved
-// maps' base the scalar offset.
+// tofs: the record offset of the atom's type map (type * cells).  A cell's corner values are
+// contiguous: 32 (FP32) or 16 bytes of the type map's record, 64 or 32 of the electrostatic and
+// desolvation pairs, read with 16-byte loads whose record-internal steps, and the pairs' base,
+// sit in the scalar offset.
 template <int PREC>
 __device__ __forceinline__ void grid_fetch(const RecDev& R, __amdgpu_buffer_rsrc_t rs, float x, float y, float z,
                                            uint32_t tofs, float q, bool valid, GridFetch& g) {
@@ -312,37 +312,39 @@ __device__ __forceinline__ void grid_fetch(const RecDev& R, __amdgpu_buffer_rsrc
     g.fx = __builtin_amdgcn_fractf(gx);   // gx - floor(gx), exact
     g.fy = __builtin_amdgcn_fractf(gy);
     g.fz = __builtin_amdgcn_fractf(gz);
-    const uint32_t nx = (uint32_t)R.nx, nxy = (uint32_t)R.nx * (uint32_t)R.ny;
-    const uint32_t base = (iz * (uint32_t)R.ny + iy) * nx + ix;
-    const uint32_t ot = (base + tofs) * ES, ot1 = ot + nx * ES;        // type map, rows y and y+1
-    const uint32_t oe = base * (2 * ES), oe1 = oe + nx * (2 * ES);     // interleaved maps
-    const uint32_t sz = nxy * ES;                                       // +z, type map
-    const uint32_t se = (uint32_t)kTypes * (uint32_t)R.map_stride * ES;   // interleaved maps' base
-    const uint32_t sez = se + 2 * sz;
+    const uint32_t cell = (iz * (uint32_t)R.ny + iy) * (uint32_t)R.nx + ix;
+    const uint32_t ot = (tofs + cell) * (8 * ES);                        // type-map record
+    const uint32_t oe = cell * (16 * ES);                                // corner pairs
+    const uint32_t se = (uint32_t)kTypes * (uint32_t)R.map_stride * (8 * ES);   // pairs' base
     if constexpr (PREC == 0) {
-      const uint32_t o[4] = {ot, ot1, ot, ot1}, so[4] = {0u, 0u, sz, sz};
-      const uint32_t oq[4] = {oe, oe1, oe, oe1}, sq[4] = {se, se, sez, sez};
+      const auto t0 = __builtin_amdgcn_raw_buffer_load_b128(rs, ot, 0u, 0);
+      const auto t1 = __builtin_amdgcn_raw_buffer_load_b128(rs, ot, 16u, 0);
+      uint32_t v[16];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const auto w = __builtin_amdgcn_raw_buffer_load_b128(rs, oe, se + 16u * k, 0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[4 * k + u] = w[u];
+      }
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const auto t = __builtin_amdgcn_raw_buffer_load_b64(rs, o[c], so[c], 0);
-        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, oq[c], sq[c], 0);
-        g.mt[2 * c] = __uint_as_float(t[0]);
-        g.mt[2 * c + 1] = __uint_as_float(t[1]);
-        g.me[2 * c] = __uint_as_float(v[0]);
-        g.md[2 * c] = __uint_as_float(v[1]);
-        g.me[2 * c + 1] = __uint_as_float(v[2]);
-        g.md[2 * c + 1] = __uint_as_float(v[3]);
+        g.mt[c] = __uint_as_float(t0[c]);
+        g.mt[4 + c] = __uint_as_float(t1[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        g.me[c] = __uint_as_float(v[2 * c]);
+        g.md[c] = __uint_as_float(v[2 * c + 1]);
       }
     } else {
-      const uint32_t o[4] = {ot, ot1, ot, ot1}, so[4] = {0u, 0u, sz, sz};
-      const uint32_t oq[4] = {oe, oe1, oe, oe1}, sq[4] = {se, se, sez, sez};
+      const auto t = __builtin_amdgcn_raw_buffer_load_b128(rs, ot, 0u, 0);
+      const auto w0 = __builtin_amdgcn_raw_buffer_load_b128(rs, oe, se, 0);
+      const auto w1 = __builtin_amdgcn_raw_buffer_load_b128(rs, oe, se + 16u, 0);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const uint32_t t = __builtin_amdgcn_raw_buffer_load_b32(rs, o[c], so[c], 0);
-        const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, oq[c], sq[c], 0);
-        unpack2<PREC>(t, g.mt[2 * c], g.mt[2 * c + 1]);
-        unpack2<PREC>(v[0], g.me[2 * c], g.md[2 * c]);
-        unpack2<PREC>(v[1], g.me[2 * c + 1], g.md[2 * c + 1]);
+      for (int k = 0; k < 4; ++k) {
+        unpack2<PREC>(t[k], g.mt[2 * k], g.mt[2 * k + 1]);
+        unpack2<PREC>(w0[k], g.me[k], g.md[k]);
+        unpack2<PREC>(w1[k], g.me[4 + k], g.md[4 + k]);
       }
     }
   }
