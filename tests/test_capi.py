@@ -110,6 +110,12 @@ def test_receptor_validation_on_host(md):
     big[0, 0, 0, 0] = 1e6
     assert lib.md_receptor_create(C.byref(d), md.mdock._fptr(big), 1, None, C.byref(h)) == -2
     assert lib.md_receptor_create(C.byref(d), md.mdock._fptr(maps), 7, None, C.byref(h)) == -1
+    # cell records of 72 stored values per node must stay below 2 GiB (checked before any map
+    # value is read): 196^3 nodes in FP32 and 247^3 in FP16 are past it
+    for n, prec in ((196, 0), (247, 1)):
+        huge = md.mdock.GridDesc(n, n, n, 0.375, (C.c_float * 3)(0, 0, 0), 7)
+        assert lib.md_receptor_create(C.byref(huge), md.mdock._fptr(maps), prec, None, C.byref(h)) == md.mdock.MD_ERANGE
+        assert "2 GiB" in lib.md_last_error().decode()
     assert not h.value
 
 
