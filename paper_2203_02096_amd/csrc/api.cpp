@@ -223,10 +223,14 @@ md_status md_receptor_create(const md_grid_desc* d, const float* maps, md_map_pr
   const long long dcount = nodes * kCellValues;
   std::vector<float> f32;
   std::vector<uint16_t> f16;
-  if (stored == MD_MAP_FP32)
-    f32.assign((size_t)dcount, 0.f);
-  else
-    f16.assign((size_t)dcount, 0);
+  try {
+    if (stored == MD_MAP_FP32)
+      f32.assign((size_t)dcount, 0.f);
+    else
+      f16.assign((size_t)dcount, 0);
+  } catch (const std::bad_alloc&) {
+    return fail(MD_ENOMEM, "md_receptor_create: out of host memory for the cell records");
+  }
   auto put = [&](long long k, float v) {
     if (stored == MD_MAP_FP32)
       f32[(size_t)k] = v;
