@@ -22,7 +22,8 @@ torch = pytest.importorskip("torch")
 SPACING = 0.375
 ORIGIN = (1.5, -2.0, 0.25)
 # (nx, ny, nz, storage precision)
-GRIDS = [(11, 13, 17, "fp32"), (11, 13, 17, "fp16"), (11, 13, 17, "bf16"), (64, 64, 64, "fp32"), (96, 96, 96, "fp16")]
+GRIDS = [(11, 13, 17, "fp32"), (11, 13, 17, "fp16"), (11, 13, 17, "bf16"), (64, 64, 64, "fp32"), (96, 96, 96, "fp16"),
+         (2, 3, 4, "fp32"), (2, 2, 2, "bf16")]   # the smallest grids: one or a few cells, most corners past the end
 
 
 def _say(*a):
