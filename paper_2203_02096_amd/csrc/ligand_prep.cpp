@@ -199,8 +199,9 @@ std::string prepare_ligand(int n, const float* xyz, const int* type, const float
 
 // Pair schedule: rows of 64 slots, lanes split into groups of about N/div lanes in which no atom
 // occurs twice per row (so the kernel's per-group force updates never collide).  Greedy row by
-// row: the remaining pairs whose atoms have the most pairs left go first, each into the first
-// group where both of its atoms are still free.  The H-bond pairs go into the first rows (their
+// row: the remaining pairs whose atoms have the most pairs left go first, each into a group where
+// both of its atoms are still free, either way round, chosen to keep the row's LDS accesses
+// spread over the banks (a slot's atoms are symmetric in the kernel).  The H-bond pairs go into the first rows (their
 // free slots then take other pairs), so the rows after them need no per-slot choice between the
 // 12-6 and 12-10 forms; when that layout takes more rows than one sequence of all pairs, the
 // latter is used and every row up to the last H-bond pair is mixed (mix_rows).  Empty slots name
@@ -229,23 +230,79 @@ void plan_ligand(LigHost& out, const PlanParams& pp) {
     ++left[v & 0xff];
     ++left[(v >> 8) & 0xff];
   }
-  // One row under construction: its slots, the atoms each lane group already holds, and how far
-  // each group is filled.
+  // LDS banks (32 four-byte banks, 32 lanes served at a time): the pair loop reads a slot's two
+  // atoms' x and y with one two-word load and z with another, from the coordinates and from its
+  // group's force copy (read, then written back).  Word w of an access lies in bank w mod 32.
+  const int pitch = lds_pitch(A);
+  const int copy_words = (int)(lds_coord_bytes(A) / 4);
+  // One row under construction: its slots (and which were turned round), the atoms each lane
+  // group already holds, how far each group is filled, and per half-row the number of words each
+  // of the row's eight accesses (i or j atom; coordinates or force copy; x-y pair or z) places in
+  // each bank, with the largest of those counts.
   struct Row {
     std::vector<int> slot;
+    std::vector<uint8_t> flip;
     std::vector<uint64_t> used;
     std::vector<int> fill;
+    std::vector<uint8_t> bank;   // [2 halves][8 accesses][32 banks]
+    std::vector<uint8_t> top;    // [2 halves][8 accesses]
   };
   auto new_row = [&]() {
     Row r;
     r.slot.assign(kWave, -1);
+    r.flip.assign(kWave, 0);
     r.used.assign(2 * K, 0);
     r.fill.resize(K);
     for (int g = 0; g < K; ++g) r.fill[g] = g * m;
+    r.bank.assign(2 * 8 * 32, 0);
+    r.top.assign(2 * 8, 0);
     return r;
   };
-  // places what fits of `rem` into the row (the pairs whose atoms have the most pairs left first,
-  // each into the first group where both atoms are still free) and keeps the rest in `rem`
+  // the words atom a touches through access group (coordinates x-y, z; force copy x-y, z) in lane
+  // group g
+  auto words = [&](int a, int g, int k, int* w) {
+    const int base = (k >= 2 ? g * copy_words : 0) + a;
+    if ((k & 1) == 0) {
+      w[0] = base;
+      w[1] = base + pitch;
+      return 2;
+    }
+    w[0] = base + 2 * pitch;
+    return 1;
+  };
+  // growth of the row's bank-conflict cycles (force copies count twice: read and write) if atom a
+  // (side 0) and atom b (side 1) took a slot of group g in half h
+  auto growth = [&](const Row& row, int h, int g, int a, int b) {
+    int inc = 0;
+    for (int side = 0; side < 2; ++side)
+      for (int k = 0; k < 4; ++k) {
+        int w[2];
+        const int nw = words(side == 0 ? a : b, g, k, w);
+        const int acc = h * 8 + side * 4 + k;
+        int top = row.top[acc];
+        for (int q = 0; q < nw; ++q) top = std::max(top, (int)row.bank[acc * 32 + (w[q] & 31)] + 1);
+        inc += (top - row.top[acc]) * (k >= 2 ? 2 : 1);
+      }
+    return inc;
+  };
+  auto take = [&](Row& row, int h, int g, int a, int b) {
+    for (int side = 0; side < 2; ++side)
+      for (int k = 0; k < 4; ++k) {
+        int w[2];
+        const int nw = words(side == 0 ? a : b, g, k, w);
+        const int acc = h * 8 + side * 4 + k;
+        for (int q = 0; q < nw; ++q) {
+          uint8_t& c = row.bank[acc * 32 + (w[q] & 31)];
+          ++c;
+          row.top[acc] = std::max(row.top[acc], c);
+        }
+      }
+  };
+  // places what fits of `rem` into the row (the pairs whose atoms have the most pairs left
+  // first) and keeps the rest in `rem`.  A pair may go into any group where both its atoms are
+  // still free, either way round: of the groups already in use and the first free one, the group
+  // and orientation that add the fewest bank-conflict cycles to the row (ties: the earlier group,
+  // the pair as listed).
   auto fill_row = [&](Row& row, std::vector<int>& rem, std::vector<int>& left, int& groups_used) {
     std::stable_sort(rem.begin(), rem.end(), [&](int x, int y) {
       const uint32_t a = out.raw_ij[x], b = out.raw_ij[y];
@@ -254,22 +311,38 @@ void plan_ligand(LigHost& out, const PlanParams& pp) {
     std::vector<int> next;
     for (int p : rem) {
       const int i = out.raw_ij[p] & 0xff, j = (out.raw_ij[p] >> 8) & 0xff;
-      bool placed = false;
-      for (int g = 0; g < K && !placed; ++g) {
+      int best_g = -1, best_flip = 0, best_inc = 0;
+      for (int g = 0; g < K; ++g) {
         const int end = std::min(kWave, (g + 1) * m);
         const bool bi = (row.used[2 * g + (i >> 6)] >> (i & 63)) & 1u;
         const bool bj = (row.used[2 * g + (j >> 6)] >> (j & 63)) & 1u;
-        if (row.fill[g] < end && !bi && !bj) {
-          row.slot[row.fill[g]++] = p;
-          row.used[2 * g + (i >> 6)] |= 1ull << (i & 63);
-          row.used[2 * g + (j >> 6)] |= 1ull << (j & 63);
-          --left[i];
-          --left[j];
-          groups_used = std::max(groups_used, g + 1);
-          placed = true;
+        if (row.fill[g] >= end || bi || bj) continue;
+        // beyond the groups in use only the first free one, so no more force copies are needed
+        // than a first-fit placement would use
+        if (best_g >= 0 && g >= groups_used) break;
+        const int h = row.fill[g] < 32 ? 0 : 1;
+        for (int f = 0; f < 2; ++f) {
+          const int inc = f == 0 ? growth(row, h, g, i, j) : growth(row, h, g, j, i);
+          if (best_g < 0 || inc < best_inc) {
+            best_g = g;
+            best_flip = f;
+            best_inc = inc;
+          }
         }
       }
-      if (!placed) next.push_back(p);
+      if (best_g < 0) {
+        next.push_back(p);
+        continue;
+      }
+      const int g = best_g, h = row.fill[g] < 32 ? 0 : 1;
+      take(row, h, g, best_flip ? j : i, best_flip ? i : j);
+      row.flip[row.fill[g]] = (uint8_t)best_flip;
+      row.slot[row.fill[g]++] = p;
+      row.used[2 * g + (i >> 6)] |= 1ull << (i & 63);
+      row.used[2 * g + (j >> 6)] |= 1ull << (j & 63);
+      --left[i];
+      --left[j];
+      groups_used = std::max(groups_used, g + 1);
     }
     rem.swap(next);
   };
@@ -318,7 +391,9 @@ void plan_ligand(LigHost& out, const PlanParams& pp) {
   const uint32_t pad = kPairPad | (uint32_t)n | ((uint32_t)n << 8);
   for (const Row& r : rows)
     for (int l = 0; l < kWave; ++l) {
-      ij.push_back(r.slot[l] < 0 ? pad : out.raw_ij[r.slot[l]]);
+      uint32_t v = r.slot[l] < 0 ? pad : out.raw_ij[r.slot[l]];
+      if (r.slot[l] >= 0 && r.flip[l]) v = (v & ~0xffffu) | ((v & 0xffu) << 8) | ((v >> 8) & 0xffu);
+      ij.push_back(v);
       coef.push_back(r.slot[l] < 0 ? make_float4(0.f, 0.f, 0.f, 0.f) : out.raw_coef[r.slot[l]]);
     }
   out.n_pairs = P;
