@@ -170,3 +170,41 @@ def test_widest_blocks(n, t):
     info, _, _ = md.md_schedule_preview(lig, lds_budget=160 * 1024, waves_per_block=16)
     assert info["waves_per_block"] == (16 if n <= 64 else 12)
     assert info["lds_bytes"] <= 160 * 1024
+
+
+def _bank_cycles_per_row(slots, m, n_atoms):
+    """LDS cycles one row's pair loop spends, per a model of the LDS: 32 four-byte banks serving 32
+    lanes at a time, each access taking as many cycles as its busiest bank has distinct words.
+    Per half-row and atom side: the x-y pair and z of the coordinates (pitch 64A + 1 words) and of
+    the lane group's force copy (read and written, so twice)."""
+    A = 2 if n_atoms > 64 else 1
+    pitch = 64 * A + 1
+    copy = ((12 * pitch + 15) // 16 * 16) // 4
+    group = np.arange(64) // m
+    rows = slots.reshape(-1, 64)
+    total = 0
+    for row in rows:
+        for atoms in (row & 0xFF, (row >> 8) & 0xFF):
+            for h in (slice(0, 32), slice(32, 64)):
+                a, g = atoms[h].astype(np.int64), group[h]
+                for base, weight in ((a, 1), (a + g * copy, 2)):
+                    for words in (np.concatenate([base, base + pitch]), base + 2 * pitch):
+                        w = np.unique(words)
+                        total += weight * np.bincount(w % 32, minlength=32).max()
+    return total / len(rows)
+
+
+# (atoms, torsions, seed, modelled cycles per row of a first-fit placement of the same pairs:
+# each pair, in the same priority order, into the first group where both its atoms are free)
+BANK_CASES = [(73, 14, 11, 72.1), (87, 17, 12, 78.5), (90, 20, 13, 79.4), (120, 24, 14, 86.3)]
+
+
+@pytest.mark.parametrize("n,t,seed,first_fit", BANK_CASES)
+def test_pair_rows_spread_over_lds_banks(n, t, seed, first_fit):
+    """The row builder places each pair in the group and orientation that add the fewest LDS
+    bank-conflict cycles (ideal: 36 per row).  For ligands of two atoms per lane it keeps the
+    modelled cycles per row at least 10 % below a first-fit placement's."""
+    lig = synth.make_ligand(n, t, 9100 + seed, configs.type_params())
+    info, slots, m = md.md_schedule_preview(lig, group_div=2)
+    assert m == 32
+    assert _bank_cycles_per_row(slots, m, n) < 0.9 * first_fit
