@@ -188,9 +188,10 @@ md_status md_ligand_autotune(const md_receptor* rec, md_ligand* lig, int n_start
 /* Host only (no device needed): the pair schedule that `plan` gives the ligand `d`, for tests and
  * inspection.  On input plan->lds_budget / group_div / waves_per_block; on output the layout
  * fields.  pair_slots (may be NULL) receives min(capacity, total_rows*64) slots, row-major, each
- * i | j << 8 | hbond << 16 in the library's internal atom order, with bit 17 set for an empty
- * slot (which names atom n_atoms at both ends); *group_lanes (may be NULL) the lanes per
- * conflict-free group.  Errors as md_ligand_create, plus MD_ERANGE for a bad plan. */
+ * i | j << 8 | hbond << 16 in the library's internal atom order (a pair may appear either way
+ * round: the schedule orients each slot to spread the row's LDS accesses over the banks), with
+ * bit 17 set for an empty slot (which names atom n_atoms at both ends); *group_lanes (may be
+ * NULL) the lanes per conflict-free group.  Errors as md_ligand_create, plus MD_ERANGE for a bad plan. */
 md_status md_schedule_preview(const md_ligand_desc* d, md_plan* plan, unsigned* pair_slots, int capacity,
                               int* group_lanes);
 md_status md_tune_table_clear(void);   /* forget every tuned size class */
